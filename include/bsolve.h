@@ -1,0 +1,240 @@
+/*
+ * bsolve.h -- C ABI of the MI355X bilateral-space solver.
+ *
+ * Implements the bilateral solver of Barron & Poole, "The Fast Bilateral
+ * Solver": build a simplified bilateral grid from a reference image
+ * (Section 2, Eq. factorization and Eq. equiv), bistochastize its blur
+ * (supplement Algorithm 1), solve A y = b with
+ *     A = lam (D_m - D_n B D_n) + diag(S c),   b = S (c o t)   (Eq. quad_min)
+ * by preconditioned conjugate gradients (supplement Algorithm 2) with the
+ * Jacobi preconditioner and flat or hierarchical initialisation (Section 4,
+ * supplement Section 2), slice y back to pixels (Eq. solution), and
+ * back-propagate onto the target and confidence (Section 3).
+ *
+ * Conventions shared by every entry point:
+ *  - Pointers named as device pointers must point to device memory of the
+ *    GPU current on the calling thread; the caller allocates and owns all of
+ *    it.  No entry point allocates device memory.  Buffers must be 4-byte
+ *    aligned, workspaces 256-byte aligned.
+ *  - `stream` is a hipStream_t (NULL = the default stream).  Every entry point
+ *    except bs_grid_vertex_count and bs_read_counters only enqueues work on
+ *    `stream` and returns; results are ready when the stream reaches them.
+ *  - Arguments are validated on the host before anything is enqueued.  On an
+ *    error nothing is launched, outputs are untouched and bs_last_error()
+ *    returns a description (thread-local).
+ *  - Images are planar float32: reference [3][H][W] (R, G, B in [0, 1]),
+ *    target [C][H][W], confidence [H][W].  Bilateral-space vectors are
+ *    vertex-major float32 [V][C] (channels contiguous per vertex) with
+ *    room for Vcap = H*W vertices.
+ *  - Readings of passages the paper leaves open (colour space, rounding,
+ *    vertex order, blur form, stopping rules) are documented with the
+ *    operation they affect below.
+ */
+#ifndef BSOLVE_H
+#define BSOLVE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum bs_status {
+    BS_OK = 0,
+    BS_EINVAL = -1,        /* an argument is invalid                            */
+    BS_EWORKSPACE = -2,    /* a workspace is smaller than its query returned     */
+    BS_EDEVICE = -3,       /* a HIP call failed; bs_last_error() holds its text  */
+    BS_EUNSUPPORTED = -4   /* valid but outside what this library implements     */
+} bs_status;
+
+#define BS_MAX_CHANNELS 64
+#define BS_MAX_LEVELS 24
+#define BS_GRID_BYTES 4096
+
+/* Grid scales of the bilateral affinity (Section 2, Eq. bilateral_affinity):
+ * sigma_xy in pixels, sigma_l and sigma_uv in 8-bit colour codes.  All three
+ * are positive integers (sigma_xy <= 128, colour scales <= 255). */
+typedef struct bs_grid_params {
+    int32_t sigma_xy;
+    int32_t sigma_l;
+    int32_t sigma_uv;
+} bs_grid_params;
+
+/* Bistochastization (supplement Algorithm 1).  The iteration
+ *     n <- sqrt(n o m / (B n)),  n = 1 initially
+ * stops when max_v |n_v (B n)_v - m_v| / m_v <= tol or after max_iters
+ * updates.  `check_every` > 0 makes the host read the device-side stop flag
+ * after every `check_every` launches (a stream synchronisation); 0 enqueues
+ * all max_iters + 1 launches without any synchronisation (graph-capturable;
+ * launches after convergence do nothing). */
+typedef struct bs_bistoch_params {
+    int32_t max_iters;     /* default 200   */
+    int32_t check_every;   /* default 8     */
+    double tol;            /* default 1e-10 */
+} bs_bistoch_params;
+
+enum { BS_INIT_FLAT = 0, BS_INIT_HIER = 1 };
+
+/* The solve (Eq. quad_min, supplement Algorithm 2, Section 4).
+ * One PCG per channel with its own scalars.  A channel stops when its
+ * recursive ||r|| / ||b|| <= rel_tol (rel_tol = 0: never), after max_iters
+ * iterations, when r^T s = 0, or when d^T A d <= 0.  `check_every` works as
+ * for bistochastization: > 0 polls the all-channels-done flag every that many
+ * iterations, 0 enqueues exactly max_iters iterations. */
+typedef struct bs_solve_params {
+    float lambda;          /* smoothness multiplier, >= 0                       */
+    int32_t init;          /* BS_INIT_FLAT or BS_INIT_HIER (default)            */
+    int32_t max_iters;     /* PCG iterations cap (the paper's default is 25)    */
+    int32_t check_every;   /* default 8                                         */
+    double rel_tol;        /* relative residual target, 0 = fixed iterations    */
+    float init_alpha;      /* hierarchical init level weighting, default 4      */
+    float init_beta;       /* default 0                                         */
+} bs_solve_params;
+
+/* Per-channel outcome, written to device memory by a solve. */
+typedef struct bs_chan_stats {
+    int32_t iters;         /* PCG iterations performed                          */
+    int32_t reason;        /* 0 running, 1 tolerance met, 2 max_iters, 3 r^T s = 0,
+                              4 d^T A d <= 0, 5 b = 0                           */
+    double rel_residual;   /* recursive ||r|| / ||b|| at exit                   */
+    double bnorm;          /* ||b||                                             */
+} bs_chan_stats;
+
+/* A grid handle: a host-side plain struct holding the grid's dimensions and
+ * device pointers into the workspace given to bs_build_grid.  Copyable; the
+ * workspace must outlive every use.  There is no destroy call. */
+typedef struct bs_grid {
+    uint64_t opaque[BS_GRID_BYTES / 8];
+} bs_grid;
+
+/* Device pointers to a built grid's arrays, for inspection and tests.
+ * counts (int32, device): [0] V, [1] K, [2] bistochastization updates,
+ * [3] bistochastization done flag, [4] ping-pong buffer of the final n,
+ * [8 + k] V_k for k < levels (0 for levels above K). */
+typedef struct bs_grid_view {
+    int32_t H, W, P, levels;           /* levels = capacity of the pyramid (K <= levels - 1) */
+    int32_t ncells_x, ncells_y;        /* spatial cells of level 0                          */
+    int64_t vcap;                      /* capacity of level-0 vertex arrays                  */
+    const int32_t* counts;
+    const double* bist_residual;       /* [1] device                                        */
+    const uint64_t* key;               /* [vcap] packed (y:16 x:16 l:8 u:8 v:8), ascending   */
+    const int32_t* idx;                /* [P] vertex of each pixel (S as an index)           */
+    const int32_t* m;                  /* [vcap] pixels per vertex, m = S 1                  */
+    const int32_t* nbr;                /* [10][vcap] neighbour id or -1, slot 2d: -1 step and
+                                          2d+1: +1 step along dim d of (y, x, l, u, v)       */
+    const int32_t* pix_ptr;            /* [vcap + 1] CSR of pixels per vertex                */
+    const int32_t* pix_list;           /* [P] pixel ids, ascending within each vertex        */
+    const double* n;                   /* [vcap] bistochastization vector n                   */
+    const float* nf;                   /* [vcap] n rounded to float                          */
+    const double* nn;                  /* [vcap] n o (N n), the smoothness diagonal / lam    */
+    int64_t level_cap[BS_MAX_LEVELS];  /* capacity of level-k arrays                         */
+    const uint64_t* level_key[BS_MAX_LEVELS];   /* [k >= 1] keys of level k                  */
+    const int32_t* parent[BS_MAX_LEVELS];       /* [k < levels-1] level-k vertex -> level k+1 */
+    const int32_t* ones[BS_MAX_LEVELS];         /* [k >= 1] level-0 vertices under each vertex (P(1)) */
+} bs_grid_view;
+
+/* ---------------------------------------------------------------------- */
+/* Grid construction: supplement Section 1 (simplified bilateral grid,     */
+/* Eq. SS) and Section 2 (bilateral pyramid).                              */
+/* ---------------------------------------------------------------------- */
+
+/* Bytes of device workspace bs_build_grid needs for an H x W image (host,
+ * pure).  Returns 0 for invalid arguments. */
+size_t bs_grid_workspace_bytes(int32_t H, int32_t W, const bs_grid_params* params);
+
+/* Builds the simplified bilateral grid of `ref` and its pyramid.
+ *  ref  device float32 [3][H][W], RGB in [0, 1].
+ * Each pixel is quantised to 8 bits (clamp(floor(255 v + 1/2), 0, 255), NaN
+ * -> 0), converted to JFIF (BT.601 full-range) YCbCr in 16.16 fixed point, and
+ * mapped to the integer grid coordinates round_half_up(v / sigma) of
+ * (y, x, l=Y, u=Cb, v=Cr).  Vertices are the distinct coordinates in ascending
+ * (y, x, l, u, v) order; each pixel lies on exactly one vertex (S S^T = D_m).
+ * The blur B is the sum over the five dimensions of [1 2 1] blurs (diagonal
+ * 10, neighbours missing from the grid contribute 0).  Pyramid level k+1
+ * halves level-k coordinates (floor) until one vertex remains.
+ *  ws   device workspace of bs_grid_workspace_bytes(H, W, params) bytes; the
+ *       grid lives in it.
+ *  out  host struct receiving the handle. */
+bs_status bs_build_grid(const float* ref, int32_t H, int32_t W, const bs_grid_params* params,
+                        void* ws, size_t ws_bytes, void* stream, bs_grid* out);
+
+/* Bistochastizes the grid's blur in float64 (supplement Algorithm 1), storing
+ * n, its float copy and n o (N n) in the grid.  Must follow bs_build_grid on
+ * the same stream. */
+bs_status bs_bistochastize(bs_grid* grid, const bs_bistoch_params* params, void* stream);
+
+/* ---------------------------------------------------------------------- */
+/* Solve, slice and backward: Eq. quad_min, Eq. solution, Section 3/4.     */
+/* ---------------------------------------------------------------------- */
+
+/* Bytes of device workspace bs_solve / bs_solve_backward need for C channels
+ * (host, pure).  Returns 0 for invalid arguments. */
+size_t bs_solve_workspace_bytes(const bs_grid* grid, int32_t C);
+
+/* Solves A y = b for C channels sharing the confidence (supplement Section 4).
+ *  target  device float32 [C][H][W];  conf device float32 [H][W], >= 0.
+ *  y       device float32 [Vcap][C] output: the bilateral-space solution.
+ *  stats   device bs_chan_stats [C] output, or NULL.
+ * S c and b = S (c o t) are deterministic per-vertex sums in ascending pixel
+ * order; diag(A) = lam n o (N n) + S c (the value of lam (m - 10 n^2) + S c at
+ * the bistochastization fixed point, free of cancellation); the Jacobi inverse
+ * is 0 where diag(A) <= 0.  Flat init is S(c t)/S(c) (0 where S c = 0); the
+ * hierarchical init is P^T(w P(b)/P(1)) / P^T(w P(S c)/P(1)) with
+ * w_0 = 1, w_k = alpha^-(beta + k); all-zero confidence gives y0 = 0.
+ * Dot products are accumulated in float64; vectors are float32. */
+bs_status bs_solve(const bs_grid* grid, const float* target, const float* conf, int32_t C,
+                   const bs_solve_params* params, float* y, void* ws, size_t ws_bytes,
+                   bs_chan_stats* stats, void* stream);
+
+/* Slices y [Vcap][C] back to pixels: x[c][p] = y[idx[p]][c] (Eq. solution).
+ *  x  device float32 [C][H][W] output. */
+bs_status bs_slice(const bs_grid* grid, const float* y, int32_t C, float* x, void* stream);
+
+/* Back-propagates dL/dx through the solver (Section 3):
+ *  u = S dL/dx,  g = A^{-1} u  (same A, preconditioner and init operator),
+ *  dL/dt[c][p] = conf[p] g[idx[p]][c],
+ *  dL/dconf[p] = sum_c g[idx[p]][c] (t[c][p] - y_hat[idx[p]][c]).
+ *  y_hat   device float32 [Vcap][C], the forward solution from bs_solve.
+ *  grad_x  device float32 [C][H][W].
+ *  grad_t  device float32 [C][H][W] output;  grad_c device float32 [H][W] output.
+ *  g_out   device float32 [Vcap][C] output receiving dL/db, or NULL. */
+bs_status bs_solve_backward(const bs_grid* grid, const float* target, const float* conf,
+                            const float* y_hat, const float* grad_x, int32_t C,
+                            const bs_solve_params* params, float* grad_t, float* grad_c,
+                            float* g_out, void* ws, size_t ws_bytes, bs_chan_stats* stats,
+                            void* stream);
+
+/* ---------------------------------------------------------------------- */
+/* Queries and diagnostics.                                                */
+/* ---------------------------------------------------------------------- */
+
+/* Copies the grid's device counters (see bs_grid_view.counts) to host
+ * `out[n]`; synchronises `stream`. */
+bs_status bs_read_counters(const bs_grid* grid, int32_t* out, int32_t n, void* stream);
+
+/* Number of vertices V of a built grid; synchronises `stream`. */
+bs_status bs_grid_vertex_count(const bs_grid* grid, int32_t* V, void* stream);
+
+/* Fills `view` with the grid's device pointers and capacities (host only). */
+bs_status bs_grid_get_view(const bs_grid* grid, bs_grid_view* view);
+
+/* Device pointers into a solve workspace, valid after bs_solve: the splatted
+ * right-hand side b [Vcap][C] (after bs_solve_backward: u = S dL/dx), S c
+ * [Vcap], diag(A) [Vcap] and the Jacobi inverse [Vcap] (host only; for
+ * inspection and tests).  Run bs_solve with max_iters = 0 to obtain the
+ * initial state y0 in y. */
+bs_status bs_solve_ws_view(const bs_grid* grid, int32_t C, void* ws, size_t ws_bytes,
+                           const float** b, const float** sc, const float** diag,
+                           const float** minv);
+
+const char* bs_status_string(bs_status status);
+const char* bs_last_error(void);
+/* Library ABI version, (major << 16) | minor. */
+int32_t bs_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BSOLVE_H */

@@ -1,0 +1,115 @@
+"""ctypes binding of libbsolve.so (the C ABI declared in include/bsolve.h).
+
+Argument marshalling only: every step of the solver runs in the HIP library.
+Importing this module loads the library and fails loudly if it is missing.
+"""
+from __future__ import annotations
+
+import ctypes as ct
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libbsolve.so")
+
+BS_OK, BS_EINVAL, BS_EWORKSPACE, BS_EDEVICE, BS_EUNSUPPORTED = 0, -1, -2, -3, -4
+BS_MAX_CHANNELS = 64
+BS_MAX_LEVELS = 24
+BS_GRID_BYTES = 4096
+BS_INIT_FLAT, BS_INIT_HIER = 0, 1
+
+# Slots of the device counter array.
+CNT_V, CNT_K, CNT_BIST_ITERS, CNT_BIST_DONE, CNT_BIST_SRC, CNT_LEVEL0 = 0, 1, 2, 3, 4, 8
+
+REASONS = {0: "running", 1: "tolerance", 2: "max_iters", 3: "rho_zero", 4: "breakdown", 5: "b_zero"}
+
+
+class GridParams(ct.Structure):
+    _fields_ = [("sigma_xy", ct.c_int32), ("sigma_l", ct.c_int32), ("sigma_uv", ct.c_int32)]
+
+
+class BistochParams(ct.Structure):
+    _fields_ = [("max_iters", ct.c_int32), ("check_every", ct.c_int32), ("tol", ct.c_double)]
+
+
+class SolveParams(ct.Structure):
+    _fields_ = [("lambda_", ct.c_float), ("init", ct.c_int32), ("max_iters", ct.c_int32),
+                ("check_every", ct.c_int32), ("rel_tol", ct.c_double),
+                ("init_alpha", ct.c_float), ("init_beta", ct.c_float)]
+
+
+class ChanStats(ct.Structure):
+    _fields_ = [("iters", ct.c_int32), ("reason", ct.c_int32), ("rel_residual", ct.c_double),
+                ("bnorm", ct.c_double)]
+
+
+class Grid(ct.Structure):
+    _fields_ = [("opaque", ct.c_uint64 * (BS_GRID_BYTES // 8))]
+
+
+class GridView(ct.Structure):
+    _fields_ = [
+        ("H", ct.c_int32), ("W", ct.c_int32), ("P", ct.c_int32), ("levels", ct.c_int32),
+        ("ncells_x", ct.c_int32), ("ncells_y", ct.c_int32), ("vcap", ct.c_int64),
+        ("counts", ct.c_void_p), ("bist_residual", ct.c_void_p), ("key", ct.c_void_p),
+        ("idx", ct.c_void_p), ("m", ct.c_void_p), ("nbr", ct.c_void_p),
+        ("pix_ptr", ct.c_void_p), ("pix_list", ct.c_void_p), ("n", ct.c_void_p),
+        ("nf", ct.c_void_p), ("nn", ct.c_void_p),
+        ("level_cap", ct.c_int64 * BS_MAX_LEVELS),
+        ("level_key", ct.c_void_p * BS_MAX_LEVELS),
+        ("parent", ct.c_void_p * BS_MAX_LEVELS),
+        ("ones", ct.c_void_p * BS_MAX_LEVELS),
+    ]
+
+
+class BsError(RuntimeError):
+    def __init__(self, status: int, where: str, detail: str):
+        super().__init__(f"{where}: {detail} (status {status})")
+        self.status = status
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(
+            f"{LIB_PATH} is missing: build it with `python -m paper_1511_03296_amd.build`")
+    return ct.CDLL(LIB_PATH)
+
+
+lib = _load()
+
+_vp, _i32, _sz = ct.c_void_p, ct.c_int32, ct.c_size_t
+_SIGS = {
+    "bs_grid_workspace_bytes": (_sz, [_i32, _i32, ct.POINTER(GridParams)]),
+    "bs_build_grid": (_i32, [_vp, _i32, _i32, ct.POINTER(GridParams), _vp, _sz, _vp,
+                             ct.POINTER(Grid)]),
+    "bs_bistochastize": (_i32, [ct.POINTER(Grid), ct.POINTER(BistochParams), _vp]),
+    "bs_solve_workspace_bytes": (_sz, [ct.POINTER(Grid), _i32]),
+    "bs_solve": (_i32, [ct.POINTER(Grid), _vp, _vp, _i32, ct.POINTER(SolveParams), _vp, _vp,
+                        _sz, _vp, _vp]),
+    "bs_slice": (_i32, [ct.POINTER(Grid), _vp, _i32, _vp, _vp]),
+    "bs_solve_backward": (_i32, [ct.POINTER(Grid), _vp, _vp, _vp, _vp, _i32,
+                                 ct.POINTER(SolveParams), _vp, _vp, _vp, _vp, _sz, _vp, _vp]),
+    "bs_read_counters": (_i32, [ct.POINTER(Grid), ct.POINTER(_i32), _i32, _vp]),
+    "bs_grid_vertex_count": (_i32, [ct.POINTER(Grid), ct.POINTER(_i32), _vp]),
+    "bs_grid_get_view": (_i32, [ct.POINTER(Grid), ct.POINTER(GridView)]),
+    "bs_solve_ws_view": (_i32, [ct.POINTER(Grid), _i32, _vp, _sz, ct.POINTER(_vp),
+                                ct.POINTER(_vp), ct.POINTER(_vp), ct.POINTER(_vp)]),
+    "bs_status_string": (ct.c_char_p, [_i32]),
+    "bs_last_error": (ct.c_char_p, []),
+    "bs_version": (_i32, []),
+}
+for _name, (_res, _args) in _SIGS.items():
+    _f = getattr(lib, _name)
+    _f.restype = _res
+    _f.argtypes = _args
+
+EXPORTED = tuple(_SIGS)
+
+
+def check(status: int, where: str) -> None:
+    """Raise on a non-OK status: ValueError for invalid arguments, BsError otherwise."""
+    if status == BS_OK:
+        return
+    detail = lib.bs_last_error().decode()
+    if status == BS_EINVAL:
+        raise ValueError(f"{where}: {detail}")
+    raise BsError(status, where, detail)

@@ -1,0 +1,626 @@
+// Simplified bilateral grid and bilateral pyramid construction (paper Section 2,
+// Eq. factorization and Eq. equiv; supplement Section 1 Eq. SS and Section 2).
+//
+// Level 0 (the grid): every pixel is mapped to integer coordinates
+// (y, x, l, u, v) and the vertices are the distinct coordinates in ascending
+// packed-key order.  Level k+1 halves the coordinates of level k.  Because the
+// spatial part (y, x) of a key is its most significant part, the ascending
+// order groups vertices by spatial cell in raster order.  So each level is
+// built without a device-wide sort:
+//   1. count:  one block per spatial cell dedups the cell's item colour keys
+//              (counting in LDS; deterministic) -> unique count per cell;
+//   2. scan:   exclusive scan of the per-cell counts -> first vertex id per cell;
+//   3. write:  one block per cell ranks each item's key among the cell's unique
+//              keys -> vertex ids, keys, multiplicities and the item CSR.
+// The items of level 0 are pixels (a cell is a rectangle of the image); the
+// items of level k >= 1 are the vertices of the 2 x 2 child cells of level k-1,
+// which are contiguous id ranges, visited in ascending id order.
+#include "bs_internal.h"
+
+#include <mutex>
+#include <vector>
+
+namespace bs {
+
+// ---------------------------------------------------------------------------
+// Errors.
+// ---------------------------------------------------------------------------
+static thread_local std::string g_last_error;
+
+void set_error(const std::string& msg) { g_last_error = msg; }
+
+bs_status fail(bs_status st, const std::string& msg) {
+    g_last_error = msg;
+    return st;
+}
+
+bs_status check_hip(hipError_t e, const char* what) {
+    g_last_error = std::string(what) + ": " + hipGetErrorString(e);
+    return BS_EDEVICE;
+}
+
+// ---------------------------------------------------------------------------
+// Layout.
+// ---------------------------------------------------------------------------
+size_t layout_grid(GridImpl& g, int H, int W, const bs_grid_params& sp, void* base) {
+    std::memset(&g, 0, sizeof(g));
+    g.magic = kGridMagic;
+    g.H = H;
+    g.W = W;
+    g.P = H * W;
+    g.sg = sp;
+    const int ncy0 = grid_coord(H - 1, sp.sigma_xy) + 1;
+    const int ncx0 = grid_coord(W - 1, sp.sigma_xy) + 1;
+    const int cl = grid_coord(255, sp.sigma_l);
+    const int cu = grid_coord(255, sp.sigma_uv);
+    int kmax = bit_length(ncy0 - 1);
+    kmax = std::max(kmax, bit_length(ncx0 - 1));
+    kmax = std::max(kmax, bit_length(cl));
+    kmax = std::max(kmax, bit_length(cu));
+    g.levels = kmax + 1;
+
+    int64_t prev_cap = g.P;
+    int max_cells = 0;
+    for (int k = 0; k < g.levels; ++k) {
+        Level& L = g.lv[k];
+        L.ncy = ((ncy0 - 1) >> k) + 1;
+        L.ncx = ((ncx0 - 1) >> k) + 1;
+        const int64_t ncells = (int64_t)L.ncy * L.ncx;
+        const int64_t colours = (int64_t)((cl >> k) + 1) * ((cu >> k) + 1) * ((cu >> k) + 1);
+        const int64_t bound = ncells * colours;
+        L.item_cap = (k == 0) ? g.P : prev_cap;
+        L.cap = std::min<int64_t>(prev_cap, bound);
+        if (L.cap < 1) L.cap = 1;
+        prev_cap = L.cap;
+        max_cells = std::max<int>(max_cells, (int)ncells);
+    }
+    g.vcap = g.lv[0].cap;
+    g.max_cells = max_cells;
+
+    Carver c(base);
+    g.counts = c.take<int32_t>(CNT_SIZE);
+    g.ticket = c.take<uint32_t>(8);
+    g.bist_res = c.take<double>(1);
+    g.bist_part = c.take<double>(kMaxGrid);
+    g.cell_cnt = c.take<int32_t>(max_cells);
+    g.cell_items = c.take<int32_t>(max_cells);
+    g.ikey = c.take<uint32_t>(g.P);
+    for (int k = 0; k < g.levels; ++k) {
+        Level& L = g.lv[k];
+        const int64_t ncells = (int64_t)L.ncy * L.ncx;
+        L.key = c.take<uint64_t>(L.cap);
+        L.mult = c.take<int32_t>(L.cap);
+        L.ones = (k == 0) ? nullptr : c.take<int32_t>(L.cap);
+        L.cell_vbase = c.take<int32_t>(ncells + 1);
+        L.cell_ibase = c.take<int32_t>(ncells + 1);
+        L.ptr = c.take<int32_t>(L.cap + 1);
+        L.list = c.take<int32_t>(L.item_cap);
+        L.item_parent = c.take<int32_t>(L.item_cap);
+    }
+    g.nbr = c.take<int32_t>(10 * g.vcap);
+    g.nbuf[0] = c.take<double>(g.vcap);
+    g.nbuf[1] = c.take<double>(g.vcap);
+    g.n64 = c.take<double>(g.vcap);
+    g.nf = c.take<float>(g.vcap);
+    g.nn = c.take<double>(g.vcap);
+    g.ws = base;
+    g.ws_bytes = align_up(c.off, 256);
+    return g.ws_bytes;
+}
+
+// ---------------------------------------------------------------------------
+// Item sources of a level.
+// ---------------------------------------------------------------------------
+
+// 8-bit code of a [0, 1] value: clamp(floor(255 v + 1/2), 0, 255), NaN -> 0.
+__device__ inline int quantise8(float v) {
+    const double s = floor((double)v * 255.0 + 0.5);
+    return s >= 255.0 ? 255 : (s >= 0.0 ? (int)s : 0);
+}
+
+__device__ inline int clamp255(int v) { return v < 0 ? 0 : (v > 255 ? 255 : v); }
+
+// Level 0: the items of a cell are the pixels of an image rectangle.
+struct PixelSource {
+    const float* ref;
+    int H, W, P, sxy, sl, suv, ncx;
+
+    struct Ctx {
+        int y0, x0, wx, n;
+    };
+    __device__ bool active(const int32_t*) const { return true; }
+    __device__ Ctx ctx(int c, int& cy, int& cx) const {
+        cy = c / ncx;
+        cx = c - cy * ncx;
+        Ctx t;
+        t.y0 = cell_lo(cy, sxy);
+        const int y1 = min(cell_lo(cy + 1, sxy), H);
+        t.x0 = cell_lo(cx, sxy);
+        const int x1 = min(cell_lo(cx + 1, sxy), W);
+        t.wx = x1 - t.x0;
+        t.n = (y1 - t.y0) * t.wx;
+        return t;
+    }
+    __device__ int gid(const Ctx& t, int j) const {
+        const int r = j / t.wx;
+        return (t.y0 + r) * W + t.x0 + (j - r * t.wx);
+    }
+    // Colour key l:8 u:8 v:8 of a pixel: 8-bit RGB -> JFIF YCbCr (16.16 fixed
+    // point, round half up) -> round_half_up(code / sigma).
+    __device__ uint32_t key(const Ctx& t, int j) const {
+        const int p = gid(t, j);
+        const int r = quantise8(ref[p]);
+        const int g = quantise8(ref[P + p]);
+        const int b = quantise8(ref[2 * P + p]);
+        const int yy = clamp255((19595 * r + 38470 * g + 7471 * b + 32768) >> 16);
+        const int cb = clamp255((-11058 * r - 21710 * g + 32768 * b + 8421376) >> 16);
+        const int cr = clamp255((32768 * r - 27439 * g - 5329 * b + 8421376) >> 16);
+        return ((uint32_t)grid_coord(yy, sl) << 16) | ((uint32_t)grid_coord(cb, suv) << 8) |
+               (uint32_t)grid_coord(cr, suv);
+    }
+};
+
+// Level k >= 1: the items of cell (cy, cx) are the level-(k-1) vertices of the
+// child cells (2cy + a, 2cx + b), a, b in {0, 1}, in ascending id order.
+struct VertexSource {
+    const uint64_t* child_key;
+    const int32_t* child_vbase;
+    const int32_t* counts;
+    int child_ncx, child_ncy, ncx, level;
+
+    struct Ctx {
+        int s[4], len[4], n;
+    };
+    __device__ bool active(const int32_t* cnt) const { return cnt[CNT_LEVEL0 + level - 1] > 1; }
+    __device__ Ctx ctx(int c, int& cy, int& cx) const {
+        cy = c / ncx;
+        cx = c - cy * ncx;
+        Ctx t;
+        t.n = 0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int yy = 2 * cy + (q >> 1), xx = 2 * cx + (q & 1);
+            int s = 0, e = 0;
+            if (yy < child_ncy && xx < child_ncx) {
+                const int cc = yy * child_ncx + xx;
+                s = child_vbase[cc];
+                e = child_vbase[cc + 1];
+            }
+            t.s[q] = s;
+            t.len[q] = e - s;
+            t.n += e - s;
+        }
+        return t;
+    }
+    __device__ int gid(const Ctx& t, int j) const {
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            if (j < t.len[q]) return t.s[q] + j;
+            j -= t.len[q];
+        }
+        return t.s[3] + j;
+    }
+    __device__ uint32_t key(const Ctx& t, int j) const {
+        const uint64_t k = child_key[gid(t, j)];
+        const uint32_t l = (uint32_t)(k >> 16) & 0xffu, u = (uint32_t)(k >> 8) & 0xffu,
+                       v = (uint32_t)k & 0xffu;
+        return ((l >> 1) << 16) | ((u >> 1) << 8) | (v >> 1);
+    }
+};
+
+// ---------------------------------------------------------------------------
+// Kernels.
+// ---------------------------------------------------------------------------
+constexpr uint32_t kFirst = 0x80000000u;
+constexpr uint32_t kKeyMask = 0x7fffffffu;
+
+template <int B>
+__device__ inline int block_sum_int(int v) {
+    __shared__ int red[B / 64];
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    int s = 0;
+#pragma unroll
+    for (int w = 0; w < B / 64; ++w) s += red[w];
+    return s;
+}
+
+// Pass 1: per cell, flag the first occurrence of each colour key among the
+// cell's items (in item order) and count the distinct keys.
+template <int B, class Src>
+__global__ void __launch_bounds__(B) level_count(Src src, int32_t* __restrict__ cell_cnt,
+                                                  int32_t* __restrict__ cell_items,
+                                                  uint32_t* __restrict__ ikey,
+                                                  const int32_t* __restrict__ counts) {
+    if (!src.active(counts)) return;
+    __shared__ uint32_t tile[kCellTile];
+    const int c = blockIdx.x;
+    int cy, cx;
+    const typename Src::Ctx t = src.ctx(c, cy, cx);
+    const int n = t.n;
+    int cnt = 0;
+    for (int base = 0; base < n; base += B) {
+        const int i = base + threadIdx.x;
+        const bool have = i < n;
+        const uint32_t ki = have ? src.key(t, i) : 0u;
+        bool first = have;
+        const int jend = min(base + B, n);
+        for (int t0 = 0; t0 < jend; t0 += kCellTile) {
+            const int tn = min(kCellTile, jend - t0);
+            __syncthreads();
+            for (int j = threadIdx.x; j < tn; j += B) tile[j] = src.key(t, t0 + j);
+            __syncthreads();
+            if (first) {
+                const int lim = min(tn, i - t0);
+                for (int j = 0; j < lim; ++j) {
+                    if (tile[j] == ki) {
+                        first = false;
+                        break;
+                    }
+                }
+            }
+        }
+        if (have) {
+            ikey[src.gid(t, i)] = ki | (first ? kFirst : 0u);
+            cnt += first ? 1 : 0;
+        }
+    }
+    cnt = block_sum_int<B>(cnt);
+    if (threadIdx.x == 0) {
+        cell_cnt[c] = cnt;
+        cell_items[c] = n;
+    }
+}
+
+// Pass 2: exclusive scan of the per-cell vertex and item counts (one block).
+// Writes the level's vertex count and, when it reaches one vertex, the
+// pyramid height K.
+constexpr int kScanBlock = 1024;
+
+__global__ void __launch_bounds__(kScanBlock) level_scan(const int32_t* __restrict__ cnt,
+                                                         const int32_t* __restrict__ items,
+                                                         int ncells, int32_t* __restrict__ vbase,
+                                                         int32_t* __restrict__ ibase,
+                                                         int32_t* __restrict__ ptr,
+                                                         int32_t* __restrict__ counts, int level) {
+    if (level > 0 && counts[CNT_LEVEL0 + level - 1] <= 1) {
+        if (threadIdx.x == 0) counts[CNT_LEVEL0 + level] = 0;
+        return;
+    }
+    __shared__ int sa[kScanBlock / 64], sb[kScanBlock / 64];
+    const int tid = threadIdx.x;
+    const int chunk = (ncells + kScanBlock - 1) / kScanBlock;
+    const int s = min(tid * chunk, ncells), e = min(s + chunk, ncells);
+    int a = 0, b = 0;
+    for (int i = s; i < e; ++i) {
+        a += cnt[i];
+        b += items[i];
+    }
+    // inclusive wave scan
+    const int lane = tid & 63, wave = tid >> 6;
+    int ia = a, ib = b;
+    for (int o = 1; o < 64; o <<= 1) {
+        const int ta = __shfl_up(ia, o, 64), tb = __shfl_up(ib, o, 64);
+        if (lane >= o) {
+            ia += ta;
+            ib += tb;
+        }
+    }
+    if (lane == 63) {
+        sa[wave] = ia;
+        sb[wave] = ib;
+    }
+    __syncthreads();
+    int wa = 0, wb = 0, ta = 0, tb = 0;
+    for (int w = 0; w < kScanBlock / 64; ++w) {
+        if (w < wave) {
+            wa += sa[w];
+            wb += sb[w];
+        }
+        ta += sa[w];
+        tb += sb[w];
+    }
+    int pa = wa + ia - a, pb = wb + ib - b;
+    for (int i = s; i < e; ++i) {
+        vbase[i] = pa;
+        ibase[i] = pb;
+        pa += cnt[i];
+        pb += items[i];
+    }
+    if (tid == 0) {
+        vbase[ncells] = ta;
+        ibase[ncells] = tb;
+        ptr[ta] = tb;
+        counts[CNT_LEVEL0 + level] = ta;
+        if (level == 0) {
+            counts[CNT_V] = ta;
+            counts[CNT_K] = (ta == 1) ? 0 : -1;
+            counts[CNT_BIST_DONE] = 0;
+            counts[CNT_BIST_ITERS] = 0;
+            counts[CNT_BIST_SRC] = 0;
+        } else if (ta == 1 && counts[CNT_K] < 0) {
+            counts[CNT_K] = level;
+        }
+    }
+}
+
+// Pass 3: per cell, rank each item's key among the cell's distinct keys and
+// write vertex ids, keys, multiplicities, P(1) sums and the item CSR.
+template <int B, class Src>
+__global__ void __launch_bounds__(B) level_write(Src src, const uint32_t* __restrict__ ikey,
+                                                  const int32_t* __restrict__ ones_prev,
+                                                  const int32_t* __restrict__ counts, Level L) {
+    if (!src.active(counts)) return;
+    __shared__ uint32_t tile[kCellTile];
+    __shared__ int32_t tones[kCellTile];
+    const int c = blockIdx.x;
+    int cy, cx;
+    const typename Src::Ctx t = src.ctx(c, cy, cx);
+    const int n = t.n;
+    const int vbase = L.cell_vbase[c], ibase = L.cell_ibase[c];
+    const uint64_t cellkey = ((uint64_t)cy << 40) | ((uint64_t)cx << 24);
+    for (int base = 0; base < n; base += B) {
+        const int i = base + threadIdx.x;
+        const bool have = i < n;
+        const int gi = have ? src.gid(t, i) : 0;
+        const uint32_t wi = have ? ikey[gi] : 0u;
+        const uint32_t ki = wi & kKeyMask;
+        int rank = 0, less = 0, mult = 0, eqb = 0, onesum = 0;
+        for (int t0 = 0; t0 < n; t0 += kCellTile) {
+            const int tn = min(kCellTile, n - t0);
+            __syncthreads();
+            for (int j = threadIdx.x; j < tn; j += B) {
+                const int gj = src.gid(t, t0 + j);
+                tile[j] = ikey[gj];
+                tones[j] = ones_prev ? ones_prev[gj] : 1;
+            }
+            __syncthreads();
+            if (have) {
+                for (int j = 0; j < tn; ++j) {
+                    const uint32_t w = tile[j];
+                    const uint32_t kj = w & kKeyMask;
+                    const int lt = kj < ki, eq = kj == ki;
+                    less += lt;
+                    rank += lt & (int)(w >> 31);
+                    mult += eq;
+                    eqb += eq & (t0 + j < i);
+                    onesum += eq ? tones[j] : 0;
+                }
+            }
+        }
+        if (have) {
+            const int v = vbase + rank;
+            L.item_parent[gi] = v;
+            if (wi & kFirst) {
+                L.key[v] = cellkey | ki;
+                L.mult[v] = mult;
+                L.ptr[v] = ibase + less;
+                if (L.ones) L.ones[v] = onesum;
+            }
+            L.list[ibase + less + eqb] = gi;
+        }
+    }
+}
+
+// Binary search of `want` in the ascending keys [s, e); -1 if absent.
+__device__ inline int find_key(const uint64_t* __restrict__ key, int s, int e, uint64_t want) {
+    while (s < e) {
+        const int mid = (s + e) >> 1;
+        const uint64_t k = key[mid];
+        if (k == want) return mid;
+        if (k < want) s = mid + 1;
+        else e = mid;
+    }
+    return -1;
+}
+
+// Neighbour table of level 0: for each vertex and unit step along each of
+// (y, x, l, u, v), the neighbour's id or -1.  Colour neighbours share the
+// vertex's spatial cell; spatial neighbours lie in the adjacent cell; both are
+// looked up in that cell's key range.
+__global__ void __launch_bounds__(kBlock) neighbour_table(const uint64_t* __restrict__ key,
+                                                           const int32_t* __restrict__ vbase,
+                                                           const int32_t* __restrict__ counts,
+                                                           int ncx, int ncy, int64_t vcap,
+                                                           int32_t* __restrict__ nbr) {
+    const int V = counts[CNT_V];
+    const XcdTiles tl((V + kBlock - 1) / kBlock);
+    for (int64_t tile = tl.first; tile < tl.end; tile += tl.step) {
+        const int v = (int)(tile * kBlock) + threadIdx.x;
+        if (v >= V) continue;
+        const uint64_t k = key[v];
+        const int cy = (int)(k >> 40), cx = (int)((k >> 24) & 0xffff);
+        const int cell = cy * ncx + cx;
+        const int s = vbase[cell], e = vbase[cell + 1];
+        // y
+        int r = -1;
+        if (cy > 0) {
+            const int cc = cell - ncx;
+            r = find_key(key, vbase[cc], vbase[cc + 1], k - (1ull << 40));
+        }
+        nbr[0 * vcap + v] = r;
+        r = -1;
+        if (cy + 1 < ncy) {
+            const int cc = cell + ncx;
+            r = find_key(key, vbase[cc], vbase[cc + 1], k + (1ull << 40));
+        }
+        nbr[1 * vcap + v] = r;
+        // x
+        r = -1;
+        if (cx > 0) r = find_key(key, vbase[cell - 1], vbase[cell], k - (1ull << 24));
+        nbr[2 * vcap + v] = r;
+        r = -1;
+        if (cx + 1 < ncx) r = find_key(key, vbase[cell + 1], vbase[cell + 2], k + (1ull << 24));
+        nbr[3 * vcap + v] = r;
+        // l, u, v within the cell
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            const int sh = 16 - 8 * d;
+            const int f = (int)((k >> sh) & 0xff);
+            r = -1;
+            if (f > 0) r = find_key(key, s, e, k - (1ull << sh));
+            nbr[(4 + 2 * d) * vcap + v] = r;
+            r = -1;
+            if (f < 255) r = find_key(key, s, e, k + (1ull << sh));
+            nbr[(5 + 2 * d) * vcap + v] = r;
+        }
+    }
+}
+
+__global__ void clear_counts(int32_t* counts, uint32_t* ticket) {
+    const int t = threadIdx.x;
+    if (t < CNT_SIZE) counts[t] = 0;
+    if (t < 8) ticket[t] = 0;
+}
+
+// ---------------------------------------------------------------------------
+// Host.
+// ---------------------------------------------------------------------------
+static bs_status validate_grid_args(int32_t H, int32_t W, const bs_grid_params* p) {
+    if (!p) return fail(BS_EINVAL, "grid params is NULL");
+    if (H < 1 || W < 1) return fail(BS_EINVAL, "image size must be positive");
+    if (H > 65535 || W > 65535) return fail(BS_EUNSUPPORTED, "image side above 65535");
+    if ((int64_t)H * W > (int64_t)1 << 30) return fail(BS_EUNSUPPORTED, "image above 2^30 pixels");
+    if (p->sigma_xy < 1 || p->sigma_l < 1 || p->sigma_uv < 1)
+        return fail(BS_EINVAL, "grid scales must be positive integers");
+    if (p->sigma_xy > 128) return fail(BS_EUNSUPPORTED, "sigma_xy above 128");
+    if (p->sigma_l > 255 || p->sigma_uv > 255) return fail(BS_EUNSUPPORTED, "colour scale above 255");
+    return BS_OK;
+}
+
+template <int B, class Src>
+static bs_status launch_level(const Src& src, GridImpl& g, int k, hipStream_t st) {
+    Level& L = g.lv[k];
+    const int ncells = L.ncy * L.ncx;
+    hipLaunchKernelGGL((level_count<B, Src>), dim3(ncells), dim3(B), 0, st, src, g.cell_cnt,
+                       g.cell_items, g.ikey, g.counts);
+    BS_CHECK_LAUNCH("level_count");
+    hipLaunchKernelGGL(level_scan, dim3(1), dim3(kScanBlock), 0, st, g.cell_cnt, g.cell_items,
+                       ncells, L.cell_vbase, L.cell_ibase, L.ptr, g.counts, k);
+    BS_CHECK_LAUNCH("level_scan");
+    const int32_t* ones_prev = (k >= 2) ? g.lv[k - 1].ones : nullptr;
+    hipLaunchKernelGGL((level_write<B, Src>), dim3(ncells), dim3(B), 0, st, src, g.ikey,
+                       ones_prev, g.counts, L);
+    BS_CHECK_LAUNCH("level_write");
+    return BS_OK;
+}
+
+}  // namespace bs
+
+using namespace bs;
+
+extern "C" size_t bs_grid_workspace_bytes(int32_t H, int32_t W, const bs_grid_params* params) {
+    if (validate_grid_args(H, W, params) != BS_OK) return 0;
+    GridImpl g;
+    return layout_grid(g, H, W, *params, nullptr);
+}
+
+extern "C" bs_status bs_build_grid(const float* ref, int32_t H, int32_t W,
+                                   const bs_grid_params* params, void* ws, size_t ws_bytes,
+                                   void* stream, bs_grid* out) {
+    bs_status st = validate_grid_args(H, W, params);
+    if (st != BS_OK) return st;
+    if (!ref || !ws || !out) return fail(BS_EINVAL, "NULL pointer argument");
+    if (((uintptr_t)ws & 255) != 0) return fail(BS_EINVAL, "workspace must be 256-byte aligned");
+    if (((uintptr_t)ref & 3) != 0) return fail(BS_EINVAL, "reference must be 4-byte aligned");
+    GridImpl g;
+    const size_t need = layout_grid(g, H, W, *params, nullptr);
+    if (ws_bytes < need)
+        return fail(BS_EWORKSPACE, "grid workspace needs " + std::to_string(need) + " bytes");
+    layout_grid(g, H, W, *params, ws);
+    hipStream_t s = (hipStream_t)stream;
+
+    hipLaunchKernelGGL(clear_counts, dim3(1), dim3(64), 0, s, g.counts, g.ticket);
+    BS_CHECK_LAUNCH("clear_counts");
+    PixelSource ps{ref, H, W, g.P, params->sigma_xy, params->sigma_l, params->sigma_uv,
+                   g.lv[0].ncx};
+    const int items = params->sigma_xy * params->sigma_xy;
+    if (items <= 64) st = launch_level<64>(ps, g, 0, s);
+    else if (items <= 128) st = launch_level<128>(ps, g, 0, s);
+    else st = launch_level<256>(ps, g, 0, s);
+    if (st != BS_OK) return st;
+
+    for (int k = 1; k < g.levels; ++k) {
+        const Level& C = g.lv[k - 1];
+        VertexSource vs{C.key, C.cell_vbase, g.counts, C.ncx, C.ncy, g.lv[k].ncx, k};
+        st = launch_level<128>(vs, g, k, s);
+        if (st != BS_OK) return st;
+    }
+    const int blocks = grid_blocks(ceil_div(g.vcap, kBlock));
+    hipLaunchKernelGGL(neighbour_table, dim3(blocks), dim3(kBlock), 0, s, g.lv[0].key,
+                       g.lv[0].cell_vbase, g.counts, g.lv[0].ncx, g.lv[0].ncy, g.vcap, g.nbr);
+    BS_CHECK_LAUNCH("neighbour_table");
+    std::memcpy(out->opaque, &g, sizeof(g));
+    return BS_OK;
+}
+
+static bs_status check_grid(const bs_grid* grid) {
+    if (!grid) return fail(BS_EINVAL, "grid is NULL");
+    if (impl(grid)->magic != kGridMagic) return fail(BS_EINVAL, "grid was not built");
+    return BS_OK;
+}
+
+extern "C" bs_status bs_read_counters(const bs_grid* grid, int32_t* out, int32_t n, void* stream) {
+    bs_status st = check_grid(grid);
+    if (st != BS_OK) return st;
+    if (!out || n < 1 || n > CNT_SIZE) return fail(BS_EINVAL, "bad counter request");
+    hipStream_t s = (hipStream_t)stream;
+    BS_TRY_HIP(hipMemcpyAsync(out, impl(grid)->counts, sizeof(int32_t) * n, hipMemcpyDeviceToHost, s));
+    BS_TRY_HIP(hipStreamSynchronize(s));
+    return BS_OK;
+}
+
+extern "C" bs_status bs_grid_vertex_count(const bs_grid* grid, int32_t* V, void* stream) {
+    if (!V) return fail(BS_EINVAL, "V is NULL");
+    return bs_read_counters(grid, V, 1, stream);
+}
+
+extern "C" bs_status bs_grid_get_view(const bs_grid* grid, bs_grid_view* v) {
+    bs_status st = check_grid(grid);
+    if (st != BS_OK) return st;
+    if (!v) return fail(BS_EINVAL, "view is NULL");
+    const GridImpl& g = *impl(grid);
+    std::memset(v, 0, sizeof(*v));
+    v->H = g.H;
+    v->W = g.W;
+    v->P = g.P;
+    v->levels = g.levels;
+    v->ncells_x = g.lv[0].ncx;
+    v->ncells_y = g.lv[0].ncy;
+    v->vcap = g.vcap;
+    v->counts = g.counts;
+    v->bist_residual = g.bist_res;
+    v->key = g.lv[0].key;
+    v->idx = g.lv[0].item_parent;
+    v->m = g.lv[0].mult;
+    v->nbr = g.nbr;
+    v->pix_ptr = g.lv[0].ptr;
+    v->pix_list = g.lv[0].list;
+    v->n = g.n64;
+    v->nf = g.nf;
+    v->nn = g.nn;
+    for (int k = 0; k < g.levels; ++k) {
+        v->level_cap[k] = g.lv[k].cap;
+        v->level_key[k] = g.lv[k].key;
+        v->ones[k] = g.lv[k].ones;
+        if (k + 1 < g.levels) v->parent[k] = g.lv[k + 1].item_parent;
+    }
+    return BS_OK;
+}
+
+extern "C" const char* bs_status_string(bs_status s) {
+    switch (s) {
+        case BS_OK: return "ok";
+        case BS_EINVAL: return "invalid argument";
+        case BS_EWORKSPACE: return "workspace too small";
+        case BS_EDEVICE: return "device error";
+        case BS_EUNSUPPORTED: return "unsupported";
+    }
+    return "unknown status";
+}
+
+extern "C" const char* bs_last_error(void) { return bs::g_last_error.c_str(); }
+
+extern "C" int32_t bs_version(void) { return (1 << 16) | 0; }

@@ -1,0 +1,200 @@
+// Internal definitions of the bilateral-solver HIP library: the grid layout
+// carved from the caller's workspace, launch helpers, error reporting and the
+// device-side reduction helpers shared by the kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <string>
+
+#include "bsolve.h"
+
+namespace bs {
+
+// ---------------------------------------------------------------------------
+// Error reporting (thread-local text behind bs_last_error).
+// ---------------------------------------------------------------------------
+void set_error(const std::string& msg);
+bs_status fail(bs_status st, const std::string& msg);
+bs_status check_hip(hipError_t e, const char* what);
+
+#define BS_TRY_HIP(expr)                                        \
+    do {                                                        \
+        hipError_t e_ = (expr);                                 \
+        if (e_ != hipSuccess) return ::bs::check_hip(e_, #expr); \
+    } while (0)
+
+// Checks the launch that was just enqueued.
+#define BS_CHECK_LAUNCH(name)                                        \
+    do {                                                             \
+        hipError_t e_ = hipGetLastError();                           \
+        if (e_ != hipSuccess) return ::bs::check_hip(e_, name);      \
+    } while (0)
+
+// ---------------------------------------------------------------------------
+// Sizes and constants.
+// ---------------------------------------------------------------------------
+constexpr int kBlock = 256;          // threads per block of streaming kernels
+constexpr int kXcds = 8;             // MI355X: 8 accelerator dies, one L2 each
+constexpr int kMaxGrid = 2048;       // blocks of a grid-stride launch
+constexpr int kCellTile = 2048;      // LDS tile of item keys in the level builders
+constexpr int kCellBlock = 128;      // threads per cell block of the level builders
+
+// Slots of the device counter array.
+enum Counter : int {
+    CNT_V = 0,            // level-0 vertex count
+    CNT_K = 1,            // pyramid top level K (first level with one vertex)
+    CNT_BIST_ITERS = 2,   // bistochastization updates applied
+    CNT_BIST_DONE = 3,    // 1 once bistochastization has stopped
+    CNT_BIST_SRC = 4,     // ping-pong buffer holding the final n
+    CNT_LEVEL0 = 8,       // V_k at CNT_LEVEL0 + k
+    CNT_SIZE = 64
+};
+
+inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+// Round-half-up grid coordinate in integers: floor((2v + s) / 2s).
+__host__ __device__ inline int grid_coord(int v, int s) { return (2 * v + s) / (2 * s); }
+
+// First index p >= 0 whose coordinate is g: ceil((2 g s - s) / 2), clamped at 0.
+__host__ __device__ inline int cell_lo(int g, int s) {
+    int t = 2 * g * s - s;
+    return t <= 0 ? 0 : (t + 1) / 2;
+}
+
+inline int bit_length(int v) {
+    int b = 0;
+    while (v > 0) { ++b; v >>= 1; }
+    return b;
+}
+
+// Number of grid-stride blocks for `units` work units, a multiple of kXcds.
+inline int grid_blocks(int64_t units) {
+    int64_t g = ceil_div(units < 1 ? 1 : units, 1);
+    g = ceil_div(g, kXcds) * kXcds;
+    if (g > kMaxGrid) g = kMaxGrid;
+    return (int)g;
+}
+
+// ---------------------------------------------------------------------------
+// Workspace carving.
+// ---------------------------------------------------------------------------
+struct Carver {
+    char* base;
+    size_t off = 0;
+    explicit Carver(void* b) : base((char*)b) {}
+    template <class T>
+    T* take(int64_t count) {
+        off = align_up(off, 256);
+        T* p = base ? (T*)(base + off) : nullptr;
+        off += (size_t)(count < 0 ? 0 : count) * sizeof(T);
+        return p;
+    }
+};
+
+// One level of the grid pyramid.  Level 0 is the grid itself: its items are
+// pixels.  The items of level k >= 1 are the vertices of level k-1.
+struct Level {
+    int64_t cap;             // vertex capacity
+    int64_t item_cap;        // item capacity (P at level 0, cap of level k-1 above)
+    int32_t ncx, ncy;        // spatial cells
+    uint64_t* key;           // [cap] packed keys, ascending
+    int32_t* mult;           // [cap] items per vertex (level 0: m)
+    int32_t* ones;           // [cap] level-0 vertices below each vertex (level >= 1)
+    int32_t* cell_vbase;     // [ncells + 1] first vertex of each cell
+    int32_t* cell_ibase;     // [ncells + 1] first CSR slot of each cell
+    int32_t* ptr;            // [cap + 1] CSR of items per vertex
+    int32_t* list;           // [item_cap] item ids
+    int32_t* item_parent;    // [item_cap] vertex of each item (level 0: idx)
+};
+
+struct GridImpl {
+    uint32_t magic;
+    int32_t H, W, P;
+    bs_grid_params sg;
+    int32_t levels;          // allocated levels, K <= levels - 1
+    int32_t bistochastized;  // set by bs_bistochastize
+    int64_t vcap;
+    size_t ws_bytes;
+    void* ws;
+    int32_t max_cells;
+    Level lv[BS_MAX_LEVELS];
+    int32_t* nbr;            // [10][vcap]
+    double* nbuf[2];         // bistochastization ping-pong
+    double* n64;             // [vcap] final n
+    float* nf;               // [vcap]
+    double* nn;              // [vcap] n o N n
+    int32_t* counts;         // [CNT_SIZE]
+    double* bist_res;        // [1]
+    double* bist_part;       // [kMaxGrid]
+    uint32_t* ticket;        // [8] last-block tickets
+    int32_t* cell_cnt;       // [max_cells] scratch
+    int32_t* cell_items;     // [max_cells] scratch
+    uint32_t* ikey;          // [P] item keys with first-occurrence flag, scratch
+};
+static_assert(sizeof(GridImpl) <= BS_GRID_BYTES, "bs_grid too small");
+
+constexpr uint32_t kGridMagic = 0xB5A7E001u;
+
+inline GridImpl* impl(bs_grid* g) { return reinterpret_cast<GridImpl*>(g->opaque); }
+inline const GridImpl* impl(const bs_grid* g) { return reinterpret_cast<const GridImpl*>(g->opaque); }
+
+// Lays out (or sizes, with base == nullptr) a grid for an H x W image.
+// Returns the bytes used; fills `g` when base != nullptr.
+size_t layout_grid(GridImpl& g, int H, int W, const bs_grid_params& sp, void* base);
+
+// ---------------------------------------------------------------------------
+// Device helpers.
+// ---------------------------------------------------------------------------
+
+// XCD-aware tile mapping for grid-stride loops.  Workgroups are dispatched to
+// the dies round-robin, so block b runs on die b % 8.  Tiles [0, T) are split
+// into 8 contiguous chunks, one per die, so that neighbouring tiles (and the
+// vertices their stencils gather) share one L2.
+struct XcdTiles {
+    int64_t first, step, end;
+    __device__ XcdTiles(int64_t T) {
+        const int G = gridDim.x;
+        const int xcd = blockIdx.x % kXcds;
+        const int local = blockIdx.x / kXcds;
+        const int per = G / kXcds;
+        const int64_t chunk = (T + kXcds - 1) / kXcds;
+        first = (int64_t)xcd * chunk + local;
+        int64_t e = (int64_t)(xcd + 1) * chunk;
+        end = e < T ? e : T;
+        step = per;
+    }
+};
+
+__device__ inline double wave_sum(double v) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+__device__ inline double wave_max(double v) {
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+// Last-block election after every block has published its partial results.
+// Returns true in exactly one block (the last to arrive), which then sees all
+// other blocks' writes; that block resets the ticket for the next launch.
+__device__ inline bool last_block(uint32_t* ticket) {
+    __shared__ bool s_last;
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t prev = atomicAdd(ticket, 1u);
+        s_last = (prev == gridDim.x - 1);
+    }
+    __syncthreads();
+    if (s_last) __threadfence();
+    return s_last;
+}
+
+}  // namespace bs

@@ -1,0 +1,235 @@
+"""Python API of the MI355X bilateral solver.
+
+PyTorch supplies device memory (the caching allocator) and the stream; every
+step of the solver runs in the HIP library behind the C ABI (``_lib``):
+
+    grid = BilateralGrid(ref, sigma_xy=8, sigma_l=4, sigma_uv=4)  # grid + bistochastization
+    y, stats = grid.solve(target, conf, lam=128.0, rel_tol=1e-5)  # PCG in bilateral space
+    x = grid.slice(y)                                             # back to pixels
+    gt, gc, g = grid.backward(target, conf, y, grad_x, lam=128.0)  # Section 3 adjoint
+
+``bilateral_solve`` wraps these in a ``torch.autograd.Function`` that is
+differentiable in the target and the confidence.
+"""
+from __future__ import annotations
+
+import ctypes as ct
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+from . import _lib as L
+
+_STATS_DTYPE = np.dtype([("iters", "<i4"), ("reason", "<i4"), ("rel_residual", "<f8"),
+                         ("bnorm", "<f8")])
+
+
+def _stream() -> int:
+    return torch.cuda.current_stream().cuda_stream
+
+
+def _dev_f32(t: torch.Tensor, name: str, shape) -> torch.Tensor:
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a CUDA (HIP) tensor")
+    if t.dtype != torch.float32:
+        raise ValueError(f"{name} must be float32")
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+    return t.contiguous()
+
+
+@dataclass
+class SolveOptions:
+    lam: float
+    max_iters: int = 25
+    rel_tol: float = 0.0
+    init: str = "hier"
+    init_alpha: float = 4.0
+    init_beta: float = 0.0
+    check_every: int = 8
+
+    def struct(self) -> L.SolveParams:
+        if self.init not in ("hier", "flat"):
+            raise ValueError("init must be 'hier' or 'flat'")
+        return L.SolveParams(float(self.lam),
+                             L.BS_INIT_HIER if self.init == "hier" else L.BS_INIT_FLAT,
+                             int(self.max_iters), int(self.check_every), float(self.rel_tol),
+                             float(self.init_alpha), float(self.init_beta))
+
+
+class BilateralGrid:
+    """A simplified bilateral grid of one reference image, bistochastized."""
+
+    def __init__(self, ref: torch.Tensor, sigma_xy: int, sigma_l: int, sigma_uv: int,
+                 bist_tol: float = 1e-10, bist_max_iters: int = 200, check_every: int = 8,
+                 bistochastize: bool = True):
+        if ref.dim() != 3 or ref.shape[0] != 3:
+            raise ValueError("reference must be [3][H][W]")
+        self.H, self.W = int(ref.shape[1]), int(ref.shape[2])
+        ref = _dev_f32(ref, "reference", (3, self.H, self.W))
+        self.device = ref.device
+        self.params = L.GridParams(int(sigma_xy), int(sigma_l), int(sigma_uv))
+        nbytes = L.lib.bs_grid_workspace_bytes(self.H, self.W, ct.byref(self.params))
+        if nbytes == 0:
+            L.check(L.lib.bs_build_grid(None, self.H, self.W, ct.byref(self.params), None, 0,
+                                        None, None), "bs_build_grid")
+        self.ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        self.handle = L.Grid()
+        L.check(L.lib.bs_build_grid(ref.data_ptr(), self.H, self.W, ct.byref(self.params),
+                                    self.ws.data_ptr(), nbytes, _stream(),
+                                    ct.byref(self.handle)), "bs_build_grid")
+        self._ref = ref
+        if bistochastize:
+            self.bistochastize(bist_tol, bist_max_iters, check_every)
+
+    # -- construction ------------------------------------------------------
+    def bistochastize(self, tol: float = 1e-10, max_iters: int = 200, check_every: int = 8):
+        p = L.BistochParams(int(max_iters), int(check_every), float(tol))
+        L.check(L.lib.bs_bistochastize(ct.byref(self.handle), ct.byref(p), _stream()),
+                "bs_bistochastize")
+
+    @property
+    def P(self) -> int:
+        return self.H * self.W
+
+    def view(self) -> L.GridView:
+        v = L.GridView()
+        L.check(L.lib.bs_grid_get_view(ct.byref(self.handle), ct.byref(v)), "bs_grid_get_view")
+        return v
+
+    def counters(self, n: int = 40) -> np.ndarray:
+        out = (ct.c_int32 * n)()
+        L.check(L.lib.bs_read_counters(ct.byref(self.handle), out, n, _stream()),
+                "bs_read_counters")
+        return np.array(out[:], dtype=np.int64)
+
+    def vertex_count(self) -> int:
+        v = ct.c_int32()
+        L.check(L.lib.bs_grid_vertex_count(ct.byref(self.handle), ct.byref(v), _stream()),
+                "bs_grid_vertex_count")
+        return int(v.value)
+
+    def array(self, ptr: int, count: int, dtype: torch.dtype) -> torch.Tensor:
+        """A device tensor aliasing `count` elements of the grid workspace at `ptr`."""
+        off = int(ptr) - self.ws.data_ptr()
+        size = torch.tensor([], dtype=dtype).element_size() * count
+        if off < 0 or off + size > self.ws.numel():
+            raise ValueError("pointer outside the grid workspace")
+        return self.ws[off:off + size].view(dtype)
+
+    @property
+    def vcap(self) -> int:
+        return int(self.view().vcap)
+
+    # -- solve -------------------------------------------------------------
+    def solve_workspace(self, C: int) -> torch.Tensor:
+        nbytes = L.lib.bs_solve_workspace_bytes(ct.byref(self.handle), int(C))
+        if nbytes == 0:
+            raise ValueError("invalid channel count")
+        return torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+
+    def solve(self, target: torch.Tensor, conf: torch.Tensor, lam: float, max_iters: int = 25,
+              rel_tol: float = 0.0, init: str = "hier", init_alpha: float = 4.0,
+              init_beta: float = 0.0, check_every: int = 8, ws: torch.Tensor | None = None,
+              y: torch.Tensor | None = None, stats: torch.Tensor | None = None):
+        """Bilateral-space solution y [Vcap][C] and per-channel stats (device bytes)."""
+        C = int(target.shape[0])
+        target = _dev_f32(target, "target", (C, self.H, self.W))
+        conf = _dev_f32(conf, "confidence", (self.H, self.W))
+        opts = SolveOptions(lam, max_iters, rel_tol, init, init_alpha, init_beta, check_every)
+        if ws is None:
+            ws = self.solve_workspace(C)
+        if y is None:
+            y = torch.empty((self.vcap, C), dtype=torch.float32, device=self.device)
+        if stats is None:
+            stats = torch.empty(C * _STATS_DTYPE.itemsize, dtype=torch.uint8, device=self.device)
+        p = opts.struct()
+        L.check(L.lib.bs_solve(ct.byref(self.handle), target.data_ptr(), conf.data_ptr(), C,
+                               ct.byref(p), y.data_ptr(), ws.data_ptr(), ws.numel(),
+                               stats.data_ptr(), _stream()), "bs_solve")
+        self._last_ws = ws
+        return y, stats
+
+    def slice(self, y: torch.Tensor, C: int | None = None, out: torch.Tensor | None = None):
+        C = int(y.shape[1]) if C is None else int(C)
+        if out is None:
+            out = torch.empty((C, self.H, self.W), dtype=torch.float32, device=self.device)
+        L.check(L.lib.bs_slice(ct.byref(self.handle), y.data_ptr(), C, out.data_ptr(), _stream()),
+                "bs_slice")
+        return out
+
+    def backward(self, target: torch.Tensor, conf: torch.Tensor, y_hat: torch.Tensor,
+                 grad_x: torch.Tensor, lam: float, max_iters: int = 25, rel_tol: float = 0.0,
+                 init: str = "hier", init_alpha: float = 4.0, init_beta: float = 0.0,
+                 check_every: int = 8, ws: torch.Tensor | None = None,
+                 stats: torch.Tensor | None = None, want_g: bool = False):
+        """(dL/dt, dL/dc, dL/db or None) from dL/dx (Section 3)."""
+        C = int(target.shape[0])
+        target = _dev_f32(target, "target", (C, self.H, self.W))
+        conf = _dev_f32(conf, "confidence", (self.H, self.W))
+        grad_x = _dev_f32(grad_x, "grad_x", (C, self.H, self.W))
+        opts = SolveOptions(lam, max_iters, rel_tol, init, init_alpha, init_beta, check_every)
+        if ws is None:
+            ws = self.solve_workspace(C)
+        gt = torch.empty((C, self.H, self.W), dtype=torch.float32, device=self.device)
+        gc = torch.empty((self.H, self.W), dtype=torch.float32, device=self.device)
+        g = torch.empty((self.vcap, C), dtype=torch.float32, device=self.device) if want_g else None
+        if stats is None:
+            stats = torch.empty(C * _STATS_DTYPE.itemsize, dtype=torch.uint8, device=self.device)
+        p = opts.struct()
+        L.check(L.lib.bs_solve_backward(ct.byref(self.handle), target.data_ptr(),
+                                        conf.data_ptr(), y_hat.data_ptr(), grad_x.data_ptr(), C,
+                                        ct.byref(p), gt.data_ptr(), gc.data_ptr(),
+                                        g.data_ptr() if g is not None else None, ws.data_ptr(),
+                                        ws.numel(), stats.data_ptr(), _stream()),
+                "bs_solve_backward")
+        self._last_ws = ws
+        return gt, gc, g, stats
+
+    def solve_ws_arrays(self, ws: torch.Tensor, C: int):
+        """Device tensors (b [Vcap][C], S c, diag(A), Jacobi inverse) of a solve workspace."""
+        ptrs = [ct.c_void_p() for _ in range(4)]
+        L.check(L.lib.bs_solve_ws_view(ct.byref(self.handle), int(C), ws.data_ptr(), ws.numel(),
+                                       *[ct.byref(p) for p in ptrs]), "bs_solve_ws_view")
+        vcap = self.vcap
+
+        def alias(ptr, count):
+            off = int(ptr.value) - ws.data_ptr()
+            return ws[off:off + 4 * count].view(torch.float32)
+
+        return (alias(ptrs[0], vcap * C).view(vcap, C), alias(ptrs[1], vcap),
+                alias(ptrs[2], vcap), alias(ptrs[3], vcap))
+
+
+def read_stats(stats: torch.Tensor) -> np.ndarray:
+    """Per-channel solve stats (iters, reason, rel_residual, bnorm) as a NumPy record array."""
+    return np.frombuffer(stats.cpu().numpy().tobytes(), dtype=_STATS_DTYPE)
+
+
+class _BilateralSolveFn(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, target, conf, grid: BilateralGrid, fwd: dict, bwd: dict):
+        y, _ = grid.solve(target, conf, **fwd)
+        x = grid.slice(y, target.shape[0])
+        ctx.grid, ctx.bwd = grid, bwd
+        ctx.save_for_backward(target, conf, y)
+        return x
+
+    @staticmethod
+    def backward(ctx, grad_x):
+        target, conf, y = ctx.saved_tensors
+        gt, gc, _, _ = ctx.grid.backward(target, conf, y, grad_x.contiguous(), **ctx.bwd)
+        return gt, gc, None, None, None
+
+
+def bilateral_solve(grid: BilateralGrid, target: torch.Tensor, conf: torch.Tensor, lam: float,
+                    max_iters: int = 25, rel_tol: float = 0.0, init: str = "hier",
+                    bwd_max_iters: int | None = None, bwd_rel_tol: float | None = None,
+                    check_every: int = 8) -> torch.Tensor:
+    """x_hat = S^T A^{-1} b, differentiable in `target` and `conf` (Section 3)."""
+    fwd = dict(lam=lam, max_iters=max_iters, rel_tol=rel_tol, init=init, check_every=check_every)
+    bwd = dict(lam=lam, max_iters=max_iters if bwd_max_iters is None else bwd_max_iters,
+               rel_tol=rel_tol if bwd_rel_tol is None else bwd_rel_tol, init=init,
+               check_every=check_every)
+    return _BilateralSolveFn.apply(target, conf, grid, fwd, bwd)

@@ -1,0 +1,92 @@
+"""Host-side checks of the C ABI: the library loads, exports every function
+include/bsolve.h declares, and rejects invalid arguments before touching the
+GPU.  None of these tests launches a kernel."""
+import ctypes as ct
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "bsolve.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?[A-Za-z_][A-Za-z0-9_]*\s*\**\s*(bs_[a-z0-9_]+)\s*\(",
+                       text, flags=re.M)
+    return sorted(set(names))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for want in ("bs_build_grid", "bs_bistochastize", "bs_solve", "bs_slice",
+                 "bs_solve_backward", "bs_grid_workspace_bytes", "bs_solve_workspace_bytes"):
+        assert want in names
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_1511_03296_amd import _lib as L
+    out = subprocess.run(["nm", "-D", "--defined-only", L.LIB_PATH], capture_output=True,
+                         text=True, check=True).stdout
+    exported = set(re.findall(r"\sT\s+(bs_[a-z0-9_]+)$", out, flags=re.M))
+    missing = [n for n in declared_functions() if n not in exported]
+    assert not missing, missing
+    assert set(L.EXPORTED) == set(declared_functions())
+    assert L.lib.bs_version() >> 16 == 1
+
+
+def test_struct_sizes_match_header_layout():
+    from paper_1511_03296_amd import _lib as L
+    assert ct.sizeof(L.Grid) == L.BS_GRID_BYTES
+    assert ct.sizeof(L.ChanStats) == 24
+    assert ct.sizeof(L.SolveParams) == 32
+    assert ct.sizeof(L.BistochParams) == 16
+
+
+def test_workspace_queries_are_pure_and_validate():
+    from paper_1511_03296_amd import _lib as L
+    p = L.GridParams(8, 4, 4)
+    n1 = L.lib.bs_grid_workspace_bytes(48, 64, ct.byref(p))
+    n2 = L.lib.bs_grid_workspace_bytes(96, 128, ct.byref(p))
+    assert n1 > 0 and n2 > n1 and n1 % 256 == 0
+    assert L.lib.bs_grid_workspace_bytes(0, 64, ct.byref(p)) == 0
+    assert L.lib.bs_grid_workspace_bytes(48, 64, ct.byref(L.GridParams(0, 4, 4))) == 0
+    assert L.lib.bs_grid_workspace_bytes(48, 64, None) == 0
+
+
+def test_invalid_arguments_are_rejected_before_launch():
+    from paper_1511_03296_amd import _lib as L
+    p = L.GridParams(8, 4, 4)
+    g = L.Grid()
+    st = L.lib.bs_build_grid(None, 48, 64, ct.byref(p), None, 0, None, ct.byref(g))
+    assert st == L.BS_EINVAL and b"NULL" in L.lib.bs_last_error()
+    st = L.lib.bs_build_grid(ct.c_void_p(256), 48, 64, ct.byref(p), ct.c_void_p(4096), 16, None,
+                             ct.byref(g))
+    assert st == L.BS_EWORKSPACE
+    st = L.lib.bs_build_grid(ct.c_void_p(256), 48, 64, ct.byref(p), ct.c_void_p(4100), 1 << 40,
+                             None, ct.byref(g))
+    assert st == L.BS_EINVAL and b"aligned" in L.lib.bs_last_error()
+    st = L.lib.bs_build_grid(ct.c_void_p(256), 70000, 64, ct.byref(p), ct.c_void_p(4096), 1 << 40,
+                             None, ct.byref(g))
+    assert st == L.BS_EUNSUPPORTED
+    # a handle that was never built
+    sp = L.SolveParams(1.0, 1, 25, 8, 0.0, 4.0, 0.0)
+    st = L.lib.bs_solve(ct.byref(g), ct.c_void_p(256), ct.c_void_p(256), 1, ct.byref(sp),
+                        ct.c_void_p(256), ct.c_void_p(4096), 1 << 30, None, None)
+    assert st == L.BS_EINVAL and b"not built" in L.lib.bs_last_error()
+    assert L.lib.bs_bistochastize(ct.byref(g), None, None) == L.BS_EINVAL
+    assert L.lib.bs_slice(ct.byref(g), ct.c_void_p(256), 1, ct.c_void_p(256), None) == L.BS_EINVAL
+    assert L.lib.bs_solve_workspace_bytes(ct.byref(g), 1) == 0
+    assert L.lib.bs_status_string(L.BS_EWORKSPACE) == b"workspace too small"
+
+
+def test_python_errors_map_statuses():
+    from paper_1511_03296_amd import _lib as L
+    L.lib.bs_build_grid(None, 48, 64, None, None, 0, None, None)
+    with pytest.raises(ValueError):
+        L.check(L.BS_EINVAL, "x")
+    with pytest.raises(L.BsError):
+        L.check(L.BS_EDEVICE, "x")
