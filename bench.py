@@ -1,0 +1,240 @@
+#!/usr/bin/env python3
+"""Throughput of the bilateral solver's hot path on one MI355X.
+
+One step = the whole path on one batch of synthetic input, inputs resident in
+HBM: build the grid and its pyramid, bistochastize, splat, initialise, PCG,
+slice (forward), then splat the upstream gradient, adjoint PCG and gradient
+scatter (backward).  Prints ONE JSON line with the Mpix/s of forward+backward
+steps, the roofline figure of the dominant kernel (timed with HIP events
+inside the library, on the launch stream) and the FP64 CPU oracle's rate on a
+bounded sample of the same workload.
+
+    python bench.py [--steps K] [--warmup W] [--workload NAME]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "Mpix/s solved to rel. residual 1e-5 (fwd and fwd+bwd), % HBM peak, vs plain"
+HBM_PEAK_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
+
+# name -> (generator kwargs, images, forward (max_iters, rel_tol), backward (max_iters, rel_tol))
+WORKLOADS = {
+    "stereo1024x768": dict(gen="stereo_refine", images=1, fwd=(25, 0.0), bwd=(25, 0.0)),
+    "depthsr2048x1536": dict(gen="depth_superres", images=1, fwd=(20000, 1e-5),
+                             bwd=(20000, 1e-5)),
+    "ramp64x48": dict(gen="tiny_ramp", images=1, fwd=(2000, 1e-5), bwd=(2000, 1e-5)),
+    "seg16x512x512": dict(gen="segmentation", images=16, fwd=(20000, 1e-6), bwd=(20000, 1e-6)),
+}
+
+
+def _source_digest() -> str:
+    h = hashlib.sha256()
+    with open(os.path.join(ROOT, "paper_1511_03296_amd", "csrc", "bs_solve.hip"), "rb") as f:
+        h.update(f.read())
+    return h.hexdigest()
+
+
+def make_problems(name: str):
+    import workloads as WL
+    spec = WORKLOADS[name]
+    gen = getattr(WL, spec["gen"])
+    return [gen(seed=i) for i in range(spec["images"])]
+
+
+def gpu_inputs(problems, dev):
+    import numpy as np
+    import torch
+    import workloads as WL
+    out = []
+    for i, p in enumerate(problems):
+        gx = p.extra.get("onehot")
+        gx = WL.random_grad(i, p.C, p.H, p.W) if gx is None else (2.0 * (p.target - gx))
+        out.append(dict(p=p, ref=torch.from_numpy(p.ref).to(dev),
+                        t=torch.from_numpy(p.target).to(dev),
+                        c=torch.from_numpy(p.conf).to(dev),
+                        gx=torch.from_numpy(np.ascontiguousarray(gx, dtype=np.float32)).to(dev)))
+    return out
+
+
+def run_step(inputs, spec, backward=True, keep=None):
+    """One pass of the hot path over every image of the batch."""
+    from paper_1511_03296_amd import BilateralGrid
+    (fi, ft), (bi, bt) = spec["fwd"], spec["bwd"]
+    fce = 0 if ft == 0.0 else 8
+    bce = 0 if bt == 0.0 else 8
+    for d in inputs:
+        p = d["p"]
+        G = BilateralGrid(d["ref"], p.sigma_xy, p.sigma_l, p.sigma_uv)
+        ws = G.solve_workspace(p.C)
+        y, st = G.solve(d["t"], d["c"], p.lam, max_iters=fi, rel_tol=ft, check_every=fce, ws=ws)
+        x = G.slice(y, p.C)
+        if backward:
+            gt, gc, _, bst = G.backward(d["t"], d["c"], y, d["gx"], p.lam, max_iters=bi,
+                                        rel_tol=bt, check_every=bce, ws=ws)
+        if keep is not None:
+            keep.append((G, st, bst if backward else None))
+
+
+def timed(inputs, spec, steps, backward=True):
+    import torch
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        run_step(inputs, spec, backward)
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / steps
+
+
+def kernel_times(inputs, spec, steps):
+    """Per-kernel average launch duration (HIP events on the launch stream)."""
+    from paper_1511_03296_amd import _lib as L
+    import ctypes as ct
+    names = ["level_count", "level_scan", "level_write", "neighbour_table", "bist_step",
+             "bist_other", "splat", "init", "pcg_start", "pcg_dir_matvec", "pcg_update", "slice",
+             "grad_scatter"]
+    L.check(L.lib.bs_timing_reset(), "timing_reset")
+    L.check(L.lib.bs_timing_enable(1), "timing_enable")
+    sec = timed(inputs, spec, steps)
+    L.check(L.lib.bs_timing_enable(0), "timing_enable")
+    out = {}
+    for n in names:
+        ms, cnt = ct.c_double(), ct.c_int64()
+        L.check(L.lib.bs_timing_read(n.encode(), ct.byref(ms), ct.byref(cnt)), "timing_read")
+        out[n] = (ms.value / steps, cnt.value / steps)
+    return sec, out
+
+
+def cpu_baseline(problems, spec, seconds):
+    """The FP64 oracle, as it stands, on a bounded sample of the workload."""
+    import numpy as np
+    from oracle import bilateral as O
+    import workloads as WL
+    (fi, ft), (bi, bt) = spec["fwd"], spec["bwd"]
+    p = problems[0]
+    sample = f"{p.name}: full forward+backward of image 0"
+    if p.pixels > 1_000_000 or ft > 0:
+        # tolerance-driven workloads: a centre crop keeps the sample bounded
+        h, w = min(p.H, 384), min(p.W, 512)
+        p = WL.crop(p, (p.H - h) // 2, (p.W - w) // 2, h, w)
+        sample = f"{p.name} ({w}x{h} centre crop), full forward+backward"
+    gx = WL.random_grad(0, p.C, p.H, p.W)
+    t0 = time.perf_counter()
+    n = 0
+    while True:
+        prm = O.Params(p.sigma_xy, p.sigma_l, p.sigma_uv, p.lam, max_iters=fi, rel_tol=ft)
+        sol = O.solve(p.ref, p.target, p.conf, prm)
+        prmb = O.Params(p.sigma_xy, p.sigma_l, p.sigma_uv, p.lam, max_iters=bi, rel_tol=bt)
+        O.solve_backward(sol, p.target, p.conf, gx, prmb)
+        n += 1
+        el = time.perf_counter() - t0
+        if el >= seconds:
+            break
+    return {"value": round(n * p.pixels / el / 1e6, 4), "unit": "Mpix/s", "cores": 1,
+            "kind": "oracle", "sample": f"{sample}, {n} step(s) in {el:.1f} s, NumPy float64, "
+                                        "one thread"}
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="stereo1024x768", choices=sorted(WORKLOADS))
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
+              "(images or row slabs would shard across GPUs, see the design notes)",
+              file=sys.stderr)
+        return 2
+
+    import torch
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        return 1
+    dev = torch.device("cuda:0")
+    spec = WORKLOADS[args.workload]
+    problems = make_problems(args.workload)
+    inputs = gpu_inputs(problems, dev)
+    pixels = sum(p.pixels for p in problems)
+    print(f"bench: {args.workload} images={len(problems)} pixels={pixels}", file=sys.stderr,
+          flush=True)
+
+    keep = []
+    for _ in range(max(1, args.warmup)):
+        keep.clear()
+        run_step(inputs, spec, True, keep)
+    torch.cuda.synchronize()
+    from paper_1511_03296_amd import read_stats
+    V = [G.vertex_count() for G, _, _ in keep]
+    fwd_iters = [int(read_stats(st)["iters"].max()) for _, st, _ in keep]
+    bwd_iters = [int(read_stats(bst)["iters"].max()) for _, _, bst in keep]
+    C = problems[0].C
+
+    sec_fb = timed(inputs, spec, args.steps, backward=True)
+    sec_f = timed(inputs, spec, args.steps, backward=False)
+    print(f"bench: fwd+bwd {sec_fb * 1e3:.3f} ms/step, fwd {sec_f * 1e3:.3f} ms/step",
+          file=sys.stderr, flush=True)
+    sec_inst, kt = kernel_times(inputs, spec, args.steps)
+    mv_ms, mv_launches = kt["pcg_dir_matvec"]
+    avg_us = mv_ms / mv_launches * 1e3 if mv_launches else float("nan")
+    bytes_per_launch = sum(V) / len(V) * (52 + 16 * C)
+    achieved = bytes_per_launch / (avg_us * 1e-6) / 1e9 if mv_launches else 0.0
+
+    traffic = None
+    if os.path.exists(TRAFFIC_FILE):
+        with open(TRAFFIC_FILE) as f:
+            tr = json.load(f)
+        if tr.get("source_sha256") == _source_digest() and tr.get("workload") == args.workload:
+            traffic = tr.get("bytes_per_launch")
+
+    line = {
+        "metric": METRIC,
+        "value": round(pixels / sec_fb / 1e6, 3),
+        "unit": "Mpix/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(sec_fb * 1e3, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "images": len(problems), "pixels": pixels,
+                   "channels": C, "sigma": [problems[0].sigma_xy, problems[0].sigma_l,
+                                            problems[0].sigma_uv],
+                   "lambda": problems[0].lam, "vertices": V[0] if len(V) == 1 else V,
+                   "fwd_pcg": list(spec["fwd"]), "bwd_pcg": list(spec["bwd"]),
+                   "fwd_iters": fwd_iters[0] if len(V) == 1 else fwd_iters,
+                   "bwd_iters": bwd_iters[0] if len(V) == 1 else bwd_iters,
+                   "parallelism": "single-gpu"},
+        "fwd_mpix_s": round(pixels / sec_f / 1e6, 3),
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": traffic, "kernel": "pcg_dir_matvec",
+                     "bytes_per_launch": int(bytes_per_launch), "avg_us": round(avg_us, 3),
+                     "launches_per_step": mv_launches},
+        "kernel_ms_per_step": {k: round(v[0], 4) for k, v in kt.items()},
+        "instrumented_ms_per_step": round(sec_inst * 1e3, 4),
+    }
+    if not args.no_cpu_baseline:
+        print("bench: cpu baseline (oracle)", file=sys.stderr, flush=True)
+        line["cpu_baseline"] = cpu_baseline(problems, spec, args.cpu_seconds)
+    print(json.dumps(line), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -1,9 +1,15 @@
 """MI355X-native bilateral solver (Barron & Poole, "The Fast Bilateral Solver").
 
 The solver runs as HIP kernels for gfx950 in ``libbsolve.so`` (C ABI in
-``include/bsolve.h``); this package is its Python binding.  Importing it loads
-the library and raises ImportError if it has not been built.
+``include/bsolve.h``); this package is its Python binding.  The first use of
+the API loads the library and raises ImportError if it has not been built
+(``python -m paper_1511_03296_amd.build``).
 """
-from .solver import BilateralGrid, SolveOptions, bilateral_solve, read_stats  # noqa: F401
-
 __all__ = ["BilateralGrid", "SolveOptions", "bilateral_solve", "read_stats"]
+
+
+def __getattr__(name):
+    if name in __all__:
+        from . import solver
+        return getattr(solver, name)
+    raise AttributeError(f"module {__name__!r} has no attribute {name!r}")

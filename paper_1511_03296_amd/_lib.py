@@ -93,6 +93,9 @@ _SIGS = {
     "bs_grid_get_view": (_i32, [ct.POINTER(Grid), ct.POINTER(GridView)]),
     "bs_solve_ws_view": (_i32, [ct.POINTER(Grid), _i32, _vp, _sz, ct.POINTER(_vp),
                                 ct.POINTER(_vp), ct.POINTER(_vp), ct.POINTER(_vp)]),
+    "bs_timing_enable": (_i32, [_i32]),
+    "bs_timing_reset": (_i32, []),
+    "bs_timing_read": (_i32, [ct.c_char_p, ct.POINTER(ct.c_double), ct.POINTER(ct.c_int64)]),
     "bs_status_string": (ct.c_char_p, [_i32]),
     "bs_last_error": (ct.c_char_p, []),
     "bs_version": (_i32, []),

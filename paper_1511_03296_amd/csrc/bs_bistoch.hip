@@ -1,10 +1,12 @@
 // Bistochastization of the grid blur (supplement Algorithm 1, Eq. equiv), in
 // float64:  n <- sqrt(n o m / (B n)),  n = 1 initially, with B = 10 I + N.
-// Each launch applies one Jacobi-style update to every vertex (reading the
-// previous n from one ping-pong buffer and writing the other) and reduces the
-// invariant residual max_v |n_v (B n)_v - m_v| / m_v of the n it read.  The
-// last block to finish decides, on the device, whether to stop; later
-// launches then return at once, so the host may enqueue them blindly.
+//
+// Launch s reads n_s from ping-pong buffer s % 2, writes n_{s+1} to the other
+// buffer and publishes per-block maxima of the invariant residual
+// max_v |n_v (B n_s)_v - m_v| / m_v.  Launch s+1 first reduces those maxima
+// (the order of a max does not matter) and decides whether n_s is the answer:
+// stop when the residual is <= tol or s >= max_iters.  Once stopped, later
+// launches return at once, so the host may enqueue them without waiting.
 #include "bs_internal.h"
 
 namespace bs {
@@ -19,23 +21,41 @@ __global__ void __launch_bounds__(kBlock) bist_init(double* __restrict__ n0,
     }
 }
 
-__global__ void __launch_bounds__(kBlock) bist_step(const int32_t* __restrict__ nbr,
-                                                     const int32_t* __restrict__ m,
-                                                     const double* __restrict__ src,
-                                                     double* __restrict__ dst, int64_t vcap,
-                                                     int32_t* __restrict__ counts,
-                                                     double* __restrict__ part,
-                                                     double* __restrict__ res_out,
-                                                     uint32_t* __restrict__ ticket, int step,
-                                                     int max_iters, double tol) {
+// Stop rule for the residual R of n_s.
+__device__ inline bool bist_stop(double R, int s, int max_iters, double tol) {
+    return R <= tol || s >= max_iters;
+}
+
+__global__ void __launch_bounds__(kRedBlock) bist_step(const int32_t* __restrict__ nbr,
+                                                        const int32_t* __restrict__ m,
+                                                        const double* __restrict__ src,
+                                                        double* __restrict__ dst, int64_t vcap,
+                                                        int32_t* __restrict__ counts,
+                                                        double* __restrict__ part,
+                                                        double* __restrict__ res_out, int step,
+                                                        int max_iters, double tol) {
 #pragma clang fp contract(off)
-    // Uniform across the grid: written by the previous launch's last block.
     if (counts[CNT_BIST_DONE]) return;
+    if (step >= 1) {
+        const double* prev = part + ((step - 1) & 1) * kRedGrid;
+        double r = 0.0;
+        for (int i = threadIdx.x; i < kRedGrid; i += kRedBlock) r = fmax(r, prev[i]);
+        const double R = block_max<kRedBlock>(r);
+        if (bist_stop(R, step - 1, max_iters, tol)) {
+            if (blockIdx.x == 0 && threadIdx.x == 0) {
+                counts[CNT_BIST_ITERS] = step - 1;
+                counts[CNT_BIST_SRC] = (step - 1) & 1;
+                *res_out = R;
+                counts[CNT_BIST_DONE] = 1;
+            }
+            return;
+        }
+    }
     const int V = counts[CNT_V];
     double lmax = 0.0;
-    const XcdTiles tl((V + kBlock - 1) / kBlock);
+    const XcdTiles tl((V + kRedBlock - 1) / kRedBlock);
     for (int64_t tile = tl.first; tile < tl.end; tile += tl.step) {
-        const int v = (int)(tile * kBlock) + threadIdx.x;
+        const int v = (int)(tile * kRedBlock) + threadIdx.x;
         if (v >= V) continue;
         const double n = src[v];
         double ns = 0.0;
@@ -52,33 +72,25 @@ __global__ void __launch_bounds__(kBlock) bist_step(const int32_t* __restrict__ 
         const double q = (n * mv) / bn;
         dst[v] = sqrt(q);
     }
-    __shared__ double red[kBlock / 64];
-    lmax = wave_max(lmax);
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = lmax;
-    __syncthreads();
+    lmax = block_max<kRedBlock>(lmax);
+    if (threadIdx.x == 0) part[(step & 1) * kRedGrid + blockIdx.x] = lmax;
+}
+
+// After the last enqueued launch `last`: decide on its residual if no launch
+// has stopped the iteration yet (single block).
+__global__ void __launch_bounds__(kRedBlock) bist_decide(int32_t* __restrict__ counts,
+                                                          const double* __restrict__ part,
+                                                          double* __restrict__ res_out, int last) {
+    if (counts[CNT_BIST_DONE]) return;
+    const double* prev = part + (last & 1) * kRedGrid;
+    double r = 0.0;
+    for (int i = threadIdx.x; i < kRedGrid; i += kRedBlock) r = fmax(r, prev[i]);
+    const double R = block_max<kRedBlock>(r);
     if (threadIdx.x == 0) {
-        double b = red[0];
-        for (int w = 1; w < kBlock / 64; ++w) b = fmax(b, red[w]);
-        part[blockIdx.x] = b;
-    }
-    if (last_block(ticket)) {
-        double b = 0.0;
-        for (int i = threadIdx.x; i < (int)gridDim.x; i += kBlock) b = fmax(b, part[i]);
-        b = wave_max(b);
-        __syncthreads();
-        if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = b;
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            double R = red[0];
-            for (int w = 1; w < kBlock / 64; ++w) R = fmax(R, red[w]);
-            if (R <= tol || step >= max_iters) {
-                counts[CNT_BIST_DONE] = 1;
-                counts[CNT_BIST_ITERS] = step;
-                counts[CNT_BIST_SRC] = step & 1;
-                *res_out = R;
-            }
-            atomicExch(ticket, 0u);
-        }
+        counts[CNT_BIST_ITERS] = last;
+        counts[CNT_BIST_SRC] = last & 1;
+        *res_out = R;
+        counts[CNT_BIST_DONE] = 1;
     }
 }
 
@@ -125,13 +137,14 @@ extern "C" bs_status bs_bistochastize(bs_grid* grid, const bs_bistoch_params* pa
     GridImpl& g = *impl(grid);
     hipStream_t s = (hipStream_t)stream;
     const int blocks = grid_blocks(ceil_div(g.vcap, kBlock));
-    hipLaunchKernelGGL(bist_init, dim3(blocks), dim3(kBlock), 0, s, g.nbuf[0], g.counts);
-    BS_CHECK_LAUNCH("bist_init");
+    BS_LAUNCH(s, K_BIST_OTHER, "bist_init", bist_init, dim3(blocks), dim3(kBlock), 0, s,
+              g.nbuf[0], g.counts);
+    int last = 0;
     for (int step = 0; step <= p.max_iters; ++step) {
-        hipLaunchKernelGGL(bist_step, dim3(blocks), dim3(kBlock), 0, s, g.nbr, g.lv[0].mult,
-                           g.nbuf[step & 1], g.nbuf[(step + 1) & 1], g.vcap, g.counts,
-                           g.bist_part, g.bist_res, g.ticket, step, p.max_iters, p.tol);
-        BS_CHECK_LAUNCH("bist_step");
+        BS_LAUNCH(s, K_BIST_STEP, "bist_step", bist_step, dim3(kRedGrid), dim3(kRedBlock), 0, s,
+                  g.nbr, g.lv[0].mult, g.nbuf[step & 1], g.nbuf[(step + 1) & 1], g.vcap,
+                  g.counts, g.bist_part, g.bist_res, step, p.max_iters, p.tol);
+        last = step;
         if (p.check_every > 0 && (step + 1) % p.check_every == 0 && step < p.max_iters) {
             int32_t done = 0;
             BS_TRY_HIP(hipMemcpyAsync(&done, g.counts + CNT_BIST_DONE, sizeof(int32_t),
@@ -140,9 +153,10 @@ extern "C" bs_status bs_bistochastize(bs_grid* grid, const bs_bistoch_params* pa
             if (done) break;
         }
     }
-    hipLaunchKernelGGL(bist_finalize, dim3(blocks), dim3(kBlock), 0, s, g.nbr, g.nbuf[0],
-                       g.nbuf[1], g.vcap, g.n64, g.nf, g.nn, g.counts);
-    BS_CHECK_LAUNCH("bist_finalize");
+    BS_LAUNCH(s, K_BIST_OTHER, "bist_decide", bist_decide, dim3(1), dim3(kRedBlock), 0, s,
+              g.counts, g.bist_part, g.bist_res, last);
+    BS_LAUNCH(s, K_BIST_OTHER, "bist_finalize", bist_finalize, dim3(blocks), dim3(kBlock), 0, s,
+              g.nbr, g.nbuf[0], g.nbuf[1], g.vcap, g.n64, g.nf, g.nn, g.counts);
     g.bistochastized = 1;
     return BS_OK;
 }

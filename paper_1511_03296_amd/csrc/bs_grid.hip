@@ -79,9 +79,8 @@ size_t layout_grid(GridImpl& g, int H, int W, const bs_grid_params& sp, void* ba
 
     Carver c(base);
     g.counts = c.take<int32_t>(CNT_SIZE);
-    g.ticket = c.take<uint32_t>(8);
     g.bist_res = c.take<double>(1);
-    g.bist_part = c.take<double>(kMaxGrid);
+    g.bist_part = c.take<double>(2 * kRedGrid);
     g.cell_cnt = c.take<int32_t>(max_cells);
     g.cell_items = c.take<int32_t>(max_cells);
     g.ikey = c.take<uint32_t>(g.P);
@@ -469,10 +468,9 @@ __global__ void __launch_bounds__(kBlock) neighbour_table(const uint64_t* __rest
     }
 }
 
-__global__ void clear_counts(int32_t* counts, uint32_t* ticket) {
+__global__ void clear_counts(int32_t* counts) {
     const int t = threadIdx.x;
     if (t < CNT_SIZE) counts[t] = 0;
-    if (t < 8) ticket[t] = 0;
 }
 
 // ---------------------------------------------------------------------------
@@ -494,16 +492,13 @@ template <int B, class Src>
 static bs_status launch_level(const Src& src, GridImpl& g, int k, hipStream_t st) {
     Level& L = g.lv[k];
     const int ncells = L.ncy * L.ncx;
-    hipLaunchKernelGGL((level_count<B, Src>), dim3(ncells), dim3(B), 0, st, src, g.cell_cnt,
+    BS_LAUNCH(st, K_LEVEL_COUNT, "level_count", (level_count<B, Src>), dim3(ncells), dim3(B), 0, st, src, g.cell_cnt,
                        g.cell_items, g.ikey, g.counts);
-    BS_CHECK_LAUNCH("level_count");
-    hipLaunchKernelGGL(level_scan, dim3(1), dim3(kScanBlock), 0, st, g.cell_cnt, g.cell_items,
+    BS_LAUNCH(st, K_LEVEL_SCAN, "level_scan", level_scan, dim3(1), dim3(kScanBlock), 0, st, g.cell_cnt, g.cell_items,
                        ncells, L.cell_vbase, L.cell_ibase, L.ptr, g.counts, k);
-    BS_CHECK_LAUNCH("level_scan");
     const int32_t* ones_prev = (k >= 2) ? g.lv[k - 1].ones : nullptr;
-    hipLaunchKernelGGL((level_write<B, Src>), dim3(ncells), dim3(B), 0, st, src, g.ikey,
+    BS_LAUNCH(st, K_LEVEL_WRITE, "level_write", (level_write<B, Src>), dim3(ncells), dim3(B), 0, st, src, g.ikey,
                        ones_prev, g.counts, L);
-    BS_CHECK_LAUNCH("level_write");
     return BS_OK;
 }
 
@@ -532,8 +527,7 @@ extern "C" bs_status bs_build_grid(const float* ref, int32_t H, int32_t W,
     layout_grid(g, H, W, *params, ws);
     hipStream_t s = (hipStream_t)stream;
 
-    hipLaunchKernelGGL(clear_counts, dim3(1), dim3(64), 0, s, g.counts, g.ticket);
-    BS_CHECK_LAUNCH("clear_counts");
+    BS_LAUNCH(s, K_BIST_OTHER, "clear_counts", clear_counts, dim3(1), dim3(64), 0, s, g.counts);
     PixelSource ps{ref, H, W, g.P, params->sigma_xy, params->sigma_l, params->sigma_uv,
                    g.lv[0].ncx};
     const int items = params->sigma_xy * params->sigma_xy;
@@ -549,9 +543,8 @@ extern "C" bs_status bs_build_grid(const float* ref, int32_t H, int32_t W,
         if (st != BS_OK) return st;
     }
     const int blocks = grid_blocks(ceil_div(g.vcap, kBlock));
-    hipLaunchKernelGGL(neighbour_table, dim3(blocks), dim3(kBlock), 0, s, g.lv[0].key,
+    BS_LAUNCH(s, K_NEIGHBOURS, "neighbour_table", neighbour_table, dim3(blocks), dim3(kBlock), 0, s, g.lv[0].key,
                        g.lv[0].cell_vbase, g.counts, g.lv[0].ncx, g.lv[0].ncy, g.vcap, g.nbr);
-    BS_CHECK_LAUNCH("neighbour_table");
     std::memcpy(out->opaque, &g, sizeof(g));
     return BS_OK;
 }

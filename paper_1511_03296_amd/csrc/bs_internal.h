@@ -36,11 +36,38 @@ bs_status check_hip(hipError_t e, const char* what);
     } while (0)
 
 // ---------------------------------------------------------------------------
+// Kernel timing hooks (see bs_timing.hip).
+// ---------------------------------------------------------------------------
+enum KernelId : int {
+    K_LEVEL_COUNT, K_LEVEL_SCAN, K_LEVEL_WRITE, K_NEIGHBOURS, K_BIST_STEP, K_BIST_OTHER,
+    K_SPLAT, K_INIT, K_PCG_START, K_PCG_DIR_MATVEC, K_PCG_UPDATE, K_SLICE, K_GRAD_SCATTER,
+    K_COUNT
+};
+void timing_begin(hipStream_t s, int id);
+void timing_end(hipStream_t s, int id);
+
+// Enqueues `launch` on `stream`, bracketed by timing events when enabled, and
+// checks it.
+#define BS_LAUNCH(stream, id, name, ...)                    \
+    do {                                                    \
+        ::bs::timing_begin(stream, id);                     \
+        hipLaunchKernelGGL(__VA_ARGS__);                    \
+        ::bs::timing_end(stream, id);                       \
+        BS_CHECK_LAUNCH(name);                              \
+    } while (0)
+
+// ---------------------------------------------------------------------------
 // Sizes and constants.
 // ---------------------------------------------------------------------------
 constexpr int kBlock = 256;          // threads per block of streaming kernels
 constexpr int kXcds = 8;             // MI355X: 8 accelerator dies, one L2 each
 constexpr int kMaxGrid = 2048;       // blocks of a grid-stride launch
+// Reducing kernels (bistochastization, PCG) run a fixed grid of kRedGrid
+// blocks of kRedBlock threads, one block per compute unit.  Each writes one
+// partial per block; the next kernel reduces them in its prologue (the kernel
+// boundary is the only grid-wide synchronisation).
+constexpr int kRedBlock = 1024;
+constexpr int kRedGrid = 256;
 constexpr int kCellTile = 2048;      // LDS tile of item keys in the level builders
 constexpr int kCellBlock = 128;      // threads per cell block of the level builders
 
@@ -131,8 +158,7 @@ struct GridImpl {
     double* nn;              // [vcap] n o N n
     int32_t* counts;         // [CNT_SIZE]
     double* bist_res;        // [1]
-    double* bist_part;       // [kMaxGrid]
-    uint32_t* ticket;        // [8] last-block tickets
+    double* bist_part;       // [2][kRedGrid] ping-pong partial maxima
     int32_t* cell_cnt;       // [max_cells] scratch
     int32_t* cell_items;     // [max_cells] scratch
     uint32_t* ikey;          // [P] item keys with first-occurrence flag, scratch
@@ -181,20 +207,32 @@ __device__ inline double wave_max(double v) {
     return v;
 }
 
-// Last-block election after every block has published its partial results.
-// Returns true in exactly one block (the last to arrive), which then sees all
-// other blocks' writes; that block resets the ticket for the next launch.
-__device__ inline bool last_block(uint32_t* ticket) {
-    __shared__ bool s_last;
-    __threadfence();
+// Block-wide sum of one double per thread, deterministic (fixed shuffle and
+// LDS trees); the result is returned to every thread.
+template <int B>
+__device__ inline double block_sum(double v) {
+    __shared__ double red[B / 64];
+    v = wave_sum(v);
     __syncthreads();
-    if (threadIdx.x == 0) {
-        uint32_t prev = atomicAdd(ticket, 1u);
-        s_last = (prev == gridDim.x - 1);
-    }
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
     __syncthreads();
-    if (s_last) __threadfence();
-    return s_last;
+    double s = 0.0;
+#pragma unroll
+    for (int w = 0; w < B / 64; ++w) s += red[w];
+    return s;
+}
+
+template <int B>
+__device__ inline double block_max(double v) {
+    __shared__ double red[B / 64];
+    v = wave_max(v);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    double s = red[0];
+#pragma unroll
+    for (int w = 1; w < B / 64; ++w) s = fmax(s, red[w]);
+    return s;
 }
 
 }  // namespace bs

@@ -21,13 +21,19 @@ namespace bs {
 
 struct ChanState {
     double rho, alpha, beta, bnorm, res;
-    int32_t active, iters, reason, pad;
+    int32_t active, iters, reason, phase;   // phase 0: initial residual not yet reduced
 };
 
 enum Ctl : int { CTL_ACTIVE = 0, CTL_SIZE = 8 };
 
+// Partials of the reducing kernels: [2 slots][3 values][C][kRedGrid].
+//   slot 0 -- written by pcg_start (r^T r, b^T b, r^T M^-1 r) and by
+//             pcg_update (r^T r, 0, r^T M^-1 r);
+//   slot 1 -- written by pcg_dir_matvec (d^T q).
+// Per-channel state, double-buffered the same way: pcg_dir_matvec reads
+// state 0 and writes state 1, pcg_update reads state 1 and writes state 0.
 struct SolveWs {
-    int C, G, vpb;
+    int C, vpb;
     float* sc;
     float* diag;
     float* minv;
@@ -37,17 +43,15 @@ struct SolveWs {
     float* q;
     float* g;
     float* up[BS_MAX_LEVELS];
-    ChanState* cs;
-    double* part;
-    uint32_t* ticket;
+    ChanState* cs[2];
+    double* part[2];
     int32_t* ctl;
     size_t bytes;
 };
 
 static size_t layout_solve(const GridImpl& g, int C, void* base, SolveWs& w) {
     w.C = C;
-    w.vpb = kBlock / C;
-    w.G = grid_blocks(ceil_div(g.vcap, w.vpb));
+    w.vpb = kRedBlock / C;
     Carver c(base);
     const int64_t n = g.vcap * C;
     w.sc = c.take<float>(g.vcap);
@@ -62,9 +66,10 @@ static size_t layout_solve(const GridImpl& g, int C, void* base, SolveWs& w) {
     w.up[0] = nullptr;
     for (int k = 1; k < BS_MAX_LEVELS; ++k)
         w.up[k] = (k < g.levels) ? c.take<float>(g.lv[k].cap * (C + 1)) : nullptr;
-    w.cs = c.take<ChanState>(C);
-    w.part = c.take<double>((int64_t)3 * C * w.G);
-    w.ticket = c.take<uint32_t>(8);
+    w.cs[0] = c.take<ChanState>(C);
+    w.cs[1] = c.take<ChanState>(C);
+    w.part[0] = c.take<double>((int64_t)3 * C * kRedGrid);
+    w.part[1] = c.take<double>((int64_t)3 * C * kRedGrid);
     w.ctl = c.take<int32_t>(CTL_SIZE);
     w.bytes = align_up(c.off, 256);
     return w.bytes;
@@ -75,12 +80,20 @@ static size_t layout_solve(const GridImpl& g, int C, void* base, SolveWs& w) {
 // ---------------------------------------------------------------------------
 
 // Sums NV per-thread values over the vertices of the block, per channel, with
-// a fixed pairwise tree; writes the block's partials to part[(k C + ch) G + b].
+// a fixed tree, and writes the block's partials to part[(k C + ch) G + block].
 template <int NV>
 __device__ inline void block_channel_partials(const double (&acc)[NV], int C, int vpb,
-                                              double* __restrict__ part, int G) {
-    __shared__ double s[NV][kBlock];
+                                              double* __restrict__ part) {
     const int t = threadIdx.x;
+    if (C == 1) {
+#pragma unroll
+        for (int k = 0; k < NV; ++k) {
+            const double v = block_sum<kRedBlock>(acc[k]);
+            if (t == 0) part[(int64_t)k * kRedGrid + blockIdx.x] = v;
+        }
+        return;
+    }
+    __shared__ double s[NV][kRedBlock];
 #pragma unroll
     for (int k = 0; k < NV; ++k) s[k][t] = acc[k];
     __syncthreads();
@@ -96,38 +109,79 @@ __device__ inline void block_channel_partials(const double (&acc)[NV], int C, in
     }
     if (t < C) {
 #pragma unroll
-        for (int k = 0; k < NV; ++k) part[((int64_t)k * C + t) * G + blockIdx.x] = s[k][t];
+        for (int k = 0; k < NV; ++k) part[((int64_t)k * C + t) * kRedGrid + blockIdx.x] = s[k][t];
     }
 }
 
-// In the last block: out[k C + ch] = sum over blocks of the partials, one wave
-// per (k, ch) pair, lanes striding over blocks, then a shuffle tree.
+// out[k C + ch] = sum over the kRedGrid blocks of the producer's partials,
+// computed identically by every block: one wave per (k, ch) pair, lanes
+// striding over blocks, then a shuffle tree.
 template <int NV>
-__device__ inline void final_channel_sums(const double* __restrict__ part, int C, int G,
-                                          double* out) {
+__device__ inline void reduce_partials(const double* __restrict__ part, int C, double* out) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    for (int pair = wave; pair < NV * C; pair += kBlock / 64) {
+    for (int pair = wave; pair < NV * C; pair += kRedBlock / 64) {
         double s = 0.0;
-        for (int b = lane; b < G; b += 64) s += part[(int64_t)pair * G + b];
+        for (int b = lane; b < kRedGrid; b += 64) s += part[(int64_t)pair * kRedGrid + b];
         s = wave_sum(s);
         if (lane == 0) out[pair] = s;
     }
     __syncthreads();
 }
 
+// Completes the previous PCG step for every channel from the slot-0 partials:
+// the initial residual (phase 0) or the end of an iteration (stopping rule).
+__device__ inline void advance_state(ChanState& st, double rr, double bb, double rho_new,
+                                     int max_iters, double tol) {
+    if (st.phase == 0) {
+        st.phase = 1;
+        st.bnorm = sqrt(bb);
+        st.rho = rho_new;
+        st.beta = 0.0;
+        st.iters = 0;
+        st.active = 0;
+        if (bb == 0.0) {
+            st.reason = 5;
+            st.res = 0.0;
+        } else {
+            st.res = sqrt(rr) / st.bnorm;
+            if (st.res <= tol) st.reason = 1;
+            else if (max_iters <= 0) st.reason = 2;
+            else if (rho_new == 0.0) st.reason = 3;
+            else {
+                st.active = 1;
+                st.reason = 0;
+            }
+        }
+        return;
+    }
+    if (!st.active) return;
+    st.beta = rho_new / st.rho;
+    st.rho = rho_new;
+    st.iters += 1;
+    st.res = sqrt(rr) / st.bnorm;
+    int reason = 0;
+    if (st.res <= tol) reason = 1;
+    else if (st.iters >= max_iters) reason = 2;
+    else if (rho_new == 0.0) reason = 3;
+    if (reason) {
+        st.active = 0;
+        st.reason = reason;
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Kernels.
 // ---------------------------------------------------------------------------
 
-__global__ void solve_prologue(ChanState* cs, int C, uint32_t* ticket, int32_t* ctl) {
+__global__ void solve_prologue(ChanState* cs0, ChanState* cs1, int C, int32_t* ctl) {
     const int t = threadIdx.x;
-    if (t < 8) ticket[t] = 0;
     if (t < CTL_SIZE) ctl[t] = 0;
     for (int c = t; c < C; c += blockDim.x) {
         ChanState z;
         z.rho = z.alpha = z.beta = z.bnorm = z.res = 0.0;
-        z.active = z.iters = z.reason = z.pad = 0;
-        cs[c] = z;
+        z.active = z.iters = z.reason = z.phase = 0;
+        cs0[c] = z;
+        cs1[c] = z;
     }
 }
 
@@ -261,14 +315,13 @@ __global__ void __launch_bounds__(kBlock) hier_final(const float* __restrict__ b
     }
 }
 
-// A z for one element: diag(A) z_v - lam n_v sum_j n_j z_j.
-// r = b - A y0 and the initial per-channel scalars.
-__global__ void __launch_bounds__(kBlock) pcg_start(
+// r = b - A y0 for one (vertex, channel) element per thread, with
+// A z = diag(A) z_v - lam n_v sum_j n_j z_j; partials r^T r, b^T b, r^T M^-1 r.
+__global__ void __launch_bounds__(kRedBlock) pcg_start(
     const int32_t* __restrict__ nbr, int64_t vcap, const float* __restrict__ nf,
     const float* __restrict__ diag, const float* __restrict__ minv, const float* __restrict__ b,
     const float* __restrict__ y, float* __restrict__ r, float lam, int C, int vpb,
-    const int32_t* __restrict__ counts, ChanState* __restrict__ cs, double* __restrict__ part,
-    uint32_t* __restrict__ ticket, int32_t* __restrict__ ctl, int max_iters, double tol) {
+    const int32_t* __restrict__ counts, double* __restrict__ part) {
     const int V = counts[CNT_V];
     const int t = threadIdx.x;
     const int vl = t / C, ch = t - vl * C;
@@ -293,54 +346,43 @@ __global__ void __launch_bounds__(kBlock) pcg_start(
         acc[1] += (double)bv * (double)bv;
         acc[2] += (double)rv * (double)(minv[v] * rv);
     }
-    block_channel_partials<3>(acc, C, vpb, part, gridDim.x);
-    if (last_block(ticket)) {
-        __shared__ double fin[3 * BS_MAX_CHANNELS];
-        final_channel_sums<3>(part, C, gridDim.x, fin);
-        if (t < C) {
-            ChanState s = cs[t];
-            const double rr = fin[t], bb = fin[C + t], rho = fin[2 * C + t];
-            s.bnorm = sqrt(bb);
-            s.rho = rho;
-            s.beta = 0.0;
-            s.iters = 0;
-            s.active = 0;
-            if (bb == 0.0) {
-                s.reason = 5;
-                s.res = 0.0;
-            } else {
-                s.res = sqrt(rr) / s.bnorm;
-                if (s.res <= tol) s.reason = 1;
-                else if (max_iters <= 0) s.reason = 2;
-                else if (rho == 0.0) s.reason = 3;
-                else {
-                    s.active = 1;
-                    s.reason = 0;
-                }
-            }
-            cs[t] = s;
-            if (s.active) atomicAdd(&ctl[CTL_ACTIVE], 1);
-        }
-        if (t == 0) atomicExch(ticket, 0u);
-    }
+    block_channel_partials<3>(acc, C, vpb, part);
 }
 
-// d = M^-1 r + beta d_old (beta = 0 on the first iteration), q = A d, d^T q.
-__global__ void __launch_bounds__(kBlock) pcg_dir_matvec(
+// Prologue: finish the previous step from the slot-0 partials (stopping rule,
+// beta).  Then  d = M^-1 r + beta d_old  (beta = 0 on the first iteration),
+// q = A d  and partials of d^T q.
+__global__ void __launch_bounds__(kRedBlock) pcg_dir_matvec(
     const int32_t* __restrict__ nbr, int64_t vcap, const float* __restrict__ nf,
     const float* __restrict__ diag, const float* __restrict__ minv, const float* __restrict__ r,
     const float* __restrict__ dold, float* __restrict__ dnew, float* __restrict__ q, float lam,
-    int C, int vpb, const int32_t* __restrict__ counts, ChanState* __restrict__ cs,
-    double* __restrict__ part, uint32_t* __restrict__ ticket, int32_t* __restrict__ ctl) {
-    if (ctl[CTL_ACTIVE] == 0) return;
-    const int V = counts[CNT_V];
+    int C, int vpb, const int32_t* __restrict__ counts, const ChanState* __restrict__ cs_in,
+    ChanState* __restrict__ cs_out, const double* __restrict__ part_in,
+    double* __restrict__ part_out, int32_t* __restrict__ ctl, int max_iters, double tol) {
+    __shared__ ChanState S[BS_MAX_CHANNELS];
+    __shared__ double fin[3 * BS_MAX_CHANNELS];
+    __shared__ int n_active;
     const int t = threadIdx.x;
+    reduce_partials<3>(part_in, C, fin);
+    if (t == 0) n_active = 0;
+    __syncthreads();
+    if (t < C) {
+        ChanState st = cs_in[t];
+        advance_state(st, fin[t], fin[C + t], fin[2 * C + t], max_iters, tol);
+        S[t] = st;
+        if (st.active) atomicAdd(&n_active, 1);
+        if (blockIdx.x == 0) cs_out[t] = st;
+    }
+    __syncthreads();
+    if (blockIdx.x == 0 && t == 0) ctl[CTL_ACTIVE] = n_active;
+    if (n_active == 0) return;
+    const int V = counts[CNT_V];
     const int vl = t / C, ch = t - vl * C;
     const bool lane_ok = vl < vpb;
-    const ChanState s = cs[lane_ok ? ch : 0];
-    const bool act = lane_ok && s.active;
-    const bool first = s.iters == 0;
-    const float beta = (float)s.beta;
+    const ChanState st = S[lane_ok ? ch : 0];
+    const bool act = lane_ok && st.active;
+    const bool first = st.iters == 0;
+    const float beta = (float)st.beta;
     double acc[1] = {0.0};
     const XcdTiles tl((V + vpb - 1) / vpb);
     for (int64_t tile = tl.first; tile < tl.end; tile += tl.step) {
@@ -365,43 +407,50 @@ __global__ void __launch_bounds__(kBlock) pcg_dir_matvec(
         q[e] = qv;
         acc[0] += (double)dv * (double)qv;
     }
-    block_channel_partials<1>(acc, C, vpb, part, gridDim.x);
-    if (last_block(ticket)) {
-        __shared__ double fin[BS_MAX_CHANNELS];
-        final_channel_sums<1>(part, C, gridDim.x, fin);
-        if (t < C) {
-            ChanState st = cs[t];
-            if (st.active) {
-                const double dq = fin[t];
-                if (!(dq > 0.0)) {
-                    st.active = 0;
-                    st.reason = 4;
-                    atomicSub(&ctl[CTL_ACTIVE], 1);
-                } else {
-                    st.alpha = st.rho / dq;
-                }
-                cs[t] = st;
-            }
-        }
-        if (t == 0) atomicExch(ticket, 0u);
-    }
+    block_channel_partials<1>(acc, C, vpb, part_out);
 }
 
-// y += alpha d, r -= alpha q, then r^T M^-1 r, r^T r and the stopping rule.
-__global__ void __launch_bounds__(kBlock) pcg_update(
+// Prologue: alpha = r^T M^-1 r / d^T q from the slot-1 partials (a channel
+// with d^T q <= 0 stops).  Then  y += alpha d,  r -= alpha q  and partials of
+// r^T r and r^T M^-1 r.
+__global__ void __launch_bounds__(kRedBlock) pcg_update(
     const float* __restrict__ minv, const float* __restrict__ d, const float* __restrict__ q,
     float* __restrict__ y, float* __restrict__ r, int C, int vpb,
-    const int32_t* __restrict__ counts, ChanState* __restrict__ cs, double* __restrict__ part,
-    uint32_t* __restrict__ ticket, int32_t* __restrict__ ctl, int max_iters, double tol) {
-    if (ctl[CTL_ACTIVE] == 0) return;
-    const int V = counts[CNT_V];
+    const int32_t* __restrict__ counts, const ChanState* __restrict__ cs_in,
+    ChanState* __restrict__ cs_out, const double* __restrict__ part_in,
+    double* __restrict__ part_out, int32_t* __restrict__ ctl) {
+    __shared__ ChanState S[BS_MAX_CHANNELS];
+    __shared__ double fin[BS_MAX_CHANNELS];
+    __shared__ int n_active;
     const int t = threadIdx.x;
+    reduce_partials<1>(part_in, C, fin);
+    if (t == 0) n_active = 0;
+    __syncthreads();
+    if (t < C) {
+        ChanState st = cs_in[t];
+        if (st.active) {
+            const double dq = fin[t];
+            if (!(dq > 0.0)) {
+                st.active = 0;
+                st.reason = 4;
+            } else {
+                st.alpha = st.rho / dq;
+            }
+        }
+        S[t] = st;
+        if (st.active) atomicAdd(&n_active, 1);
+        if (blockIdx.x == 0) cs_out[t] = st;
+    }
+    __syncthreads();
+    if (blockIdx.x == 0 && t == 0) ctl[CTL_ACTIVE] = n_active;
+    if (n_active == 0) return;
+    const int V = counts[CNT_V];
     const int vl = t / C, ch = t - vl * C;
     const bool lane_ok = vl < vpb;
-    const ChanState s = cs[lane_ok ? ch : 0];
-    const bool act = lane_ok && s.active;
-    const float alpha = (float)s.alpha;
-    double acc[2] = {0.0, 0.0};
+    const ChanState st = S[lane_ok ? ch : 0];
+    const bool act = lane_ok && st.active;
+    const float alpha = (float)st.alpha;
+    double acc[3] = {0.0, 0.0, 0.0};
     const XcdTiles tl((V + vpb - 1) / vpb);
     for (int64_t tile = tl.first; tile < tl.end; tile += tl.step) {
         const int v = (int)(tile * vpb) + vl;
@@ -410,46 +459,33 @@ __global__ void __launch_bounds__(kBlock) pcg_update(
         y[e] += alpha * d[e];
         const float rv = r[e] - alpha * q[e];
         r[e] = rv;
-        acc[0] += (double)rv * (double)(minv[v] * rv);
-        acc[1] += (double)rv * (double)rv;
+        acc[0] += (double)rv * (double)rv;
+        acc[2] += (double)rv * (double)(minv[v] * rv);
     }
-    block_channel_partials<2>(acc, C, vpb, part, gridDim.x);
-    if (last_block(ticket)) {
-        __shared__ double fin[2 * BS_MAX_CHANNELS];
-        final_channel_sums<2>(part, C, gridDim.x, fin);
-        if (t < C) {
-            ChanState st = cs[t];
-            if (st.active) {
-                const double rho_new = fin[t], rr = fin[C + t];
-                st.beta = rho_new / st.rho;
-                st.rho = rho_new;
-                st.iters += 1;
-                st.res = sqrt(rr) / st.bnorm;
-                int reason = 0;
-                if (st.res <= tol) reason = 1;
-                else if (st.iters >= max_iters) reason = 2;
-                else if (rho_new == 0.0) reason = 3;
-                if (reason) {
-                    st.active = 0;
-                    st.reason = reason;
-                    atomicSub(&ctl[CTL_ACTIVE], 1);
-                }
-                cs[t] = st;
-            }
-        }
-        if (t == 0) atomicExch(ticket, 0u);
-    }
+    block_channel_partials<3>(acc, C, vpb, part_out);
 }
 
-__global__ void write_stats(const ChanState* __restrict__ cs, int C, bs_chan_stats* out) {
+// After the last enqueued iteration (single block): completes the pending
+// step from the slot-0 partials and writes the per-channel stats.
+__global__ void __launch_bounds__(kRedBlock) pcg_finish(ChanState* __restrict__ cs,
+                                                         const double* __restrict__ part, int C,
+                                                         int max_iters, double tol,
+                                                         bs_chan_stats* __restrict__ out) {
+    __shared__ double fin[3 * BS_MAX_CHANNELS];
     const int t = threadIdx.x;
+    reduce_partials<3>(part, C, fin);
     if (t < C) {
-        bs_chan_stats o;
-        o.iters = cs[t].iters;
-        o.reason = cs[t].reason;
-        o.rel_residual = cs[t].res;
-        o.bnorm = cs[t].bnorm;
-        out[t] = o;
+        ChanState st = cs[t];
+        advance_state(st, fin[t], fin[C + t], fin[2 * C + t], max_iters, tol);
+        cs[t] = st;
+        if (out) {
+            bs_chan_stats o;
+            o.iters = st.iters;
+            o.reason = st.reason;
+            o.rel_residual = st.res;
+            o.bnorm = st.bnorm;
+            out[t] = o;
+        }
     }
 }
 
@@ -518,54 +554,50 @@ static bs_status run_init(const GridImpl& g, const SolveWs& w, const bs_solve_pa
     const int C = w.C;
     const int blocks = grid_blocks(ceil_div(g.vcap * C, kBlock));
     if (p.init == BS_INIT_FLAT) {
-        hipLaunchKernelGGL(flat_init_kernel, dim3(blocks), dim3(kBlock), 0, s, w.b, w.sc, C,
+        BS_LAUNCH(s, K_INIT, "flat_init", flat_init_kernel, dim3(blocks), dim3(kBlock), 0, s, w.b, w.sc, C,
                            g.counts, y);
-        BS_CHECK_LAUNCH("flat_init");
         return BS_OK;
     }
     for (int k = 1; k < g.levels; ++k) {
         const int bk = grid_blocks(ceil_div(g.lv[k].cap * (C + 1), kBlock));
-        hipLaunchKernelGGL(pyr_up, dim3(bk), dim3(kBlock), 0, s, g.lv[k].ptr, g.lv[k].list, w.b,
+        BS_LAUNCH(s, K_INIT, "pyr_up", pyr_up, dim3(bk), dim3(kBlock), 0, s, g.lv[k].ptr, g.lv[k].list, w.b,
                            w.sc, (const float*)(k >= 2 ? w.up[k - 1] : nullptr), w.up[k], C, k,
                            g.counts);
-        BS_CHECK_LAUNCH("pyr_up");
     }
     for (int k = g.levels - 1; k >= 1; --k) {
         const int bk = grid_blocks(ceil_div(g.lv[k].cap * (C + 1), kBlock));
         const float wk = (float)std::pow((double)p.init_alpha, -((double)p.init_beta + k));
         const float* upp = (k + 1 < g.levels) ? w.up[k + 1] : nullptr;
         const int32_t* par = (k + 1 < g.levels) ? g.lv[k + 1].item_parent : nullptr;
-        hipLaunchKernelGGL(pyr_down, dim3(bk), dim3(kBlock), 0, s, w.up[k], upp, par,
+        BS_LAUNCH(s, K_INIT, "pyr_down", pyr_down, dim3(bk), dim3(kBlock), 0, s, w.up[k], upp, par,
                            g.lv[k].ones, wk, C, k, g.counts);
-        BS_CHECK_LAUNCH("pyr_down");
     }
     const int32_t* par0 = g.levels > 1 ? g.lv[1].item_parent : nullptr;
     const float* up1 = g.levels > 1 ? w.up[1] : nullptr;
-    hipLaunchKernelGGL(hier_final, dim3(blocks), dim3(kBlock), 0, s, w.b, w.sc, up1, par0, C,
+    BS_LAUNCH(s, K_INIT, "hier_final", hier_final, dim3(blocks), dim3(kBlock), 0, s, w.b, w.sc, up1, par0, C,
                        g.counts, y);
-    BS_CHECK_LAUNCH("hier_final");
     return BS_OK;
 }
 
 // PCG on A y = w.b from the state already in y.
 static bs_status run_pcg(const GridImpl& g, const SolveWs& w, const bs_solve_params& p,
-                         float* y, hipStream_t s) {
+                         float* y, bs_chan_stats* stats, hipStream_t s) {
     const int C = w.C;
-    hipLaunchKernelGGL(pcg_start, dim3(w.G), dim3(kBlock), 0, s, g.nbr, g.vcap, g.nf, w.diag,
-                       w.minv, w.b, y, w.r, p.lambda, C, w.vpb, g.counts, w.cs, w.part,
-                       w.ticket, w.ctl, p.max_iters, p.rel_tol);
-    BS_CHECK_LAUNCH("pcg_start");
+    BS_LAUNCH(s, K_INIT, "solve_prologue", solve_prologue, dim3(1), dim3(64), 0, s, w.cs[0],
+              w.cs[1], C, w.ctl);
+    BS_LAUNCH(s, K_PCG_START, "pcg_start", pcg_start, dim3(kRedGrid), dim3(kRedBlock), 0, s,
+              g.nbr, g.vcap, g.nf, w.diag, w.minv, w.b, y, w.r, p.lambda, C, w.vpb, g.counts,
+              w.part[0]);
     for (int it = 0; it < p.max_iters; ++it) {
         float* dn = w.d[it & 1];
         const float* dold = w.d[(it + 1) & 1];
-        hipLaunchKernelGGL(pcg_dir_matvec, dim3(w.G), dim3(kBlock), 0, s, g.nbr, g.vcap, g.nf,
-                           w.diag, w.minv, w.r, dold, dn, w.q, p.lambda, C, w.vpb, g.counts,
-                           w.cs, w.part, w.ticket, w.ctl);
-        BS_CHECK_LAUNCH("pcg_dir_matvec");
-        hipLaunchKernelGGL(pcg_update, dim3(w.G), dim3(kBlock), 0, s, w.minv, dn, w.q, y, w.r,
-                           C, w.vpb, g.counts, w.cs, w.part, w.ticket, w.ctl, p.max_iters,
-                           p.rel_tol);
-        BS_CHECK_LAUNCH("pcg_update");
+        BS_LAUNCH(s, K_PCG_DIR_MATVEC, "pcg_dir_matvec", pcg_dir_matvec, dim3(kRedGrid),
+                  dim3(kRedBlock), 0, s, g.nbr, g.vcap, g.nf, w.diag, w.minv, w.r, dold, dn, w.q,
+                  p.lambda, C, w.vpb, g.counts, w.cs[0], w.cs[1], w.part[0], w.part[1], w.ctl,
+                  p.max_iters, p.rel_tol);
+        BS_LAUNCH(s, K_PCG_UPDATE, "pcg_update", pcg_update, dim3(kRedGrid), dim3(kRedBlock), 0,
+                  s, w.minv, dn, w.q, y, w.r, C, w.vpb, g.counts, w.cs[1], w.cs[0], w.part[1],
+                  w.part[0], w.ctl);
         if (p.check_every > 0 && (it + 1) % p.check_every == 0 && it + 1 < p.max_iters) {
             int32_t active = 0;
             BS_TRY_HIP(hipMemcpyAsync(&active, w.ctl + CTL_ACTIVE, sizeof(int32_t),
@@ -574,6 +606,8 @@ static bs_status run_pcg(const GridImpl& g, const SolveWs& w, const bs_solve_par
             if (active == 0) break;
         }
     }
+    BS_LAUNCH(s, K_INIT, "pcg_finish", pcg_finish, dim3(1), dim3(kRedBlock), 0, s, w.cs[0],
+              w.part[0], C, p.max_iters, p.rel_tol, stats);
     return BS_OK;
 }
 
@@ -619,21 +653,14 @@ extern "C" bs_status bs_solve(const bs_grid* grid, const float* target, const fl
     hipStream_t s = (hipStream_t)stream;
     const bs_solve_params& p = *params;
 
-    hipLaunchKernelGGL(solve_prologue, dim3(1), dim3(64), 0, s, w.cs, C, w.ticket, w.ctl);
-    BS_CHECK_LAUNCH("solve_prologue");
     const int vblocks = grid_blocks(ceil_div(g.vcap, kBlock));
-    hipLaunchKernelGGL(splat_kernel<true>, dim3(vblocks), dim3(kBlock), 0, s, g.lv[0].ptr,
+    BS_LAUNCH(s, K_SPLAT, "splat", splat_kernel<true>, dim3(vblocks), dim3(kBlock), 0, s, g.lv[0].ptr,
                        g.lv[0].list, conf, target, C, g.P, g.nn, (double)p.lambda, g.counts,
                        w.sc, w.diag, w.minv, w.b);
-    BS_CHECK_LAUNCH("splat");
     st = run_init(g, w, p, y, s);
     if (st != BS_OK) return st;
-    st = run_pcg(g, w, p, y, s);
+    st = run_pcg(g, w, p, y, stats, s);
     if (st != BS_OK) return st;
-    if (stats) {
-        hipLaunchKernelGGL(write_stats, dim3(1), dim3(64), 0, s, w.cs, C, stats);
-        BS_CHECK_LAUNCH("write_stats");
-    }
     return BS_OK;
 }
 
@@ -646,9 +673,8 @@ extern "C" bs_status bs_slice(const bs_grid* grid, const float* y, int32_t C, fl
     const GridImpl& g = *impl(grid);
     hipStream_t s = (hipStream_t)stream;
     const int blocks = grid_blocks(ceil_div(g.P, kBlock));
-    hipLaunchKernelGGL(slice_kernel, dim3(blocks), dim3(kBlock), 0, s, g.lv[0].item_parent, y, C,
+    BS_LAUNCH(s, K_SLICE, "slice", slice_kernel, dim3(blocks), dim3(kBlock), 0, s, g.lv[0].item_parent, y, C,
                        g.P, x);
-    BS_CHECK_LAUNCH("slice");
     return BS_OK;
 }
 
@@ -675,24 +701,16 @@ extern "C" bs_status bs_solve_backward(const bs_grid* grid, const float* target,
     const bs_solve_params& p = *params;
     float* gb = g_out ? g_out : w.g;
 
-    hipLaunchKernelGGL(solve_prologue, dim3(1), dim3(64), 0, s, w.cs, C, w.ticket, w.ctl);
-    BS_CHECK_LAUNCH("solve_prologue");
     const int vblocks = grid_blocks(ceil_div(g.vcap, kBlock));
-    hipLaunchKernelGGL(splat_kernel<false>, dim3(vblocks), dim3(kBlock), 0, s, g.lv[0].ptr,
+    BS_LAUNCH(s, K_SPLAT, "splat_grad", splat_kernel<false>, dim3(vblocks), dim3(kBlock), 0, s, g.lv[0].ptr,
                        g.lv[0].list, conf, grad_x, C, g.P, g.nn, (double)p.lambda, g.counts,
                        w.sc, w.diag, w.minv, w.b);
-    BS_CHECK_LAUNCH("splat_grad");
     st = run_init(g, w, p, gb, s);
     if (st != BS_OK) return st;
-    st = run_pcg(g, w, p, gb, s);
+    st = run_pcg(g, w, p, gb, stats, s);
     if (st != BS_OK) return st;
     const int pblocks = grid_blocks(ceil_div(g.P, kBlock));
-    hipLaunchKernelGGL(grad_scatter, dim3(pblocks), dim3(kBlock), 0, s, g.lv[0].item_parent, gb,
+    BS_LAUNCH(s, K_GRAD_SCATTER, "grad_scatter", grad_scatter, dim3(pblocks), dim3(kBlock), 0, s, g.lv[0].item_parent, gb,
                        y_hat, target, conf, C, g.P, grad_t, grad_c);
-    BS_CHECK_LAUNCH("grad_scatter");
-    if (stats) {
-        hipLaunchKernelGGL(write_stats, dim3(1), dim3(64), 0, s, w.cs, C, stats);
-        BS_CHECK_LAUNCH("write_stats");
-    }
     return BS_OK;
 }

@@ -181,7 +181,8 @@ def test_backward_parity():
     G, ws, y, x, st, sol, prm = _solve_both(p)
     gx = WL.random_grad(3, p.C, p.H, p.W)
     gt, gc, gb, bst = G.backward(to_dev(p.target), to_dev(p.conf), y, to_dev(gx), prm.lam,
-                                 max_iters=prm.max_iters, rel_tol=prm.rel_tol, want_g=True)
+                                 max_iters=prm.max_iters, rel_tol=prm.rel_tol, want_g=True,
+                                 ws=ws)
     torch.cuda.synchronize()
     og = O.solve_backward(sol, p.target, p.conf, gx, prm, y_hat=y.cpu().numpy()[: sol.grid.V])
     V = sol.grid.V
