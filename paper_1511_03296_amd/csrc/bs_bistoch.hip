@@ -36,11 +36,29 @@ __global__ void __launch_bounds__(kRedBlock) bist_step(const int32_t* __restrict
                                                         int max_iters, double tol) {
 #pragma clang fp contract(off)
     if (counts[CNT_BIST_DONE]) return;
+    const int V = counts[CNT_V];
+    const XcdTiles tl((V + kRedBlock - 1) / kRedBlock);
+    // The previous launch's maxima, then the first tile's operands, are loaded
+    // before the stop decision: loads complete in issue order, so waiting for
+    // the maxima leaves the operand loads in flight during the reduction.
+    double prevmax = 0.0;
+    if (step >= 1 && threadIdx.x < kRedGrid)
+        prevmax = part[((step - 1) & 1) * kRedGrid + threadIdx.x];
+    int v = (int)(tl.first * kRedBlock) + threadIdx.x;
+    bool have = tl.first < tl.end && v < V;
+    double n = 0.0, nbv[10];
+    int mv = 1;
+    if (have) {
+        n = src[v];
+        mv = m[v];
+#pragma unroll
+        for (int j = 0; j < 10; ++j) {
+            const int u = nbr[j * vcap + v];
+            nbv[j] = (u >= 0) ? src[u] : 0.0;
+        }
+    }
     if (step >= 1) {
-        const double* prev = part + ((step - 1) & 1) * kRedGrid;
-        double r = 0.0;
-        for (int i = threadIdx.x; i < kRedGrid; i += kRedBlock) r = fmax(r, prev[i]);
-        const double R = block_max<kRedBlock>(r);
+        const double R = block_max<kRedBlock>(prevmax);
         if (bist_stop(R, step - 1, max_iters, tol)) {
             if (blockIdx.x == 0 && threadIdx.x == 0) {
                 counts[CNT_BIST_ITERS] = step - 1;
@@ -51,25 +69,31 @@ __global__ void __launch_bounds__(kRedBlock) bist_step(const int32_t* __restrict
             return;
         }
     }
-    const int V = counts[CNT_V];
     double lmax = 0.0;
-    const XcdTiles tl((V + kRedBlock - 1) / kRedBlock);
     for (int64_t tile = tl.first; tile < tl.end; tile += tl.step) {
-        const int v = (int)(tile * kRedBlock) + threadIdx.x;
-        if (v >= V) continue;
-        const double n = src[v];
+        if (tile != tl.first) {
+            v = (int)(tile * kRedBlock) + threadIdx.x;
+            have = v < V;
+            if (have) {
+                n = src[v];
+                mv = m[v];
+#pragma unroll
+                for (int j = 0; j < 10; ++j) {
+                    const int u = nbr[j * vcap + v];
+                    nbv[j] = (u >= 0) ? src[u] : 0.0;
+                }
+            }
+        }
+        if (!have) continue;
         double ns = 0.0;
 #pragma unroll
-        for (int j = 0; j < 10; ++j) {
-            const int u = nbr[j * vcap + v];
-            ns += (u >= 0) ? src[u] : 0.0;
-        }
+        for (int j = 0; j < 10; ++j) ns += nbv[j];
         const double bn = 10.0 * n + ns;
-        const double mv = (double)m[v];
+        const double md = (double)mv;
         const double prod = n * bn;
-        const double r = fabs(prod - mv) / mv;
+        const double r = fabs(prod - md) / md;
         lmax = fmax(lmax, r);
-        const double q = (n * mv) / bn;
+        const double q = (n * md) / bn;
         dst[v] = sqrt(q);
     }
     lmax = block_max<kRedBlock>(lmax);

@@ -226,44 +226,95 @@ __device__ inline int block_sum_int(int v) {
     return s;
 }
 
-// Pass 1: per cell, flag the first occurrence of each colour key among the
-// cell's items (in item order) and count the distinct keys.
+// Cells with at most CAP items are sorted in LDS: the items' packed
+// (colour key, item index) pairs are bitonic-sorted, so equal keys form runs in
+// ascending item order.  Larger cells (only possible at coarse pyramid levels
+// of unusual images) use a quadratic counting pass tiled through LDS; both
+// give identical results.
+// CAP is a power of two >= 64; the quadratic fallback tiles CAP items at a time
+// through the same LDS.
+template <int CAP>
+struct CellSmem {
+    uint64_t s[CAP];      // sorted (key << 32 | item) pairs
+    int32_t rank[CAP];    // local vertex of each sorted position
+    int32_t start[CAP];   // sorted position of each local vertex's first item
+};
+
+// Sorts the cell's (key, item) pairs ascending; returns the padded size.
 template <int B, class Src>
+__device__ inline int sort_cell(const Src& src, const typename Src::Ctx& t, int n,
+                                uint64_t* __restrict__ s) {
+    int N = 64;
+    while (N < n) N <<= 1;
+    for (int i = threadIdx.x; i < N; i += B)
+        s[i] = i < n ? (((uint64_t)src.key(t, i) << 32) | (uint32_t)i) : ~0ull;
+    __syncthreads();
+    for (int k = 2; k <= N; k <<= 1) {
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            for (int i = threadIdx.x; i < N; i += B) {
+                const int ixj = i ^ j;
+                if (ixj > i) {
+                    const uint64_t a = s[i], b = s[ixj];
+                    if ((a > b) == ((i & k) == 0)) {
+                        s[i] = b;
+                        s[ixj] = a;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+    return N;
+}
+
+__device__ inline bool run_head(const uint64_t* s, int i) {
+    return i == 0 || (s[i] >> 32) != (s[i - 1] >> 32);
+}
+
+// Pass 1: the number of distinct colour keys (future vertices) of each cell.
+template <int B, int CAP, class Src>
 __global__ void __launch_bounds__(B) level_count(Src src, int32_t* __restrict__ cell_cnt,
                                                   int32_t* __restrict__ cell_items,
                                                   uint32_t* __restrict__ ikey,
                                                   const int32_t* __restrict__ counts) {
     if (!src.active(counts)) return;
-    __shared__ uint32_t tile[kCellTile];
+    __shared__ CellSmem<CAP> sm;
     const int c = blockIdx.x;
     int cy, cx;
     const typename Src::Ctx t = src.ctx(c, cy, cx);
     const int n = t.n;
     int cnt = 0;
-    for (int base = 0; base < n; base += B) {
-        const int i = base + threadIdx.x;
-        const bool have = i < n;
-        const uint32_t ki = have ? src.key(t, i) : 0u;
-        bool first = have;
-        const int jend = min(base + B, n);
-        for (int t0 = 0; t0 < jend; t0 += kCellTile) {
-            const int tn = min(kCellTile, jend - t0);
-            __syncthreads();
-            for (int j = threadIdx.x; j < tn; j += B) tile[j] = src.key(t, t0 + j);
-            __syncthreads();
-            if (first) {
-                const int lim = min(tn, i - t0);
-                for (int j = 0; j < lim; ++j) {
-                    if (tile[j] == ki) {
-                        first = false;
-                        break;
+    if (n <= CAP) {
+        sort_cell<B>(src, t, n, sm.s);
+        for (int i = threadIdx.x; i < n; i += B) cnt += run_head(sm.s, i) ? 1 : 0;
+    } else {
+        // quadratic fallback: flag the first occurrence of each key in item order
+        uint32_t* tile = reinterpret_cast<uint32_t*>(sm.s);
+        for (int base = 0; base < n; base += B) {
+            const int i = base + threadIdx.x;
+            const bool have = i < n;
+            const uint32_t ki = have ? src.key(t, i) : 0u;
+            bool first = have;
+            const int jend = min(base + B, n);
+            for (int t0 = 0; t0 < jend; t0 += CAP) {
+                const int tn = min(CAP, jend - t0);
+                __syncthreads();
+                for (int j = threadIdx.x; j < tn; j += B) tile[j] = src.key(t, t0 + j);
+                __syncthreads();
+                if (first) {
+                    const int lim = min(tn, i - t0);
+                    for (int j = 0; j < lim; ++j) {
+                        if (tile[j] == ki) {
+                            first = false;
+                            break;
+                        }
                     }
                 }
             }
-        }
-        if (have) {
-            ikey[src.gid(t, i)] = ki | (first ? kFirst : 0u);
-            cnt += first ? 1 : 0;
+            if (have) {
+                ikey[src.gid(t, i)] = ki | (first ? kFirst : 0u);
+                cnt += first ? 1 : 0;
+            }
         }
     }
     cnt = block_sum_int<B>(cnt);
@@ -345,21 +396,82 @@ __global__ void __launch_bounds__(kScanBlock) level_scan(const int32_t* __restri
     }
 }
 
-// Pass 3: per cell, rank each item's key among the cell's distinct keys and
-// write vertex ids, keys, multiplicities, P(1) sums and the item CSR.
-template <int B, class Src>
+// Pass 3: per cell, the vertex of each item, the vertices' keys,
+// multiplicities and P(1) sums, and the item CSR (items of a vertex in
+// ascending item order).
+template <int B, int CAP, class Src>
 __global__ void __launch_bounds__(B) level_write(Src src, const uint32_t* __restrict__ ikey,
                                                   const int32_t* __restrict__ ones_prev,
                                                   const int32_t* __restrict__ counts, Level L) {
     if (!src.active(counts)) return;
-    __shared__ uint32_t tile[kCellTile];
-    __shared__ int32_t tones[kCellTile];
+    __shared__ CellSmem<CAP> sm;
+    __shared__ int wsum[B / 64];
     const int c = blockIdx.x;
     int cy, cx;
     const typename Src::Ctx t = src.ctx(c, cy, cx);
     const int n = t.n;
     const int vbase = L.cell_vbase[c], ibase = L.cell_ibase[c];
     const uint64_t cellkey = ((uint64_t)cy << 40) | ((uint64_t)cx << 24);
+    if (n <= CAP) {
+        const int N = sort_cell<B>(src, t, n, sm.s);
+        // local vertex of each sorted position: inclusive scan of run heads
+        const int per = (N + B - 1) / B;
+        const int i0 = threadIdx.x * per;
+        int local = 0;
+        for (int q = 0; q < per; ++q) {
+            const int i = i0 + q;
+            if (i < n && run_head(sm.s, i)) ++local;
+        }
+        const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+        int incl = local;
+        for (int o = 1; o < 64; o <<= 1) {
+            const int y = __shfl_up(incl, o, 64);
+            if (lane >= o) incl += y;
+        }
+        if (lane == 63) wsum[wave] = incl;
+        __syncthreads();
+        int before = incl - local;
+        for (int w = 0; w < wave; ++w) before += wsum[w];
+        const int cnt = [&] {
+            int tot = 0;
+            for (int w = 0; w < B / 64; ++w) tot += wsum[w];
+            return tot;
+        }();
+        int r = before - 1;
+        for (int q = 0; q < per; ++q) {
+            const int i = i0 + q;
+            if (i >= n) break;
+            if (run_head(sm.s, i)) {
+                ++r;
+                sm.start[r] = i;
+            }
+            sm.rank[i] = r;
+        }
+        __syncthreads();
+        for (int i = threadIdx.x; i < n; i += B) {
+            const int r2 = sm.rank[i];
+            const int gi = src.gid(t, (int)(sm.s[i] & 0xffffffffu));
+            const int v = vbase + r2;
+            L.item_parent[gi] = v;
+            L.list[ibase + i] = gi;
+            if (sm.start[r2] == i) {
+                const int end = (r2 + 1 < cnt) ? sm.start[r2 + 1] : n;
+                L.key[v] = cellkey | (sm.s[i] >> 32);
+                L.ptr[v] = ibase + i;
+                L.mult[v] = end - i;
+                if (L.ones) {
+                    int sum = 0;
+                    for (int q = i; q < end; ++q)
+                        sum += ones_prev ? ones_prev[src.gid(t, (int)(sm.s[q] & 0xffffffffu))] : 1;
+                    L.ones[v] = sum;
+                }
+            }
+        }
+        return;
+    }
+    // quadratic fallback, using the first-occurrence flags of pass 1
+    uint32_t* tile = reinterpret_cast<uint32_t*>(sm.s);
+    int32_t* tones = reinterpret_cast<int32_t*>(sm.s) + CAP;
     for (int base = 0; base < n; base += B) {
         const int i = base + threadIdx.x;
         const bool have = i < n;
@@ -367,8 +479,8 @@ __global__ void __launch_bounds__(B) level_write(Src src, const uint32_t* __rest
         const uint32_t wi = have ? ikey[gi] : 0u;
         const uint32_t ki = wi & kKeyMask;
         int rank = 0, less = 0, mult = 0, eqb = 0, onesum = 0;
-        for (int t0 = 0; t0 < n; t0 += kCellTile) {
-            const int tn = min(kCellTile, n - t0);
+        for (int t0 = 0; t0 < n; t0 += CAP) {
+            const int tn = min(CAP, n - t0);
             __syncthreads();
             for (int j = threadIdx.x; j < tn; j += B) {
                 const int gj = src.gid(t, t0 + j);
@@ -488,16 +600,16 @@ static bs_status validate_grid_args(int32_t H, int32_t W, const bs_grid_params* 
     return BS_OK;
 }
 
-template <int B, class Src>
+template <int B, int CAP, class Src>
 static bs_status launch_level(const Src& src, GridImpl& g, int k, hipStream_t st) {
     Level& L = g.lv[k];
     const int ncells = L.ncy * L.ncx;
-    BS_LAUNCH(st, K_LEVEL_COUNT, "level_count", (level_count<B, Src>), dim3(ncells), dim3(B), 0, st, src, g.cell_cnt,
+    BS_LAUNCH(st, K_LEVEL_COUNT, "level_count", (level_count<B, CAP, Src>), dim3(ncells), dim3(B), 0, st, src, g.cell_cnt,
                        g.cell_items, g.ikey, g.counts);
     BS_LAUNCH(st, K_LEVEL_SCAN, "level_scan", level_scan, dim3(1), dim3(kScanBlock), 0, st, g.cell_cnt, g.cell_items,
                        ncells, L.cell_vbase, L.cell_ibase, L.ptr, g.counts, k);
     const int32_t* ones_prev = (k >= 2) ? g.lv[k - 1].ones : nullptr;
-    BS_LAUNCH(st, K_LEVEL_WRITE, "level_write", (level_write<B, Src>), dim3(ncells), dim3(B), 0, st, src, g.ikey,
+    BS_LAUNCH(st, K_LEVEL_WRITE, "level_write", (level_write<B, CAP, Src>), dim3(ncells), dim3(B), 0, st, src, g.ikey,
                        ones_prev, g.counts, L);
     return BS_OK;
 }
@@ -531,15 +643,16 @@ extern "C" bs_status bs_build_grid(const float* ref, int32_t H, int32_t W,
     PixelSource ps{ref, H, W, g.P, params->sigma_xy, params->sigma_l, params->sigma_uv,
                    g.lv[0].ncx};
     const int items = params->sigma_xy * params->sigma_xy;
-    if (items <= 64) st = launch_level<64>(ps, g, 0, s);
-    else if (items <= 128) st = launch_level<128>(ps, g, 0, s);
-    else st = launch_level<256>(ps, g, 0, s);
+    if (items <= 64) st = launch_level<64, 64>(ps, g, 0, s);
+    else if (items <= 256) st = launch_level<256, 256>(ps, g, 0, s);
+    else if (items <= 1024) st = launch_level<256, 1024>(ps, g, 0, s);
+    else st = launch_level<256, 2048>(ps, g, 0, s);
     if (st != BS_OK) return st;
 
     for (int k = 1; k < g.levels; ++k) {
         const Level& C = g.lv[k - 1];
         VertexSource vs{C.key, C.cell_vbase, g.counts, C.ncx, C.ncy, g.lv[k].ncx, k};
-        st = launch_level<128>(vs, g, k, s);
+        st = launch_level<128, 1024>(vs, g, k, s);
         if (st != BS_OK) return st;
     }
     const int blocks = grid_blocks(ceil_div(g.vcap, kBlock));

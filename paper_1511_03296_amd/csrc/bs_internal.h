@@ -40,7 +40,7 @@ bs_status check_hip(hipError_t e, const char* what);
 // ---------------------------------------------------------------------------
 enum KernelId : int {
     K_LEVEL_COUNT, K_LEVEL_SCAN, K_LEVEL_WRITE, K_NEIGHBOURS, K_BIST_STEP, K_BIST_OTHER,
-    K_SPLAT, K_INIT, K_PCG_START, K_PCG_DIR_MATVEC, K_PCG_UPDATE, K_SLICE, K_GRAD_SCATTER,
+    K_SPLAT, K_INIT, K_PCG_START, K_PCG_ITER, K_SLICE, K_GRAD_SCATTER,
     K_COUNT
 };
 void timing_begin(hipStream_t s, int id);
@@ -63,13 +63,14 @@ constexpr int kBlock = 256;          // threads per block of streaming kernels
 constexpr int kXcds = 8;             // MI355X: 8 accelerator dies, one L2 each
 constexpr int kMaxGrid = 2048;       // blocks of a grid-stride launch
 // Reducing kernels (bistochastization, PCG) run a fixed grid of kRedGrid
-// blocks of kRedBlock threads, one block per compute unit.  Each writes one
+// blocks of kRedBlock threads, one block per compute unit: small blocks
+// spread even small grids over every compute unit, whose address units bound
+// the neighbour gathers.  Each writes one
 // partial per block; the next kernel reduces them in its prologue (the kernel
 // boundary is the only grid-wide synchronisation).
-constexpr int kRedBlock = 1024;
+constexpr int kRedBlock = 256;
 constexpr int kRedGrid = 256;
-constexpr int kCellTile = 2048;      // LDS tile of item keys in the level builders
-constexpr int kCellBlock = 128;      // threads per cell block of the level builders
+static_assert(kRedGrid <= kRedBlock && kRedGrid % 64 == 0, "one partial per thread");
 
 // Slots of the device counter array.
 enum Counter : int {

@@ -7,14 +7,20 @@
 // all C channels, so the neighbour table is read once per vertex and the
 // channel gathers of one neighbour are contiguous.
 //
-// PCG runs one independent PCG per channel.  One iteration is two kernels:
-//   dir_matvec:  d = M^-1 r + beta d  (fused; the neighbours' new d values are
-//                recomputed from r and the previous d, so no separate
-//                direction pass is needed),  q = A d,  partial d^T q;
-//   update:      y += alpha d,  r -= alpha q,  partial r^T M^-1 r and r^T r.
-// Dot products accumulate in float64; each kernel's last block reduces the
-// per-block partials in a fixed order and updates the per-channel scalars,
-// so results are deterministic and no host synchronisation is needed.
+// PCG runs one independent PCG per channel, in the single-reduction
+// arrangement of Chronopoulos and Gear: with u = M^-1 r, w = A u, s = A p it
+// carries s and w by recurrence, so both inner products of an iteration,
+// gamma = r^T u and delta = w^T u, come from one pass:
+//   p = u + beta p,  s = w + beta s,  y += alpha p,  r -= alpha s,
+//   u = M^-1 r,  w = A u,  gamma = r^T u,  delta = w^T u,
+//   beta' = gamma' / gamma,  alpha' = gamma' / (delta' - beta' gamma' / alpha).
+// In exact arithmetic its iterates are those of the preconditioned CG the
+// paper uses (supplement Algorithm 2); one kernel per iteration computes the
+// neighbours' new u values from the gathered old r, w and s, so every
+// iteration is one launch and one grid-wide reduction.  Dot products
+// accumulate in float64; the next kernel reduces the per-block partials in its
+// prologue in a fixed order, so results are deterministic and no host
+// synchronisation is needed.
 #include "bs_internal.h"
 
 namespace bs {
@@ -26,21 +32,20 @@ struct ChanState {
 
 enum Ctl : int { CTL_ACTIVE = 0, CTL_SIZE = 8 };
 
-// Partials of the reducing kernels: [2 slots][3 values][C][kRedGrid].
-//   slot 0 -- written by pcg_start (r^T r, b^T b, r^T M^-1 r) and by
-//             pcg_update (r^T r, 0, r^T M^-1 r);
-//   slot 1 -- written by pcg_dir_matvec (d^T q).
-// Per-channel state, double-buffered the same way: pcg_dir_matvec reads
-// state 0 and writes state 1, pcg_update reads state 1 and writes state 0.
+// Partials of the reducing kernels: [2 slots][3 values][C][kRedGrid], values
+// (r^T r, gamma = r^T u, delta = w^T u); pcg_init_r writes b^T b as value 0.
+// Launch j reads slot j % 2 and writes the other; the per-channel state is
+// double-buffered the same way (block 0 writes the new state).
 struct SolveWs {
     int C, vpb;
     float* sc;
     float* diag;
     float* minv;
     float* b;
-    float* r;
-    float* d[2];
-    float* q;
+    float* r[2];
+    float* w[2];
+    float* sv[2];
+    float* p;
     float* g;
     float* up[BS_MAX_LEVELS];
     ChanState* cs[2];
@@ -58,10 +63,12 @@ static size_t layout_solve(const GridImpl& g, int C, void* base, SolveWs& w) {
     w.diag = c.take<float>(g.vcap);
     w.minv = c.take<float>(g.vcap);
     w.b = c.take<float>(n);
-    w.r = c.take<float>(n);
-    w.d[0] = c.take<float>(n);
-    w.d[1] = c.take<float>(n);
-    w.q = c.take<float>(n);
+    for (int i = 0; i < 2; ++i) {
+        w.r[i] = c.take<float>(n);
+        w.w[i] = c.take<float>(n);
+        w.sv[i] = c.take<float>(n);
+    }
+    w.p = c.take<float>(n);
     w.g = c.take<float>(n);
     w.up[0] = nullptr;
     for (int k = 1; k < BS_MAX_LEVELS; ++k)
@@ -86,10 +93,21 @@ __device__ inline void block_channel_partials(const double (&acc)[NV], int C, in
                                               double* __restrict__ part) {
     const int t = threadIdx.x;
     if (C == 1) {
+        // one channel: shuffle trees per wave, then one pass over the waves
+        __shared__ double red[NV][kRedBlock / 64];
+        double v[NV];
 #pragma unroll
-        for (int k = 0; k < NV; ++k) {
-            const double v = block_sum<kRedBlock>(acc[k]);
-            if (t == 0) part[(int64_t)k * kRedGrid + blockIdx.x] = v;
+        for (int k = 0; k < NV; ++k) v[k] = wave_sum(acc[k]);
+        __syncthreads();
+        if ((t & 63) == 0) {
+#pragma unroll
+            for (int k = 0; k < NV; ++k) red[k][t >> 6] = v[k];
+        }
+        __syncthreads();
+        if (t < NV) {
+            double s = 0.0;
+            for (int w = 0; w < kRedBlock / 64; ++w) s += red[t][w];
+            part[(int64_t)t * kRedGrid + blockIdx.x] = s;
         }
         return;
     }
@@ -114,60 +132,115 @@ __device__ inline void block_channel_partials(const double (&acc)[NV], int C, in
 }
 
 // out[k C + ch] = sum over the kRedGrid blocks of the producer's partials,
-// computed identically by every block: one wave per (k, ch) pair, lanes
-// striding over blocks, then a shuffle tree.
-template <int NV>
-__device__ inline void reduce_partials(const double* __restrict__ part, int C, double* out) {
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    for (int pair = wave; pair < NV * C; pair += kRedBlock / 64) {
-        double s = 0.0;
-        for (int b = lane; b < kRedGrid; b += 64) s += part[(int64_t)pair * kRedGrid + b];
-        s = wave_sum(s);
-        if (lane == 0) out[pair] = s;
-    }
-    __syncthreads();
-}
+// computed identically by every block.  The NV C sums are spread over the
+// block: q lanes (a power of two <= 64, so a group lies in one wave) share a
+// sum, each adding every q-th partial, then a shuffle tree over the group.
+// Loading (load) and summing (sum) are split so that callers can issue other
+// loads in between; loads complete in issue order, so waiting for these does
+// not wait for loads issued after them.
+struct PartialSums {
+    static constexpr int kMax = 8;   // partials per thread held in registers
+    double v[kMax];
+    int pairs, q, pair, seg;
+    bool held;
 
-// Completes the previous PCG step for every channel from the slot-0 partials:
-// the initial residual (phase 0) or the end of an iteration (stopping rule).
-__device__ inline void advance_state(ChanState& st, double rr, double bb, double rho_new,
-                                     int max_iters, double tol) {
-    if (st.phase == 0) {
-        st.phase = 1;
-        st.bnorm = sqrt(bb);
-        st.rho = rho_new;
-        st.beta = 0.0;
-        st.iters = 0;
-        st.active = 0;
-        if (bb == 0.0) {
-            st.reason = 5;
-            st.res = 0.0;
+    __device__ void load(const double* __restrict__ part, int nv_c) {
+        pairs = nv_c;
+        q = 64;
+        while (q > 1 && q * pairs > kRedBlock) q >>= 1;
+        pair = threadIdx.x / q;
+        seg = threadIdx.x - pair * q;
+        held = pairs * q <= kRedBlock && kRedGrid / q <= kMax;
+        if (held && pair < pairs) {
+#pragma unroll
+            for (int i = 0; i < kMax; ++i)
+                if (i < kRedGrid / q) v[i] = part[(int64_t)pair * kRedGrid + seg + q * i];
+        }
+    }
+
+    __device__ void sum(const double* __restrict__ part, double* out) {
+        if (held) {
+            double s = 0.0;
+#pragma unroll
+            for (int i = 0; i < kMax; ++i)
+                if (i < kRedGrid / q && pair < pairs) s += v[i];
+            for (int o = q >> 1; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+            if (seg == 0 && pair < pairs) out[pair] = s;
         } else {
-            st.res = sqrt(rr) / st.bnorm;
-            if (st.res <= tol) st.reason = 1;
-            else if (max_iters <= 0) st.reason = 2;
-            else if (rho_new == 0.0) st.reason = 3;
-            else {
-                st.active = 1;
-                st.reason = 0;
+            for (int base = 0; base < pairs; base += kRedBlock / q) {
+                const int pr = base + pair;
+                double s = 0.0;
+                if (pr < pairs)
+                    for (int b = seg; b < kRedGrid; b += q) s += part[(int64_t)pr * kRedGrid + b];
+                for (int o = q >> 1; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+                if (seg == 0 && pr < pairs) out[pr] = s;
             }
         }
-        return;
+        __syncthreads();
     }
-    if (!st.active) return;
-    st.beta = rho_new / st.rho;
-    st.rho = rho_new;
-    st.iters += 1;
-    st.res = sqrt(rr) / st.bnorm;
-    int reason = 0;
-    if (st.res <= tol) reason = 1;
-    else if (st.iters >= max_iters) reason = 2;
-    else if (rho_new == 0.0) reason = 3;
-    if (reason) {
-        st.active = 0;
-        st.reason = reason;
-    }
+};
+
+template <int NV>
+__device__ inline void reduce_partials(const double* __restrict__ part, int C, double* out) {
+    PartialSums ps;
+    ps.load(part, NV * C);
+    ps.sum(part, out);
 }
+
+// Completes the previous PCG step of one channel from the reduced partials
+// r^T r, gamma and delta: the start (phase 0) or the end of an iteration,
+// with the stopping rule, then the next alpha and beta.
+__device__ inline void advance_state(ChanState& st, double rr, double gam, double del,
+                                     int max_iters, double tol) {
+    int reason = 0;
+    if (st.phase == 0) {
+        st.phase = 1;
+        st.iters = 0;
+        st.active = 0;
+        if (st.bnorm == 0.0) {
+            st.reason = 5;
+            st.res = 0.0;
+            return;
+        }
+        st.res = sqrt(rr) / st.bnorm;
+        if (st.res <= tol) reason = 1;
+        else if (max_iters <= 0) reason = 2;
+        else if (gam == 0.0) reason = 3;
+        else if (!(del > 0.0)) reason = 4;
+        else {
+            st.beta = 0.0;
+            st.alpha = gam / del;
+            st.rho = gam;
+        }
+    } else {
+        if (!st.active) return;
+        st.iters += 1;
+        st.res = sqrt(rr) / st.bnorm;
+        if (st.res <= tol) reason = 1;
+        else if (st.iters >= max_iters) reason = 2;
+        else if (gam == 0.0) reason = 3;
+        else {
+            const double beta = gam / st.rho;
+            const double den = del - beta * gam / st.alpha;   // = p^T A p
+            if (!(den > 0.0)) reason = 4;
+            else {
+                st.beta = beta;
+                st.alpha = gam / den;
+                st.rho = gam;
+            }
+        }
+    }
+    st.active = reason == 0;
+    if (reason) st.reason = reason;
+}
+
+// Recurrences shared by a vertex and its neighbours, written with explicit
+// fused multiply-adds so both evaluate them identically:
+//   s = w + beta s_old,  r' = r - alpha s,  u' = M^-1 r'.
+__device__ inline float cg_s(float w, float s_old, float beta, bool first) {
+    return first ? w : fmaf(beta, s_old, w);
+}
+__device__ inline float cg_r(float r, float s, float alpha) { return fmaf(-alpha, s, r); }
 
 // ---------------------------------------------------------------------------
 // Kernels.
@@ -221,6 +294,94 @@ __global__ void __launch_bounds__(kBlock) splat_kernel(
         diag_out[v] = (float)d;
         minv_out[v] = d > 0.0 ? (float)(1.0 / d) : 0.0f;
     }
+}
+
+// The same sums computed per spatial cell of the grid: every pixel of a cell
+// lies on one of the cell's vertices, so a block stages the cell's pixels in
+// LDS with coalesced row loads and each (vertex, channel) thread sums its own
+// pixels, in ascending pixel order, from LDS.  CAP bounds the cell's pixels.
+constexpr int kSplatVals = 4096;   // floats of staged values per channel chunk
+
+template <int B, int CAP, bool WEIGHTED>
+__global__ void __launch_bounds__(B) splat_cells(
+    int H, int W, int sxy, int ncx, const int32_t* __restrict__ cell_vbase,
+    const int32_t* __restrict__ cell_ibase, const int32_t* __restrict__ ptr,
+    const int32_t* __restrict__ list, const float* __restrict__ conf,
+    const float* __restrict__ vals, int C, int P, const double* __restrict__ nn, double lam,
+    float* __restrict__ sc_out, float* __restrict__ diag_out, float* __restrict__ minv_out,
+    float* __restrict__ b) {
+    __shared__ float cv[CAP];
+    __shared__ int32_t lst[CAP];
+    __shared__ float tv[kSplatVals];
+    const int c = blockIdx.x;
+    const int cy = c / ncx, cx = c - cy * ncx;
+    const int y0 = cell_lo(cy, sxy), y1 = min(cell_lo(cy + 1, sxy), H);
+    const int x0 = cell_lo(cx, sxy), x1 = min(cell_lo(cx + 1, sxy), W);
+    const int wx = x1 - x0, n = (y1 - y0) * wx;
+    const int vbase = cell_vbase[c], cnt = cell_vbase[c + 1] - vbase, ibase = cell_ibase[c];
+    for (int j = threadIdx.x; j < n; j += B) {
+        const int r = j / wx;
+        cv[j] = conf[(y0 + r) * W + x0 + (j - r * wx)];
+        const int pq = list[ibase + j];
+        const int py = pq / W;
+        lst[j] = (py - y0) * wx + (pq - py * W - x0);
+    }
+    __syncthreads();
+    for (int k = threadIdx.x; k < cnt; k += B) {
+        const int s0 = ptr[vbase + k] - ibase, s1 = ptr[vbase + k + 1] - ibase;
+        double sc = 0.0;
+        for (int q = s0; q < s1; ++q) sc += (double)cv[lst[q]];
+        const double d = lam * nn[vbase + k] + sc;
+        sc_out[vbase + k] = (float)sc;
+        diag_out[vbase + k] = (float)d;
+        minv_out[vbase + k] = d > 0.0 ? (float)(1.0 / d) : 0.0f;
+    }
+    const int CH = max(1, min(C, kSplatVals / max(n, 1)));
+    for (int c0 = 0; c0 < C; c0 += CH) {
+        const int cn = min(CH, C - c0);
+        __syncthreads();
+        for (int e = threadIdx.x; e < cn * n; e += B) {
+            const int cc = e / n, j = e - cc * n;
+            const int r = j / wx;
+            tv[cc * n + j] = vals[(int64_t)(c0 + cc) * P + (y0 + r) * W + x0 + (j - r * wx)];
+        }
+        __syncthreads();
+        for (int e = threadIdx.x; e < cnt * cn; e += B) {
+            const int k = e / cn, cc = e - k * cn;
+            const int s0 = ptr[vbase + k] - ibase, s1 = ptr[vbase + k + 1] - ibase;
+            double acc = 0.0;
+            for (int q = s0; q < s1; ++q) {
+                const int jl = lst[q];
+                acc += WEIGHTED ? (double)cv[jl] * (double)tv[cc * n + jl] : (double)tv[cc * n + jl];
+            }
+            b[(int64_t)(vbase + k) * C + c0 + cc] = (float)acc;
+        }
+    }
+}
+
+// Launches the splat: per cell when a cell's pixels fit the LDS staging,
+// otherwise per vertex.
+template <bool WEIGHTED>
+static bs_status launch_splat(const GridImpl& g, const float* conf, const float* vals, int C,
+                              double lam, float* sc, float* diag, float* minv, float* b,
+                              hipStream_t s) {
+    const Level& L = g.lv[0];
+    const int items = g.sg.sigma_xy * g.sg.sigma_xy;
+    const int ncells = L.ncx * L.ncy;
+#define BS_SPLAT_CELLS(B, CAP)                                                                  \
+    BS_LAUNCH(s, K_SPLAT, "splat_cells", (splat_cells<B, CAP, WEIGHTED>), dim3(ncells), dim3(B), \
+              0, s, g.H, g.W, g.sg.sigma_xy, L.ncx, L.cell_vbase, L.cell_ibase, L.ptr, L.list,   \
+              conf, vals, C, g.P, g.nn, lam, sc, diag, minv, b)
+    if (items <= 64) BS_SPLAT_CELLS(64, 64);
+    else if (items <= 256) BS_SPLAT_CELLS(256, 256);
+    else if (items <= 1024) BS_SPLAT_CELLS(256, 1024);
+    else {
+        const int vblocks = grid_blocks(ceil_div(g.vcap, kBlock));
+        BS_LAUNCH(s, K_SPLAT, "splat", splat_kernel<WEIGHTED>, dim3(vblocks), dim3(kBlock), 0, s,
+                  L.ptr, L.list, conf, vals, C, g.P, g.nn, lam, g.counts, sc, diag, minv, b);
+    }
+#undef BS_SPLAT_CELLS
+    return BS_OK;
 }
 
 // Flat init: y = b / S c, 0 where S c = 0.
@@ -315,18 +476,18 @@ __global__ void __launch_bounds__(kBlock) hier_final(const float* __restrict__ b
     }
 }
 
-// r = b - A y0 for one (vertex, channel) element per thread, with
-// A z = diag(A) z_v - lam n_v sum_j n_j z_j; partials r^T r, b^T b, r^T M^-1 r.
-__global__ void __launch_bounds__(kRedBlock) pcg_start(
+// r0 = b - A y0, one (vertex, channel) element per thread, with
+// A z = diag(A) z_v - lam n_v sum_j n_j z_j; partials b^T b.
+__global__ void __launch_bounds__(kRedBlock) pcg_init_r(
     const int32_t* __restrict__ nbr, int64_t vcap, const float* __restrict__ nf,
-    const float* __restrict__ diag, const float* __restrict__ minv, const float* __restrict__ b,
-    const float* __restrict__ y, float* __restrict__ r, float lam, int C, int vpb,
-    const int32_t* __restrict__ counts, double* __restrict__ part) {
+    const float* __restrict__ diag, const float* __restrict__ b, const float* __restrict__ y,
+    float* __restrict__ r, float lam, int C, int vpb, const int32_t* __restrict__ counts,
+    double* __restrict__ part) {
     const int V = counts[CNT_V];
     const int t = threadIdx.x;
     const int vl = t / C, ch = t - vl * C;
     const bool lane_ok = vl < vpb;
-    double acc[3] = {0.0, 0.0, 0.0};
+    double acc[1] = {0.0};
     const XcdTiles tl((V + vpb - 1) / vpb);
     for (int64_t tile = tl.first; tile < tl.end; tile += tl.step) {
         const int v = (int)(tile * vpb) + vl;
@@ -340,134 +501,185 @@ __global__ void __launch_bounds__(kRedBlock) pcg_start(
         const int64_t e = (int64_t)v * C + ch;
         const float ay = diag[v] * y[e] - lam * nf[v] * ns;
         const float bv = b[e];
-        const float rv = bv - ay;
-        r[e] = rv;
-        acc[0] += (double)rv * (double)rv;
-        acc[1] += (double)bv * (double)bv;
-        acc[2] += (double)rv * (double)(minv[v] * rv);
+        r[e] = bv - ay;
+        acc[0] += (double)bv * (double)bv;
     }
-    block_channel_partials<3>(acc, C, vpb, part);
+    block_channel_partials<1>(acc, C, vpb, part);
 }
 
-// Prologue: finish the previous step from the slot-0 partials (stopping rule,
-// beta).  Then  d = M^-1 r + beta d_old  (beta = 0 on the first iteration),
-// q = A d  and partials of d^T q.
-__global__ void __launch_bounds__(kRedBlock) pcg_dir_matvec(
+// Prologue: ||b|| into the initial state.  Then u0 = M^-1 r0 (gathered),
+// w0 = A u0, partials r^T r, r^T u, w^T u.
+__global__ void __launch_bounds__(kRedBlock) pcg_init_w(
     const int32_t* __restrict__ nbr, int64_t vcap, const float* __restrict__ nf,
     const float* __restrict__ diag, const float* __restrict__ minv, const float* __restrict__ r,
-    const float* __restrict__ dold, float* __restrict__ dnew, float* __restrict__ q, float lam,
-    int C, int vpb, const int32_t* __restrict__ counts, const ChanState* __restrict__ cs_in,
+    float* __restrict__ w, float lam, int C, int vpb, const int32_t* __restrict__ counts,
+    const double* __restrict__ part_in, double* __restrict__ part_out,
+    ChanState* __restrict__ cs_out) {
+    __shared__ double fin[BS_MAX_CHANNELS];
+    const int t = threadIdx.x;
+    reduce_partials<1>(part_in, C, fin);
+    if (blockIdx.x == 0 && t < C) {
+        ChanState z;
+        z.rho = z.alpha = z.beta = z.res = 0.0;
+        z.bnorm = sqrt(fin[t]);
+        z.active = z.iters = z.reason = z.phase = 0;
+        cs_out[t] = z;
+    }
+    const int V = counts[CNT_V];
+    const int vl = t / C, ch = t - vl * C;
+    const bool lane_ok = vl < vpb;
+    double acc[3] = {0.0, 0.0, 0.0};
+    const XcdTiles tl((V + vpb - 1) / vpb);
+    for (int64_t tile = tl.first; tile < tl.end; tile += tl.step) {
+        const int v = (int)(tile * vpb) + vl;
+        if (!lane_ok || v >= V) continue;
+        float ns = 0.0f;
+#pragma unroll
+        for (int j = 0; j < 10; ++j) {
+            const int u = nbr[j * vcap + v];
+            if (u >= 0) ns += nf[u] * (minv[u] * r[(int64_t)u * C + ch]);
+        }
+        const int64_t e = (int64_t)v * C + ch;
+        const float rv = r[e];
+        const float uv = minv[v] * rv;
+        const float wv = diag[v] * uv - lam * nf[v] * ns;
+        w[e] = wv;
+        acc[0] += (double)rv * (double)rv;
+        acc[1] += (double)rv * (double)uv;
+        acc[2] += (double)wv * (double)uv;
+    }
+    block_channel_partials<3>(acc, C, vpb, part_out);
+}
+
+// Operands of one (vertex, channel) element of a PCG iteration.  Loading
+// them does not depend on the iteration's scalars, so the first tile's loads
+// are issued before the prologue and overlap its reduction.
+struct IterOperands {
+    int v;
+    int nb[10];
+    float r[10], w[10], s[10], mi[10], nf[10];
+    float rv, wv, sv, pv, yv, miv, dv, nfv;
+};
+
+__device__ inline bool load_iter(IterOperands& o, int64_t tile, int vpb, int vl, int ch, int C,
+                                 int V, int64_t vcap, const int32_t* __restrict__ nbr,
+                                 const float* __restrict__ nf, const float* __restrict__ diag,
+                                 const float* __restrict__ minv, const float* __restrict__ rin,
+                                 const float* __restrict__ win, const float* __restrict__ sold,
+                                 const float* __restrict__ p, const float* __restrict__ y) {
+    o.v = (int)(tile * vpb) + vl;
+    if (o.v >= V) return false;
+#pragma unroll
+    for (int j = 0; j < 10; ++j) o.nb[j] = nbr[j * vcap + o.v];
+#pragma unroll
+    for (int j = 0; j < 10; ++j) {
+        const int u = o.nb[j] >= 0 ? o.nb[j] : o.v;
+        const int64_t eu = (int64_t)u * C + ch;
+        o.r[j] = rin[eu];
+        o.w[j] = win[eu];
+        o.s[j] = sold[eu];
+        o.mi[j] = minv[u];
+        o.nf[j] = nf[u];
+    }
+    const int64_t e = (int64_t)o.v * C + ch;
+    o.rv = rin[e];
+    o.wv = win[e];
+    o.sv = sold[e];
+    o.pv = p[e];
+    o.yv = y[e];
+    o.miv = minv[o.v];
+    o.dv = diag[o.v];
+    o.nfv = nf[o.v];
+    return true;
+}
+
+// One PCG iteration.  Prologue: finish the previous step (stopping rule,
+// alpha, beta) from the reduced partials.  Then, per element,
+//   p = u + beta p,  s = w + beta s,  y += alpha p,  r' = r - alpha s,
+//   u' = M^-1 r',  w' = A u'  (the neighbours' u' recomputed from their
+//   gathered r, w and s),  partials r'^T r', r'^T u', w'^T u'.
+__global__ void __launch_bounds__(kRedBlock) pcg_iter(
+    const int32_t* __restrict__ nbr, int64_t vcap, const float* __restrict__ nf,
+    const float* __restrict__ diag, const float* __restrict__ minv,
+    const float* __restrict__ rin, float* __restrict__ rout, const float* __restrict__ win,
+    float* __restrict__ wout, const float* __restrict__ sold, float* __restrict__ snew,
+    float* __restrict__ p, float* __restrict__ y, float lam, int C, int vpb,
+    const int32_t* __restrict__ counts, const ChanState* __restrict__ cs_in,
     ChanState* __restrict__ cs_out, const double* __restrict__ part_in,
     double* __restrict__ part_out, int32_t* __restrict__ ctl, int max_iters, double tol) {
     __shared__ ChanState S[BS_MAX_CHANNELS];
     __shared__ double fin[3 * BS_MAX_CHANNELS];
     __shared__ int n_active;
     const int t = threadIdx.x;
-    reduce_partials<3>(part_in, C, fin);
+    const int V = counts[CNT_V];
+    const int vl = t / C, ch = t - vl * C;
+    const bool lane_ok = vl < vpb;
+    const XcdTiles tl((V + vpb - 1) / vpb);
+    // Loads complete in issue order, so the partials and the state are loaded
+    // before the first tile's operands: waiting for them does not wait for
+    // the gathers, which stay in flight during the reduction.
+    PartialSums ps;
+    ps.load(part_in, 3 * C);
+    ChanState st0;
+    if (t < C) st0 = cs_in[t];
+    IterOperands o;
+    bool have = lane_ok && tl.first < tl.end &&
+                load_iter(o, tl.first, vpb, vl, ch, C, V, vcap, nbr, nf, diag, minv, rin, win,
+                          sold, p, y);
+    ps.sum(part_in, fin);
     if (t == 0) n_active = 0;
     __syncthreads();
     if (t < C) {
-        ChanState st = cs_in[t];
-        advance_state(st, fin[t], fin[C + t], fin[2 * C + t], max_iters, tol);
-        S[t] = st;
-        if (st.active) atomicAdd(&n_active, 1);
-        if (blockIdx.x == 0) cs_out[t] = st;
+        advance_state(st0, fin[t], fin[C + t], fin[2 * C + t], max_iters, tol);
+        S[t] = st0;
+        if (st0.active) atomicAdd(&n_active, 1);
+        if (blockIdx.x == 0) cs_out[t] = st0;
     }
     __syncthreads();
     if (blockIdx.x == 0 && t == 0) ctl[CTL_ACTIVE] = n_active;
     if (n_active == 0) return;
-    const int V = counts[CNT_V];
-    const int vl = t / C, ch = t - vl * C;
-    const bool lane_ok = vl < vpb;
     const ChanState st = S[lane_ok ? ch : 0];
     const bool act = lane_ok && st.active;
     const bool first = st.iters == 0;
-    const float beta = (float)st.beta;
-    double acc[1] = {0.0};
-    const XcdTiles tl((V + vpb - 1) / vpb);
+    const float alpha = (float)st.alpha, beta = (float)st.beta;
+    double acc[3] = {0.0, 0.0, 0.0};
     for (int64_t tile = tl.first; tile < tl.end; tile += tl.step) {
-        const int v = (int)(tile * vpb) + vl;
-        if (!act || v >= V) continue;
+        if (tile != tl.first)
+            have = lane_ok && load_iter(o, tile, vpb, vl, ch, C, V, vcap, nbr, nf, diag, minv,
+                                        rin, win, sold, p, y);
+        if (!act || !have) continue;
         float ns = 0.0f;
 #pragma unroll
         for (int j = 0; j < 10; ++j) {
-            const int u = nbr[j * vcap + v];
-            if (u >= 0) {
-                const int64_t eu = (int64_t)u * C + ch;
-                float du = minv[u] * r[eu];
-                if (!first) du += beta * dold[eu];
-                ns += nf[u] * du;
+            if (o.nb[j] >= 0) {
+                const float su = cg_s(o.w[j], first ? 0.0f : o.s[j], beta, first);
+                const float ru = cg_r(o.r[j], su, alpha);
+                ns += o.nf[j] * (o.mi[j] * ru);
             }
         }
-        const int64_t e = (int64_t)v * C + ch;
-        float dv = minv[v] * r[e];
-        if (!first) dv += beta * dold[e];
-        const float qv = diag[v] * dv - lam * nf[v] * ns;
-        dnew[e] = dv;
-        q[e] = qv;
-        acc[0] += (double)dv * (double)qv;
-    }
-    block_channel_partials<1>(acc, C, vpb, part_out);
-}
-
-// Prologue: alpha = r^T M^-1 r / d^T q from the slot-1 partials (a channel
-// with d^T q <= 0 stops).  Then  y += alpha d,  r -= alpha q  and partials of
-// r^T r and r^T M^-1 r.
-__global__ void __launch_bounds__(kRedBlock) pcg_update(
-    const float* __restrict__ minv, const float* __restrict__ d, const float* __restrict__ q,
-    float* __restrict__ y, float* __restrict__ r, int C, int vpb,
-    const int32_t* __restrict__ counts, const ChanState* __restrict__ cs_in,
-    ChanState* __restrict__ cs_out, const double* __restrict__ part_in,
-    double* __restrict__ part_out, int32_t* __restrict__ ctl) {
-    __shared__ ChanState S[BS_MAX_CHANNELS];
-    __shared__ double fin[BS_MAX_CHANNELS];
-    __shared__ int n_active;
-    const int t = threadIdx.x;
-    reduce_partials<1>(part_in, C, fin);
-    if (t == 0) n_active = 0;
-    __syncthreads();
-    if (t < C) {
-        ChanState st = cs_in[t];
-        if (st.active) {
-            const double dq = fin[t];
-            if (!(dq > 0.0)) {
-                st.active = 0;
-                st.reason = 4;
-            } else {
-                st.alpha = st.rho / dq;
-            }
-        }
-        S[t] = st;
-        if (st.active) atomicAdd(&n_active, 1);
-        if (blockIdx.x == 0) cs_out[t] = st;
-    }
-    __syncthreads();
-    if (blockIdx.x == 0 && t == 0) ctl[CTL_ACTIVE] = n_active;
-    if (n_active == 0) return;
-    const int V = counts[CNT_V];
-    const int vl = t / C, ch = t - vl * C;
-    const bool lane_ok = vl < vpb;
-    const ChanState st = S[lane_ok ? ch : 0];
-    const bool act = lane_ok && st.active;
-    const float alpha = (float)st.alpha;
-    double acc[3] = {0.0, 0.0, 0.0};
-    const XcdTiles tl((V + vpb - 1) / vpb);
-    for (int64_t tile = tl.first; tile < tl.end; tile += tl.step) {
-        const int v = (int)(tile * vpb) + vl;
-        if (!act || v >= V) continue;
-        const int64_t e = (int64_t)v * C + ch;
-        y[e] += alpha * d[e];
-        const float rv = r[e] - alpha * q[e];
-        r[e] = rv;
-        acc[0] += (double)rv * (double)rv;
-        acc[2] += (double)rv * (double)(minv[v] * rv);
+        const int64_t e = (int64_t)o.v * C + ch;
+        const float uv = o.miv * o.rv;
+        const float pv = first ? uv : fmaf(beta, o.pv, uv);
+        const float sv = cg_s(o.wv, first ? 0.0f : o.sv, beta, first);
+        const float r1 = cg_r(o.rv, sv, alpha);
+        const float u1 = o.miv * r1;
+        const float w1 = o.dv * u1 - lam * o.nfv * ns;
+        y[e] = fmaf(alpha, pv, o.yv);
+        p[e] = pv;
+        snew[e] = sv;
+        rout[e] = r1;
+        wout[e] = w1;
+        acc[0] += (double)r1 * (double)r1;
+        acc[1] += (double)r1 * (double)u1;
+        acc[2] += (double)w1 * (double)u1;
     }
     block_channel_partials<3>(acc, C, vpb, part_out);
 }
 
 // After the last enqueued iteration (single block): completes the pending
-// step from the slot-0 partials and writes the per-channel stats.
-__global__ void __launch_bounds__(kRedBlock) pcg_finish(ChanState* __restrict__ cs,
+// step and writes the per-channel stats.
+__global__ void __launch_bounds__(kRedBlock) pcg_finish(const ChanState* __restrict__ cs_in,
+                                                         ChanState* __restrict__ cs_out,
                                                          const double* __restrict__ part, int C,
                                                          int max_iters, double tol,
                                                          bs_chan_stats* __restrict__ out) {
@@ -475,9 +687,9 @@ __global__ void __launch_bounds__(kRedBlock) pcg_finish(ChanState* __restrict__ 
     const int t = threadIdx.x;
     reduce_partials<3>(part, C, fin);
     if (t < C) {
-        ChanState st = cs[t];
+        ChanState st = cs_in[t];
         advance_state(st, fin[t], fin[C + t], fin[2 * C + t], max_iters, tol);
-        cs[t] = st;
+        cs_out[t] = st;
         if (out) {
             bs_chan_stats o;
             o.iters = st.iters;
@@ -585,20 +797,21 @@ static bs_status run_pcg(const GridImpl& g, const SolveWs& w, const bs_solve_par
     const int C = w.C;
     BS_LAUNCH(s, K_INIT, "solve_prologue", solve_prologue, dim3(1), dim3(64), 0, s, w.cs[0],
               w.cs[1], C, w.ctl);
-    BS_LAUNCH(s, K_PCG_START, "pcg_start", pcg_start, dim3(kRedGrid), dim3(kRedBlock), 0, s,
-              g.nbr, g.vcap, g.nf, w.diag, w.minv, w.b, y, w.r, p.lambda, C, w.vpb, g.counts,
-              w.part[0]);
+    BS_LAUNCH(s, K_PCG_START, "pcg_init_r", pcg_init_r, dim3(kRedGrid), dim3(kRedBlock), 0, s,
+              g.nbr, g.vcap, g.nf, w.diag, w.b, y, w.r[0], p.lambda, C, w.vpb, g.counts,
+              w.part[1]);
+    BS_LAUNCH(s, K_PCG_START, "pcg_init_w", pcg_init_w, dim3(kRedGrid), dim3(kRedBlock), 0, s,
+              g.nbr, g.vcap, g.nf, w.diag, w.minv, w.r[0], w.w[0], p.lambda, C, w.vpb, g.counts,
+              w.part[1], w.part[0], w.cs[0]);
+    int n = 0;
     for (int it = 0; it < p.max_iters; ++it) {
-        float* dn = w.d[it & 1];
-        const float* dold = w.d[(it + 1) & 1];
-        BS_LAUNCH(s, K_PCG_DIR_MATVEC, "pcg_dir_matvec", pcg_dir_matvec, dim3(kRedGrid),
-                  dim3(kRedBlock), 0, s, g.nbr, g.vcap, g.nf, w.diag, w.minv, w.r, dold, dn, w.q,
-                  p.lambda, C, w.vpb, g.counts, w.cs[0], w.cs[1], w.part[0], w.part[1], w.ctl,
-                  p.max_iters, p.rel_tol);
-        BS_LAUNCH(s, K_PCG_UPDATE, "pcg_update", pcg_update, dim3(kRedGrid), dim3(kRedBlock), 0,
-                  s, w.minv, dn, w.q, y, w.r, C, w.vpb, g.counts, w.cs[1], w.cs[0], w.part[1],
-                  w.part[0], w.ctl);
-        if (p.check_every > 0 && (it + 1) % p.check_every == 0 && it + 1 < p.max_iters) {
+        const int a = it & 1, b = a ^ 1;
+        BS_LAUNCH(s, K_PCG_ITER, "pcg_iter", pcg_iter, dim3(kRedGrid), dim3(kRedBlock), 0, s,
+                  g.nbr, g.vcap, g.nf, w.diag, w.minv, w.r[a], w.r[b], w.w[a], w.w[b], w.sv[b],
+                  w.sv[a], w.p, y, p.lambda, C, w.vpb, g.counts, w.cs[a], w.cs[b], w.part[a],
+                  w.part[b], w.ctl, p.max_iters, p.rel_tol);
+        n = it + 1;
+        if (p.check_every > 0 && n % p.check_every == 0 && n < p.max_iters) {
             int32_t active = 0;
             BS_TRY_HIP(hipMemcpyAsync(&active, w.ctl + CTL_ACTIVE, sizeof(int32_t),
                                       hipMemcpyDeviceToHost, s));
@@ -606,8 +819,8 @@ static bs_status run_pcg(const GridImpl& g, const SolveWs& w, const bs_solve_par
             if (active == 0) break;
         }
     }
-    BS_LAUNCH(s, K_INIT, "pcg_finish", pcg_finish, dim3(1), dim3(kRedBlock), 0, s, w.cs[0],
-              w.part[0], C, p.max_iters, p.rel_tol, stats);
+    BS_LAUNCH(s, K_INIT, "pcg_finish", pcg_finish, dim3(1), dim3(kRedBlock), 0, s, w.cs[n & 1],
+              w.cs[(n & 1) ^ 1], w.part[n & 1], C, p.max_iters, p.rel_tol, stats);
     return BS_OK;
 }
 
@@ -653,10 +866,8 @@ extern "C" bs_status bs_solve(const bs_grid* grid, const float* target, const fl
     hipStream_t s = (hipStream_t)stream;
     const bs_solve_params& p = *params;
 
-    const int vblocks = grid_blocks(ceil_div(g.vcap, kBlock));
-    BS_LAUNCH(s, K_SPLAT, "splat", splat_kernel<true>, dim3(vblocks), dim3(kBlock), 0, s, g.lv[0].ptr,
-                       g.lv[0].list, conf, target, C, g.P, g.nn, (double)p.lambda, g.counts,
-                       w.sc, w.diag, w.minv, w.b);
+    st = launch_splat<true>(g, conf, target, C, (double)p.lambda, w.sc, w.diag, w.minv, w.b, s);
+    if (st != BS_OK) return st;
     st = run_init(g, w, p, y, s);
     if (st != BS_OK) return st;
     st = run_pcg(g, w, p, y, stats, s);
@@ -701,10 +912,9 @@ extern "C" bs_status bs_solve_backward(const bs_grid* grid, const float* target,
     const bs_solve_params& p = *params;
     float* gb = g_out ? g_out : w.g;
 
-    const int vblocks = grid_blocks(ceil_div(g.vcap, kBlock));
-    BS_LAUNCH(s, K_SPLAT, "splat_grad", splat_kernel<false>, dim3(vblocks), dim3(kBlock), 0, s, g.lv[0].ptr,
-                       g.lv[0].list, conf, grad_x, C, g.P, g.nn, (double)p.lambda, g.counts,
-                       w.sc, w.diag, w.minv, w.b);
+    st = launch_splat<false>(g, conf, grad_x, C, (double)p.lambda, w.sc, w.diag, w.minv, w.b,
+                             s);
+    if (st != BS_OK) return st;
     st = run_init(g, w, p, gb, s);
     if (st != BS_OK) return st;
     st = run_pcg(g, w, p, gb, stats, s);
