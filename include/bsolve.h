@@ -233,8 +233,8 @@ bs_status bs_solve_ws_view(const bs_grid* grid, int32_t C, void* ws, size_t ws_b
  * graph-capturable).  bs_timing_read waits for the recorded events and
  * returns the summed elapsed milliseconds and launch count of one kernel:
  * "level_count", "level_scan", "level_write", "neighbour_table", "bist_step",
- * "bist_other", "splat", "init", "pcg_start", "pcg_iter", "slice" or
- * "grad_scatter".  bs_timing_reset clears the sums. */
+ * "bist_other", "splat", "init", "pcg_start", "pcg_matvec", "pcg_update",
+ * "pcg_reduce", "slice" or "grad_scatter".  bs_timing_reset clears the sums. */
 bs_status bs_timing_enable(int32_t on);
 bs_status bs_timing_reset(void);
 bs_status bs_timing_read(const char* kernel, double* total_ms, int64_t* launches);

@@ -35,6 +35,7 @@ __global__ void __launch_bounds__(kRedBlock) bist_step(const int32_t* __restrict
                                                         double* __restrict__ res_out, int step,
                                                         int max_iters, double tol) {
 #pragma clang fp contract(off)
+    const int G = gridDim.x;
     if (counts[CNT_BIST_DONE]) return;
     const int V = counts[CNT_V];
     const XcdTiles tl((V + kRedBlock - 1) / kRedBlock);
@@ -42,8 +43,10 @@ __global__ void __launch_bounds__(kRedBlock) bist_step(const int32_t* __restrict
     // before the stop decision: loads complete in issue order, so waiting for
     // the maxima leaves the operand loads in flight during the reduction.
     double prevmax = 0.0;
-    if (step >= 1 && threadIdx.x < kRedGrid)
-        prevmax = part[((step - 1) & 1) * kRedGrid + threadIdx.x];
+    if (step >= 1) {
+        const double* prev = part + ((step - 1) & 1) * kRedGridMax;
+        for (int i = threadIdx.x; i < G; i += kRedBlock) prevmax = fmax(prevmax, prev[i]);
+    }
     int v = (int)(tl.first * kRedBlock) + threadIdx.x;
     bool have = tl.first < tl.end && v < V;
     double n = 0.0, nbv[10];
@@ -97,18 +100,19 @@ __global__ void __launch_bounds__(kRedBlock) bist_step(const int32_t* __restrict
         dst[v] = sqrt(q);
     }
     lmax = block_max<kRedBlock>(lmax);
-    if (threadIdx.x == 0) part[(step & 1) * kRedGrid + blockIdx.x] = lmax;
+    if (threadIdx.x == 0) part[(step & 1) * kRedGridMax + partial_slot()] = lmax;
 }
 
 // After the last enqueued launch `last`: decide on its residual if no launch
 // has stopped the iteration yet (single block).
 __global__ void __launch_bounds__(kRedBlock) bist_decide(int32_t* __restrict__ counts,
                                                           const double* __restrict__ part,
-                                                          double* __restrict__ res_out, int last) {
+                                                          double* __restrict__ res_out, int last,
+                                                          int G) {
     if (counts[CNT_BIST_DONE]) return;
-    const double* prev = part + (last & 1) * kRedGrid;
+    const double* prev = part + (last & 1) * kRedGridMax;
     double r = 0.0;
-    for (int i = threadIdx.x; i < kRedGrid; i += kRedBlock) r = fmax(r, prev[i]);
+    for (int i = threadIdx.x; i < G; i += kRedBlock) r = fmax(r, prev[i]);
     const double R = block_max<kRedBlock>(r);
     if (threadIdx.x == 0) {
         counts[CNT_BIST_ITERS] = last;
@@ -163,9 +167,10 @@ extern "C" bs_status bs_bistochastize(bs_grid* grid, const bs_bistoch_params* pa
     const int blocks = grid_blocks(ceil_div(g.vcap, kBlock));
     BS_LAUNCH(s, K_BIST_OTHER, "bist_init", bist_init, dim3(blocks), dim3(kBlock), 0, s,
               g.nbuf[0], g.counts);
+    const int G = red_grid(g.vcap);
     int last = 0;
     for (int step = 0; step <= p.max_iters; ++step) {
-        BS_LAUNCH(s, K_BIST_STEP, "bist_step", bist_step, dim3(kRedGrid), dim3(kRedBlock), 0, s,
+        BS_LAUNCH(s, K_BIST_STEP, "bist_step", bist_step, dim3(G), dim3(kRedBlock), 0, s,
                   g.nbr, g.lv[0].mult, g.nbuf[step & 1], g.nbuf[(step + 1) & 1], g.vcap,
                   g.counts, g.bist_part, g.bist_res, step, p.max_iters, p.tol);
         last = step;
@@ -178,7 +183,7 @@ extern "C" bs_status bs_bistochastize(bs_grid* grid, const bs_bistoch_params* pa
         }
     }
     BS_LAUNCH(s, K_BIST_OTHER, "bist_decide", bist_decide, dim3(1), dim3(kRedBlock), 0, s,
-              g.counts, g.bist_part, g.bist_res, last);
+              g.counts, g.bist_part, g.bist_res, last, G);
     BS_LAUNCH(s, K_BIST_OTHER, "bist_finalize", bist_finalize, dim3(blocks), dim3(kBlock), 0, s,
               g.nbr, g.nbuf[0], g.nbuf[1], g.vcap, g.n64, g.nf, g.nn, g.counts);
     g.bistochastized = 1;

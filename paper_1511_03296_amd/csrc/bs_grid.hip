@@ -80,7 +80,7 @@ size_t layout_grid(GridImpl& g, int H, int W, const bs_grid_params& sp, void* ba
     Carver c(base);
     g.counts = c.take<int32_t>(CNT_SIZE);
     g.bist_res = c.take<double>(1);
-    g.bist_part = c.take<double>(2 * kRedGrid);
+    g.bist_part = c.take<double>(2 * kRedGridMax);
     g.cell_cnt = c.take<int32_t>(max_cells);
     g.cell_items = c.take<int32_t>(max_cells);
     g.ikey = c.take<uint32_t>(g.P);

@@ -40,7 +40,8 @@ bs_status check_hip(hipError_t e, const char* what);
 // ---------------------------------------------------------------------------
 enum KernelId : int {
     K_LEVEL_COUNT, K_LEVEL_SCAN, K_LEVEL_WRITE, K_NEIGHBOURS, K_BIST_STEP, K_BIST_OTHER,
-    K_SPLAT, K_INIT, K_PCG_START, K_PCG_ITER, K_SLICE, K_GRAD_SCATTER,
+    K_SPLAT, K_INIT, K_PCG_START, K_PCG_MATVEC, K_PCG_UPDATE, K_PCG_REDUCE, K_SLICE,
+    K_GRAD_SCATTER,
     K_COUNT
 };
 void timing_begin(hipStream_t s, int id);
@@ -62,15 +63,23 @@ void timing_end(hipStream_t s, int id);
 constexpr int kBlock = 256;          // threads per block of streaming kernels
 constexpr int kXcds = 8;             // MI355X: 8 accelerator dies, one L2 each
 constexpr int kMaxGrid = 2048;       // blocks of a grid-stride launch
-// Reducing kernels (bistochastization, PCG) run a fixed grid of kRedGrid
-// blocks of kRedBlock threads, one block per compute unit: small blocks
-// spread even small grids over every compute unit, whose address units bound
-// the neighbour gathers.  Each writes one
+// Reducing kernels (bistochastization, PCG) run G blocks of kRedBlock threads
+// (G from red_grid): small blocks spread even small grids over every compute
+// unit, whose address units bound the neighbour gathers.  Each writes one
 // partial per block; the next kernel reduces them in its prologue (the kernel
 // boundary is the only grid-wide synchronisation).
 constexpr int kRedBlock = 256;
-constexpr int kRedGrid = 256;
-static_assert(kRedGrid <= kRedBlock && kRedGrid % 64 == 0, "one partial per thread");
+constexpr int kRedGridSmall = 256;    // one block per compute unit
+constexpr int kRedGridLarge = 1024;   // four: more waves in flight for large grids
+constexpr int kRedGridMax = kRedGridLarge;
+static_assert(kRedGridMax % kRedBlock == 0, "partials per thread");
+
+// Grid of the reducing kernels for `elements` (vertex, channel) elements (an
+// upper bound known on the host): small grids are latency-bound and favour
+// cheap prologue reductions, large ones bandwidth-bound and favour occupancy.
+inline int red_grid(int64_t elements) {
+    return elements >= (int64_t)1 << 21 ? kRedGridLarge : kRedGridSmall;
+}
 
 // Slots of the device counter array.
 enum Counter : int {
@@ -159,7 +168,7 @@ struct GridImpl {
     double* nn;              // [vcap] n o N n
     int32_t* counts;         // [CNT_SIZE]
     double* bist_res;        // [1]
-    double* bist_part;       // [2][kRedGrid] ping-pong partial maxima
+    double* bist_part;       // [2][kRedGridMax] ping-pong partial maxima
     int32_t* cell_cnt;       // [max_cells] scratch
     int32_t* cell_items;     // [max_cells] scratch
     uint32_t* ikey;          // [P] item keys with first-occurrence flag, scratch
@@ -197,6 +206,12 @@ struct XcdTiles {
         step = per;
     }
 };
+
+// Slot of this block's partial result: blocks of one die get consecutive
+// slots, so a cache line of partials is written from one die only.
+__device__ inline int partial_slot() {
+    return (blockIdx.x % kXcds) * (gridDim.x / kXcds) + blockIdx.x / kXcds;
+}
 
 __device__ inline double wave_sum(double v) {
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);

@@ -7,49 +7,58 @@
 // all C channels, so the neighbour table is read once per vertex and the
 // channel gathers of one neighbour are contiguous.
 //
-// PCG runs one independent PCG per channel, in the single-reduction
-// arrangement of Chronopoulos and Gear: with u = M^-1 r, w = A u, s = A p it
-// carries s and w by recurrence, so both inner products of an iteration,
-// gamma = r^T u and delta = w^T u, come from one pass:
-//   p = u + beta p,  s = w + beta s,  y += alpha p,  r -= alpha s,
-//   u = M^-1 r,  w = A u,  gamma = r^T u,  delta = w^T u,
-//   beta' = gamma' / gamma,  alpha' = gamma' / (delta' - beta' gamma' / alpha).
-// In exact arithmetic its iterates are those of the preconditioned CG the
-// paper uses (supplement Algorithm 2); one kernel per iteration computes the
-// neighbours' new u values from the gathered old r, w and s, so every
-// iteration is one launch and one grid-wide reduction.  Dot products
-// accumulate in float64; the next kernel reduces the per-block partials in its
-// prologue in a fixed order, so results are deterministic and no host
-// synchronisation is needed.
+// PCG (supplement Algorithm 2) runs one independent PCG per channel.  One
+// iteration is two kernels, each with one grid-wide reduction:
+//   pcg_matvec:  d = M^-1 r + beta d  (fused: the neighbours' new d values are
+//                recomputed from their gathered r and old d),  q = A d, d^T q;
+//   pcg_update:  y += alpha d,  r -= alpha q,  r^T r,  r^T M^-1 r.
+// A z is evaluated in Laplacian form,
+//   (A z)_v = (S c)_v z_v + lam n_v sum_u n_u (z_v - z_u),
+// which equals diag(A) z - lam n o N(n o z) with diag(A) = lam n o N n + S c,
+// but cancels constants exactly and keeps float32 rounding relative to the
+// result rather than to lam m z (the difference matters where confidence is
+// sparse).  Dot products accumulate in float64; the next kernel reduces the
+// per-block partials in its prologue in a fixed order, so results are
+// deterministic and no host synchronisation is needed.
 #include "bs_internal.h"
 
 namespace bs {
 
-struct ChanState {
+// One record per 128-byte cache line: each block reads back its own record,
+// written by the block of the same index (same die) in the previous launch.
+// With 48- or 64-byte records a line held records of blocks on two dies and
+// that read cost ~12 us per launch on MI355X.
+struct alignas(128) ChanState {
     double rho, alpha, beta, bnorm, res;
     int32_t active, iters, reason, phase;   // phase 0: initial residual not yet reduced
 };
+static_assert(sizeof(ChanState) == 128, "one record per cache line");
 
 enum Ctl : int { CTL_ACTIVE = 0, CTL_SIZE = 8 };
 
-// Partials of the reducing kernels: [2 slots][3 values][C][kRedGrid], values
-// (r^T r, gamma = r^T u, delta = w^T u); pcg_init_r writes b^T b as value 0.
-// Launch j reads slot j % 2 and writes the other; the per-channel state is
-// double-buffered the same way (block 0 writes the new state).
+// Partials of the reducing kernels: [2 slots][3 values][C][G].
+//   slot 0 -- pcg_start (r^T r, b^T b, r^T M^-1 r), pcg_update (r^T r, 0, r^T M^-1 r);
+//   slot 1 -- pcg_matvec (d^T q).
+// Per-channel state, double-buffered the same way: pcg_matvec reads state 0
+// and writes state 1, pcg_update reads state 1 and writes state 0.  Every
+// block computes the same state from the same partials and keeps its own copy
+// (slot [block][C]): block b always runs on die b % 8, so its copy stays in
+// that die's L2, whereas reading one copy written by another die's block cost
+// ~12 us per launch.
 struct SolveWs {
-    int C, vpb;
+    int C, vpb, G;
     float* sc;
     float* diag;
     float* minv;
     float* b;
-    float* r[2];
-    float* w[2];
-    float* sv[2];
-    float* p;
+    float* r;
+    float* d[2];
+    float* q;
     float* g;
     float* up[BS_MAX_LEVELS];
     ChanState* cs[2];
     double* part[2];
+    double* sums[2];     // [3][C] reduced partials when pcg_reduce is used
     int32_t* ctl;
     size_t bytes;
 };
@@ -57,26 +66,27 @@ struct SolveWs {
 static size_t layout_solve(const GridImpl& g, int C, void* base, SolveWs& w) {
     w.C = C;
     w.vpb = kRedBlock / C;
+    w.G = red_grid(g.vcap * C);
     Carver c(base);
     const int64_t n = g.vcap * C;
     w.sc = c.take<float>(g.vcap);
     w.diag = c.take<float>(g.vcap);
     w.minv = c.take<float>(g.vcap);
     w.b = c.take<float>(n);
-    for (int i = 0; i < 2; ++i) {
-        w.r[i] = c.take<float>(n);
-        w.w[i] = c.take<float>(n);
-        w.sv[i] = c.take<float>(n);
-    }
-    w.p = c.take<float>(n);
+    w.r = c.take<float>(n);
+    w.d[0] = c.take<float>(n);
+    w.d[1] = c.take<float>(n);
+    w.q = c.take<float>(n);
     w.g = c.take<float>(n);
     w.up[0] = nullptr;
     for (int k = 1; k < BS_MAX_LEVELS; ++k)
         w.up[k] = (k < g.levels) ? c.take<float>(g.lv[k].cap * (C + 1)) : nullptr;
-    w.cs[0] = c.take<ChanState>(C);
-    w.cs[1] = c.take<ChanState>(C);
-    w.part[0] = c.take<double>((int64_t)3 * C * kRedGrid);
-    w.part[1] = c.take<double>((int64_t)3 * C * kRedGrid);
+    w.cs[0] = c.take<ChanState>((int64_t)kRedGridMax * C);
+    w.cs[1] = c.take<ChanState>((int64_t)kRedGridMax * C);
+    w.part[0] = c.take<double>((int64_t)3 * C * kRedGridMax);
+    w.part[1] = c.take<double>((int64_t)3 * C * kRedGridMax);
+    w.sums[0] = c.take<double>(3 * C);
+    w.sums[1] = c.take<double>(3 * C);
     w.ctl = c.take<int32_t>(CTL_SIZE);
     w.bytes = align_up(c.off, 256);
     return w.bytes;
@@ -87,7 +97,8 @@ static size_t layout_solve(const GridImpl& g, int C, void* base, SolveWs& w) {
 // ---------------------------------------------------------------------------
 
 // Sums NV per-thread values over the vertices of the block, per channel, with
-// a fixed tree, and writes the block's partials to part[(k C + ch) G + block].
+// a fixed tree, and writes the block's partials to part[(k C + ch) G + block]
+// (G = gridDim.x).
 template <int NV>
 __device__ inline void block_channel_partials(const double (&acc)[NV], int C, int vpb,
                                               double* __restrict__ part) {
@@ -107,7 +118,7 @@ __device__ inline void block_channel_partials(const double (&acc)[NV], int C, in
         if (t < NV) {
             double s = 0.0;
             for (int w = 0; w < kRedBlock / 64; ++w) s += red[t][w];
-            part[(int64_t)t * kRedGrid + blockIdx.x] = s;
+            part[(int64_t)t * gridDim.x + partial_slot()] = s;
         }
         return;
     }
@@ -127,11 +138,11 @@ __device__ inline void block_channel_partials(const double (&acc)[NV], int C, in
     }
     if (t < C) {
 #pragma unroll
-        for (int k = 0; k < NV; ++k) part[((int64_t)k * C + t) * kRedGrid + blockIdx.x] = s[k][t];
+        for (int k = 0; k < NV; ++k) part[((int64_t)k * C + t) * gridDim.x + partial_slot()] = s[k][t];
     }
 }
 
-// out[k C + ch] = sum over the kRedGrid blocks of the producer's partials,
+// out[k C + ch] = sum over the G blocks of the producer's partials,
 // computed identically by every block.  The NV C sums are spread over the
 // block: q lanes (a power of two <= 64, so a group lies in one wave) share a
 // sum, each adding every q-th partial, then a shuffle tree over the group.
@@ -139,31 +150,53 @@ __device__ inline void block_channel_partials(const double (&acc)[NV], int C, in
 // loads in between; loads complete in issue order, so waiting for these does
 // not wait for loads issued after them.
 struct PartialSums {
-    static constexpr int kMax = 8;   // partials per thread held in registers
+    static constexpr int kMax = 16;   // partials per thread held in registers
     double v[kMax];
-    int pairs, q, pair, seg;
+    int pairs, q, pair, seg, G;
     bool held;
+    const double* pre;   // sums already reduced by pcg_reduce, or nullptr
 
-    __device__ void load(const double* __restrict__ part, int nv_c) {
-        pairs = nv_c;
-        q = 64;
+    // Lanes per pair for `pairs` sums over G partials, and whether each lane's
+    // share fits in registers (the host uses the same rule to decide when to
+    // run pcg_reduce instead).
+    __host__ __device__ static int lanes(int pairs) {
+        int q = 64;
         while (q > 1 && q * pairs > kRedBlock) q >>= 1;
+        return q;
+    }
+    __host__ __device__ static bool fits(int pairs, int G) {
+        const int q = lanes(pairs);
+        return pairs * q <= kRedBlock && G / q <= kMax;
+    }
+
+    __device__ void load(const double* __restrict__ part, int nv_c, int grid,
+                         const double* __restrict__ sums = nullptr) {
+        pre = sums;
+        pairs = nv_c;
+        G = grid;
+        if (pre) {
+            if ((int)threadIdx.x < pairs) v[0] = pre[threadIdx.x];
+            return;
+        }
+        q = lanes(pairs);
         pair = threadIdx.x / q;
         seg = threadIdx.x - pair * q;
-        held = pairs * q <= kRedBlock && kRedGrid / q <= kMax;
+        held = fits(pairs, G);
         if (held && pair < pairs) {
 #pragma unroll
             for (int i = 0; i < kMax; ++i)
-                if (i < kRedGrid / q) v[i] = part[(int64_t)pair * kRedGrid + seg + q * i];
+                if (i < G / q) v[i] = part[(int64_t)pair * G + seg + q * i];
         }
     }
 
     __device__ void sum(const double* __restrict__ part, double* out) {
-        if (held) {
+        if (pre) {
+            if ((int)threadIdx.x < pairs) out[threadIdx.x] = v[0];
+        } else if (held) {
             double s = 0.0;
 #pragma unroll
             for (int i = 0; i < kMax; ++i)
-                if (i < kRedGrid / q && pair < pairs) s += v[i];
+                if (i < G / q && pair < pairs) s += v[i];
             for (int o = q >> 1; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
             if (seg == 0 && pair < pairs) out[pair] = s;
         } else {
@@ -171,7 +204,7 @@ struct PartialSums {
                 const int pr = base + pair;
                 double s = 0.0;
                 if (pr < pairs)
-                    for (int b = seg; b < kRedGrid; b += q) s += part[(int64_t)pr * kRedGrid + b];
+                    for (int b = seg; b < G; b += q) s += part[(int64_t)pr * G + b];
                 for (int o = q >> 1; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
                 if (seg == 0 && pr < pairs) out[pr] = s;
             }
@@ -181,80 +214,71 @@ struct PartialSums {
 };
 
 template <int NV>
-__device__ inline void reduce_partials(const double* __restrict__ part, int C, double* out) {
+__device__ inline void reduce_partials(const double* __restrict__ part, int C, int G,
+                                       double* out, const double* __restrict__ sums = nullptr) {
     PartialSums ps;
-    ps.load(part, NV * C);
+    ps.load(part, NV * C, G, sums);
     ps.sum(part, out);
 }
 
-// Completes the previous PCG step of one channel from the reduced partials
-// r^T r, gamma and delta: the start (phase 0) or the end of an iteration,
-// with the stopping rule, then the next alpha and beta.
-__device__ inline void advance_state(ChanState& st, double rr, double gam, double del,
+// With many channels the per-block partials are reduced once, by one block per
+// (value, channel) pair, rather than redundantly in every consumer block.
+__global__ void __launch_bounds__(kRedBlock) pcg_reduce(const double* __restrict__ part,
+                                                         double* __restrict__ sums, int G) {
+    double v = 0.0;
+    for (int i = threadIdx.x; i < G; i += kRedBlock) v += part[(int64_t)blockIdx.x * G + i];
+    const double s = block_sum<kRedBlock>(v);
+    if (threadIdx.x == 0) sums[blockIdx.x] = s;
+}
+
+// Completes the previous PCG step of one channel from the reduced slot-0
+// partials: the initial residual (phase 0) or the end of an iteration, with
+// the stopping rule and the next beta.
+__device__ inline void advance_state(ChanState& st, double rr, double bb, double rho_new,
                                      int max_iters, double tol) {
     int reason = 0;
     if (st.phase == 0) {
         st.phase = 1;
+        st.bnorm = sqrt(bb);
+        st.rho = rho_new;
+        st.beta = 0.0;
         st.iters = 0;
-        st.active = 0;
-        if (st.bnorm == 0.0) {
-            st.reason = 5;
+        if (bb == 0.0) {
             st.res = 0.0;
-            return;
-        }
-        st.res = sqrt(rr) / st.bnorm;
-        if (st.res <= tol) reason = 1;
-        else if (max_iters <= 0) reason = 2;
-        else if (gam == 0.0) reason = 3;
-        else if (!(del > 0.0)) reason = 4;
-        else {
-            st.beta = 0.0;
-            st.alpha = gam / del;
-            st.rho = gam;
+            reason = 5;
+        } else {
+            st.res = sqrt(rr) / st.bnorm;
+            if (st.res <= tol) reason = 1;
+            else if (max_iters <= 0) reason = 2;
+            else if (rho_new == 0.0) reason = 3;
         }
     } else {
         if (!st.active) return;
+        st.beta = rho_new / st.rho;
+        st.rho = rho_new;
         st.iters += 1;
         st.res = sqrt(rr) / st.bnorm;
         if (st.res <= tol) reason = 1;
         else if (st.iters >= max_iters) reason = 2;
-        else if (gam == 0.0) reason = 3;
-        else {
-            const double beta = gam / st.rho;
-            const double den = del - beta * gam / st.alpha;   // = p^T A p
-            if (!(den > 0.0)) reason = 4;
-            else {
-                st.beta = beta;
-                st.alpha = gam / den;
-                st.rho = gam;
-            }
-        }
+        else if (rho_new == 0.0) reason = 3;
     }
     st.active = reason == 0;
     if (reason) st.reason = reason;
 }
 
-// Recurrences shared by a vertex and its neighbours, written with explicit
-// fused multiply-adds so both evaluate them identically:
-//   s = w + beta s_old,  r' = r - alpha s,  u' = M^-1 r'.
-__device__ inline float cg_s(float w, float s_old, float beta, bool first) {
-    return first ? w : fmaf(beta, s_old, w);
-}
-__device__ inline float cg_r(float r, float s, float alpha) { return fmaf(-alpha, s, r); }
-
 // ---------------------------------------------------------------------------
 // Kernels.
 // ---------------------------------------------------------------------------
 
-__global__ void solve_prologue(ChanState* cs0, ChanState* cs1, int C, int32_t* ctl) {
-    const int t = threadIdx.x;
+__global__ void solve_prologue(ChanState* cs0, ChanState* cs1, int n, int32_t* ctl) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t < CTL_SIZE) ctl[t] = 0;
-    for (int c = t; c < C; c += blockDim.x) {
+    if (t < n) {
         ChanState z;
         z.rho = z.alpha = z.beta = z.bnorm = z.res = 0.0;
         z.active = z.iters = z.reason = z.phase = 0;
-        cs0[c] = z;
-        cs1[c] = z;
+        cs0[t] = z;
+        cs1[t] = z;
     }
 }
 
@@ -476,56 +500,15 @@ __global__ void __launch_bounds__(kBlock) hier_final(const float* __restrict__ b
     }
 }
 
-// r0 = b - A y0, one (vertex, channel) element per thread, with
-// A z = diag(A) z_v - lam n_v sum_j n_j z_j; partials b^T b.
-__global__ void __launch_bounds__(kRedBlock) pcg_init_r(
+// r = b - A y0, one (vertex, channel) element per thread; partials r^T r,
+// b^T b, r^T M^-1 r.
+__global__ void __launch_bounds__(kRedBlock) pcg_start(
     const int32_t* __restrict__ nbr, int64_t vcap, const float* __restrict__ nf,
-    const float* __restrict__ diag, const float* __restrict__ b, const float* __restrict__ y,
-    float* __restrict__ r, float lam, int C, int vpb, const int32_t* __restrict__ counts,
-    double* __restrict__ part) {
+    const float* __restrict__ sc, const float* __restrict__ minv, const float* __restrict__ b,
+    const float* __restrict__ y, float* __restrict__ r, float lam, int C, int vpb,
+    const int32_t* __restrict__ counts, double* __restrict__ part) {
     const int V = counts[CNT_V];
     const int t = threadIdx.x;
-    const int vl = t / C, ch = t - vl * C;
-    const bool lane_ok = vl < vpb;
-    double acc[1] = {0.0};
-    const XcdTiles tl((V + vpb - 1) / vpb);
-    for (int64_t tile = tl.first; tile < tl.end; tile += tl.step) {
-        const int v = (int)(tile * vpb) + vl;
-        if (!lane_ok || v >= V) continue;
-        float ns = 0.0f;
-#pragma unroll
-        for (int j = 0; j < 10; ++j) {
-            const int u = nbr[j * vcap + v];
-            if (u >= 0) ns += nf[u] * y[(int64_t)u * C + ch];
-        }
-        const int64_t e = (int64_t)v * C + ch;
-        const float ay = diag[v] * y[e] - lam * nf[v] * ns;
-        const float bv = b[e];
-        r[e] = bv - ay;
-        acc[0] += (double)bv * (double)bv;
-    }
-    block_channel_partials<1>(acc, C, vpb, part);
-}
-
-// Prologue: ||b|| into the initial state.  Then u0 = M^-1 r0 (gathered),
-// w0 = A u0, partials r^T r, r^T u, w^T u.
-__global__ void __launch_bounds__(kRedBlock) pcg_init_w(
-    const int32_t* __restrict__ nbr, int64_t vcap, const float* __restrict__ nf,
-    const float* __restrict__ diag, const float* __restrict__ minv, const float* __restrict__ r,
-    float* __restrict__ w, float lam, int C, int vpb, const int32_t* __restrict__ counts,
-    const double* __restrict__ part_in, double* __restrict__ part_out,
-    ChanState* __restrict__ cs_out) {
-    __shared__ double fin[BS_MAX_CHANNELS];
-    const int t = threadIdx.x;
-    reduce_partials<1>(part_in, C, fin);
-    if (blockIdx.x == 0 && t < C) {
-        ChanState z;
-        z.rho = z.alpha = z.beta = z.res = 0.0;
-        z.bnorm = sqrt(fin[t]);
-        z.active = z.iters = z.reason = z.phase = 0;
-        cs_out[t] = z;
-    }
-    const int V = counts[CNT_V];
     const int vl = t / C, ch = t - vl * C;
     const bool lane_ok = vl < vpb;
     double acc[3] = {0.0, 0.0, 0.0};
@@ -533,40 +516,40 @@ __global__ void __launch_bounds__(kRedBlock) pcg_init_w(
     for (int64_t tile = tl.first; tile < tl.end; tile += tl.step) {
         const int v = (int)(tile * vpb) + vl;
         if (!lane_ok || v >= V) continue;
+        const int64_t e = (int64_t)v * C + ch;
+        const float yv = y[e];
         float ns = 0.0f;
 #pragma unroll
         for (int j = 0; j < 10; ++j) {
             const int u = nbr[j * vcap + v];
-            if (u >= 0) ns += nf[u] * (minv[u] * r[(int64_t)u * C + ch]);
+            if (u >= 0) ns += nf[u] * (yv - y[(int64_t)u * C + ch]);
         }
-        const int64_t e = (int64_t)v * C + ch;
-        const float rv = r[e];
-        const float uv = minv[v] * rv;
-        const float wv = diag[v] * uv - lam * nf[v] * ns;
-        w[e] = wv;
+        const float ay = sc[v] * yv + lam * nf[v] * ns;
+        const float bv = b[e];
+        const float rv = bv - ay;
+        r[e] = rv;
         acc[0] += (double)rv * (double)rv;
-        acc[1] += (double)rv * (double)uv;
-        acc[2] += (double)wv * (double)uv;
+        acc[1] += (double)bv * (double)bv;
+        acc[2] += (double)rv * (double)(minv[v] * rv);
     }
-    block_channel_partials<3>(acc, C, vpb, part_out);
+    block_channel_partials<3>(acc, C, vpb, part);
 }
 
-// Operands of one (vertex, channel) element of a PCG iteration.  Loading
-// them does not depend on the iteration's scalars, so the first tile's loads
-// are issued before the prologue and overlap its reduction.
-struct IterOperands {
+// Operands of one (vertex, channel) element of pcg_matvec.  Loading them does
+// not depend on the iteration's scalars, so the first tile's loads are issued
+// before the prologue and overlap its reduction.
+struct MatvecOperands {
     int v;
     int nb[10];
-    float r[10], w[10], s[10], mi[10], nf[10];
-    float rv, wv, sv, pv, yv, miv, dv, nfv;
+    float r[10], d[10], mi[10], nf[10];
+    float rv, dv, miv, scv, nfv;
 };
 
-__device__ inline bool load_iter(IterOperands& o, int64_t tile, int vpb, int vl, int ch, int C,
-                                 int V, int64_t vcap, const int32_t* __restrict__ nbr,
-                                 const float* __restrict__ nf, const float* __restrict__ diag,
-                                 const float* __restrict__ minv, const float* __restrict__ rin,
-                                 const float* __restrict__ win, const float* __restrict__ sold,
-                                 const float* __restrict__ p, const float* __restrict__ y) {
+__device__ inline bool load_matvec(MatvecOperands& o, int64_t tile, int vpb, int vl, int ch,
+                                   int C, int V, int64_t vcap, const int32_t* __restrict__ nbr,
+                                   const float* __restrict__ nf, const float* __restrict__ sc,
+                                   const float* __restrict__ minv, const float* __restrict__ r,
+                                   const float* __restrict__ dold) {
     o.v = (int)(tile * vpb) + vl;
     if (o.v >= V) return false;
 #pragma unroll
@@ -575,38 +558,36 @@ __device__ inline bool load_iter(IterOperands& o, int64_t tile, int vpb, int vl,
     for (int j = 0; j < 10; ++j) {
         const int u = o.nb[j] >= 0 ? o.nb[j] : o.v;
         const int64_t eu = (int64_t)u * C + ch;
-        o.r[j] = rin[eu];
-        o.w[j] = win[eu];
-        o.s[j] = sold[eu];
+        o.r[j] = r[eu];
+        o.d[j] = dold[eu];
         o.mi[j] = minv[u];
         o.nf[j] = nf[u];
     }
     const int64_t e = (int64_t)o.v * C + ch;
-    o.rv = rin[e];
-    o.wv = win[e];
-    o.sv = sold[e];
-    o.pv = p[e];
-    o.yv = y[e];
+    o.rv = r[e];
+    o.dv = dold[e];
     o.miv = minv[o.v];
-    o.dv = diag[o.v];
+    o.scv = sc[o.v];
     o.nfv = nf[o.v];
     return true;
 }
 
-// One PCG iteration.  Prologue: finish the previous step (stopping rule,
-// alpha, beta) from the reduced partials.  Then, per element,
-//   p = u + beta p,  s = w + beta s,  y += alpha p,  r' = r - alpha s,
-//   u' = M^-1 r',  w' = A u'  (the neighbours' u' recomputed from their
-//   gathered r, w and s),  partials r'^T r', r'^T u', w'^T u'.
-__global__ void __launch_bounds__(kRedBlock) pcg_iter(
+// New search direction of one element: M^-1 r + beta d_old (M^-1 r first).
+__device__ inline float pcg_dir(float r, float d_old, float mi, float beta, bool first) {
+    const float s = mi * r;
+    return first ? s : fmaf(beta, d_old, s);
+}
+
+// Prologue: finish the previous step (stopping rule, beta) from the slot-0
+// partials.  Then d = M^-1 r + beta d_old, q = A d and partials of d^T q.
+__global__ void __launch_bounds__(kRedBlock) pcg_matvec(
     const int32_t* __restrict__ nbr, int64_t vcap, const float* __restrict__ nf,
-    const float* __restrict__ diag, const float* __restrict__ minv,
-    const float* __restrict__ rin, float* __restrict__ rout, const float* __restrict__ win,
-    float* __restrict__ wout, const float* __restrict__ sold, float* __restrict__ snew,
-    float* __restrict__ p, float* __restrict__ y, float lam, int C, int vpb,
-    const int32_t* __restrict__ counts, const ChanState* __restrict__ cs_in,
+    const float* __restrict__ sc, const float* __restrict__ minv, const float* __restrict__ r,
+    const float* __restrict__ dold, float* __restrict__ dnew, float* __restrict__ q, float lam,
+    int C, int vpb, const int32_t* __restrict__ counts, const ChanState* __restrict__ cs_in,
     ChanState* __restrict__ cs_out, const double* __restrict__ part_in,
-    double* __restrict__ part_out, int32_t* __restrict__ ctl, int max_iters, double tol) {
+    const double* __restrict__ sums_in, double* __restrict__ part_out,
+    int32_t* __restrict__ ctl, int max_iters, double tol) {
     __shared__ ChanState S[BS_MAX_CHANNELS];
     __shared__ double fin[3 * BS_MAX_CHANNELS];
     __shared__ int n_active;
@@ -615,17 +596,15 @@ __global__ void __launch_bounds__(kRedBlock) pcg_iter(
     const int vl = t / C, ch = t - vl * C;
     const bool lane_ok = vl < vpb;
     const XcdTiles tl((V + vpb - 1) / vpb);
-    // Loads complete in issue order, so the partials and the state are loaded
-    // before the first tile's operands: waiting for them does not wait for
-    // the gathers, which stay in flight during the reduction.
+    // Loads complete in issue order: partials and state first, then the first
+    // tile's operands, which stay in flight during the reduction.
     PartialSums ps;
-    ps.load(part_in, 3 * C);
+    ps.load(part_in, 3 * C, gridDim.x, sums_in);
     ChanState st0;
-    if (t < C) st0 = cs_in[t];
-    IterOperands o;
+    if (t < C) st0 = cs_in[(int64_t)blockIdx.x * C + t];
+    MatvecOperands o;
     bool have = lane_ok && tl.first < tl.end &&
-                load_iter(o, tl.first, vpb, vl, ch, C, V, vcap, nbr, nf, diag, minv, rin, win,
-                          sold, p, y);
+                load_matvec(o, tl.first, vpb, vl, ch, C, V, vcap, nbr, nf, sc, minv, r, dold);
     ps.sum(part_in, fin);
     if (t == 0) n_active = 0;
     __syncthreads();
@@ -633,7 +612,7 @@ __global__ void __launch_bounds__(kRedBlock) pcg_iter(
         advance_state(st0, fin[t], fin[C + t], fin[2 * C + t], max_iters, tol);
         S[t] = st0;
         if (st0.active) atomicAdd(&n_active, 1);
-        if (blockIdx.x == 0) cs_out[t] = st0;
+        cs_out[(int64_t)blockIdx.x * C + t] = st0;
     }
     __syncthreads();
     if (blockIdx.x == 0 && t == 0) ctl[CTL_ACTIVE] = n_active;
@@ -641,37 +620,106 @@ __global__ void __launch_bounds__(kRedBlock) pcg_iter(
     const ChanState st = S[lane_ok ? ch : 0];
     const bool act = lane_ok && st.active;
     const bool first = st.iters == 0;
-    const float alpha = (float)st.alpha, beta = (float)st.beta;
-    double acc[3] = {0.0, 0.0, 0.0};
+    const float beta = (float)st.beta;
+    double acc[1] = {0.0};
     for (int64_t tile = tl.first; tile < tl.end; tile += tl.step) {
         if (tile != tl.first)
-            have = lane_ok && load_iter(o, tile, vpb, vl, ch, C, V, vcap, nbr, nf, diag, minv,
-                                        rin, win, sold, p, y);
+            have = lane_ok &&
+                   load_matvec(o, tile, vpb, vl, ch, C, V, vcap, nbr, nf, sc, minv, r, dold);
         if (!act || !have) continue;
+        const float dv = pcg_dir(o.rv, o.dv, o.miv, beta, first);
         float ns = 0.0f;
 #pragma unroll
         for (int j = 0; j < 10; ++j) {
-            if (o.nb[j] >= 0) {
-                const float su = cg_s(o.w[j], first ? 0.0f : o.s[j], beta, first);
-                const float ru = cg_r(o.r[j], su, alpha);
-                ns += o.nf[j] * (o.mi[j] * ru);
+            if (o.nb[j] >= 0) ns += o.nf[j] * (dv - pcg_dir(o.r[j], o.d[j], o.mi[j], beta, first));
+        }
+        const float qv = o.scv * dv + lam * o.nfv * ns;
+        const int64_t e = (int64_t)o.v * C + ch;
+        dnew[e] = dv;
+        q[e] = qv;
+        acc[0] += (double)dv * (double)qv;
+    }
+    block_channel_partials<1>(acc, C, vpb, part_out);
+}
+
+// Prologue: alpha = r^T M^-1 r / d^T q from the slot-1 partials (a channel
+// with d^T q <= 0 stops).  Then y += alpha d, r -= alpha q and partials of
+// r^T r and r^T M^-1 r.
+__global__ void __launch_bounds__(kRedBlock) pcg_update(
+    const float* __restrict__ minv, const float* __restrict__ d, const float* __restrict__ q,
+    float* __restrict__ y, float* __restrict__ r, int C, int vpb,
+    const int32_t* __restrict__ counts, const ChanState* __restrict__ cs_in,
+    ChanState* __restrict__ cs_out, const double* __restrict__ part_in,
+    const double* __restrict__ sums_in, double* __restrict__ part_out,
+    int32_t* __restrict__ ctl) {
+    __shared__ ChanState S[BS_MAX_CHANNELS];
+    __shared__ double fin[BS_MAX_CHANNELS];
+    __shared__ int n_active;
+    const int t = threadIdx.x;
+    const int V = counts[CNT_V];
+    const int vl = t / C, ch = t - vl * C;
+    const bool lane_ok = vl < vpb;
+    const XcdTiles tl((V + vpb - 1) / vpb);
+    PartialSums ps;
+    ps.load(part_in, C, gridDim.x, sums_in);
+    ChanState st0;
+    if (t < C) st0 = cs_in[(int64_t)blockIdx.x * C + t];
+    // first tile's operands in flight during the reduction
+    int v = (int)(tl.first * vpb) + vl;
+    bool have = lane_ok && tl.first < tl.end && v < V;
+    float yv = 0.0f, dv = 0.0f, rv = 0.0f, qv = 0.0f, miv = 0.0f;
+    if (have) {
+        const int64_t e = (int64_t)v * C + ch;
+        yv = y[e];
+        dv = d[e];
+        rv = r[e];
+        qv = q[e];
+        miv = minv[v];
+    }
+    ps.sum(part_in, fin);
+    if (t == 0) n_active = 0;
+    __syncthreads();
+    if (t < C) {
+        if (st0.active) {
+            const double dq = fin[t];
+            if (!(dq > 0.0)) {
+                st0.active = 0;
+                st0.reason = 4;
+            } else {
+                st0.alpha = st0.rho / dq;
             }
         }
-        const int64_t e = (int64_t)o.v * C + ch;
-        const float uv = o.miv * o.rv;
-        const float pv = first ? uv : fmaf(beta, o.pv, uv);
-        const float sv = cg_s(o.wv, first ? 0.0f : o.sv, beta, first);
-        const float r1 = cg_r(o.rv, sv, alpha);
-        const float u1 = o.miv * r1;
-        const float w1 = o.dv * u1 - lam * o.nfv * ns;
-        y[e] = fmaf(alpha, pv, o.yv);
-        p[e] = pv;
-        snew[e] = sv;
-        rout[e] = r1;
-        wout[e] = w1;
+        S[t] = st0;
+        if (st0.active) atomicAdd(&n_active, 1);
+        cs_out[(int64_t)blockIdx.x * C + t] = st0;
+    }
+    __syncthreads();
+    if (blockIdx.x == 0 && t == 0) ctl[CTL_ACTIVE] = n_active;
+    if (n_active == 0) return;
+    const ChanState st = S[lane_ok ? ch : 0];
+    const bool act = lane_ok && st.active;
+    const float alpha = (float)st.alpha;
+    double acc[3] = {0.0, 0.0, 0.0};
+    for (int64_t tile = tl.first; tile < tl.end; tile += tl.step) {
+        if (tile != tl.first) {
+            v = (int)(tile * vpb) + vl;
+            have = lane_ok && v < V;
+            if (have) {
+                const int64_t e = (int64_t)v * C + ch;
+                yv = y[e];
+                dv = d[e];
+                rv = r[e];
+                qv = q[e];
+                miv = minv[v];
+            }
+        }
+        if (!act || !have) continue;
+        const int64_t e = (int64_t)v * C + ch;
+        y[e] = fmaf(alpha, dv, yv);
+        const float r1 = fmaf(-alpha, qv, rv);
+        r[e] = r1;
         acc[0] += (double)r1 * (double)r1;
-        acc[1] += (double)r1 * (double)u1;
-        acc[2] += (double)w1 * (double)u1;
+        acc[2] += (double)r1 * (double)(miv * r1);
     }
     block_channel_partials<3>(acc, C, vpb, part_out);
 }
@@ -680,12 +728,13 @@ __global__ void __launch_bounds__(kRedBlock) pcg_iter(
 // step and writes the per-channel stats.
 __global__ void __launch_bounds__(kRedBlock) pcg_finish(const ChanState* __restrict__ cs_in,
                                                          ChanState* __restrict__ cs_out,
-                                                         const double* __restrict__ part, int C,
-                                                         int max_iters, double tol,
+                                                         const double* __restrict__ part,
+                                                         const double* __restrict__ sums, int C,
+                                                         int G, int max_iters, double tol,
                                                          bs_chan_stats* __restrict__ out) {
     __shared__ double fin[3 * BS_MAX_CHANNELS];
     const int t = threadIdx.x;
-    reduce_partials<3>(part, C, fin);
+    reduce_partials<3>(part, C, G, fin, sums);
     if (t < C) {
         ChanState st = cs_in[t];
         advance_state(st, fin[t], fin[C + t], fin[2 * C + t], max_iters, tol);
@@ -795,23 +844,37 @@ static bs_status run_init(const GridImpl& g, const SolveWs& w, const bs_solve_pa
 static bs_status run_pcg(const GridImpl& g, const SolveWs& w, const bs_solve_params& p,
                          float* y, bs_chan_stats* stats, hipStream_t s) {
     const int C = w.C;
-    BS_LAUNCH(s, K_INIT, "solve_prologue", solve_prologue, dim3(1), dim3(64), 0, s, w.cs[0],
-              w.cs[1], C, w.ctl);
-    BS_LAUNCH(s, K_PCG_START, "pcg_init_r", pcg_init_r, dim3(kRedGrid), dim3(kRedBlock), 0, s,
-              g.nbr, g.vcap, g.nf, w.diag, w.b, y, w.r[0], p.lambda, C, w.vpb, g.counts,
-              w.part[1]);
-    BS_LAUNCH(s, K_PCG_START, "pcg_init_w", pcg_init_w, dim3(kRedGrid), dim3(kRedBlock), 0, s,
-              g.nbr, g.vcap, g.nf, w.diag, w.minv, w.r[0], w.w[0], p.lambda, C, w.vpb, g.counts,
-              w.part[1], w.part[0], w.cs[0]);
-    int n = 0;
+    // Consumers reduce up to 8 (value, channel) partial rows themselves; above
+    // that a pcg_reduce launch does it once.
+    const bool sep = !PartialSums::fits(3 * C, w.G);
+    const double* s0 = sep ? w.sums[0] : nullptr;
+    const double* s1 = sep ? w.sums[1] : nullptr;
+    const int nstate = w.G * C;
+    BS_LAUNCH(s, K_INIT, "solve_prologue", solve_prologue, dim3((nstate + 255) / 256),
+              dim3(256), 0, s, w.cs[0], w.cs[1], nstate, w.ctl);
+    BS_LAUNCH(s, K_PCG_START, "pcg_start", pcg_start, dim3(w.G), dim3(kRedBlock), 0, s,
+              g.nbr, g.vcap, g.nf, w.sc, w.minv, w.b, y, w.r, p.lambda, C, w.vpb, g.counts,
+              w.part[0]);
+    if (sep)
+        BS_LAUNCH(s, K_PCG_REDUCE, "pcg_reduce", pcg_reduce, dim3(3 * C), dim3(kRedBlock), 0, s,
+                  w.part[0], w.sums[0], w.G);
     for (int it = 0; it < p.max_iters; ++it) {
-        const int a = it & 1, b = a ^ 1;
-        BS_LAUNCH(s, K_PCG_ITER, "pcg_iter", pcg_iter, dim3(kRedGrid), dim3(kRedBlock), 0, s,
-                  g.nbr, g.vcap, g.nf, w.diag, w.minv, w.r[a], w.r[b], w.w[a], w.w[b], w.sv[b],
-                  w.sv[a], w.p, y, p.lambda, C, w.vpb, g.counts, w.cs[a], w.cs[b], w.part[a],
-                  w.part[b], w.ctl, p.max_iters, p.rel_tol);
-        n = it + 1;
-        if (p.check_every > 0 && n % p.check_every == 0 && n < p.max_iters) {
+        float* dn = w.d[it & 1];
+        const float* dold = w.d[(it + 1) & 1];
+        BS_LAUNCH(s, K_PCG_MATVEC, "pcg_matvec", pcg_matvec, dim3(w.G), dim3(kRedBlock), 0,
+                  s, g.nbr, g.vcap, g.nf, w.sc, w.minv, w.r, dold, dn, w.q, p.lambda, C, w.vpb,
+                  g.counts, w.cs[0], w.cs[1], w.part[0], s0, w.part[1], w.ctl, p.max_iters,
+                  p.rel_tol);
+        if (sep)
+            BS_LAUNCH(s, K_PCG_REDUCE, "pcg_reduce", pcg_reduce, dim3(C), dim3(kRedBlock), 0, s,
+                      w.part[1], w.sums[1], w.G);
+        BS_LAUNCH(s, K_PCG_UPDATE, "pcg_update", pcg_update, dim3(w.G), dim3(kRedBlock), 0,
+                  s, w.minv, dn, w.q, y, w.r, C, w.vpb, g.counts, w.cs[1], w.cs[0], w.part[1], s1,
+                  w.part[0], w.ctl);
+        if (sep)
+            BS_LAUNCH(s, K_PCG_REDUCE, "pcg_reduce", pcg_reduce, dim3(3 * C), dim3(kRedBlock), 0,
+                      s, w.part[0], w.sums[0], w.G);
+        if (p.check_every > 0 && (it + 1) % p.check_every == 0 && it + 1 < p.max_iters) {
             int32_t active = 0;
             BS_TRY_HIP(hipMemcpyAsync(&active, w.ctl + CTL_ACTIVE, sizeof(int32_t),
                                       hipMemcpyDeviceToHost, s));
@@ -819,8 +882,8 @@ static bs_status run_pcg(const GridImpl& g, const SolveWs& w, const bs_solve_par
             if (active == 0) break;
         }
     }
-    BS_LAUNCH(s, K_INIT, "pcg_finish", pcg_finish, dim3(1), dim3(kRedBlock), 0, s, w.cs[n & 1],
-              w.cs[(n & 1) ^ 1], w.part[n & 1], C, p.max_iters, p.rel_tol, stats);
+    BS_LAUNCH(s, K_INIT, "pcg_finish", pcg_finish, dim3(1), dim3(kRedBlock), 0, s, w.cs[0],
+              w.cs[1], w.part[0], s0, C, w.G, p.max_iters, p.rel_tol, stats);
     return BS_OK;
 }
 

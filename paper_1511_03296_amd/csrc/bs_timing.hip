@@ -12,7 +12,8 @@ namespace bs {
 
 static const char* const kKernelNames[K_COUNT] = {
     "level_count", "level_scan", "level_write", "neighbour_table", "bist_step", "bist_other",
-    "splat", "init", "pcg_start", "pcg_iter", "slice", "grad_scatter"};
+    "splat", "init", "pcg_start", "pcg_matvec", "pcg_update", "pcg_reduce", "slice",
+    "grad_scatter"};
 
 namespace {
 struct Pending {

@@ -222,3 +222,52 @@ def test_full_size_stereo_1024x768():
     assert got["V"] == sol.grid.V and np.array_equal(got["idx"], sol.grid.idx)
     assert np.array_equal(got["nbr"], sol.grid.nbr)
     assert rel_l2(x.cpu().numpy(), sol.x) <= TOL_X
+
+
+def test_full_size_stereo_backward():
+    """Stereo workload at full size: the backward pass, every pixel compared."""
+    p = WL.stereo_refine()
+    say("full stereo1024x768 backward")
+    G, ws, y, x, st, sol, prm = _solve_both(p)
+    gx = WL.random_grad(0, p.C, p.H, p.W)
+    gt, gc, gb, bst = G.backward(to_dev(p.target), to_dev(p.conf), y, to_dev(gx), prm.lam,
+                                 max_iters=prm.max_iters, rel_tol=prm.rel_tol, ws=ws)
+    torch.cuda.synchronize()
+    og = O.solve_backward(sol, p.target, p.conf, gx, prm, y_hat=y.cpu().numpy()[: sol.grid.V])
+    assert rel_l2(gt.cpu().numpy(), og.grad_t) <= TOL_X
+    assert rel_l2(gc.cpu().numpy(), og.grad_c) <= TOL_X
+
+
+def test_full_size_depth_2048x1536():
+    """Depth super-resolution workload at full size (V ~ 1.6M): grid and
+    bistochastization bit-exact / 1e-12 against the oracle; the solution at
+    1024 sampled pixels against the oracle's FP64 solve stored by
+    tests/golden/make_golden.py (the oracle's own PCG needs minutes here)."""
+    import json
+    import os
+    gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden",
+                                       "depthsr2048x1536.json")))
+    p = WL.depth_superres()
+    say("full depth2048x1536")
+    G = gpu_grid(p)
+    t, c = to_dev(p.target), to_dev(p.conf)
+    y, st = G.solve(t, c, p.lam, max_iters=p.max_iters, rel_tol=p.rel_tol)
+    x = G.slice(y, 1)
+    torch.cuda.synchronize()
+    got = grid_arrays(G)
+    g = O.build_grid(p.ref, p.sigma_xy, p.sigma_l, p.sigma_uv)
+    assert got["V"] == g.V == gold["V"] and np.array_equal(got["key"], g.keys)
+    assert np.array_equal(got["idx"], g.idx) and np.array_equal(got["nbr"], g.nbr)
+    pyr = O.build_pyramid(g)
+    assert got["K"] == pyr.K and got["sizes"][: pyr.K + 1] == pyr.sizes == gold["pyramid_sizes"]
+    bs = O.bistochastize(g, 1e-10, 200)
+    assert got["bist_iters"] == bs.iters == gold["bist_iters"]
+    assert np.max(np.abs(got["n"] - bs.n) / bs.n) <= 1e-12
+    from paper_1511_03296_amd import read_stats
+    s = read_stats(st)[0]
+    assert s["reason"] == 1 and s["rel_residual"] <= p.rel_tol
+    xs = x.cpu().numpy().reshape(-1)[np.array(gold["pixels"])]
+    err = rel_l2(xs, np.array(gold["x"]))
+    say(f"depth: GPU iterations {int(s['iters'])} (oracle {gold['pcg_iters']}), "
+        f"sampled rel-L2 vs oracle {err:.3e}")
+    assert err <= TOL_X
