@@ -36,7 +36,13 @@ WORKLOADS = {
     "depthsr2048x1536": dict(gen="depth_superres", images=1, fwd=(20000, 1e-5),
                              bwd=(20000, 1e-5), grad="conf_weighted"),
     "ramp64x48": dict(gen="tiny_ramp", images=1, fwd=(2000, 1e-5), bwd=(2000, 1e-5)),
-    "seg16x512x512": dict(gen="segmentation", images=16, fwd=(20000, 1e-6), bwd=(20000, 1e-6)),
+    # batched forms: every image of the batch through the batch engine (images
+    # on concurrent library streams); the same images solved one after another
+    # by the single-image path give the "vs plain" ratio
+    "seg16x512x512": dict(gen="segmentation", images=16, batch=True, fwd=(20000, 1e-6),
+                          bwd=(20000, 1e-6)),
+    "mixed64": dict(gen="mixed_batch", images=64, batch=True, fwd=(20000, 1e-5),
+                    bwd=(20000, 1e-5)),
 }
 
 
@@ -51,6 +57,8 @@ def make_problems(name: str):
     import workloads as WL
     spec = WORKLOADS[name]
     gen = getattr(WL, spec["gen"])
+    if spec["gen"] == "mixed_batch":
+        return gen(seed=0, count=spec["images"])
     return [gen(seed=i) for i in range(spec["images"])]
 
 
@@ -71,12 +79,16 @@ def gpu_inputs(problems, spec, dev):
     return out
 
 
-def run_step(inputs, spec, backward=True, keep=None):
-    """One pass of the hot path over every image of the batch."""
+def run_step(inputs, spec, backward=True, keep=None, streams=0):
+    """One pass of the hot path over every image of the batch: through the
+    batch engine on `streams` library streams, or (streams=0) image after
+    image through the single-image path."""
     from paper_1511_03296_amd import BilateralGrid
     (fi, ft), (bi, bt) = spec["fwd"], spec["bwd"]
     fce = 0 if ft == 0.0 else 8
     bce = 0 if bt == 0.0 else 8
+    if streams > 0:
+        return run_batch_step(inputs, spec, backward, keep, streams)
     for d in inputs:
         p = d["p"]
         G = BilateralGrid(d["ref"], p.sigma_xy, p.sigma_l, p.sigma_uv)
@@ -87,20 +99,42 @@ def run_step(inputs, spec, backward=True, keep=None):
             gt, gc, _, bst = G.backward(d["t"], d["c"], y, d["gx"], p.lam, max_iters=bi,
                                         rel_tol=bt, check_every=bce, ws=ws)
         if keep is not None:
-            keep.append((G, st, bst if backward else None))
+            keep.append((G.vertex_count(), st, bst if backward else None))
 
 
-def timed(inputs, spec, steps, backward=True):
+def run_batch_step(inputs, spec, backward, keep, streams):
+    from paper_1511_03296_amd import BatchState, SolveOptions
+    (fi, ft), (bi, bt) = spec["fwd"], spec["bwd"]
+    lam = inputs[0]["p"].lam
+    assert all(d["p"].lam == lam for d in inputs), "one lambda per batch"
+    state = BatchState([d["ref"] for d in inputs], [d["t"] for d in inputs],
+                       [d["c"] for d in inputs],
+                       [(d["p"].sigma_xy, d["p"].sigma_l, d["p"].sigma_uv) for d in inputs],
+                       streams)
+    want = keep is not None
+    fwd = SolveOptions(lam, fi, ft, check_every=0 if ft == 0.0 else 8)
+    bwd = SolveOptions(lam, bi, bt, check_every=0 if bt == 0.0 else 8)
+    _, fst = state.forward(fwd, stats=want)
+    bst = None
+    if backward:
+        _, _, bst = state.backward([d["gx"] for d in inputs], bwd, stats=want)
+    if want:
+        V = state.vertex_counts()
+        for i in range(len(inputs)):
+            keep.append((V[i], fst[i], bst[i] if backward else None))
+
+
+def timed(inputs, spec, steps, backward=True, streams=0):
     import torch
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps):
-        run_step(inputs, spec, backward)
+        run_step(inputs, spec, backward, streams=streams)
     torch.cuda.synchronize()
     return (time.perf_counter() - t0) / steps
 
 
-def kernel_times(inputs, spec, steps):
+def kernel_times(inputs, spec, steps, streams=0):
     """Per-kernel average launch duration (HIP events on the launch stream)."""
     from paper_1511_03296_amd import _lib as L
     import ctypes as ct
@@ -110,7 +144,7 @@ def kernel_times(inputs, spec, steps):
              "grad_scatter"]
     L.check(L.lib.bs_timing_reset(), "timing_reset")
     L.check(L.lib.bs_timing_enable(1), "timing_enable")
-    sec = timed(inputs, spec, steps)
+    sec = timed(inputs, spec, steps, streams=streams)
     L.check(L.lib.bs_timing_enable(0), "timing_enable")
     out = {}
     for n in names:
@@ -158,6 +192,8 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="stereo1024x768", choices=sorted(WORKLOADS))
+    ap.add_argument("--streams", type=int, default=4,
+                    help="library streams of the batch engine (batched workloads)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -189,33 +225,45 @@ def main() -> int:
         torch.cuda.synchronize()
         del src, dst
 
+    streams = args.streams if spec.get("batch") else 0
     keep = []
     for _ in range(max(1, args.warmup)):
         keep.clear()
-        run_step(inputs, spec, True, keep)
-    torch.cuda.synchronize()
+        run_step(inputs, spec, True, keep, streams)
+        torch.cuda.synchronize()
+        print("bench: warmup step done", file=sys.stderr, flush=True)
     from paper_1511_03296_amd import read_stats
-    V = [G.vertex_count() for G, _, _ in keep]
+    V = [v for v, _, _ in keep]
     fwd_iters = [int(read_stats(st)["iters"].max()) for _, st, _ in keep]
     bwd_iters = [int(read_stats(bst)["iters"].max()) for _, _, bst in keep]
     C = problems[0].C
 
     t0 = time.perf_counter()
-    run_step(inputs, spec, True)
+    run_step(inputs, spec, True, streams=streams)
     host_ms = (time.perf_counter() - t0) * 1e3
     torch.cuda.synchronize()
-    print(f"bench: host enqueue of one step {host_ms:.3f} ms", file=sys.stderr, flush=True)
-    sec_fb = timed(inputs, spec, args.steps, backward=True)
-    sec_f = timed(inputs, spec, args.steps, backward=False)
+    print(f"bench: host time of one step's calls {host_ms:.3f} ms", file=sys.stderr, flush=True)
+    sec_fb = timed(inputs, spec, args.steps, backward=True, streams=streams)
+    sec_f = timed(inputs, spec, args.steps, backward=False, streams=streams)
     print(f"bench: fwd+bwd {sec_fb * 1e3:.3f} ms/step, fwd {sec_f * 1e3:.3f} ms/step",
           file=sys.stderr, flush=True)
-    sec_inst, kt = kernel_times(inputs, spec, args.steps)
+    plain = None
+    if streams:
+        sec_plain = timed(inputs, spec, args.steps, backward=True, streams=0)
+        plain = pixels / sec_plain / 1e6
+        print(f"bench: plain single-image path fwd+bwd {sec_plain * 1e3:.3f} ms/step",
+              file=sys.stderr, flush=True)
+    sec_inst, kt = kernel_times(inputs, spec, args.steps, streams)
     mv_ms, mv_launches = kt["pcg_matvec"]
-    avg_us = mv_ms / mv_launches * 1e3 if mv_launches else float("nan")
     # pcg_matvec reads the neighbour table (40 B), n, S c and M^-1 (4 B each)
-    # and r, d (4C B each), and writes the new d and q (4C B each)
-    bytes_per_launch = sum(V) / len(V) * (52 + 16 * C)
-    achieved = bytes_per_launch / (avg_us * 1e-6) / 1e9 if mv_launches else 0.0
+    # and r, d (4C B each), and writes the new d and q (4C B each): algorithmic
+    # bytes of one step's launches over their summed durations.  Launches past
+    # convergence (between stop polls) return at once and count as time only.
+    step_bytes = sum(v * (52 + 16 * p.C) * (fi + bi) for v, p, fi, bi in
+                     zip(V, problems, fwd_iters, bwd_iters))
+    avg_us = mv_ms / mv_launches * 1e3 if mv_launches else float("nan")
+    bytes_per_launch = step_bytes / mv_launches if mv_launches else 0.0
+    achieved = step_bytes / (mv_ms * 1e-3) / 1e9 if mv_launches else 0.0
 
     traffic = None
     if os.path.exists(TRAFFIC_FILE):
@@ -238,14 +286,19 @@ def main() -> int:
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": args.workload, "images": len(problems), "pixels": pixels,
-                   "channels": C, "sigma": [problems[0].sigma_xy, problems[0].sigma_l,
-                                            problems[0].sigma_uv],
+                   "channels": C if len(V) == 1 else [p.C for p in problems],
+                   "sigma": [[p.sigma_xy, p.sigma_l, p.sigma_uv] for p in problems]
+                   if len({p.sigma_xy for p in problems}) > 1
+                   else [problems[0].sigma_xy, problems[0].sigma_l, problems[0].sigma_uv],
                    "lambda": problems[0].lam, "vertices": V[0] if len(V) == 1 else V,
                    "fwd_pcg": list(spec["fwd"]), "bwd_pcg": list(spec["bwd"]),
                    "fwd_iters": fwd_iters[0] if len(V) == 1 else fwd_iters,
                    "bwd_iters": bwd_iters[0] if len(V) == 1 else bwd_iters,
-                   "parallelism": "single-gpu"},
+                   "parallelism": "single-gpu",
+                   "engine": f"batch, {streams} streams" if streams else "single-image"},
         "fwd_mpix_s": round(pixels / sec_f / 1e6, 3),
+        "plain_mpix_s": None if plain is None else round(plain, 3),
+        "vs_plain": None if plain is None else round(pixels / sec_fb / 1e6 / plain, 3),
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic, "kernel": "pcg_matvec",

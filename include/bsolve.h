@@ -206,6 +206,57 @@ bs_status bs_solve_backward(const bs_grid* grid, const float* target, const floa
                             void* stream);
 
 /* ---------------------------------------------------------------------- */
+/* Batches: many images of uneven size and channel count (Section 3's      */
+/* forward and backward over a batch, e.g. a segmentation minibatch).      */
+/* ---------------------------------------------------------------------- */
+
+/* One image of a batch.  All pointers are device pointers except as noted.
+ *  ref [3][H][W], target [C][H][W], conf [H][W]: inputs as for bs_build_grid
+ *      and bs_solve.
+ *  grid_ws, grid_ws_bytes: the image's grid workspace
+ *      (bs_grid_workspace_bytes(H, W, &sigma) bytes), kept by the caller from
+ *      the forward to the backward call.
+ *  y  [Vcap][C]: written by bs_batch_forward, read by bs_batch_backward.
+ *  x  [C][H][W]: the sliced output of bs_batch_forward, or NULL.
+ *  grad_x [C][H][W] in, grad_t [C][H][W] and grad_c [H][W] out: backward.
+ *  stats [C]: per-channel outcome of the image's last solve, or NULL. */
+typedef struct bs_batch_item {
+    const float* ref;
+    const float* target;
+    const float* conf;
+    int32_t H, W, C;
+    bs_grid_params sigma;
+    void* grid_ws;
+    size_t grid_ws_bytes;
+    float* y;
+    float* x;
+    const float* grad_x;
+    float* grad_t;
+    float* grad_c;
+    bs_chan_stats* stats;
+} bs_batch_item;
+
+/* Scratch bytes the batch calls need for `n_streams` concurrent streams
+ * (1..16); 0 for invalid arguments (host, pure). */
+size_t bs_batch_workspace_bytes(const bs_batch_item* items, int32_t n, int32_t n_streams);
+
+/* Forward pass of every image: grid, bistochastization, solve, slice.  Runs
+ * the images on `n_streams` library-owned streams driven by as many host
+ * threads (largest images first), after the work already enqueued on
+ * `stream`; `stream` then waits for the batch.  Returns when every image has
+ * been enqueued (convergence polls synchronise the library's streams only).
+ *  grids  host array [n] receiving the grid handles, for bs_batch_backward. */
+bs_status bs_batch_forward(const bs_batch_item* items, int32_t n, const bs_solve_params* params,
+                           const bs_bistoch_params* bist, bs_grid* grids, int32_t n_streams,
+                           void* ws, size_t ws_bytes, void* stream);
+
+/* Backward pass of every image (as bs_solve_backward) on the grids of a
+ * previous bs_batch_forward with the same items. */
+bs_status bs_batch_backward(const bs_batch_item* items, int32_t n, const bs_grid* grids,
+                            const bs_solve_params* params, int32_t n_streams, void* ws,
+                            size_t ws_bytes, void* stream);
+
+/* ---------------------------------------------------------------------- */
 /* Queries and diagnostics.                                                */
 /* ---------------------------------------------------------------------- */
 

@@ -5,7 +5,8 @@ The solver runs as HIP kernels for gfx950 in ``libbsolve.so`` (C ABI in
 the API loads the library and raises ImportError if it has not been built
 (``python -m paper_1511_03296_amd.build``).
 """
-__all__ = ["BilateralGrid", "SolveOptions", "bilateral_solve", "read_stats"]
+__all__ = ["BilateralGrid", "SolveOptions", "bilateral_solve", "read_stats", "BatchState",
+           "bilateral_solve_batch"]
 
 
 def __getattr__(name):

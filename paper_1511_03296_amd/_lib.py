@@ -61,6 +61,14 @@ class GridView(ct.Structure):
     ]
 
 
+class BatchItem(ct.Structure):
+    _fields_ = [("ref", ct.c_void_p), ("target", ct.c_void_p), ("conf", ct.c_void_p),
+                ("H", ct.c_int32), ("W", ct.c_int32), ("C", ct.c_int32),
+                ("sigma", GridParams), ("grid_ws", ct.c_void_p), ("grid_ws_bytes", ct.c_size_t),
+                ("y", ct.c_void_p), ("x", ct.c_void_p), ("grad_x", ct.c_void_p),
+                ("grad_t", ct.c_void_p), ("grad_c", ct.c_void_p), ("stats", ct.c_void_p)]
+
+
 class BsError(RuntimeError):
     def __init__(self, status: int, where: str, detail: str):
         super().__init__(f"{where}: {detail} (status {status})")
@@ -93,6 +101,11 @@ _SIGS = {
     "bs_grid_get_view": (_i32, [ct.POINTER(Grid), ct.POINTER(GridView)]),
     "bs_solve_ws_view": (_i32, [ct.POINTER(Grid), _i32, _vp, _sz, ct.POINTER(_vp),
                                 ct.POINTER(_vp), ct.POINTER(_vp), ct.POINTER(_vp)]),
+    "bs_batch_workspace_bytes": (_sz, [ct.POINTER(BatchItem), _i32, _i32]),
+    "bs_batch_forward": (_i32, [ct.POINTER(BatchItem), _i32, ct.POINTER(SolveParams),
+                                ct.POINTER(BistochParams), ct.POINTER(Grid), _i32, _vp, _sz, _vp]),
+    "bs_batch_backward": (_i32, [ct.POINTER(BatchItem), _i32, ct.POINTER(Grid),
+                                 ct.POINTER(SolveParams), _i32, _vp, _sz, _vp]),
     "bs_timing_enable": (_i32, [_i32]),
     "bs_timing_reset": (_i32, []),
     "bs_timing_read": (_i32, [ct.c_char_p, ct.POINTER(ct.c_double), ct.POINTER(ct.c_int64)]),

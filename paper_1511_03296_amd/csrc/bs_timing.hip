@@ -1,7 +1,9 @@
 // Optional kernel timing for benchmarks: when enabled, every launch of the
 // library's kernels is bracketed by a pair of hipEvents recorded on the launch
 // stream, and bs_timing_read sums the elapsed times per kernel.  Disabled by
-// default; when disabled the hooks cost one relaxed atomic load.
+// default; when disabled the hooks cost one relaxed atomic load.  The event
+// that opens a launch is kept per host thread, so the batch engine's worker
+// threads may time their streams concurrently.
 #include "bs_internal.h"
 
 #include <atomic>
@@ -25,7 +27,6 @@ struct Timing {
     std::atomic<bool> on{false};
     std::vector<hipEvent_t> pool;
     std::vector<Pending> pending;
-    hipEvent_t open[K_COUNT] = {};
     double total_ms[K_COUNT] = {};
     int64_t launches[K_COUNT] = {};
 };
@@ -56,6 +57,7 @@ bs_status drain(Timing& t) {
     t.pending.clear();
     return BS_OK;
 }
+thread_local hipEvent_t t_open[K_COUNT] = {};
 }  // namespace
 
 void timing_begin(hipStream_t s, int id) {
@@ -63,15 +65,15 @@ void timing_begin(hipStream_t s, int id) {
     if (!t.on.load(std::memory_order_relaxed)) return;
     std::lock_guard<std::mutex> g(t.mu);
     hipEvent_t e = take_event(t);
-    if (e && hipEventRecord(e, s) == hipSuccess) t.open[id] = e;
+    if (e && hipEventRecord(e, s) == hipSuccess) t_open[id] = e;
 }
 
 void timing_end(hipStream_t s, int id) {
     Timing& t = T();
     if (!t.on.load(std::memory_order_relaxed)) return;
     std::lock_guard<std::mutex> g(t.mu);
-    hipEvent_t start = t.open[id];
-    t.open[id] = nullptr;
+    hipEvent_t start = t_open[id];
+    t_open[id] = nullptr;
     if (!start) return;
     hipEvent_t e = take_event(t);
     if (e && hipEventRecord(e, s) == hipSuccess) t.pending.push_back({id, start, e});

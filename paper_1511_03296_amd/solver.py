@@ -233,3 +233,121 @@ def bilateral_solve(grid: BilateralGrid, target: torch.Tensor, conf: torch.Tenso
                rel_tol=rel_tol if bwd_rel_tol is None else bwd_rel_tol, init=init,
                check_every=check_every)
     return _BilateralSolveFn.apply(target, conf, grid, fwd, bwd)
+
+
+class BatchState:
+    """Grids, workspaces and solutions of a batch, kept from forward to backward."""
+
+    def __init__(self, refs, targets, confs, sigmas, n_streams: int):
+        n = len(refs)
+        if not (len(targets) == len(confs) == len(sigmas) == n) or n == 0:
+            raise ValueError("refs, targets, confs and sigmas must have the same non-zero length")
+        self.n, self.n_streams = n, int(n_streams)
+        self.items = (L.BatchItem * n)()
+        self.grids = (L.Grid * n)()
+        self.keep = []
+        self.ys, self.grid_ws = [], []
+        dev = refs[0].device
+        for i, (ref, t, c, sg) in enumerate(zip(refs, targets, confs, sigmas)):
+            H, W = int(ref.shape[1]), int(ref.shape[2])
+            C = int(t.shape[0])
+            ref = _dev_f32(ref, f"refs[{i}]", (3, H, W))
+            t = _dev_f32(t, f"targets[{i}]", (C, H, W))
+            c = _dev_f32(c, f"confs[{i}]", (H, W))
+            gp = L.GridParams(*[int(v) for v in sg])
+            nb = L.lib.bs_grid_workspace_bytes(H, W, ct.byref(gp))
+            if nb == 0:
+                raise ValueError(f"image {i}: " + L.lib.bs_last_error().decode())
+            gws = torch.empty(nb, dtype=torch.uint8, device=dev)
+            vcap = H * W
+            y = torch.empty((vcap, C), dtype=torch.float32, device=dev)
+            it = self.items[i]
+            it.ref, it.target, it.conf = ref.data_ptr(), t.data_ptr(), c.data_ptr()
+            it.H, it.W, it.C, it.sigma = H, W, C, gp
+            it.grid_ws, it.grid_ws_bytes = gws.data_ptr(), nb
+            it.y, it.x, it.grad_x, it.grad_t, it.grad_c, it.stats = y.data_ptr(), None, None, None, None, None
+            self.keep += [ref, t, c]
+            self.ys.append(y)
+            self.grid_ws.append(gws)
+        nbytes = L.lib.bs_batch_workspace_bytes(self.items, n, self.n_streams)
+        if nbytes == 0:
+            raise ValueError("invalid batch")
+        self.ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+        self.shapes = [(int(t.shape[0]), int(r.shape[1]), int(r.shape[2]))
+                       for r, t in zip(refs, targets)]
+        self.device = dev
+
+    def vertex_counts(self) -> list[int]:
+        """V of every image's grid (after forward; synchronises the stream)."""
+        out = []
+        for i in range(self.n):
+            v = ct.c_int32()
+            L.check(L.lib.bs_grid_vertex_count(ct.byref(self.grids[i]), ct.byref(v), _stream()),
+                    "bs_grid_vertex_count")
+            out.append(int(v.value))
+        return out
+
+    def forward(self, opts: SolveOptions, bist_tol=1e-10, bist_max_iters=200, stats=False):
+        xs = [torch.empty(s, dtype=torch.float32, device=self.device) for s in self.shapes]
+        st = [torch.empty(s[0] * _STATS_DTYPE.itemsize, dtype=torch.uint8, device=self.device)
+              for s in self.shapes] if stats else None
+        for i, x in enumerate(xs):
+            self.items[i].x = x.data_ptr()
+            self.items[i].stats = st[i].data_ptr() if stats else None
+        p = opts.struct()
+        b = L.BistochParams(int(bist_max_iters), 8, float(bist_tol))
+        L.check(L.lib.bs_batch_forward(self.items, self.n, ct.byref(p), ct.byref(b), self.grids,
+                                       self.n_streams, self.ws.data_ptr(), self.ws.numel(),
+                                       _stream()), "bs_batch_forward")
+        for i in range(self.n):
+            self.items[i].x = None
+        return xs, st
+
+    def backward(self, grad_xs, opts: SolveOptions, stats=False):
+        gts = [torch.empty(s, dtype=torch.float32, device=self.device) for s in self.shapes]
+        gcs = [torch.empty(s[1:], dtype=torch.float32, device=self.device) for s in self.shapes]
+        st = [torch.empty(s[0] * _STATS_DTYPE.itemsize, dtype=torch.uint8, device=self.device)
+              for s in self.shapes] if stats else None
+        gx_keep = []
+        for i, (g, gt, gc) in enumerate(zip(grad_xs, gts, gcs)):
+            g = _dev_f32(g, f"grad_x[{i}]", self.shapes[i])
+            gx_keep.append(g)
+            it = self.items[i]
+            it.grad_x, it.grad_t, it.grad_c = g.data_ptr(), gt.data_ptr(), gc.data_ptr()
+            it.stats = st[i].data_ptr() if stats else None
+        p = opts.struct()
+        L.check(L.lib.bs_batch_backward(self.items, self.n, self.grids, ct.byref(p),
+                                        self.n_streams, self.ws.data_ptr(), self.ws.numel(),
+                                        _stream()), "bs_batch_backward")
+        return gts, gcs, st
+
+
+class _BatchSolveFn(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, meta, *tensors):
+        n = meta["n"]
+        refs, targets, confs = tensors[:n], tensors[n:2 * n], tensors[2 * n:]
+        state = BatchState(refs, targets, confs, meta["sigmas"], meta["n_streams"])
+        xs, _ = state.forward(meta["fwd"])
+        ctx.state, ctx.meta = state, meta
+        return tuple(xs)
+
+    @staticmethod
+    def backward(ctx, *grad_xs):
+        n = ctx.meta["n"]
+        gts, gcs, _ = ctx.state.backward([g.contiguous() for g in grad_xs], ctx.meta["bwd"])
+        return (None,) + (None,) * n + tuple(gts) + tuple(gcs)
+
+
+def bilateral_solve_batch(refs, targets, confs, sigmas, lam: float, max_iters: int = 25,
+                          rel_tol: float = 0.0, bwd_max_iters: int | None = None,
+                          bwd_rel_tol: float | None = None, init: str = "hier",
+                          n_streams: int = 4):
+    """x_hat for a batch of images of any sizes and channel counts (lists of
+    tensors), differentiable in the targets and confidences."""
+    n = len(refs)
+    meta = dict(n=n, sigmas=[tuple(s) for s in sigmas], n_streams=n_streams,
+                fwd=SolveOptions(lam, max_iters, rel_tol, init),
+                bwd=SolveOptions(lam, max_iters if bwd_max_iters is None else bwd_max_iters,
+                                 rel_tol if bwd_rel_tol is None else bwd_rel_tol, init))
+    return list(_BatchSolveFn.apply(meta, *refs, *targets, *confs))
