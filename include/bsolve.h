@@ -236,22 +236,35 @@ typedef struct bs_batch_item {
     bs_chan_stats* stats;
 } bs_batch_item;
 
-/* Scratch bytes the batch calls need for `n_streams` concurrent streams
- * (1..16); 0 for invalid arguments (host, pure). */
+/* Scratch bytes of the batch calls: every image's solve workspace plus the
+ * batched PCG's tables (independent of n_streams, which must be in 1..16);
+ * 0 for invalid arguments (host, pure).  One workspace serves a forward call
+ * and the backward call that follows it. */
 size_t bs_batch_workspace_bytes(const bs_batch_item* items, int32_t n, int32_t n_streams);
 
-/* Forward pass of every image: grid, bistochastization, solve, slice.  Runs
- * the images on `n_streams` library-owned streams driven by as many host
- * threads (largest images first), after the work already enqueued on
- * `stream`; `stream` then waits for the batch.  Returns when every image has
- * been enqueued (convergence polls synchronise the library's streams only).
- *  grids  host array [n] receiving the grid handles, for bs_batch_backward. */
+/* Forward pass of every image: grid, bistochastization, solve, slice, with
+ * the same params for all images.  The per-image set-up (grid,
+ * bistochastization, splat, initial state) runs on `n_streams` library-owned
+ * streams driven by as many host threads, largest images first.  The PCG
+ * then runs over all images together: images with the same lane width
+ * (C = 1; C = 2; C >= 3) share one launch per PCG phase, each image keeping
+ * its own per-channel stopping rule.  Everything is ordered after the work
+ * already enqueued on `stream`, and the PCG, slices and copies run on
+ * `stream`.  Returns after enqueueing the slices; the call synchronises
+ * `stream` while it runs (vertex counts, convergence polls).  Results match
+ * bs_solve per image to the solver's tolerance (the block-partial sums run in
+ * another order) and are deterministic for a given batch.
+ *  grids  host array [n] receiving the grid handles, for bs_batch_backward.
+ * Errors: BS_EINVAL for a bad item or parameter (the message names the item),
+ * BS_EWORKSPACE for a short or misaligned (256 bytes) workspace. */
 bs_status bs_batch_forward(const bs_batch_item* items, int32_t n, const bs_solve_params* params,
                            const bs_bistoch_params* bist, bs_grid* grids, int32_t n_streams,
                            void* ws, size_t ws_bytes, void* stream);
 
-/* Backward pass of every image (as bs_solve_backward) on the grids of a
- * previous bs_batch_forward with the same items. */
+/* Backward pass of every image (as bs_solve_backward: splat of grad_x,
+ * adjoint PCG, gradient scatter) on the grids of a previous bs_batch_forward
+ * with the same items, y holding the forward solutions; batched as the
+ * forward call. */
 bs_status bs_batch_backward(const bs_batch_item* items, int32_t n, const bs_grid* grids,
                             const bs_solve_params* params, int32_t n_streams, void* ws,
                             size_t ws_bytes, void* stream);
@@ -271,10 +284,15 @@ bs_status bs_grid_vertex_count(const bs_grid* grid, int32_t* V, void* stream);
 bs_status bs_grid_get_view(const bs_grid* grid, bs_grid_view* view);
 
 /* Device pointers into a solve workspace, valid after bs_solve: the splatted
- * right-hand side b [Vcap][C] (after bs_solve_backward: u = S dL/dx), S c
- * [Vcap], diag(A) [Vcap] and the Jacobi inverse [Vcap] (host only; for
- * inspection and tests).  Run bs_solve with max_iters = 0 to obtain the
- * initial state y0 in y. */
+ * right-hand side b [Vcap][Cs] with Cs = bs_solve_channel_stride(C) (after
+ * bs_solve_backward: u = S dL/dx; channels C..Cs-1 are zero), S c [Vcap],
+ * diag(A) [Vcap] and the Jacobi inverse [Vcap] (host only; for inspection and
+ * tests).  Run bs_solve with max_iters = 0 to obtain the initial state y0 in
+ * y. */
+/* Channel stride of the solver's internal [V][Cs] vectors for C channels: C
+ * for C <= 2, else C rounded up to a multiple of 4 (0 for C outside 1..64). */
+int32_t bs_solve_channel_stride(int32_t C);
+
 bs_status bs_solve_ws_view(const bs_grid* grid, int32_t C, void* ws, size_t ws_bytes,
                            const float** b, const float** sc, const float** diag,
                            const float** minv);

@@ -99,6 +99,7 @@ _SIGS = {
     "bs_read_counters": (_i32, [ct.POINTER(Grid), ct.POINTER(_i32), _i32, _vp]),
     "bs_grid_vertex_count": (_i32, [ct.POINTER(Grid), ct.POINTER(_i32), _vp]),
     "bs_grid_get_view": (_i32, [ct.POINTER(Grid), ct.POINTER(GridView)]),
+    "bs_solve_channel_stride": (_i32, [_i32]),
     "bs_solve_ws_view": (_i32, [ct.POINTER(Grid), _i32, _vp, _sz, ct.POINTER(_vp),
                                 ct.POINTER(_vp), ct.POINTER(_vp), ct.POINTER(_vp)]),
     "bs_batch_workspace_bytes": (_sz, [ct.POINTER(BatchItem), _i32, _i32]),

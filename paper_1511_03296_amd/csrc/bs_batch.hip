@@ -1,13 +1,19 @@
-// Batch engine: many images of uneven size and channel count solved
-// concurrently.  A small pool of host threads, each owning one HIP stream,
-// takes images from a shared queue (largest first) and runs the per-image
-// path on its stream: grid build, bistochastization, solve, slice (forward)
-// or splat, adjoint solve, gradient scatter (backward).  The single-image
-// kernels are latency-bound below ~10^5 vertices, so images on different
-// streams overlap on the device; each thread's convergence polls only block
-// its own stream.  The batch is ordered after the caller's stream and the
-// caller's stream waits for it, so the calls compose with stream-ordered work.
-#include "bs_internal.h"
+// Batch engine: many images of uneven size and channel count solved together.
+//
+// Per-image set-up runs concurrently: a small pool of host threads, each owning
+// one HIP stream, takes images from a shared queue (largest first) and builds
+// the grid, bistochastizes it, splats the right-hand side and computes the
+// initial state.  The PCG then runs over all images at once: images that share
+// a lane width (1, 2 or 4 channels per lane) form a group whose every PCG
+// phase is ONE launch, each block working on one image through a block-to-image
+// table, each image with its own channel state, partials and stopping rule;
+// blocks of stopped images return at once.  Small images, which alone are
+// latency-bound, thus share launches with large ones.  Finally each image's
+// solution is sliced (forward) or its gradients scattered (backward).
+//
+// The batch is ordered after the caller's stream and the caller's stream
+// waits for it, so the calls compose with stream-ordered work.
+#include "bs_solve_impl.h"
 
 #include <algorithm>
 #include <atomic>
@@ -21,6 +27,7 @@ namespace bs {
 namespace {
 
 constexpr int kMaxStreams = 16;
+constexpr int kTilesPerBlock = 4;   // PCG tiles per block of a batched launch
 
 struct StreamPool {
     std::mutex mu;
@@ -54,12 +61,32 @@ bs_status ensure_pool(int n, int device) {
     return BS_OK;
 }
 
-size_t item_solve_bytes(const bs_batch_item& it) {
+// Grid of an item as laid out (sizes only), for workspace sizing.
+GridImpl sized_grid(const bs_batch_item& it) {
     GridImpl g;
+    std::memset(&g, 0, sizeof(g));
     layout_grid(g, it.H, it.W, it.sigma, nullptr);
-    bs_grid tmp;
-    std::memcpy(tmp.opaque, &g, sizeof(g));
-    return bs_solve_workspace_bytes(&tmp, it.C);
+    return g;
+}
+
+size_t item_solve_bytes(const bs_batch_item& it) {
+    const GridImpl g = sized_grid(it);
+    SolveWs w;
+    return align_up(layout_solve(g, it.C, kRedGridMax, nullptr, w), 256);
+}
+
+// Device tables of the batched PCG: images (grouped), block-to-image map and
+// active counters.
+size_t table_bytes(int n) {
+    return align_up((size_t)n * sizeof(PcgImage), 256) +
+           align_up((size_t)n * kRedGridMax * sizeof(int32_t), 256) +
+           align_up((size_t)n * sizeof(int32_t), 256);
+}
+
+size_t batch_bytes(const bs_batch_item* items, int n) {
+    size_t total = table_bytes(n);
+    for (int i = 0; i < n; ++i) total += item_solve_bytes(items[i]);
+    return total;
 }
 
 bs_status validate_items(const bs_batch_item* items, int n, int n_streams, bool backward) {
@@ -75,30 +102,27 @@ bs_status validate_items(const bs_batch_item* items, int n, int n_streams, bool 
         if (!it.grid_ws || it.grid_ws_bytes < need)
             return fail(BS_EWORKSPACE, tag + "grid workspace needs " + std::to_string(need));
         if (!it.ref || !it.target || !it.conf || !it.y) return fail(BS_EINVAL, tag + "NULL input");
+        if (((uintptr_t)it.target | (uintptr_t)it.conf | (uintptr_t)it.y) & 3)
+            return fail(BS_EINVAL, tag + "misaligned buffer");
         if (backward && (!it.grad_x || !it.grad_t || !it.grad_c))
             return fail(BS_EINVAL, tag + "NULL gradient buffer");
     }
     return BS_OK;
 }
 
-// Runs `work(item, stream, ws)` for every item on n_streams worker threads.
+// Runs `work(item, stream)` for every item on n_streams worker threads, each
+// with its own stream, ordered after `cs` and joined back into it.
 template <class Work>
-bs_status run_pool(const bs_batch_item* items, int n, int n_streams, void* ws, size_t ws_bytes,
-                   size_t per_stream, void* caller_stream, Work work) {
+bs_status for_each_item(const bs_batch_item* items, int n, int n_streams, hipStream_t cs,
+                        Work work) {
     int device = 0;
     BS_TRY_HIP(hipGetDevice(&device));
     StreamPool& p = pool();
     std::lock_guard<std::mutex> lock(p.mu);
     bs_status st = ensure_pool(n_streams, device);
     if (st != BS_OK) return st;
-    if (((uintptr_t)ws & 255) != 0) return fail(BS_EINVAL, "workspace must be 256-byte aligned");
-    if (ws_bytes < per_stream * n_streams)
-        return fail(BS_EWORKSPACE,
-                    "batch workspace needs " + std::to_string(per_stream * n_streams) + " bytes");
-    hipStream_t cs = (hipStream_t)caller_stream;
     BS_TRY_HIP(hipEventRecord(p.start, cs));
     for (int s = 0; s < n_streams; ++s) BS_TRY_HIP(hipStreamWaitEvent(p.streams[s], p.start, 0));
-
     // largest images first
     std::vector<int> order(n);
     std::iota(order.begin(), order.end(), 0);
@@ -113,13 +137,12 @@ bs_status run_pool(const bs_batch_item* items, int n, int n_streams, void* ws, s
     std::string first_msg;
     auto worker = [&](int s) {
         hipSetDevice(device);
-        void* mine = (char*)ws + per_stream * s;
         for (;;) {
             if (failed.load()) return;
             const int k = next.fetch_add(1);
             if (k >= n) return;
             const int i = order[k];
-            const bs_status r = work(i, p.streams[s], mine, per_stream);
+            const bs_status r = work(i, p.streams[s]);
             if (r != BS_OK) {
                 std::lock_guard<std::mutex> g(err_mu);
                 if (first_err == BS_OK) {
@@ -143,10 +166,104 @@ bs_status run_pool(const bs_batch_item* items, int n, int n_streams, void* ws, s
     return BS_OK;
 }
 
-size_t per_stream_bytes(const bs_batch_item* items, int n) {
-    size_t m = 0;
-    for (int i = 0; i < n; ++i) m = std::max(m, item_solve_bytes(items[i]));
-    return align_up(m, 256);
+// Per-image solve state of a batch call.
+struct Plan {
+    SolveWs w;
+    float* yw;   // solution (forward) or adjoint solution (backward), stride Cp
+};
+
+// Carves every image's solve workspace after the tables (the layout depends
+// only on the image size, grid scales and channel count).
+bs_status carve(const bs_batch_item* items, int n, void* ws, size_t ws_bytes,
+                std::vector<Plan>& plans) {
+    if (((uintptr_t)ws & 255) != 0) return fail(BS_EINVAL, "workspace must be 256-byte aligned");
+    const size_t need = batch_bytes(items, n);
+    if (!ws || ws_bytes < need)
+        return fail(BS_EWORKSPACE, "batch workspace needs " + std::to_string(need) + " bytes");
+    plans.assign(n, Plan{});
+    size_t off = table_bytes(n);
+    for (int i = 0; i < n; ++i) {
+        const GridImpl g = sized_grid(items[i]);
+        off += align_up(layout_solve(g, items[i].C, kRedGridMax, (char*)ws + off, plans[i].w), 256);
+        plans[i].yw = nullptr;
+    }
+    return BS_OK;
+}
+
+// The batched PCG over every image: groups by lane width, one launch per
+// phase and group; groups run one after another on `cs`.
+bs_status batched_pcg(const bs_batch_item* items, int n, const bs_grid* grids,
+                      std::vector<Plan>& plans, const bs_solve_params& p, void* ws,
+                      hipStream_t cs) {
+    // vertex counts decide each image's share of blocks
+    std::vector<int32_t> V(n);
+    for (int i = 0; i < n; ++i)
+        BS_TRY_HIP(hipMemcpyAsync(&V[i], impl(&grids[i])->counts + CNT_V, sizeof(int32_t),
+                                  hipMemcpyDeviceToHost, cs));
+    BS_TRY_HIP(hipStreamSynchronize(cs));
+
+    char* base = (char*)ws;
+    PcgImage* d_imgs = (PcgImage*)base;
+    int32_t* d_blk = (int32_t*)(base + align_up((size_t)n * sizeof(PcgImage), 256));
+    int32_t* d_act = (int32_t*)((char*)d_blk + align_up((size_t)n * kRedGridMax * sizeof(int32_t), 256));
+
+    struct Group {
+        int K, first, count, G, max_cp;
+        size_t blk_first;
+    };
+    std::vector<PcgImage> imgs;
+    std::vector<int32_t> blk;
+    std::vector<Group> groups;
+    for (int K : {4, 2, 1}) {
+        Group gr{K, (int)imgs.size(), 0, 0, 0, blk.size()};
+        for (int i = 0; i < n; ++i) {
+            Plan& pl = plans[i];
+            if (pl.w.K != K) continue;
+            const GridImpl& g = *impl(&grids[i]);
+            const int Lv = pl.w.Cp / K, vpb = kRedBlock / Lv;
+            const int64_t tiles = ceil_div(std::max<int32_t>(V[i], 1), vpb);
+            int nb = (int)ceil_div(ceil_div(tiles, kTilesPerBlock), kXcds) * kXcds;
+            nb = std::min(std::max(nb, kXcds), kRedGridMax);
+            pl.w.nb = nb;
+            PcgImage I = make_image(g, pl.w, p.lambda, pl.yw, items[i].stats);
+            I.active = d_act + imgs.size();
+            I.block0 = gr.G;
+            for (int b = 0; b < nb; ++b) blk.push_back(gr.count);
+            gr.G += nb;
+            gr.max_cp = std::max(gr.max_cp, pl.w.Cp);
+            gr.count += 1;
+            imgs.push_back(I);
+        }
+        if (gr.count > 0) groups.push_back(gr);
+    }
+    // the block map holds each group's local image indices
+    BS_TRY_HIP(hipMemcpyAsync(d_imgs, imgs.data(), imgs.size() * sizeof(PcgImage),
+                              hipMemcpyHostToDevice, cs));
+    BS_TRY_HIP(hipMemcpyAsync(d_blk, blk.data(), blk.size() * sizeof(int32_t),
+                              hipMemcpyHostToDevice, cs));
+    // the host vectors must outlive the copies
+    BS_TRY_HIP(hipStreamSynchronize(cs));
+    for (const Group& gr : groups) {
+        const bs_status st =
+            run_pcg(gr.K, imgs.data() + gr.first, gr.count, d_imgs + gr.first,
+                    d_blk + gr.blk_first, gr.G, gr.max_cp, p, d_act + gr.first, cs);
+        if (st != BS_OK) return st;
+    }
+    return BS_OK;
+}
+
+bs_status check_params(const bs_solve_params* p) {
+    if (!p) return fail(BS_EINVAL, "NULL params");
+    if (!(p->lambda >= 0.0f) || !std::isfinite(p->lambda))
+        return fail(BS_EINVAL, "lambda must be finite and >= 0");
+    if (p->init != BS_INIT_FLAT && p->init != BS_INIT_HIER) return fail(BS_EINVAL, "unknown init");
+    if (p->max_iters < 0 || p->check_every < 0) return fail(BS_EINVAL, "negative iteration count");
+    if (!(p->rel_tol >= 0.0)) return fail(BS_EINVAL, "rel_tol must be >= 0");
+    if (p->init == BS_INIT_HIER && !(p->init_alpha > 0.0f && std::isfinite(p->init_alpha)))
+        return fail(BS_EINVAL, "init_alpha must be positive");
+    if (p->init == BS_INIT_HIER && !std::isfinite(p->init_beta))
+        return fail(BS_EINVAL, "init_beta must be finite");
+    return BS_OK;
 }
 
 }  // namespace
@@ -161,7 +278,7 @@ extern "C" size_t bs_batch_workspace_bytes(const bs_batch_item* items, int32_t n
         if (items[i].C < 1 || items[i].C > BS_MAX_CHANNELS ||
             bs_grid_workspace_bytes(items[i].H, items[i].W, &items[i].sigma) == 0)
             return 0;
-    return per_stream_bytes(items, n) * n_streams;
+    return batch_bytes(items, n);
 }
 
 extern "C" bs_status bs_batch_forward(const bs_batch_item* items, int32_t n,
@@ -171,22 +288,43 @@ extern "C" bs_status bs_batch_forward(const bs_batch_item* items, int32_t n,
                                       void* stream) {
     bs_status st = validate_items(items, n, n_streams, false);
     if (st != BS_OK) return st;
-    if (!params || !grids) return fail(BS_EINVAL, "NULL params or grid array");
-    const size_t per = per_stream_bytes(items, n);
-    return run_pool(items, n, n_streams, ws, ws_bytes, per, stream,
-                    [&](int i, hipStream_t s, void* mine, size_t mine_bytes) -> bs_status {
-                        const bs_batch_item& it = items[i];
-                        bs_status r = bs_build_grid(it.ref, it.H, it.W, &it.sigma, it.grid_ws,
-                                                    it.grid_ws_bytes, s, &grids[i]);
-                        if (r != BS_OK) return r;
-                        r = bs_bistochastize(&grids[i], bist, s);
-                        if (r != BS_OK) return r;
-                        r = bs_solve(&grids[i], it.target, it.conf, it.C, params, it.y, mine,
-                                     mine_bytes, it.stats, s);
-                        if (r != BS_OK) return r;
-                        if (it.x) r = bs_slice(&grids[i], it.y, it.C, it.x, s);
-                        return r;
-                    });
+    st = check_params(params);
+    if (st != BS_OK) return st;
+    if (!grids) return fail(BS_EINVAL, "NULL grid array");
+    const bs_solve_params& p = *params;
+    hipStream_t cs = (hipStream_t)stream;
+    std::vector<Plan> plans;
+    st = carve(items, n, ws, ws_bytes, plans);
+    if (st != BS_OK) return st;
+    // set-up per image: grid, bistochastization, splat and initial state
+    st = for_each_item(items, n, n_streams, cs, [&](int i, hipStream_t s) -> bs_status {
+        const bs_batch_item& it = items[i];
+        bs_status r = bs_build_grid(it.ref, it.H, it.W, &it.sigma, it.grid_ws, it.grid_ws_bytes, s,
+                                    &grids[i]);
+        if (r != BS_OK) return r;
+        r = bs_bistochastize(&grids[i], bist, s);
+        if (r != BS_OK) return r;
+        const GridImpl& g = *impl(&grids[i]);
+        Plan& pl = plans[i];
+        pl.yw = (pl.w.Cp == it.C && ((uintptr_t)it.y & 15) == 0) ? it.y : pl.w.yi;
+        return solve_setup(g, pl.w, it.conf, it.target, true, p, pl.yw, s);
+    });
+    if (st != BS_OK) return st;
+    st = batched_pcg(items, n, grids, plans, p, ws, cs);
+    if (st != BS_OK) return st;
+    for (int i = 0; i < n; ++i) {
+        const bs_batch_item& it = items[i];
+        const GridImpl& g = *impl(&grids[i]);
+        if (plans[i].yw != it.y) {
+            st = copy_unpadded(g, plans[i].yw, it.C, plans[i].w.Cp, it.y, cs);
+            if (st != BS_OK) return st;
+        }
+        if (it.x) {
+            st = bs_slice(&grids[i], it.y, it.C, it.x, cs);
+            if (st != BS_OK) return st;
+        }
+    }
+    return BS_OK;
 }
 
 extern "C" bs_status bs_batch_backward(const bs_batch_item* items, int32_t n,
@@ -195,13 +333,32 @@ extern "C" bs_status bs_batch_backward(const bs_batch_item* items, int32_t n,
                                        void* stream) {
     bs_status st = validate_items(items, n, n_streams, true);
     if (st != BS_OK) return st;
-    if (!params || !grids) return fail(BS_EINVAL, "NULL params or grid array");
-    const size_t per = per_stream_bytes(items, n);
-    return run_pool(items, n, n_streams, ws, ws_bytes, per, stream,
-                    [&](int i, hipStream_t s, void* mine, size_t mine_bytes) -> bs_status {
-                        const bs_batch_item& it = items[i];
-                        return bs_solve_backward(&grids[i], it.target, it.conf, it.y, it.grad_x,
-                                                 it.C, params, it.grad_t, it.grad_c, nullptr,
-                                                 mine, mine_bytes, it.stats, s);
-                    });
+    st = check_params(params);
+    if (st != BS_OK) return st;
+    if (!grids) return fail(BS_EINVAL, "NULL grid array");
+    for (int i = 0; i < n; ++i)
+        if (impl(&grids[i])->magic != kGridMagic || !impl(&grids[i])->bistochastized)
+            return fail(BS_EINVAL, "item " + std::to_string(i) + ": grid was not built");
+    const bs_solve_params& p = *params;
+    hipStream_t cs = (hipStream_t)stream;
+    std::vector<Plan> plans;
+    st = carve(items, n, ws, ws_bytes, plans);
+    if (st != BS_OK) return st;
+    // set-up per image: splat of dL/dx and initial state of the adjoint solve
+    st = for_each_item(items, n, n_streams, cs, [&](int i, hipStream_t s) -> bs_status {
+        const bs_batch_item& it = items[i];
+        Plan& pl = plans[i];
+        pl.yw = pl.w.yi;
+        return solve_setup(*impl(&grids[i]), pl.w, it.conf, it.grad_x, false, p, pl.yw, s);
+    });
+    if (st != BS_OK) return st;
+    st = batched_pcg(items, n, grids, plans, p, ws, cs);
+    if (st != BS_OK) return st;
+    for (int i = 0; i < n; ++i) {
+        const bs_batch_item& it = items[i];
+        st = grad_scatter_launch(*impl(&grids[i]), plans[i].yw, plans[i].w.Cp, it.y, it.target,
+                                 it.conf, it.C, it.grad_t, it.grad_c, cs);
+        if (st != BS_OK) return st;
+    }
+    return BS_OK;
 }

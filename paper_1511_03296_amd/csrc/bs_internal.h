@@ -194,11 +194,13 @@ size_t layout_grid(GridImpl& g, int H, int W, const bs_grid_params& sp, void* ba
 // vertices their stencils gather) share one L2.
 struct XcdTiles {
     int64_t first, step, end;
-    __device__ XcdTiles(int64_t T) {
-        const int G = gridDim.x;
-        const int xcd = blockIdx.x % kXcds;
-        const int local = blockIdx.x / kXcds;
-        const int per = G / kXcds;
+    __device__ XcdTiles(int64_t T) : XcdTiles(T, blockIdx.x, gridDim.x) {}
+    // Block j of nb blocks working on one image (j % 8 is the block's die:
+    // the image's first block and nb are multiples of 8).
+    __device__ XcdTiles(int64_t T, int j, int nb) {
+        const int xcd = j % kXcds;
+        const int local = j / kXcds;
+        const int per = nb / kXcds;
         const int64_t chunk = (T + kXcds - 1) / kXcds;
         first = (int64_t)xcd * chunk + local;
         int64_t e = (int64_t)(xcd + 1) * chunk;
@@ -207,11 +209,12 @@ struct XcdTiles {
     }
 };
 
-// Slot of this block's partial result: blocks of one die get consecutive
-// slots, so a cache line of partials is written from one die only.
-__device__ inline int partial_slot() {
-    return (blockIdx.x % kXcds) * (gridDim.x / kXcds) + blockIdx.x / kXcds;
+// Slot of block j's partial result among nb: blocks of one die get
+// consecutive slots, so a cache line of partials is written from one die only.
+__device__ inline int partial_slot(int j, int nb) {
+    return (j % kXcds) * (nb / kXcds) + j / kXcds;
 }
+__device__ inline int partial_slot() { return partial_slot(blockIdx.x, gridDim.x); }
 
 __device__ inline double wave_sum(double v) {
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);

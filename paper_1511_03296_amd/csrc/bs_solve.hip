@@ -1,11 +1,13 @@
 // The bilateral-space solve (paper Eq. quad_min and Eq. solution, supplement
 // Algorithm 2, Section 4 initialisation) and its backward pass (Section 3).
 //
-// Layouts: pixel planes [C][P] float32; bilateral-space vectors [V][C]
-// float32, channels contiguous per vertex.  A thread of the vertex kernels
-// owns one (vertex, channel) element: a block covers vpb = 256 / C vertices of
-// all C channels, so the neighbour table is read once per vertex and the
-// channel gathers of one neighbour are contiguous.
+// Layouts: pixel planes [C][P] float32; bilateral-space vectors [V][Cp]
+// float32, channels contiguous per vertex, with the channel stride Cp padded
+// to a multiple of 4 when C >= 3 (padding channels hold zeros and never
+// iterate).  A lane of the vertex kernels owns K = 1, 2 or 4 consecutive
+// channels of one vertex (one float, float2 or float4 access); Lv = Cp / K
+// lanes cover a vertex, so the neighbour table and the per-vertex scalars are
+// read by Lv lanes rather than by every channel.
 //
 // PCG (supplement Algorithm 2) runs one independent PCG per channel.  One
 // iteration is two kernels, each with one grid-wide reduction:
@@ -20,130 +22,158 @@
 // sparse).  Dot products accumulate in float64; the next kernel reduces the
 // per-block partials in its prologue in a fixed order, so results are
 // deterministic and no host synchronisation is needed.
-#include "bs_internal.h"
+//
+// The PCG kernels take either one image or a table of images: a batch of
+// images of any sizes runs each PCG phase as one launch, every block working
+// on one image (a per-block image table), each image with its own channel
+// state, partials and stopping rule.
+#include "bs_solve_impl.h"
 
 namespace bs {
 
-// One record per 128-byte cache line: each block reads back its own record,
-// written by the block of the same index (same die) in the previous launch.
-// With 48- or 64-byte records a line held records of blocks on two dies and
-// that read cost ~12 us per launch on MI355X.
-struct alignas(128) ChanState {
-    double rho, alpha, beta, bnorm, res;
-    int32_t active, iters, reason, phase;   // phase 0: initial residual not yet reduced
-};
-static_assert(sizeof(ChanState) == 128, "one record per cache line");
+enum Ctl : int { CTL_SIZE = 8 };
 
-enum Ctl : int { CTL_ACTIVE = 0, CTL_SIZE = 8 };
-
-// Partials of the reducing kernels: [2 slots][3 values][C][G].
-//   slot 0 -- pcg_start (r^T r, b^T b, r^T M^-1 r), pcg_update (r^T r, 0, r^T M^-1 r);
-//   slot 1 -- pcg_matvec (d^T q).
-// Per-channel state, double-buffered the same way: pcg_matvec reads state 0
-// and writes state 1, pcg_update reads state 1 and writes state 0.  Every
-// block computes the same state from the same partials and keeps its own copy
-// (slot [block][C]): block b always runs on die b % 8, so its copy stays in
-// that die's L2, whereas reading one copy written by another die's block cost
-// ~12 us per launch.
-struct SolveWs {
-    int C, vpb, G;
-    float* sc;
-    float* diag;
-    float* minv;
-    float* b;
-    float* r;
-    float* d[2];
-    float* q;
-    float* g;
-    float* up[BS_MAX_LEVELS];
-    ChanState* cs[2];
-    double* part[2];
-    double* sums[2];     // [3][C] reduced partials when pcg_reduce is used
-    int32_t* ctl;
-    size_t bytes;
-};
-
-static size_t layout_solve(const GridImpl& g, int C, void* base, SolveWs& w) {
+size_t layout_solve(const GridImpl& g, int C, int nb, void* base, SolveWs& w) {
     w.C = C;
-    w.vpb = kRedBlock / C;
-    w.G = red_grid(g.vcap * C);
+    w.Cp = padded_channels(C);
+    w.K = lane_width(C);
+    w.nb = nb > 0 ? nb : solve_blocks(g, C);
     Carver c(base);
-    const int64_t n = g.vcap * C;
+    const int64_t n = g.vcap * w.Cp;
     w.sc = c.take<float>(g.vcap);
     w.diag = c.take<float>(g.vcap);
     w.minv = c.take<float>(g.vcap);
+    w.nfm = c.take<float2>(g.vcap);
     w.b = c.take<float>(n);
     w.r = c.take<float>(n);
     w.d[0] = c.take<float>(n);
     w.d[1] = c.take<float>(n);
     w.q = c.take<float>(n);
-    w.g = c.take<float>(n);
+    w.yi = c.take<float>(n);
     w.up[0] = nullptr;
     for (int k = 1; k < BS_MAX_LEVELS; ++k)
-        w.up[k] = (k < g.levels) ? c.take<float>(g.lv[k].cap * (C + 1)) : nullptr;
-    w.cs[0] = c.take<ChanState>((int64_t)kRedGridMax * C);
-    w.cs[1] = c.take<ChanState>((int64_t)kRedGridMax * C);
-    w.part[0] = c.take<double>((int64_t)3 * C * kRedGridMax);
-    w.part[1] = c.take<double>((int64_t)3 * C * kRedGridMax);
-    w.sums[0] = c.take<double>(3 * C);
-    w.sums[1] = c.take<double>(3 * C);
-    w.ctl = c.take<int32_t>(CTL_SIZE);
+        w.up[k] = (k < g.levels) ? c.take<float>(g.lv[k].cap * (w.Cp + 1)) : nullptr;
+    w.cs[0] = c.take<ChanRec>((int64_t)w.nb * w.Cp);
+    w.cs[1] = c.take<ChanRec>((int64_t)w.nb * w.Cp);
+    w.part[0] = c.take<double>((int64_t)3 * w.Cp * w.nb);
+    w.part[1] = c.take<double>((int64_t)3 * w.Cp * w.nb);
+    w.sums[0] = c.take<double>(3 * w.Cp);
+    w.sums[1] = c.take<double>(3 * w.Cp);
+    w.act = c.take<int32_t>(CTL_SIZE);
     w.bytes = align_up(c.off, 256);
     return w.bytes;
 }
 
+int solve_blocks(const GridImpl& g, int C) {
+    return red_grid(g.vcap * (padded_channels(C) / lane_width(C)));
+}
+
 // ---------------------------------------------------------------------------
-// Reductions over (vertex, channel) blocks.
+// K-wide lane values.
+// ---------------------------------------------------------------------------
+template <int K>
+struct Vec {
+    float v[K];
+};
+
+template <int K>
+__device__ inline Vec<K> ldv(const float* __restrict__ p) {
+    Vec<K> o;
+    if constexpr (K == 4) {
+        const float4 t = *reinterpret_cast<const float4*>(p);
+        o.v[0] = t.x;
+        o.v[1] = t.y;
+        o.v[2] = t.z;
+        o.v[3] = t.w;
+    } else if constexpr (K == 2) {
+        const float2 t = *reinterpret_cast<const float2*>(p);
+        o.v[0] = t.x;
+        o.v[1] = t.y;
+    } else {
+        o.v[0] = *p;
+    }
+    return o;
+}
+
+template <int K>
+__device__ inline void stv(float* __restrict__ p, const Vec<K>& a) {
+    if constexpr (K == 4) {
+        *reinterpret_cast<float4*>(p) = make_float4(a.v[0], a.v[1], a.v[2], a.v[3]);
+    } else if constexpr (K == 2) {
+        *reinterpret_cast<float2*>(p) = make_float2(a.v[0], a.v[1]);
+    } else {
+        *p = a.v[0];
+    }
+}
+
+// Lane geometry of one image: lane t owns channels [g K, g K + K) of the
+// tile's vertex vl.
+struct Lanes {
+    int Lv, vpb, vl, g;
+    bool ok;
+    __device__ Lanes(int Cp, int K) {
+        Lv = Cp / K;
+        vpb = kRedBlock / Lv;
+        vl = (int)threadIdx.x / Lv;
+        g = (int)threadIdx.x - vl * Lv;
+        ok = vl < vpb;
+    }
+};
+
+// ---------------------------------------------------------------------------
+// Reductions over the lanes of a block.
 // ---------------------------------------------------------------------------
 
-// Sums NV per-thread values over the vertices of the block, per channel, with
-// a fixed tree, and writes the block's partials to part[(k C + ch) G + block]
-// (G = gridDim.x).
-template <int NV>
-__device__ inline void block_channel_partials(const double (&acc)[NV], int C, int vpb,
-                                              double* __restrict__ part) {
+// Sums NV x K per-lane values over the vertices of the block, per channel,
+// with a fixed tree, and writes the block's partials to
+// part[(k Cp + ch) nb + slot].
+template <int NV, int K>
+__device__ inline void lane_partials(const double (&acc)[NV][K], const Lanes& ln, int Cp,
+                                     int nb, int slot, double* __restrict__ part) {
     const int t = threadIdx.x;
-    if (C == 1) {
-        // one channel: shuffle trees per wave, then one pass over the waves
-        __shared__ double red[NV][kRedBlock / 64];
-        double v[NV];
+    if (ln.Lv == 1) {
+        // one lane per vertex: shuffle trees per wave, then one pass over the waves
+        __shared__ double red[NV * K][kRedBlock / 64];
+        double v[NV * K];
 #pragma unroll
-        for (int k = 0; k < NV; ++k) v[k] = wave_sum(acc[k]);
+        for (int i = 0; i < NV * K; ++i) v[i] = wave_sum(acc[i / K][i % K]);
         __syncthreads();
         if ((t & 63) == 0) {
 #pragma unroll
-            for (int k = 0; k < NV; ++k) red[k][t >> 6] = v[k];
+            for (int i = 0; i < NV * K; ++i) red[i][t >> 6] = v[i];
         }
         __syncthreads();
-        if (t < NV) {
+        if (t < NV * K) {
             double s = 0.0;
             for (int w = 0; w < kRedBlock / 64; ++w) s += red[t][w];
-            part[(int64_t)t * gridDim.x + partial_slot()] = s;
+            part[((int64_t)(t / K) * Cp + t % K) * nb + slot] = s;
         }
         return;
     }
-    __shared__ double s[NV][kRedBlock];
+    // one tree for all NV x K values: every index below is a constant
+    __shared__ double s[NV * K][kRedBlock];
 #pragma unroll
-    for (int k = 0; k < NV; ++k) s[k][t] = acc[k];
+    for (int i = 0; i < NV * K; ++i) s[i][t] = acc[i / K][i % K];
     __syncthreads();
-    int n = vpb;
+    int n = ln.vpb;
     while (n > 1) {
         const int h = (n + 1) >> 1;
-        if (t < (n - h) * C) {
+        if (t < (n - h) * ln.Lv) {
 #pragma unroll
-            for (int k = 0; k < NV; ++k) s[k][t] += s[k][t + h * C];
+            for (int i = 0; i < NV * K; ++i) s[i][t] += s[i][t + h * ln.Lv];
         }
         __syncthreads();
         n = h;
     }
-    if (t < C) {
+    if (t < ln.Lv) {
 #pragma unroll
-        for (int k = 0; k < NV; ++k) part[((int64_t)k * C + t) * gridDim.x + partial_slot()] = s[k][t];
+        for (int i = 0; i < NV * K; ++i)
+            part[((int64_t)(i / K) * Cp + t * K + i % K) * nb + slot] = s[i][t];
     }
 }
 
-// out[k C + ch] = sum over the G blocks of the producer's partials,
-// computed identically by every block.  The NV C sums are spread over the
+// out[k Cp + ch] = sum over the nb blocks of the producer's partials,
+// computed identically by every block.  The pair sums are spread over the
 // block: q lanes (a power of two <= 64, so a group lies in one wave) share a
 // sum, each adding every q-th partial, then a shuffle tree over the group.
 // Loading (load) and summing (sum) are split so that callers can issue other
@@ -159,13 +189,14 @@ struct PartialSums {
     // Lanes per pair for `pairs` sums over G partials, and whether each lane's
     // share fits in registers (the host uses the same rule to decide when to
     // run pcg_reduce instead).
-    __host__ __device__ static int lanes(int pairs) {
+    // (q divides G, so that the q lanes of a sum share its G partials evenly.)
+    __host__ __device__ static int lanes(int pairs, int G) {
         int q = 64;
-        while (q > 1 && q * pairs > kRedBlock) q >>= 1;
+        while (q > 1 && (q * pairs > kRedBlock || G % q != 0)) q >>= 1;
         return q;
     }
     __host__ __device__ static bool fits(int pairs, int G) {
-        const int q = lanes(pairs);
+        const int q = lanes(pairs, G);
         return pairs * q <= kRedBlock && G / q <= kMax;
     }
 
@@ -178,7 +209,7 @@ struct PartialSums {
             if ((int)threadIdx.x < pairs) v[0] = pre[threadIdx.x];
             return;
         }
-        q = lanes(pairs);
+        q = lanes(pairs, G);
         pair = threadIdx.x / q;
         seg = threadIdx.x - pair * q;
         held = fits(pairs, G);
@@ -214,83 +245,96 @@ struct PartialSums {
 };
 
 template <int NV>
-__device__ inline void reduce_partials(const double* __restrict__ part, int C, int G,
+__device__ inline void reduce_partials(const double* __restrict__ part, int Cp, int G,
                                        double* out, const double* __restrict__ sums = nullptr) {
     PartialSums ps;
-    ps.load(part, NV * C, G, sums);
+    ps.load(part, NV * Cp, G, sums);
     ps.sum(part, out);
 }
 
-// With many channels the per-block partials are reduced once, by one block per
-// (value, channel) pair, rather than redundantly in every consumer block.
-__global__ void __launch_bounds__(kRedBlock) pcg_reduce(const double* __restrict__ part,
-                                                         double* __restrict__ sums, int G) {
-    double v = 0.0;
-    for (int i = threadIdx.x; i < G; i += kRedBlock) v += part[(int64_t)blockIdx.x * G + i];
-    const double s = block_sum<kRedBlock>(v);
-    if (threadIdx.x == 0) sums[blockIdx.x] = s;
+// Field-wise copies of a channel state: whole-struct copies leave parts of
+// the state in private memory (spilled to LDS or scratch).
+__device__ inline ChanState load_state(const ChanState& r) {
+    ChanState s;
+    s.rho = r.rho;
+    s.alpha = r.alpha;
+    s.beta = r.beta;
+    s.bnorm = r.bnorm;
+    s.res = r.res;
+    s.active = r.active;
+    s.iters = r.iters;
+    s.reason = r.reason;
+    s.phase = r.phase;
+    return s;
+}
+
+__device__ inline void store_state(ChanState& d, const ChanState& s) {
+    d.rho = s.rho;
+    d.alpha = s.alpha;
+    d.beta = s.beta;
+    d.bnorm = s.bnorm;
+    d.res = s.res;
+    d.active = s.active;
+    d.iters = s.iters;
+    d.reason = s.reason;
+    d.phase = s.phase;
+}
+
+__device__ inline ChanState zero_state() {
+    ChanState z;
+    z.rho = z.alpha = z.beta = z.bnorm = z.res = 0.0;
+    z.active = z.iters = z.reason = z.phase = 0;
+    return z;
 }
 
 // Completes the previous PCG step of one channel from the reduced slot-0
 // partials: the initial residual (phase 0) or the end of an iteration, with
 // the stopping rule and the next beta.
-__device__ inline void advance_state(ChanState& st, double rr, double bb, double rho_new,
-                                     int max_iters, double tol) {
+__device__ inline ChanState advance_state(const ChanState& st, double rr, double bb,
+                                          double rho_new, int max_iters, double tol) {
+    ChanState o = load_state(st);
+    if (st.phase != 0 && !st.active) return o;
     int reason = 0;
     if (st.phase == 0) {
-        st.phase = 1;
-        st.bnorm = sqrt(bb);
-        st.rho = rho_new;
-        st.beta = 0.0;
-        st.iters = 0;
-        if (bb == 0.0) {
-            st.res = 0.0;
-            reason = 5;
-        } else {
-            st.res = sqrt(rr) / st.bnorm;
-            if (st.res <= tol) reason = 1;
-            else if (max_iters <= 0) reason = 2;
-            else if (rho_new == 0.0) reason = 3;
-        }
+        o.phase = 1;
+        o.bnorm = sqrt(bb);
+        o.rho = rho_new;
+        o.beta = 0.0;
+        o.iters = 0;
+        o.res = bb == 0.0 ? 0.0 : sqrt(rr) / o.bnorm;
+        if (bb == 0.0) reason = 5;
+        else if (o.res <= tol) reason = 1;
+        else if (max_iters <= 0) reason = 2;
+        else if (rho_new == 0.0) reason = 3;
     } else {
-        if (!st.active) return;
-        st.beta = rho_new / st.rho;
-        st.rho = rho_new;
-        st.iters += 1;
-        st.res = sqrt(rr) / st.bnorm;
-        if (st.res <= tol) reason = 1;
-        else if (st.iters >= max_iters) reason = 2;
+        o.beta = rho_new / st.rho;
+        o.rho = rho_new;
+        o.iters = st.iters + 1;
+        o.res = sqrt(rr) / st.bnorm;
+        if (o.res <= tol) reason = 1;
+        else if (o.iters >= max_iters) reason = 2;
         else if (rho_new == 0.0) reason = 3;
     }
-    st.active = reason == 0;
-    if (reason) st.reason = reason;
+    o.active = reason == 0;
+    o.reason = reason ? reason : st.reason;
+    return o;
 }
 
 // ---------------------------------------------------------------------------
-// Kernels.
+// Splat and initialisation (per image).
 // ---------------------------------------------------------------------------
-
-__global__ void solve_prologue(ChanState* cs0, ChanState* cs1, int n, int32_t* ctl) {
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t < CTL_SIZE) ctl[t] = 0;
-    if (t < n) {
-        ChanState z;
-        z.rho = z.alpha = z.beta = z.bnorm = z.res = 0.0;
-        z.active = z.iters = z.reason = z.phase = 0;
-        cs0[t] = z;
-        cs1[t] = z;
-    }
-}
 
 // S c, b = S (v o t) (or S t when `weighted` is false) as ascending-pixel sums
-// in float64, and diag(A) = lam n o (N n) + S c with its Jacobi inverse.
+// in float64, diag(A) = lam n o (N n) + S c with its Jacobi inverse, and the
+// packed per-vertex scalars {n, 1 / diag(A)} of the PCG kernels.  b has
+// stride Cp; channels C..Cp-1 are zero.
 template <bool WEIGHTED>
 __global__ void __launch_bounds__(kBlock) splat_kernel(
     const int32_t* __restrict__ ptr, const int32_t* __restrict__ list,
-    const float* __restrict__ conf, const float* __restrict__ vals, int C, int P,
-    const double* __restrict__ nn, double lam, const int32_t* __restrict__ counts,
-    float* __restrict__ sc_out, float* __restrict__ diag_out, float* __restrict__ minv_out,
-    float* __restrict__ b) {
+    const float* __restrict__ conf, const float* __restrict__ vals, int C, int Cp, int P,
+    const double* __restrict__ nn, const float* __restrict__ nf, double lam,
+    const int32_t* __restrict__ counts, float* __restrict__ sc_out, float* __restrict__ diag_out,
+    float* __restrict__ minv_out, float2* __restrict__ nfm, float* __restrict__ b) {
     const int V = counts[CNT_V];
     const XcdTiles tl((V + kBlock - 1) / kBlock);
     for (int64_t tile = tl.first; tile < tl.end; tile += tl.step) {
@@ -311,12 +355,15 @@ __global__ void __launch_bounds__(kBlock) splat_kernel(
             }
 #pragma unroll
             for (int k = 0; k < 8; ++k)
-                if (k < cn) b[(int64_t)v * C + c0 + k] = (float)acc[k];
+                if (k < cn) b[(int64_t)v * Cp + c0 + k] = (float)acc[k];
         }
+        for (int c = C; c < Cp; ++c) b[(int64_t)v * Cp + c] = 0.0f;
         const double d = lam * nn[v] + sc;
+        const float mi = d > 0.0 ? (float)(1.0 / d) : 0.0f;
         sc_out[v] = (float)sc;
         diag_out[v] = (float)d;
-        minv_out[v] = d > 0.0 ? (float)(1.0 / d) : 0.0f;
+        minv_out[v] = mi;
+        nfm[v] = make_float2(nf[v], mi);
     }
 }
 
@@ -331,8 +378,9 @@ __global__ void __launch_bounds__(B) splat_cells(
     int H, int W, int sxy, int ncx, const int32_t* __restrict__ cell_vbase,
     const int32_t* __restrict__ cell_ibase, const int32_t* __restrict__ ptr,
     const int32_t* __restrict__ list, const float* __restrict__ conf,
-    const float* __restrict__ vals, int C, int P, const double* __restrict__ nn, double lam,
-    float* __restrict__ sc_out, float* __restrict__ diag_out, float* __restrict__ minv_out,
+    const float* __restrict__ vals, int C, int Cp, int P, const double* __restrict__ nn,
+    const float* __restrict__ nf, double lam, float* __restrict__ sc_out,
+    float* __restrict__ diag_out, float* __restrict__ minv_out, float2* __restrict__ nfm,
     float* __restrict__ b) {
     __shared__ float cv[CAP];
     __shared__ int32_t lst[CAP];
@@ -356,9 +404,11 @@ __global__ void __launch_bounds__(B) splat_cells(
         double sc = 0.0;
         for (int q = s0; q < s1; ++q) sc += (double)cv[lst[q]];
         const double d = lam * nn[vbase + k] + sc;
+        const float mi = d > 0.0 ? (float)(1.0 / d) : 0.0f;
         sc_out[vbase + k] = (float)sc;
         diag_out[vbase + k] = (float)d;
-        minv_out[vbase + k] = d > 0.0 ? (float)(1.0 / d) : 0.0f;
+        minv_out[vbase + k] = mi;
+        nfm[vbase + k] = make_float2(nf[vbase + k], mi);
     }
     const int CH = max(1, min(C, kSplatVals / max(n, 1)));
     for (int c0 = 0; c0 < C; c0 += CH) {
@@ -378,31 +428,36 @@ __global__ void __launch_bounds__(B) splat_cells(
                 const int jl = lst[q];
                 acc += WEIGHTED ? (double)cv[jl] * (double)tv[cc * n + jl] : (double)tv[cc * n + jl];
             }
-            b[(int64_t)(vbase + k) * C + c0 + cc] = (float)acc;
+            b[(int64_t)(vbase + k) * Cp + c0 + cc] = (float)acc;
         }
+    }
+    const int pad = Cp - C;
+    for (int e = threadIdx.x; e < cnt * pad; e += B) {
+        const int k = e / pad, cc = e - k * pad;
+        b[(int64_t)(vbase + k) * Cp + C + cc] = 0.0f;
     }
 }
 
 // Launches the splat: per cell when a cell's pixels fit the LDS staging,
 // otherwise per vertex.
 template <bool WEIGHTED>
-static bs_status launch_splat(const GridImpl& g, const float* conf, const float* vals, int C,
-                              double lam, float* sc, float* diag, float* minv, float* b,
-                              hipStream_t s) {
+static bs_status launch_splat(const GridImpl& g, const SolveWs& w, const float* conf,
+                              const float* vals, double lam, hipStream_t s) {
     const Level& L = g.lv[0];
     const int items = g.sg.sigma_xy * g.sg.sigma_xy;
     const int ncells = L.ncx * L.ncy;
 #define BS_SPLAT_CELLS(B, CAP)                                                                  \
     BS_LAUNCH(s, K_SPLAT, "splat_cells", (splat_cells<B, CAP, WEIGHTED>), dim3(ncells), dim3(B), \
               0, s, g.H, g.W, g.sg.sigma_xy, L.ncx, L.cell_vbase, L.cell_ibase, L.ptr, L.list,   \
-              conf, vals, C, g.P, g.nn, lam, sc, diag, minv, b)
+              conf, vals, w.C, w.Cp, g.P, g.nn, g.nf, lam, w.sc, w.diag, w.minv, w.nfm, w.b)
     if (items <= 64) BS_SPLAT_CELLS(64, 64);
     else if (items <= 256) BS_SPLAT_CELLS(256, 256);
     else if (items <= 1024) BS_SPLAT_CELLS(256, 1024);
     else {
         const int vblocks = grid_blocks(ceil_div(g.vcap, kBlock));
         BS_LAUNCH(s, K_SPLAT, "splat", splat_kernel<WEIGHTED>, dim3(vblocks), dim3(kBlock), 0, s,
-                  L.ptr, L.list, conf, vals, C, g.P, g.nn, lam, g.counts, sc, diag, minv, b);
+                  L.ptr, L.list, conf, vals, w.C, w.Cp, g.P, g.nn, g.nf, lam, g.counts, w.sc,
+                  w.diag, w.minv, w.nfm, w.b);
     }
 #undef BS_SPLAT_CELLS
     return BS_OK;
@@ -500,76 +555,125 @@ __global__ void __launch_bounds__(kBlock) hier_final(const float* __restrict__ b
     }
 }
 
-// r = b - A y0, one (vertex, channel) element per thread; partials r^T r,
-// b^T b, r^T M^-1 r.
-__global__ void __launch_bounds__(kRedBlock) pcg_start(
-    const int32_t* __restrict__ nbr, int64_t vcap, const float* __restrict__ nf,
-    const float* __restrict__ sc, const float* __restrict__ minv, const float* __restrict__ b,
-    const float* __restrict__ y, float* __restrict__ r, float lam, int C, int vpb,
-    const int32_t* __restrict__ counts, double* __restrict__ part) {
-    const int V = counts[CNT_V];
-    const int t = threadIdx.x;
-    const int vl = t / C, ch = t - vl * C;
-    const bool lane_ok = vl < vpb;
-    double acc[3] = {0.0, 0.0, 0.0};
-    const XcdTiles tl((V + vpb - 1) / vpb);
-    for (int64_t tile = tl.first; tile < tl.end; tile += tl.step) {
-        const int v = (int)(tile * vpb) + vl;
-        if (!lane_ok || v >= V) continue;
-        const int64_t e = (int64_t)v * C + ch;
-        const float yv = y[e];
-        float ns = 0.0f;
-#pragma unroll
-        for (int j = 0; j < 10; ++j) {
-            const int u = nbr[j * vcap + v];
-            if (u >= 0) ns += nf[u] * (yv - y[(int64_t)u * C + ch]);
-        }
-        const float ay = sc[v] * yv + lam * nf[v] * ns;
-        const float bv = b[e];
-        const float rv = bv - ay;
-        r[e] = rv;
-        acc[0] += (double)rv * (double)rv;
-        acc[1] += (double)bv * (double)bv;
-        acc[2] += (double)rv * (double)(minv[v] * rv);
+// ---------------------------------------------------------------------------
+// PCG kernels.  Each takes one image (MULTI false, by value) or a table of
+// images with the image of every block (MULTI true).
+// ---------------------------------------------------------------------------
+
+template <bool MULTI>
+__device__ inline const PcgImage& block_image(const PcgArgs& a, int& jb) {
+    if constexpr (MULTI) {
+        const PcgImage& I = a.imgs[a.blk2img[blockIdx.x]];
+        jb = (int)blockIdx.x - I.block0;
+        return I;
+    } else {
+        jb = (int)blockIdx.x;
+        return a.one;
     }
-    block_channel_partials<3>(acc, C, vpb, part);
 }
 
-// Operands of one (vertex, channel) element of pcg_matvec.  Loading them does
-// not depend on the iteration's scalars, so the first tile's loads are issued
-// before the prologue and overlap its reduction.
-struct MatvecOperands {
+// Clears the channel state; the image is active until its first stop test.
+template <bool MULTI>
+__global__ void __launch_bounds__(kRedBlock) pcg_prologue(PcgArgs a) {
+    int jb;
+    const PcgImage& I = block_image<MULTI>(a, jb);
+    const int t = threadIdx.x;
+    if (t < I.Cp) {
+        const ChanState z = zero_state();
+        store_state(I.cs[0][(int64_t)jb * I.Cp + t].s, z);
+        store_state(I.cs[1][(int64_t)jb * I.Cp + t].s, z);
+    }
+    if (jb == 0 && t == 0) *I.active = 1;
+}
+
+// r = b - A y0; partials r^T r, b^T b, r^T M^-1 r.
+template <int K, bool MULTI>
+__global__ void __launch_bounds__(kRedBlock) pcg_start(PcgArgs a) {
+    int jb;
+    const PcgImage& I = block_image<MULTI>(a, jb);
+    const int V = I.counts[CNT_V];
+    const int Cp = I.Cp, nb = I.nb;
+    const Lanes ln(Cp, K);
+    const float lam = I.lam;
+    double acc[3][K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) acc[0][k] = acc[1][k] = acc[2][k] = 0.0;
+    const XcdTiles tl((V + ln.vpb - 1) / ln.vpb, jb, nb);
+    for (int64_t tile = tl.first; tile < tl.end; tile += tl.step) {
+        const int v = (int)(tile * ln.vpb) + ln.vl;
+        if (!ln.ok || v >= V) continue;
+        const int64_t e = (int64_t)v * Cp + ln.g * K;
+        const Vec<K> yv = ldv<K>(I.y + e);
+        float ns[K];
+#pragma unroll
+        for (int k = 0; k < K; ++k) ns[k] = 0.0f;
+#pragma unroll
+        for (int j = 0; j < 10; ++j) {
+            const int u = I.nbr[j * I.vcap + v];
+            if (u >= 0) {
+                const float nu = I.nfm[u].x;
+                const Vec<K> yu = ldv<K>(I.y + (int64_t)u * Cp + ln.g * K);
+#pragma unroll
+                for (int k = 0; k < K; ++k) ns[k] += nu * (yv.v[k] - yu.v[k]);
+            }
+        }
+        const float2 nmv = I.nfm[v];
+        const float scv = I.sc[v];
+        const Vec<K> bv = ldv<K>(I.b + e);
+        Vec<K> rv;
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const float ay = scv * yv.v[k] + lam * nmv.x * ns[k];
+            rv.v[k] = bv.v[k] - ay;
+            acc[0][k] += (double)rv.v[k] * (double)rv.v[k];
+            acc[1][k] += (double)bv.v[k] * (double)bv.v[k];
+            acc[2][k] += (double)rv.v[k] * (double)(nmv.y * rv.v[k]);
+        }
+        stv<K>(I.r + e, rv);
+    }
+    lane_partials<3, K>(acc, ln, Cp, nb, partial_slot(jb, nb), I.part[0]);
+}
+
+// Operands of one lane of pcg_matvec.  Loading them does not depend on the
+// iteration's scalars, so the first tile's loads are issued before the
+// prologue and overlap its reduction.
+template <int K>
+struct MatOps {
     int v;
     int nb[10];
-    float r[10], d[10], mi[10], nf[10];
-    float rv, dv, miv, scv, nfv;
+    Vec<K> r[10], d[10];
+    float2 nm[10];
+    Vec<K> rv, dv;
+    float2 nmv;
+    float scv;
 };
 
-__device__ inline bool load_matvec(MatvecOperands& o, int64_t tile, int vpb, int vl, int ch,
-                                   int C, int V, int64_t vcap, const int32_t* __restrict__ nbr,
-                                   const float* __restrict__ nf, const float* __restrict__ sc,
-                                   const float* __restrict__ minv, const float* __restrict__ r,
-                                   const float* __restrict__ dold) {
-    o.v = (int)(tile * vpb) + vl;
-    if (o.v >= V) return false;
+// Neighbour indices of vertex v (phase 1 of a tile's loads).
+__device__ inline void load_nbr(int (&nb)[10], int v, const PcgImage& I) {
 #pragma unroll
-    for (int j = 0; j < 10; ++j) o.nb[j] = nbr[j * vcap + o.v];
+    for (int j = 0; j < 10; ++j) nb[j] = I.nbr[j * I.vcap + v];
+}
+
+// The gathers and per-vertex operands of vertex v (phase 2).
+template <int K>
+__device__ inline void load_ops(MatOps<K>& o, int v, const int (&nb)[10], const Lanes& ln,
+                                const PcgImage& I, const float* __restrict__ dold) {
+    o.v = v;
+    const int Cp = I.Cp;
 #pragma unroll
     for (int j = 0; j < 10; ++j) {
-        const int u = o.nb[j] >= 0 ? o.nb[j] : o.v;
-        const int64_t eu = (int64_t)u * C + ch;
-        o.r[j] = r[eu];
-        o.d[j] = dold[eu];
-        o.mi[j] = minv[u];
-        o.nf[j] = nf[u];
+        o.nb[j] = nb[j];
+        const int u = nb[j] >= 0 ? nb[j] : v;
+        const int64_t eu = (int64_t)u * Cp + ln.g * K;
+        o.r[j] = ldv<K>(I.r + eu);
+        o.d[j] = ldv<K>(dold + eu);
+        o.nm[j] = I.nfm[u];
     }
-    const int64_t e = (int64_t)o.v * C + ch;
-    o.rv = r[e];
-    o.dv = dold[e];
-    o.miv = minv[o.v];
-    o.scv = sc[o.v];
-    o.nfv = nf[o.v];
-    return true;
+    const int64_t e = (int64_t)v * Cp + ln.g * K;
+    o.rv = ldv<K>(I.r + e);
+    o.dv = ldv<K>(dold + e);
+    o.nmv = I.nfm[v];
+    o.scv = I.sc[v];
 }
 
 // New search direction of one element: M^-1 r + beta d_old (M^-1 r first).
@@ -580,106 +684,145 @@ __device__ inline float pcg_dir(float r, float d_old, float mi, float beta, bool
 
 // Prologue: finish the previous step (stopping rule, beta) from the slot-0
 // partials.  Then d = M^-1 r + beta d_old, q = A d and partials of d^T q.
-__global__ void __launch_bounds__(kRedBlock) pcg_matvec(
-    const int32_t* __restrict__ nbr, int64_t vcap, const float* __restrict__ nf,
-    const float* __restrict__ sc, const float* __restrict__ minv, const float* __restrict__ r,
-    const float* __restrict__ dold, float* __restrict__ dnew, float* __restrict__ q, float lam,
-    int C, int vpb, const int32_t* __restrict__ counts, const ChanState* __restrict__ cs_in,
-    ChanState* __restrict__ cs_out, const double* __restrict__ part_in,
-    const double* __restrict__ sums_in, double* __restrict__ part_out,
-    int32_t* __restrict__ ctl, int max_iters, double tol) {
+// Iteration `it` writes d[it % 2] and reads d[(it + 1) % 2].
+template <int K, bool MULTI>
+__global__ void __launch_bounds__(kRedBlock) pcg_matvec(PcgArgs a, int it) {
     __shared__ ChanState S[BS_MAX_CHANNELS];
     __shared__ double fin[3 * BS_MAX_CHANNELS];
     __shared__ int n_active;
+    int jb;
+    const PcgImage& I = block_image<MULTI>(a, jb);
+    if constexpr (MULTI) {
+        if (*I.active == 0) return;   // stopped image
+    }
     const int t = threadIdx.x;
-    const int V = counts[CNT_V];
-    const int vl = t / C, ch = t - vl * C;
-    const bool lane_ok = vl < vpb;
-    const XcdTiles tl((V + vpb - 1) / vpb);
+    const int V = I.counts[CNT_V];
+    const int Cp = I.Cp, nb = I.nb;
+    const Lanes ln(Cp, K);
+    const float* dold = I.d[(it + 1) & 1];
+    float* dnew = I.d[it & 1];
+    const XcdTiles tl((V + ln.vpb - 1) / ln.vpb, jb, nb);
     // Loads complete in issue order: partials and state first, then the first
     // tile's operands, which stay in flight during the reduction.
     PartialSums ps;
-    ps.load(part_in, 3 * C, gridDim.x, sums_in);
-    ChanState st0;
-    if (t < C) st0 = cs_in[(int64_t)blockIdx.x * C + t];
-    MatvecOperands o;
-    bool have = lane_ok && tl.first < tl.end &&
-                load_matvec(o, tl.first, vpb, vl, ch, C, V, vcap, nbr, nf, sc, minv, r, dold);
-    ps.sum(part_in, fin);
+    ps.load(I.part[0], 3 * Cp, nb, I.sums[0]);
+    // every lane loads a record (lanes >= Cp a duplicate): a conditional load
+    // merged with a default would be waited for before the operand loads
+    ChanState st0 = load_state(I.cs[0][(int64_t)jb * Cp + min(t, Cp - 1)].s);
+    MatOps<K> o;
+    int nbn[10];
+    int v = (int)(tl.first * ln.vpb) + ln.vl;
+    bool have = ln.ok && tl.first < tl.end && v < V;
+    if (have) {
+        load_nbr(nbn, v, I);
+        load_ops<K>(o, v, nbn, ln, I, dold);
+    }
+    ps.sum(I.part[0], fin);
     if (t == 0) n_active = 0;
     __syncthreads();
-    if (t < C) {
-        advance_state(st0, fin[t], fin[C + t], fin[2 * C + t], max_iters, tol);
-        S[t] = st0;
+    if (t < Cp) {
+        st0 = advance_state(st0, fin[t], fin[Cp + t], fin[2 * Cp + t], a.max_iters, a.tol);
+        store_state(S[t], st0);
         if (st0.active) atomicAdd(&n_active, 1);
-        cs_out[(int64_t)blockIdx.x * C + t] = st0;
+        store_state(I.cs[1][(int64_t)jb * Cp + t].s, st0);
     }
     __syncthreads();
-    if (blockIdx.x == 0 && t == 0) ctl[CTL_ACTIVE] = n_active;
+    if (jb == 0 && t == 0) *I.active = n_active;
     if (n_active == 0) return;
-    const ChanState st = S[lane_ok ? ch : 0];
-    const bool act = lane_ok && st.active;
-    const bool first = st.iters == 0;
-    const float beta = (float)st.beta;
-    double acc[1] = {0.0};
-    for (int64_t tile = tl.first; tile < tl.end; tile += tl.step) {
-        if (tile != tl.first)
-            have = lane_ok &&
-                   load_matvec(o, tile, vpb, vl, ch, C, V, vcap, nbr, nf, sc, minv, r, dold);
-        if (!act || !have) continue;
-        const float dv = pcg_dir(o.rv, o.dv, o.miv, beta, first);
-        float ns = 0.0f;
+    float beta[K];
+    bool first[K], act[K];
+    bool any = false;
 #pragma unroll
-        for (int j = 0; j < 10; ++j) {
-            if (o.nb[j] >= 0) ns += o.nf[j] * (dv - pcg_dir(o.r[j], o.d[j], o.mi[j], beta, first));
-        }
-        const float qv = o.scv * dv + lam * o.nfv * ns;
-        const int64_t e = (int64_t)o.v * C + ch;
-        dnew[e] = dv;
-        q[e] = qv;
-        acc[0] += (double)dv * (double)qv;
+    for (int k = 0; k < K; ++k) {
+        const ChanState& s = S[ln.ok ? ln.g * K + k : 0];
+        beta[k] = (float)s.beta;
+        first[k] = s.iters == 0;
+        act[k] = ln.ok && s.active;
+        any = any || act[k];
     }
-    block_channel_partials<1>(acc, C, vpb, part_out);
+    const float lam = I.lam;
+    double acc[1][K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) acc[0][k] = 0.0;
+    // Software pipeline over the block's tiles: the next tile's neighbour
+    // indices are loaded before this tile's arithmetic waits for its gathers,
+    // and its gathers are issued as soon as this tile is stored.
+    for (int64_t tile = tl.first; tile < tl.end; tile += tl.step) {
+        const int64_t nt = tile + tl.step;
+        const int vn = (int)(nt * ln.vpb) + ln.vl;
+        const bool hn = any && ln.ok && nt < tl.end && vn < V;
+        if (hn) load_nbr(nbn, vn, I);
+        if (any && have) {
+            Vec<K> dv, qv;
+#pragma unroll
+            for (int k = 0; k < K; ++k)
+                dv.v[k] = pcg_dir(o.rv.v[k], o.dv.v[k], o.nmv.y, beta[k], first[k]);
+            float ns[K];
+#pragma unroll
+            for (int k = 0; k < K; ++k) ns[k] = 0.0f;
+#pragma unroll
+            for (int j = 0; j < 10; ++j) {
+                if (o.nb[j] >= 0) {
+#pragma unroll
+                    for (int k = 0; k < K; ++k)
+                        ns[k] += o.nm[j].x *
+                                 (dv.v[k] - pcg_dir(o.r[j].v[k], o.d[j].v[k], o.nm[j].y, beta[k], first[k]));
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < K; ++k) qv.v[k] = o.scv * dv.v[k] + lam * o.nmv.x * ns[k];
+            const int64_t e = (int64_t)o.v * Cp + ln.g * K;
+            stv<K>(dnew + e, dv);
+            stv<K>(I.q + e, qv);
+#pragma unroll
+            for (int k = 0; k < K; ++k)
+                if (act[k]) acc[0][k] += (double)dv.v[k] * (double)qv.v[k];
+        }
+        if (hn) load_ops<K>(o, vn, nbn, ln, I, dold);
+        have = hn;
+    }
+    lane_partials<1, K>(acc, ln, Cp, nb, partial_slot(jb, nb), I.part[1]);
 }
 
 // Prologue: alpha = r^T M^-1 r / d^T q from the slot-1 partials (a channel
 // with d^T q <= 0 stops).  Then y += alpha d, r -= alpha q and partials of
-// r^T r and r^T M^-1 r.
-__global__ void __launch_bounds__(kRedBlock) pcg_update(
-    const float* __restrict__ minv, const float* __restrict__ d, const float* __restrict__ q,
-    float* __restrict__ y, float* __restrict__ r, int C, int vpb,
-    const int32_t* __restrict__ counts, const ChanState* __restrict__ cs_in,
-    ChanState* __restrict__ cs_out, const double* __restrict__ part_in,
-    const double* __restrict__ sums_in, double* __restrict__ part_out,
-    int32_t* __restrict__ ctl) {
+// r^T r and r^T M^-1 r.  Stopped channels keep their values.
+template <int K, bool MULTI>
+__global__ void __launch_bounds__(kRedBlock) pcg_update(PcgArgs a, int it) {
     __shared__ ChanState S[BS_MAX_CHANNELS];
     __shared__ double fin[BS_MAX_CHANNELS];
     __shared__ int n_active;
-    const int t = threadIdx.x;
-    const int V = counts[CNT_V];
-    const int vl = t / C, ch = t - vl * C;
-    const bool lane_ok = vl < vpb;
-    const XcdTiles tl((V + vpb - 1) / vpb);
-    PartialSums ps;
-    ps.load(part_in, C, gridDim.x, sums_in);
-    ChanState st0;
-    if (t < C) st0 = cs_in[(int64_t)blockIdx.x * C + t];
-    // first tile's operands in flight during the reduction
-    int v = (int)(tl.first * vpb) + vl;
-    bool have = lane_ok && tl.first < tl.end && v < V;
-    float yv = 0.0f, dv = 0.0f, rv = 0.0f, qv = 0.0f, miv = 0.0f;
-    if (have) {
-        const int64_t e = (int64_t)v * C + ch;
-        yv = y[e];
-        dv = d[e];
-        rv = r[e];
-        qv = q[e];
-        miv = minv[v];
+    int jb;
+    const PcgImage& I = block_image<MULTI>(a, jb);
+    if constexpr (MULTI) {
+        if (*I.active == 0) return;
     }
-    ps.sum(part_in, fin);
+    const int t = threadIdx.x;
+    const int V = I.counts[CNT_V];
+    const int Cp = I.Cp, nb = I.nb;
+    const Lanes ln(Cp, K);
+    const float* d = I.d[it & 1];
+    const XcdTiles tl((V + ln.vpb - 1) / ln.vpb, jb, nb);
+    PartialSums ps;
+    ps.load(I.part[1], Cp, nb, I.sums[1]);
+    ChanState st0 = load_state(I.cs[1][(int64_t)jb * Cp + min(t, Cp - 1)].s);
+    // first tile's operands in flight during the reduction
+    int v = (int)(tl.first * ln.vpb) + ln.vl;
+    bool have = ln.ok && tl.first < tl.end && v < V;
+    Vec<K> yv, dv, rv, qv;
+    float miv = 0.0f;
+    if (have) {
+        const int64_t e = (int64_t)v * Cp + ln.g * K;
+        yv = ldv<K>(I.y + e);
+        dv = ldv<K>(d + e);
+        rv = ldv<K>(I.r + e);
+        qv = ldv<K>(I.q + e);
+        miv = I.nfm[v].y;
+    }
+    ps.sum(I.part[1], fin);
     if (t == 0) n_active = 0;
     __syncthreads();
-    if (t < C) {
+    if (t < Cp) {
         if (st0.active) {
             const double dq = fin[t];
             if (!(dq > 0.0)) {
@@ -689,64 +832,121 @@ __global__ void __launch_bounds__(kRedBlock) pcg_update(
                 st0.alpha = st0.rho / dq;
             }
         }
-        S[t] = st0;
+        store_state(S[t], st0);
         if (st0.active) atomicAdd(&n_active, 1);
-        cs_out[(int64_t)blockIdx.x * C + t] = st0;
+        store_state(I.cs[0][(int64_t)jb * Cp + t].s, st0);
     }
     __syncthreads();
-    if (blockIdx.x == 0 && t == 0) ctl[CTL_ACTIVE] = n_active;
+    if (jb == 0 && t == 0) *I.active = n_active;
     if (n_active == 0) return;
-    const ChanState st = S[lane_ok ? ch : 0];
-    const bool act = lane_ok && st.active;
-    const float alpha = (float)st.alpha;
-    double acc[3] = {0.0, 0.0, 0.0};
-    for (int64_t tile = tl.first; tile < tl.end; tile += tl.step) {
-        if (tile != tl.first) {
-            v = (int)(tile * vpb) + vl;
-            have = lane_ok && v < V;
-            if (have) {
-                const int64_t e = (int64_t)v * C + ch;
-                yv = y[e];
-                dv = d[e];
-                rv = r[e];
-                qv = q[e];
-                miv = minv[v];
-            }
-        }
-        if (!act || !have) continue;
-        const int64_t e = (int64_t)v * C + ch;
-        y[e] = fmaf(alpha, dv, yv);
-        const float r1 = fmaf(-alpha, qv, rv);
-        r[e] = r1;
-        acc[0] += (double)r1 * (double)r1;
-        acc[2] += (double)r1 * (double)(miv * r1);
+    float alpha[K];
+    bool act[K];
+    bool any = false;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const ChanState& s = S[ln.ok ? ln.g * K + k : 0];
+        alpha[k] = (float)s.alpha;
+        act[k] = ln.ok && s.active;
+        any = any || act[k];
     }
-    block_channel_partials<3>(acc, C, vpb, part_out);
+    double acc[3][K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) acc[0][k] = acc[1][k] = acc[2][k] = 0.0;
+    // Software pipeline: the next tile's operands are loaded before this
+    // tile's arithmetic waits for its own.
+    for (int64_t tile = tl.first; tile < tl.end; tile += tl.step) {
+        const int64_t nt = tile + tl.step;
+        const int vn = (int)(nt * ln.vpb) + ln.vl;
+        const bool hn = any && ln.ok && nt < tl.end && vn < V;
+        Vec<K> yn, dn, rn, qn;
+        float min_ = 0.0f;
+        if (hn) {
+            const int64_t e = (int64_t)vn * Cp + ln.g * K;
+            yn = ldv<K>(I.y + e);
+            dn = ldv<K>(d + e);
+            rn = ldv<K>(I.r + e);
+            qn = ldv<K>(I.q + e);
+            min_ = I.nfm[vn].y;
+        }
+        if (any && have) {
+            Vec<K> y1, r1;
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                if (act[k]) {
+                    y1.v[k] = fmaf(alpha[k], dv.v[k], yv.v[k]);
+                    r1.v[k] = fmaf(-alpha[k], qv.v[k], rv.v[k]);
+                    acc[0][k] += (double)r1.v[k] * (double)r1.v[k];
+                    acc[2][k] += (double)r1.v[k] * (double)(miv * r1.v[k]);
+                } else {
+                    y1.v[k] = yv.v[k];
+                    r1.v[k] = rv.v[k];
+                }
+            }
+            const int64_t e = (int64_t)v * Cp + ln.g * K;
+            stv<K>(I.y + e, y1);
+            stv<K>(I.r + e, r1);
+        }
+        v = vn;
+        have = hn;
+        yv = yn;
+        dv = dn;
+        rv = rn;
+        qv = qn;
+        miv = min_;
+    }
+    lane_partials<3, K>(acc, ln, Cp, nb, partial_slot(jb, nb), I.part[0]);
 }
 
-// After the last enqueued iteration (single block): completes the pending
-// step and writes the per-channel stats.
-__global__ void __launch_bounds__(kRedBlock) pcg_finish(const ChanState* __restrict__ cs_in,
-                                                         ChanState* __restrict__ cs_out,
-                                                         const double* __restrict__ part,
-                                                         const double* __restrict__ sums, int C,
-                                                         int G, int max_iters, double tol,
-                                                         bs_chan_stats* __restrict__ out) {
+// With many channels the per-block partials are reduced once, by one block
+// per (value, channel) pair, rather than redundantly in every consumer block.
+// Block (pair, image); `mult` values per channel in slot `which`.
+template <bool MULTI>
+__global__ void __launch_bounds__(kRedBlock) pcg_reduce(PcgArgs a, int which, int mult) {
+    const PcgImage& I = MULTI ? a.imgs[blockIdx.y] : a.one;
+    double* sums = I.sums[which];
+    if (!sums || (int)blockIdx.x >= mult * I.Cp) return;
+    if constexpr (MULTI) {
+        if (*I.active == 0) return;
+    }
+    const double* part = I.part[which];
+    const int G = I.nb;
+    double v = 0.0;
+    for (int i = threadIdx.x; i < G; i += kRedBlock) v += part[(int64_t)blockIdx.x * G + i];
+    const double s = block_sum<kRedBlock>(v);
+    if (threadIdx.x == 0) sums[blockIdx.x] = s;
+}
+
+// After the last enqueued iteration (one block per image): completes the
+// pending step and writes the per-channel stats.
+template <bool MULTI>
+__global__ void __launch_bounds__(kRedBlock) pcg_finish(PcgArgs a) {
     __shared__ double fin[3 * BS_MAX_CHANNELS];
+    const PcgImage& I = MULTI ? a.imgs[blockIdx.x] : a.one;
     const int t = threadIdx.x;
-    reduce_partials<3>(part, C, G, fin, sums);
-    if (t < C) {
-        ChanState st = cs_in[t];
-        advance_state(st, fin[t], fin[C + t], fin[2 * C + t], max_iters, tol);
-        cs_out[t] = st;
-        if (out) {
-            bs_chan_stats o;
-            o.iters = st.iters;
-            o.reason = st.reason;
-            o.rel_residual = st.res;
-            o.bnorm = st.bnorm;
-            out[t] = o;
-        }
+    reduce_partials<3>(I.part[0], I.Cp, I.nb, fin, I.sums[0]);
+    if (t < I.C && I.stats) {
+        ChanState st = load_state(I.cs[0][t].s);
+        st = advance_state(st, fin[t], fin[I.Cp + t], fin[2 * I.Cp + t], a.max_iters, a.tol);
+        bs_chan_stats o;
+        o.iters = st.iters;
+        o.reason = st.reason;
+        o.rel_residual = st.res;
+        o.bnorm = st.bnorm;
+        I.stats[t] = o;
+    }
+}
+
+// y[v][c] = src[v][c] for c < C, src with stride Cp.
+__global__ void __launch_bounds__(kBlock) unpad_kernel(const float* __restrict__ src, int Cp,
+                                                        int C, const int32_t* __restrict__ counts,
+                                                        float* __restrict__ dst) {
+    const int64_t n = (int64_t)counts[CNT_V] * C;
+    const XcdTiles tl((n + kBlock - 1) / kBlock);
+    for (int64_t tile = tl.first; tile < tl.end; tile += tl.step) {
+        const int64_t e = tile * kBlock + threadIdx.x;
+        if (e >= n) continue;
+        const int64_t v = e / C;
+        dst[e] = src[v * Cp + (e - v * C)];
     }
 }
 
@@ -764,8 +964,9 @@ __global__ void __launch_bounds__(kBlock) slice_kernel(const int32_t* __restrict
 }
 
 // dL/dt[c][p] = conf[p] g[idx[p]][c];  dL/dconf[p] = sum_c g[idx][c] (t[c][p] - y[idx][c]).
+// g has stride Cg, y stride C.
 __global__ void __launch_bounds__(kBlock) grad_scatter(const int32_t* __restrict__ idx,
-                                                        const float* __restrict__ g,
+                                                        const float* __restrict__ g, int Cg,
                                                         const float* __restrict__ yhat,
                                                         const float* __restrict__ target,
                                                         const float* __restrict__ conf, int C,
@@ -779,7 +980,7 @@ __global__ void __launch_bounds__(kBlock) grad_scatter(const int32_t* __restrict
         const float cp = conf[p];
         float s = 0.0f;
         for (int c = 0; c < C; ++c) {
-            const float gv = g[v * C + c];
+            const float gv = g[v * Cg + c];
             gt[(int64_t)c * P + p] = cp * gv;
             s += gv * (target[(int64_t)c * P + p] - yhat[v * C + c]);
         }
@@ -809,81 +1010,154 @@ static bs_status validate_solve(const bs_grid* grid, int C, const bs_solve_param
 
 static bool misaligned(const void* p) { return ((uintptr_t)p & 3) != 0; }
 
-// Initial state into `y` from the right-hand side already splatted into w.b.
+// Initial state into `y` (stride Cp) from the right-hand side in w.b.
 static bs_status run_init(const GridImpl& g, const SolveWs& w, const bs_solve_params& p,
                           float* y, hipStream_t s) {
-    const int C = w.C;
+    const int C = w.Cp;
     const int blocks = grid_blocks(ceil_div(g.vcap * C, kBlock));
     if (p.init == BS_INIT_FLAT) {
-        BS_LAUNCH(s, K_INIT, "flat_init", flat_init_kernel, dim3(blocks), dim3(kBlock), 0, s, w.b, w.sc, C,
-                           g.counts, y);
+        BS_LAUNCH(s, K_INIT, "flat_init", flat_init_kernel, dim3(blocks), dim3(kBlock), 0, s, w.b,
+                  w.sc, C, g.counts, y);
         return BS_OK;
     }
     for (int k = 1; k < g.levels; ++k) {
         const int bk = grid_blocks(ceil_div(g.lv[k].cap * (C + 1), kBlock));
-        BS_LAUNCH(s, K_INIT, "pyr_up", pyr_up, dim3(bk), dim3(kBlock), 0, s, g.lv[k].ptr, g.lv[k].list, w.b,
-                           w.sc, (const float*)(k >= 2 ? w.up[k - 1] : nullptr), w.up[k], C, k,
-                           g.counts);
+        BS_LAUNCH(s, K_INIT, "pyr_up", pyr_up, dim3(bk), dim3(kBlock), 0, s, g.lv[k].ptr,
+                  g.lv[k].list, w.b, w.sc, (const float*)(k >= 2 ? w.up[k - 1] : nullptr),
+                  w.up[k], C, k, g.counts);
     }
     for (int k = g.levels - 1; k >= 1; --k) {
         const int bk = grid_blocks(ceil_div(g.lv[k].cap * (C + 1), kBlock));
         const float wk = (float)std::pow((double)p.init_alpha, -((double)p.init_beta + k));
         const float* upp = (k + 1 < g.levels) ? w.up[k + 1] : nullptr;
         const int32_t* par = (k + 1 < g.levels) ? g.lv[k + 1].item_parent : nullptr;
-        BS_LAUNCH(s, K_INIT, "pyr_down", pyr_down, dim3(bk), dim3(kBlock), 0, s, w.up[k], upp, par,
-                           g.lv[k].ones, wk, C, k, g.counts);
+        BS_LAUNCH(s, K_INIT, "pyr_down", pyr_down, dim3(bk), dim3(kBlock), 0, s, w.up[k], upp,
+                  par, g.lv[k].ones, wk, C, k, g.counts);
     }
     const int32_t* par0 = g.levels > 1 ? g.lv[1].item_parent : nullptr;
     const float* up1 = g.levels > 1 ? w.up[1] : nullptr;
-    BS_LAUNCH(s, K_INIT, "hier_final", hier_final, dim3(blocks), dim3(kBlock), 0, s, w.b, w.sc, up1, par0, C,
-                       g.counts, y);
+    BS_LAUNCH(s, K_INIT, "hier_final", hier_final, dim3(blocks), dim3(kBlock), 0, s, w.b, w.sc,
+              up1, par0, C, g.counts, y);
     return BS_OK;
 }
 
-// PCG on A y = w.b from the state already in y.
-static bs_status run_pcg(const GridImpl& g, const SolveWs& w, const bs_solve_params& p,
-                         float* y, bs_chan_stats* stats, hipStream_t s) {
-    const int C = w.C;
-    // Consumers reduce up to 8 (value, channel) partial rows themselves; above
-    // that a pcg_reduce launch does it once.
-    const bool sep = !PartialSums::fits(3 * C, w.G);
-    const double* s0 = sep ? w.sums[0] : nullptr;
-    const double* s1 = sep ? w.sums[1] : nullptr;
-    const int nstate = w.G * C;
-    BS_LAUNCH(s, K_INIT, "solve_prologue", solve_prologue, dim3((nstate + 255) / 256),
-              dim3(256), 0, s, w.cs[0], w.cs[1], nstate, w.ctl);
-    BS_LAUNCH(s, K_PCG_START, "pcg_start", pcg_start, dim3(w.G), dim3(kRedBlock), 0, s,
-              g.nbr, g.vcap, g.nf, w.sc, w.minv, w.b, y, w.r, p.lambda, C, w.vpb, g.counts,
-              w.part[0]);
+bs_status solve_setup(const GridImpl& g, const SolveWs& w, const float* conf, const float* vals,
+                      bool weighted, const bs_solve_params& p, float* yw, hipStream_t s) {
+    const bs_status st = weighted ? launch_splat<true>(g, w, conf, vals, (double)p.lambda, s)
+                                  : launch_splat<false>(g, w, conf, vals, (double)p.lambda, s);
+    if (st != BS_OK) return st;
+    return run_init(g, w, p, yw, s);
+}
+
+PcgImage make_image(const GridImpl& g, const SolveWs& w, float lam, float* yw,
+                    bs_chan_stats* stats) {
+    PcgImage I;
+    std::memset(&I, 0, sizeof(I));
+    I.nbr = g.nbr;
+    I.nfm = w.nfm;
+    I.sc = w.sc;
+    I.b = w.b;
+    I.y = yw;
+    I.r = w.r;
+    I.d[0] = w.d[0];
+    I.d[1] = w.d[1];
+    I.q = w.q;
+    I.counts = g.counts;
+    I.cs[0] = w.cs[0];
+    I.cs[1] = w.cs[1];
+    I.part[0] = w.part[0];
+    I.part[1] = w.part[1];
+    // Consumers reduce the partials themselves while they fit in registers;
+    // beyond that a pcg_reduce launch does it once.
+    const bool sep = !PartialSums::fits(3 * w.Cp, w.nb);
+    I.sums[0] = sep ? w.sums[0] : nullptr;
+    I.sums[1] = sep ? w.sums[1] : nullptr;
+    I.active = w.act;
+    I.stats = stats;
+    I.vcap = g.vcap;
+    I.lam = lam;
+    I.C = w.C;
+    I.Cp = w.Cp;
+    I.nb = w.nb;
+    I.block0 = 0;
+    return I;
+}
+
+template <int K, bool MULTI>
+static bs_status run_pcg_k(const PcgArgs& a, int n, int G, int max_cp, bool sep,
+                           const bs_solve_params& p, const int32_t* act, hipStream_t s) {
+    const dim3 grid(G), block(kRedBlock);
+    BS_LAUNCH(s, K_INIT, "pcg_prologue", pcg_prologue<MULTI>, grid, block, 0, s, a);
+    BS_LAUNCH(s, K_PCG_START, "pcg_start", (pcg_start<K, MULTI>), grid, block, 0, s, a);
     if (sep)
-        BS_LAUNCH(s, K_PCG_REDUCE, "pcg_reduce", pcg_reduce, dim3(3 * C), dim3(kRedBlock), 0, s,
-                  w.part[0], w.sums[0], w.G);
+        BS_LAUNCH(s, K_PCG_REDUCE, "pcg_reduce", pcg_reduce<MULTI>, dim3(3 * max_cp, n), block, 0,
+                  s, a, 0, 3);
+    std::vector<int32_t> poll(n);
     for (int it = 0; it < p.max_iters; ++it) {
-        float* dn = w.d[it & 1];
-        const float* dold = w.d[(it + 1) & 1];
-        BS_LAUNCH(s, K_PCG_MATVEC, "pcg_matvec", pcg_matvec, dim3(w.G), dim3(kRedBlock), 0,
-                  s, g.nbr, g.vcap, g.nf, w.sc, w.minv, w.r, dold, dn, w.q, p.lambda, C, w.vpb,
-                  g.counts, w.cs[0], w.cs[1], w.part[0], s0, w.part[1], w.ctl, p.max_iters,
-                  p.rel_tol);
+        BS_LAUNCH(s, K_PCG_MATVEC, "pcg_matvec", (pcg_matvec<K, MULTI>), grid, block, 0, s, a, it);
         if (sep)
-            BS_LAUNCH(s, K_PCG_REDUCE, "pcg_reduce", pcg_reduce, dim3(C), dim3(kRedBlock), 0, s,
-                      w.part[1], w.sums[1], w.G);
-        BS_LAUNCH(s, K_PCG_UPDATE, "pcg_update", pcg_update, dim3(w.G), dim3(kRedBlock), 0,
-                  s, w.minv, dn, w.q, y, w.r, C, w.vpb, g.counts, w.cs[1], w.cs[0], w.part[1], s1,
-                  w.part[0], w.ctl);
+            BS_LAUNCH(s, K_PCG_REDUCE, "pcg_reduce", pcg_reduce<MULTI>, dim3(max_cp, n), block, 0,
+                      s, a, 1, 1);
+        BS_LAUNCH(s, K_PCG_UPDATE, "pcg_update", (pcg_update<K, MULTI>), grid, block, 0, s, a, it);
         if (sep)
-            BS_LAUNCH(s, K_PCG_REDUCE, "pcg_reduce", pcg_reduce, dim3(3 * C), dim3(kRedBlock), 0,
-                      s, w.part[0], w.sums[0], w.G);
+            BS_LAUNCH(s, K_PCG_REDUCE, "pcg_reduce", pcg_reduce<MULTI>, dim3(3 * max_cp, n), block,
+                      0, s, a, 0, 3);
         if (p.check_every > 0 && (it + 1) % p.check_every == 0 && it + 1 < p.max_iters) {
-            int32_t active = 0;
-            BS_TRY_HIP(hipMemcpyAsync(&active, w.ctl + CTL_ACTIVE, sizeof(int32_t),
+            BS_TRY_HIP(hipMemcpyAsync(poll.data(), act, sizeof(int32_t) * n,
                                       hipMemcpyDeviceToHost, s));
             BS_TRY_HIP(hipStreamSynchronize(s));
-            if (active == 0) break;
+            bool any = false;
+            for (int i = 0; i < n; ++i) any = any || poll[i] != 0;
+            if (!any) break;
         }
     }
-    BS_LAUNCH(s, K_INIT, "pcg_finish", pcg_finish, dim3(1), dim3(kRedBlock), 0, s, w.cs[0],
-              w.cs[1], w.part[0], s0, C, w.G, p.max_iters, p.rel_tol, stats);
+    BS_LAUNCH(s, K_INIT, "pcg_finish", pcg_finish<MULTI>, dim3(n), block, 0, s, a);
+    return BS_OK;
+}
+
+bs_status run_pcg(int K, const PcgImage* imgs, int n, const PcgImage* dev_imgs,
+                  const int32_t* blk2img, int G, int max_cp, const bs_solve_params& p,
+                  const int32_t* act, hipStream_t s) {
+    PcgArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.one = imgs[0];
+    a.imgs = dev_imgs;
+    a.blk2img = blk2img;
+    a.max_iters = p.max_iters;
+    a.tol = p.rel_tol;
+    bool sep = false;
+    for (int i = 0; i < n; ++i) sep = sep || imgs[i].sums[0] != nullptr;
+    const bool multi = n > 1;
+    if (multi && (!dev_imgs || !blk2img)) return fail(BS_EINVAL, "image tables missing");
+    switch (K) {
+        case 1:
+            return multi ? run_pcg_k<1, true>(a, n, G, max_cp, sep, p, act, s)
+                         : run_pcg_k<1, false>(a, n, G, max_cp, sep, p, act, s);
+        case 2:
+            return multi ? run_pcg_k<2, true>(a, n, G, max_cp, sep, p, act, s)
+                         : run_pcg_k<2, false>(a, n, G, max_cp, sep, p, act, s);
+        case 4:
+            return multi ? run_pcg_k<4, true>(a, n, G, max_cp, sep, p, act, s)
+                         : run_pcg_k<4, false>(a, n, G, max_cp, sep, p, act, s);
+        default:
+            return fail(BS_EINVAL, "unsupported lane width");
+    }
+}
+
+bs_status copy_unpadded(const GridImpl& g, const float* yw, int C, int Cp, float* y,
+                        hipStream_t s) {
+    const int blocks = grid_blocks(ceil_div(g.vcap * C, kBlock));
+    BS_LAUNCH(s, K_INIT, "unpad", unpad_kernel, dim3(blocks), dim3(kBlock), 0, s, yw, Cp, C,
+              g.counts, y);
+    return BS_OK;
+}
+
+bs_status grad_scatter_launch(const GridImpl& g, const float* gb, int Cp, const float* y_hat,
+                              const float* target, const float* conf, int C, float* grad_t,
+                              float* grad_c, hipStream_t s) {
+    const int pblocks = grid_blocks(ceil_div(g.P, kBlock));
+    BS_LAUNCH(s, K_GRAD_SCATTER, "grad_scatter", grad_scatter, dim3(pblocks), dim3(kBlock), 0, s,
+              g.lv[0].item_parent, gb, Cp, y_hat, target, conf, C, g.P, grad_t, grad_c);
     return BS_OK;
 }
 
@@ -894,7 +1168,7 @@ using namespace bs;
 extern "C" size_t bs_solve_workspace_bytes(const bs_grid* grid, int32_t C) {
     if (!grid || impl(grid)->magic != kGridMagic || C < 1 || C > BS_MAX_CHANNELS) return 0;
     SolveWs w;
-    return layout_solve(*impl(grid), C, nullptr, w);
+    return layout_solve(*impl(grid), C, 0, nullptr, w);
 }
 
 extern "C" bs_status bs_solve_ws_view(const bs_grid* grid, int32_t C, void* ws, size_t ws_bytes,
@@ -903,13 +1177,18 @@ extern "C" bs_status bs_solve_ws_view(const bs_grid* grid, int32_t C, void* ws, 
     if (!grid || impl(grid)->magic != kGridMagic || C < 1 || C > BS_MAX_CHANNELS)
         return fail(BS_EINVAL, "bad grid or channel count");
     SolveWs w;
-    if (ws_bytes < layout_solve(*impl(grid), C, nullptr, w)) return fail(BS_EWORKSPACE, "workspace too small");
-    layout_solve(*impl(grid), C, ws, w);
+    if (ws_bytes < layout_solve(*impl(grid), C, 0, nullptr, w))
+        return fail(BS_EWORKSPACE, "workspace too small");
+    layout_solve(*impl(grid), C, 0, ws, w);
     if (b) *b = w.b;
     if (sc) *sc = w.sc;
     if (diag) *diag = w.diag;
     if (minv) *minv = w.minv;
     return BS_OK;
+}
+
+extern "C" int32_t bs_solve_channel_stride(int32_t C) {
+    return (C < 1 || C > BS_MAX_CHANNELS) ? 0 : padded_channels(C);
 }
 
 extern "C" bs_status bs_solve(const bs_grid* grid, const float* target, const float* conf,
@@ -922,19 +1201,20 @@ extern "C" bs_status bs_solve(const bs_grid* grid, const float* target, const fl
         return fail(BS_EINVAL, "misaligned buffer");
     const GridImpl& g = *impl(grid);
     SolveWs w;
-    const size_t need = layout_solve(g, C, nullptr, w);
+    const size_t need = layout_solve(g, C, 0, nullptr, w);
     if (ws_bytes < need)
         return fail(BS_EWORKSPACE, "solve workspace needs " + std::to_string(need) + " bytes");
-    layout_solve(g, C, ws, w);
+    layout_solve(g, C, 0, ws, w);
     hipStream_t s = (hipStream_t)stream;
     const bs_solve_params& p = *params;
-
-    st = launch_splat<true>(g, conf, target, C, (double)p.lambda, w.sc, w.diag, w.minv, w.b, s);
+    // y is used in place unless the channel stride is padded
+    float* yw = (w.Cp == C && ((uintptr_t)y & 15) == 0) ? y : w.yi;
+    st = solve_setup(g, w, conf, target, true, p, yw, s);
     if (st != BS_OK) return st;
-    st = run_init(g, w, p, y, s);
+    const PcgImage I = make_image(g, w, p.lambda, yw, stats);
+    st = run_pcg(w.K, &I, 1, nullptr, nullptr, w.nb, w.Cp, p, w.act, s);
     if (st != BS_OK) return st;
-    st = run_pcg(g, w, p, y, stats, s);
-    if (st != BS_OK) return st;
+    if (yw != y) return copy_unpadded(g, yw, C, w.Cp, y, s);
     return BS_OK;
 }
 
@@ -947,8 +1227,8 @@ extern "C" bs_status bs_slice(const bs_grid* grid, const float* y, int32_t C, fl
     const GridImpl& g = *impl(grid);
     hipStream_t s = (hipStream_t)stream;
     const int blocks = grid_blocks(ceil_div(g.P, kBlock));
-    BS_LAUNCH(s, K_SLICE, "slice", slice_kernel, dim3(blocks), dim3(kBlock), 0, s, g.lv[0].item_parent, y, C,
-                       g.P, x);
+    BS_LAUNCH(s, K_SLICE, "slice", slice_kernel, dim3(blocks), dim3(kBlock), 0, s,
+              g.lv[0].item_parent, y, C, g.P, x);
     return BS_OK;
 }
 
@@ -967,23 +1247,21 @@ extern "C" bs_status bs_solve_backward(const bs_grid* grid, const float* target,
         return fail(BS_EINVAL, "misaligned buffer");
     const GridImpl& g = *impl(grid);
     SolveWs w;
-    const size_t need = layout_solve(g, C, nullptr, w);
+    const size_t need = layout_solve(g, C, 0, nullptr, w);
     if (ws_bytes < need)
         return fail(BS_EWORKSPACE, "solve workspace needs " + std::to_string(need) + " bytes");
-    layout_solve(g, C, ws, w);
+    layout_solve(g, C, 0, ws, w);
     hipStream_t s = (hipStream_t)stream;
     const bs_solve_params& p = *params;
-    float* gb = g_out ? g_out : w.g;
-
-    st = launch_splat<false>(g, conf, grad_x, C, (double)p.lambda, w.sc, w.diag, w.minv, w.b,
-                             s);
+    // the adjoint solution goes to g_out in place unless the stride is padded
+    float* gb = (g_out && w.Cp == C && ((uintptr_t)g_out & 15) == 0) ? g_out : w.yi;
+    st = solve_setup(g, w, conf, grad_x, false, p, gb, s);
     if (st != BS_OK) return st;
-    st = run_init(g, w, p, gb, s);
+    const PcgImage I = make_image(g, w, p.lambda, gb, stats);
+    st = run_pcg(w.K, &I, 1, nullptr, nullptr, w.nb, w.Cp, p, w.act, s);
     if (st != BS_OK) return st;
-    st = run_pcg(g, w, p, gb, stats, s);
+    st = grad_scatter_launch(g, gb, w.Cp, y_hat, target, conf, C, grad_t, grad_c, s);
     if (st != BS_OK) return st;
-    const int pblocks = grid_blocks(ceil_div(g.P, kBlock));
-    BS_LAUNCH(s, K_GRAD_SCATTER, "grad_scatter", grad_scatter, dim3(pblocks), dim3(kBlock), 0, s, g.lv[0].item_parent, gb,
-                       y_hat, target, conf, C, g.P, grad_t, grad_c);
+    if (g_out && gb != g_out) return copy_unpadded(g, gb, C, w.Cp, g_out, s);
     return BS_OK;
 }

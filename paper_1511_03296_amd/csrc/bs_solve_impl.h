@@ -1,0 +1,116 @@
+// Internal interface of the solve: workspace layout, the per-image PCG
+// descriptor and the host sequencing shared by the single-image entry points
+// and the batch engine.
+#pragma once
+
+#include "bs_internal.h"
+
+namespace bs {
+
+// PCG state of one channel.
+struct ChanState {
+    double rho, alpha, beta, bnorm, res;
+    int32_t active, iters, reason, phase;   // phase 0: initial residual not yet reduced
+};
+
+// One record per 128-byte cache line: each block reads back its own record,
+// written by the block of the same index (same die) in the previous launch.
+// With 48- or 64-byte records a line held records of blocks on two dies and
+// that read cost ~12 us per launch on MI355X.  Only the payload is copied.
+struct alignas(128) ChanRec {
+    ChanState s;
+};
+static_assert(sizeof(ChanRec) == 128, "one record per cache line");
+
+// Channels per lane of the vertex kernels (1, 2 or 4: float, float2, float4
+// accesses) and the padded channel stride of the bilateral-space vectors.
+inline int lane_width(int C) { return C == 1 ? 1 : (C == 2 ? 2 : 4); }
+inline int padded_channels(int C) { return C <= 2 ? C : (C + 3) & ~3; }
+
+// One image of a PCG launch.  In a launch over several images, blocks
+// [block0, block0 + nb) work on this image; block0 and nb are multiples of 8,
+// so the image's local block j runs on die j % 8.  Vectors are [V][Cp].
+struct PcgImage {
+    const int32_t* nbr;      // [10][vcap] neighbour table
+    const float2* nfm;       // [V] {n, 1 / diag(A)}
+    const float* sc;         // [V] S c
+    const float* b;          // right-hand side
+    float* y;                // solution (initial state on entry)
+    float* r;
+    float* d[2];             // search directions, ping-pong
+    float* q;
+    const int32_t* counts;   // V = counts[CNT_V]
+    ChanRec* cs[2];          // [nb][Cp] per-block channel state, ping-pong
+    double* part[2];         // [3][Cp][nb] per-block partials: 0 start/update, 1 matvec
+    double* sums[2];         // [3][Cp] partials reduced by pcg_reduce, or nullptr
+    int32_t* active;         // channels still iterating (written by local block 0)
+    bs_chan_stats* stats;    // [C] or nullptr
+    int64_t vcap;
+    float lam;
+    int32_t C, Cp, nb, block0;
+};
+
+// Kernel argument of the PCG kernels: one image by value, or a table of
+// images and the image of every block.
+struct PcgArgs {
+    PcgImage one;
+    const PcgImage* imgs;
+    const int32_t* blk2img;
+    int32_t max_iters;
+    double tol;
+};
+
+struct SolveWs {
+    int C, Cp, K, nb;
+    float* sc;
+    float* diag;
+    float* minv;
+    float2* nfm;
+    float* b;
+    float* r;
+    float* d[2];
+    float* q;
+    float* yi;               // [V][Cp] solution when the caller's buffer is not used in place
+    float* up[BS_MAX_LEVELS];
+    ChanRec* cs[2];
+    double* part[2];
+    double* sums[2];
+    int32_t* act;
+    size_t bytes;
+};
+
+// Lays out (base != nullptr) or sizes a solve workspace for C channels with
+// nb reducing blocks (0: the single-image default).
+size_t layout_solve(const GridImpl& g, int C, int nb, void* base, SolveWs& w);
+
+// Reducing blocks of a single-image solve.
+int solve_blocks(const GridImpl& g, int C);
+
+// Splat (weighted: b = S(c o t), else b = S t) and initial state into yw.
+bs_status solve_setup(const GridImpl& g, const SolveWs& w, const float* conf, const float* vals,
+                      bool weighted, const bs_solve_params& p, float* yw, hipStream_t s);
+
+// The descriptor of one image's PCG (block0 = 0).
+PcgImage make_image(const GridImpl& g, const SolveWs& w, float lam, float* yw,
+                    bs_chan_stats* stats);
+
+// PCG over n images sharing lane width K.  `dev_imgs` / `blk2img` are device
+// copies of `imgs` and of the block-to-image map (ignored for n == 1, which
+// passes the image by value, with block0 = 0); G is the launch's block count,
+// max_cp the largest Cp; `act` is the device array the images' active
+// counters point into (contiguous, n entries), polled every check_every
+// iterations.
+bs_status run_pcg(int K, const PcgImage* imgs, int n, const PcgImage* dev_imgs,
+                  const int32_t* blk2img, int G, int max_cp, const bs_solve_params& p,
+                  const int32_t* act, hipStream_t s);
+
+// y[v][c] = yw[v][c] for c < C (yw has stride Cp).
+bs_status copy_unpadded(const GridImpl& g, const float* yw, int C, int Cp, float* y,
+                        hipStream_t s);
+
+// dL/dt, dL/dc from the adjoint solution g (stride Cp).
+bs_status grad_scatter_launch(const GridImpl& g, const float* gb, int Cp, const float* y_hat,
+                              const float* target, const float* conf, int C, float* grad_t,
+                              float* grad_c, hipStream_t s);
+
+}  // namespace bs

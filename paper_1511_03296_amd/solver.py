@@ -188,7 +188,8 @@ class BilateralGrid:
         return gt, gc, g, stats
 
     def solve_ws_arrays(self, ws: torch.Tensor, C: int):
-        """Device tensors (b [Vcap][C], S c, diag(A), Jacobi inverse) of a solve workspace."""
+        """Device tensors (b [Vcap][C] (a strided view), S c, diag(A), Jacobi inverse) of a
+        solve workspace."""
         ptrs = [ct.c_void_p() for _ in range(4)]
         L.check(L.lib.bs_solve_ws_view(ct.byref(self.handle), int(C), ws.data_ptr(), ws.numel(),
                                        *[ct.byref(p) for p in ptrs]), "bs_solve_ws_view")
@@ -198,7 +199,8 @@ class BilateralGrid:
             off = int(ptr.value) - ws.data_ptr()
             return ws[off:off + 4 * count].view(torch.float32)
 
-        return (alias(ptrs[0], vcap * C).view(vcap, C), alias(ptrs[1], vcap),
+        cs = int(L.lib.bs_solve_channel_stride(int(C)))
+        return (alias(ptrs[0], vcap * cs).view(vcap, cs)[:, :C], alias(ptrs[1], vcap),
                 alias(ptrs[2], vcap), alias(ptrs[3], vcap))
 
 

@@ -1,7 +1,8 @@
-"""GPU tests of the batch engine: a batch of images of uneven size, channel
-count and grid scale must reproduce the single-image path bit for bit (same
-deterministic kernels), forward and backward, and the batched autograd
-Function must agree with the per-image one."""
+"""GPU tests of the batch engine.  The batched PCG gives every image its own
+share of blocks, so its float64 reductions run in another order than the
+single-image path's: the batch is compared with the single-image path and with
+the oracle to the parity bar, and with itself bit for bit across stream counts
+(the reductions are deterministic)."""
 import numpy as np
 import pytest
 import torch
@@ -12,41 +13,76 @@ from tests.gpu_helpers import params, rel_l2, say, to_dev
 
 pytestmark = pytest.mark.gpu
 
+TOL = 1e-4
 
-def small_batch(n=7, seed=3):
+
+def small_batch(n=7, seed=3, rel_tol=1e-6):
     return WL.mixed_batch(seed=seed, count=n, wmin=40, wmax=200, hmin=30, hmax=150,
-                          rel_tol=1e-5, max_iters=3000)
+                          rel_tol=rel_tol, max_iters=3000)
 
 
-def test_batch_forward_backward_matches_single_image():
-    from paper_1511_03296_amd import BilateralGrid, BatchState, SolveOptions
-    probs = small_batch()
-    say("batch forward/backward " + " ".join(f"{p.W}x{p.H}c{p.C}s{p.sigma_xy}" for p in probs))
+def _inputs(probs):
     refs = [to_dev(p.ref) for p in probs]
     ts = [to_dev(p.target) for p in probs]
     cs = [to_dev(p.conf) for p in probs]
-    gxs = [to_dev(WL.random_grad(i, p.C, p.H, p.W)) for i, p in enumerate(probs)]
     sig = [(p.sigma_xy, p.sigma_l, p.sigma_uv) for p in probs]
-    opts = SolveOptions(probs[0].lam, 3000, 1e-5)
+    return refs, ts, cs, sig
+
+
+def test_batch_forward_backward():
+    from paper_1511_03296_amd import BilateralGrid, BatchState, SolveOptions
+    probs = small_batch()
+    # channel counts 1 and 21 (lane widths 1 and 4), grid scales 8 and 16
+    say("batch forward/backward " + " ".join(f"{p.W}x{p.H}c{p.C}s{p.sigma_xy}" for p in probs))
+    refs, ts, cs, sig = _inputs(probs)
+    gxs = [to_dev(WL.random_grad(i, p.C, p.H, p.W)) for i, p in enumerate(probs)]
+    opts = SolveOptions(probs[0].lam, 3000, 1e-6)
+    runs = []
     for streams in (1, 3):
         st = BatchState(refs, ts, cs, sig, streams)
         xs, _ = st.forward(opts)
         gts, gcs, _ = st.backward(gxs, opts)
         torch.cuda.synchronize()
-        for i, p in enumerate(probs):
-            G = BilateralGrid(refs[i], *sig[i])
-            y, _ = G.solve(ts[i], cs[i], p.lam, max_iters=3000, rel_tol=1e-5)
-            x = G.slice(y, p.C)
-            gt, gc, _, _ = G.backward(ts[i], cs[i], y, gxs[i], p.lam, max_iters=3000,
-                                      rel_tol=1e-5)
-            torch.cuda.synchronize()
-            assert torch.equal(x, xs[i]), (streams, i)
-            assert torch.equal(gt, gts[i]) and torch.equal(gc, gcs[i]), (streams, i)
-    # and the batch against the oracle's minimiser on two of its images
+        runs.append((xs, gts, gcs))
+    for a, b in zip(runs[0], runs[1]):
+        for u, v in zip(a, b):
+            assert torch.equal(u, v)
+    xs, gts, gcs = runs[0]
+    for i, p in enumerate(probs):
+        G = BilateralGrid(refs[i], *sig[i])
+        y, _ = G.solve(ts[i], cs[i], p.lam, max_iters=3000, rel_tol=1e-6)
+        x = G.slice(y, p.C)
+        gt, gc, _, _ = G.backward(ts[i], cs[i], y, gxs[i], p.lam, max_iters=3000, rel_tol=1e-6)
+        torch.cuda.synchronize()
+        assert rel_l2(xs[i].cpu().numpy(), x.cpu().numpy()) <= TOL, i
+        assert rel_l2(gts[i].cpu().numpy(), gt.cpu().numpy()) <= TOL, i
+        assert rel_l2(gcs[i].cpu().numpy(), gc.cpu().numpy()) <= TOL, i
+    # against the oracle's minimiser and its gradient on two of the images
     for i in (0, len(probs) - 1):
         p = probs[i]
-        sol = O.solve(p.ref, p.target, p.conf, params(p, rel_tol=1e-10, max_iters=5000))
-        assert rel_l2(xs[i].cpu().numpy(), sol.x) <= 1e-4, i
+        prm = params(p, rel_tol=1e-10, max_iters=5000)
+        sol = O.solve(p.ref, p.target, p.conf, prm)
+        assert rel_l2(xs[i].cpu().numpy(), sol.x) <= TOL, i
+        og = O.solve_backward(sol, p.target, p.conf, WL.random_grad(i, p.C, p.H, p.W), prm)
+        assert rel_l2(gts[i].cpu().numpy(), og.grad_t) <= TOL, i
+        assert rel_l2(gcs[i].cpu().numpy(), og.grad_c) <= TOL, i
+
+
+def test_batch_two_channel_group_and_single_image_group():
+    """Groups of lane width 2 (two C=2 images), 1 (one image) and 4 (one C=3
+    image, padded to a channel stride of 4)."""
+    from paper_1511_03296_amd import BatchState, SolveOptions
+    pool = small_batch(n=12, seed=5)
+    probs = [p for p in pool if p.C == 2][:2] + [p for p in pool if p.C == 1][:1]
+    probs += [WL.tiny_ramp(seed=4, channels=3)]
+    say("batch groups " + " ".join(f"{p.W}x{p.H}c{p.C}" for p in probs))
+    refs, ts, cs, sig = _inputs(probs)
+    st = BatchState(refs, ts, cs, sig, 2)
+    xs, stats = st.forward(SolveOptions(128.0, 3000, 1e-6), stats=True)
+    torch.cuda.synchronize()
+    for i, p in enumerate(probs):
+        sol = O.solve(p.ref, p.target, p.conf, params(p, lam=128.0, rel_tol=1e-10, max_iters=5000))
+        assert rel_l2(xs[i].cpu().numpy(), sol.x) <= TOL, (i, p.C)
 
 
 def test_batched_autograd_matches_single():
@@ -68,8 +104,9 @@ def test_batched_autograd_matches_single():
                              rel_tol=1e-6)
         (x1 * x1).sum().backward()
         torch.cuda.synchronize()
-        assert torch.equal(x1.detach(), xs[i].detach())
-        assert torch.equal(t1.grad, ts[i].grad) and torch.equal(c1.grad, cs[i].grad)
+        assert rel_l2(xs[i].detach().cpu().numpy(), x1.detach().cpu().numpy()) <= TOL
+        assert rel_l2(ts[i].grad.cpu().numpy(), t1.grad.cpu().numpy()) <= TOL
+        assert rel_l2(cs[i].grad.cpu().numpy(), c1.grad.cpu().numpy()) <= TOL
 
 
 def test_batch_rejects_bad_items():
