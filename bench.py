@@ -196,6 +196,8 @@ def main() -> int:
                     help="library streams of the batch engine (batched workloads)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-plain", action="store_true",
+                    help="batched workloads: skip the single-image comparison (counter runs)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="copy a MIB-sized device buffer once (a reference kernel of known "
                          "traffic for hardware counters)")
@@ -248,7 +250,7 @@ def main() -> int:
     print(f"bench: fwd+bwd {sec_fb * 1e3:.3f} ms/step, fwd {sec_f * 1e3:.3f} ms/step",
           file=sys.stderr, flush=True)
     plain = None
-    if streams:
+    if streams and not args.no_plain:
         sec_plain = timed(inputs, spec, args.steps, backward=True, streams=0)
         plain = pixels / sec_plain / 1e6
         print(f"bench: plain single-image path fwd+bwd {sec_plain * 1e3:.3f} ms/step",
@@ -269,8 +271,9 @@ def main() -> int:
     if os.path.exists(TRAFFIC_FILE):
         with open(TRAFFIC_FILE) as f:
             tr = json.load(f)
-        if tr.get("source_sha256") == _source_digest() and tr.get("workload") == args.workload:
-            traffic = tr.get("bytes_per_launch")
+        wl = tr.get("workloads", {}).get(args.workload)
+        if tr.get("source_sha256") == _source_digest() and wl:
+            traffic = wl.get("bytes_per_launch")
 
     line = {
         "metric": METRIC,
