@@ -143,7 +143,8 @@ typedef struct bs_grid_view {
  * pure).  Returns 0 for invalid arguments. */
 size_t bs_grid_workspace_bytes(int32_t H, int32_t W, const bs_grid_params* params);
 
-/* Builds the simplified bilateral grid of `ref` and its pyramid.
+/* Builds the simplified bilateral grid of `ref` (its pyramid is built by the
+ * first bs_bistochastize call on the handle).
  *  ref  device float32 [3][H][W], RGB in [0, 1].
  * Each pixel is quantised to 8 bits (clamp(floor(255 v + 1/2), 0, 255), NaN
  * -> 0), converted to JFIF (BT.601 full-range) YCbCr in 16.16 fixed point, and
@@ -160,8 +161,11 @@ bs_status bs_build_grid(const float* ref, int32_t H, int32_t W, const bs_grid_pa
                         void* ws, size_t ws_bytes, void* stream, bs_grid* out);
 
 /* Bistochastizes the grid's blur in float64 (supplement Algorithm 1), storing
- * n, its float copy and n o (N n) in the grid.  Must follow bs_build_grid on
- * the same stream. */
+ * n, its float copy and n o (N n) in the grid.  The first call on a handle
+ * also builds the pyramid levels k >= 1, on a library stream that overlaps the
+ * bistochastization and is joined back into `stream` before the call returns
+ * (work enqueued on `stream` afterwards sees both).  Must follow
+ * bs_build_grid on the same stream; updates the handle. */
 bs_status bs_bistochastize(bs_grid* grid, const bs_bistoch_params* params, void* stream);
 
 /* ---------------------------------------------------------------------- */

@@ -9,7 +9,41 @@
 // launches return at once, so the host may enqueue them without waiting.
 #include "bs_internal.h"
 
+#include <mutex>
+#include <vector>
+
 namespace bs {
+
+namespace {
+constexpr int kSideStreams = 8;
+struct SideStreams {
+    std::mutex mu;
+    std::vector<std::vector<hipStream_t>> per_device;
+};
+SideStreams& sides() {
+    static SideStreams s;
+    return s;
+}
+}  // namespace
+
+bs_status side_stream(hipStream_t s, hipStream_t* out) {
+    int dev = 0;
+    BS_TRY_HIP(hipGetDevice(&dev));
+    SideStreams& ss = sides();
+    std::lock_guard<std::mutex> lock(ss.mu);
+    if ((int)ss.per_device.size() <= dev) ss.per_device.resize(dev + 1);
+    std::vector<hipStream_t>& v = ss.per_device[dev];
+    if (v.empty()) {
+        for (int i = 0; i < kSideStreams; ++i) {
+            hipStream_t h;
+            BS_TRY_HIP(hipStreamCreateWithFlags(&h, hipStreamNonBlocking));
+            v.push_back(h);
+        }
+    }
+    const uintptr_t key = (uintptr_t)s;
+    *out = v[(key >> 8 ^ key >> 4) % kSideStreams];
+    return BS_OK;
+}
 
 __global__ void __launch_bounds__(kBlock) bist_init(double* __restrict__ n0,
                                                      const int32_t* __restrict__ counts) {
@@ -164,6 +198,22 @@ extern "C" bs_status bs_bistochastize(bs_grid* grid, const bs_bistoch_params* pa
         return fail(BS_EINVAL, "bistochastization parameters out of range");
     GridImpl& g = *impl(grid);
     hipStream_t s = (hipStream_t)stream;
+    // The pyramid levels k >= 1 and the bistochastization both read level 0
+    // only: the pyramid is built on a side stream meanwhile and joined below.
+    hipStream_t side = nullptr;
+    hipEvent_t fork = nullptr, join = nullptr;
+    if (!g.pyramid_built) {
+        BS_TRY_HIP(hipEventCreateWithFlags(&fork, hipEventDisableTiming));
+        BS_TRY_HIP(hipEventCreateWithFlags(&join, hipEventDisableTiming));
+        bs_status st = side_stream(s, &side);
+        if (st != BS_OK) return st;
+        BS_TRY_HIP(hipEventRecord(fork, s));
+        BS_TRY_HIP(hipStreamWaitEvent(side, fork, 0));
+        st = build_pyramid(g, side);
+        if (st != BS_OK) return st;
+        BS_TRY_HIP(hipEventRecord(join, side));
+        g.pyramid_built = 1;
+    }
     const int blocks = grid_blocks(ceil_div(g.vcap, kBlock));
     BS_LAUNCH(s, K_BIST_OTHER, "bist_init", bist_init, dim3(blocks), dim3(kBlock), 0, s,
               g.nbuf[0], g.counts);
@@ -186,6 +236,11 @@ extern "C" bs_status bs_bistochastize(bs_grid* grid, const bs_bistoch_params* pa
               g.counts, g.bist_part, g.bist_res, last, G);
     BS_LAUNCH(s, K_BIST_OTHER, "bist_finalize", bist_finalize, dim3(blocks), dim3(kBlock), 0, s,
               g.nbr, g.nbuf[0], g.nbuf[1], g.vcap, g.n64, g.nf, g.nn, g.counts);
+    if (join) {
+        BS_TRY_HIP(hipStreamWaitEvent(s, join, 0));
+        BS_TRY_HIP(hipEventDestroy(fork));
+        BS_TRY_HIP(hipEventDestroy(join));
+    }
     g.bistochastized = 1;
     return BS_OK;
 }

@@ -614,6 +614,19 @@ static bs_status launch_level(const Src& src, GridImpl& g, int k, hipStream_t st
     return BS_OK;
 }
 
+// Pyramid levels k >= 1 (they read level 0 only, so they may run on another
+// stream than the bistochastization, which also reads level 0 only).
+bs_status build_pyramid(const GridImpl& g0, hipStream_t s) {
+    GridImpl& g = const_cast<GridImpl&>(g0);
+    for (int k = 1; k < g.levels; ++k) {
+        const Level& C = g.lv[k - 1];
+        VertexSource vs{C.key, C.cell_vbase, g.counts, C.ncx, C.ncy, g.lv[k].ncx, k};
+        const bs_status st = launch_level<128, 1024>(vs, g, k, s);
+        if (st != BS_OK) return st;
+    }
+    return BS_OK;
+}
+
 }  // namespace bs
 
 using namespace bs;
@@ -649,12 +662,6 @@ extern "C" bs_status bs_build_grid(const float* ref, int32_t H, int32_t W,
     else st = launch_level<256, 2048>(ps, g, 0, s);
     if (st != BS_OK) return st;
 
-    for (int k = 1; k < g.levels; ++k) {
-        const Level& C = g.lv[k - 1];
-        VertexSource vs{C.key, C.cell_vbase, g.counts, C.ncx, C.ncy, g.lv[k].ncx, k};
-        st = launch_level<128, 1024>(vs, g, k, s);
-        if (st != BS_OK) return st;
-    }
     const int blocks = grid_blocks(ceil_div(g.vcap, kBlock));
     BS_LAUNCH(s, K_NEIGHBOURS, "neighbour_table", neighbour_table, dim3(blocks), dim3(kBlock), 0, s, g.lv[0].key,
                        g.lv[0].cell_vbase, g.counts, g.lv[0].ncx, g.lv[0].ncy, g.vcap, g.nbr);

@@ -156,6 +156,7 @@ struct GridImpl {
     bs_grid_params sg;
     int32_t levels;          // allocated levels, K <= levels - 1
     int32_t bistochastized;  // set by bs_bistochastize
+    int32_t pyramid_built;   // levels k >= 1 enqueued (by the first bs_bistochastize)
     int64_t vcap;
     size_t ws_bytes;
     void* ws;
@@ -179,6 +180,13 @@ constexpr uint32_t kGridMagic = 0xB5A7E001u;
 
 inline GridImpl* impl(bs_grid* g) { return reinterpret_cast<GridImpl*>(g->opaque); }
 inline const GridImpl* impl(const bs_grid* g) { return reinterpret_cast<const GridImpl*>(g->opaque); }
+
+// Enqueues the pyramid levels k >= 1 of a grid whose level 0 is built.
+bs_status build_pyramid(const GridImpl& g, hipStream_t s);
+
+// A library-owned stream of the current device paired with `s` (default
+// priority, created once), for work that may overlap work on `s`.
+bs_status side_stream(hipStream_t s, hipStream_t* out);
 
 // Lays out (or sizes, with base == nullptr) a grid for an H x W image.
 // Returns the bytes used; fills `g` when base != nullptr.

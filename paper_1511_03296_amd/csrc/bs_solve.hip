@@ -528,6 +528,64 @@ __global__ void __launch_bounds__(kBlock) pyr_down(float* __restrict__ up,
     }
 }
 
+// The small top of the pyramid, levels k0 .. levels-1, in one block: the lift
+// bottom-up, then the collapse top-down, with the arithmetic of pyr_up and
+// pyr_down (the coarse levels would otherwise cost two launches each).
+constexpr int kSmallPyrElems = 16384;   // cap_k x (C + 1) of a level done in one block
+
+struct PyrLevels {
+    int k0, levels;
+    const int32_t* cptr[BS_MAX_LEVELS];    // level k: CSR of children (level k-1 vertices)
+    const int32_t* clist[BS_MAX_LEVELS];
+    const int32_t* ones[BS_MAX_LEVELS];
+    const int32_t* parent[BS_MAX_LEVELS];  // level k vertex -> level k+1 vertex
+    float* up[BS_MAX_LEVELS];
+    float wk[BS_MAX_LEVELS];
+};
+
+__global__ void __launch_bounds__(1024) pyr_small(PyrLevels a, const float* __restrict__ b,
+                                                   const float* __restrict__ sc, int C,
+                                                   const int32_t* __restrict__ counts) {
+    const int K = counts[CNT_K];
+    const int C1 = C + 1;
+    for (int k = a.k0; k < a.levels && k <= K; ++k) {
+        const int Vk = counts[CNT_LEVEL0 + k];
+        const float* prev = k >= 2 ? a.up[k - 1] : nullptr;
+        const int32_t* cptr = a.cptr[k];
+        const int32_t* clist = a.clist[k];
+        float* up = a.up[k];
+        const int64_t n = (int64_t)Vk * C1;
+        for (int64_t e = threadIdx.x; e < n; e += blockDim.x) {
+            const int u = (int)(e / C1), ch = (int)(e - (int64_t)u * C1);
+            double s = 0.0;
+            for (int j = cptr[u]; j < cptr[u + 1]; ++j) {
+                const int c = clist[j];
+                if (prev) s += (double)prev[(int64_t)c * C1 + ch];
+                else s += (double)(ch < C ? b[(int64_t)c * C + ch] : sc[c]);
+            }
+            up[e] = (float)s;
+        }
+        __syncthreads();
+    }
+    for (int k = a.levels - 1; k >= a.k0; --k) {
+        if (K < k) continue;
+        const int Vk = counts[CNT_LEVEL0 + k];
+        float* up = a.up[k];
+        const float* upp = (k < K) ? a.up[k + 1] : nullptr;
+        const int32_t* parent = a.parent[k];
+        const int32_t* ones = a.ones[k];
+        const float wk = a.wk[k];
+        const int64_t n = (int64_t)Vk * C1;
+        for (int64_t e = threadIdx.x; e < n; e += blockDim.x) {
+            const int u = (int)(e / C1), ch = (int)(e - (int64_t)u * C1);
+            float v = wk * up[e] / (float)ones[u];
+            if (upp) v += upp[(int64_t)parent[u] * C1 + ch];
+            up[e] = v;
+        }
+        __syncthreads();
+    }
+}
+
 // Level 0 of the collapse and the ratio of the two push-pull filters:
 // y0 = (b + acc_1[parent]) / (S c + acc_1[parent][C]), 0 where the
 // denominator is 0 (zero total confidence).
@@ -660,14 +718,18 @@ __device__ inline void load_ops(MatOps<K>& o, int v, const int (&nb)[10], const 
                                 const PcgImage& I, const float* __restrict__ dold) {
     o.v = v;
     const int Cp = I.Cp;
+    // Missing neighbours (about half of the slots) load nothing: the lanes
+    // are masked off, which halves the bytes the texture path delivers.
 #pragma unroll
     for (int j = 0; j < 10; ++j) {
         o.nb[j] = nb[j];
-        const int u = nb[j] >= 0 ? nb[j] : v;
-        const int64_t eu = (int64_t)u * Cp + ln.g * K;
-        o.r[j] = ldv<K>(I.r + eu);
-        o.d[j] = ldv<K>(dold + eu);
-        o.nm[j] = I.nfm[u];
+        const int u = nb[j];
+        if (u >= 0) {
+            const int64_t eu = (int64_t)u * Cp + ln.g * K;
+            o.r[j] = ldv<K>(I.r + eu);
+            o.d[j] = ldv<K>(dold + eu);
+            o.nm[j] = I.nfm[u];
+        }
     }
     const int64_t e = (int64_t)v * Cp + ln.g * K;
     o.rv = ldv<K>(I.r + e);
@@ -1020,13 +1082,32 @@ static bs_status run_init(const GridImpl& g, const SolveWs& w, const bs_solve_pa
                   w.sc, C, g.counts, y);
         return BS_OK;
     }
-    for (int k = 1; k < g.levels; ++k) {
+    // levels k0.. are small enough for one block (capacities decrease with k)
+    int k0 = 1;
+    while (k0 < g.levels && g.lv[k0].cap * (C + 1) > kSmallPyrElems) ++k0;
+    for (int k = 1; k < k0; ++k) {
         const int bk = grid_blocks(ceil_div(g.lv[k].cap * (C + 1), kBlock));
         BS_LAUNCH(s, K_INIT, "pyr_up", pyr_up, dim3(bk), dim3(kBlock), 0, s, g.lv[k].ptr,
                   g.lv[k].list, w.b, w.sc, (const float*)(k >= 2 ? w.up[k - 1] : nullptr),
                   w.up[k], C, k, g.counts);
     }
-    for (int k = g.levels - 1; k >= 1; --k) {
+    if (k0 < g.levels) {
+        PyrLevels a;
+        std::memset(&a, 0, sizeof(a));
+        a.k0 = k0;
+        a.levels = g.levels;
+        for (int k = 1; k < g.levels; ++k) {
+            a.cptr[k] = g.lv[k].ptr;
+            a.clist[k] = g.lv[k].list;
+            a.ones[k] = g.lv[k].ones;
+            a.parent[k] = (k + 1 < g.levels) ? g.lv[k + 1].item_parent : nullptr;
+            a.up[k] = w.up[k];
+            a.wk[k] = (float)std::pow((double)p.init_alpha, -((double)p.init_beta + k));
+        }
+        BS_LAUNCH(s, K_INIT, "pyr_small", pyr_small, dim3(1), dim3(1024), 0, s, a, w.b, w.sc, C,
+                  g.counts);
+    }
+    for (int k = k0 - 1; k >= 1; --k) {
         const int bk = grid_blocks(ceil_div(g.lv[k].cap * (C + 1), kBlock));
         const float wk = (float)std::pow((double)p.init_alpha, -((double)p.init_beta + k));
         const float* upp = (k + 1 < g.levels) ? w.up[k + 1] : nullptr;
