@@ -251,7 +251,8 @@ size_t bs_batch_workspace_bytes(const bs_batch_item* items, int32_t n, int32_t n
  * bistochastization, splat, initial state) runs on `n_streams` library-owned
  * streams driven by as many host threads, largest images first.  The PCG
  * then runs over all images together: images with the same lane width
- * (C = 1; C = 2; C >= 3) share one launch per PCG phase, each image keeping
+ * (channels per lane: 1, 2, 3 or 4, see bs_solve_channel_stride) share one
+ * launch per PCG phase, each image keeping
  * its own per-channel stopping rule.  Everything is ordered after the work
  * already enqueued on `stream`, and the PCG, slices and copies run on
  * `stream`.  Returns after enqueueing the slices; the call synchronises
@@ -294,7 +295,8 @@ bs_status bs_grid_get_view(const bs_grid* grid, bs_grid_view* view);
  * tests).  Run bs_solve with max_iters = 0 to obtain the initial state y0 in
  * y. */
 /* Channel stride of the solver's internal [V][Cs] vectors for C channels: C
- * for C <= 2, else C rounded up to a multiple of 4 (0 for C outside 1..64). */
+ * for C <= 2, for C divisible by 4 or by 3, else C rounded up to a multiple
+ * of 4 (0 for C outside 1..64). */
 int32_t bs_solve_channel_stride(int32_t C);
 
 bs_status bs_solve_ws_view(const bs_grid* grid, int32_t C, void* ws, size_t ws_bytes,

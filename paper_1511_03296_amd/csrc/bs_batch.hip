@@ -4,7 +4,7 @@
 // one HIP stream, takes images from a shared queue (largest first) and builds
 // the grid, bistochastizes it, splats the right-hand side and computes the
 // initial state.  The PCG then runs over all images at once: images that share
-// a lane width (1, 2 or 4 channels per lane) form a group whose every PCG
+// a lane width (1 to 4 channels per lane) form a group whose every PCG
 // phase is ONE launch, each block working on one image through a block-to-image
 // table, each image with its own channel state, partials and stopping rule;
 // blocks of stopped images return at once.  Small images, which alone are
@@ -28,8 +28,8 @@ namespace {
 
 constexpr int kMaxStreams = 16;
 // PCG tiles per block of a batched launch: fewer, longer-running blocks
-// measured faster (16 tiles for 4-channel lanes, 8 otherwise).
-inline int tiles_per_block(int K) { return K == 4 ? 16 : 8; }
+// measured faster (16 tiles for 3- and 4-channel lanes, 8 otherwise).
+inline int tiles_per_block(int K) { return K >= 3 ? 16 : 8; }
 
 struct StreamPool {
     std::mutex mu;
@@ -216,7 +216,7 @@ bs_status batched_pcg(const bs_batch_item* items, int n, const bs_grid* grids,
     std::vector<PcgImage> imgs;
     std::vector<int32_t> blk;
     std::vector<Group> groups;
-    for (int K : {4, 2, 1}) {
+    for (int K : {4, 3, 2, 1}) {
         Group gr{K, (int)imgs.size(), 0, 0, 0, blk.size()};
         for (int i = 0; i < n; ++i) {
             Plan& pl = plans[i];

@@ -2,12 +2,13 @@
 // Algorithm 2, Section 4 initialisation) and its backward pass (Section 3).
 //
 // Layouts: pixel planes [C][P] float32; bilateral-space vectors [V][Cp]
-// float32, channels contiguous per vertex, with the channel stride Cp padded
-// to a multiple of 4 when C >= 3 (padding channels hold zeros and never
-// iterate).  A lane of the vertex kernels owns K = 1, 2 or 4 consecutive
-// channels of one vertex (one float, float2 or float4 access); Lv = Cp / K
-// lanes cover a vertex, so the neighbour table and the per-vertex scalars are
-// read by Lv lanes rather than by every channel.
+// float32, channels contiguous per vertex.  A lane of the vertex kernels owns
+// K consecutive channels of one vertex: K = C for C <= 2, else 4 when 4
+// divides C, 3 when 3 does, 4 otherwise (one float, float2, 3-float or float4
+// access).  The channel stride Cp is C rounded up to a multiple of K (padding
+// channels hold zeros and never iterate); Lv = Cp / K lanes cover a vertex, so
+// the neighbour table and the per-vertex scalars are read by Lv lanes rather
+// than by every channel.
 //
 // PCG (supplement Algorithm 2) runs one independent PCG per channel.  One
 // iteration is two kernels, each with one grid-wide reduction:
@@ -32,6 +33,21 @@
 namespace bs {
 
 enum Ctl : int { CTL_SIZE = 8 };
+
+// A pointer into global memory.  The PCG kernels reach their vectors through
+// such typed pointers: pointers read from a table in memory carry no address
+// space, and accesses through them would be flat instructions, which also
+// count against the LDS counter (every LDS wait would then wait for the
+// outstanding memory loads too).
+// (The host compilation pass only type-checks the kernels; there it is a
+// plain pointer.  No value of this type crosses between host and device.)
+#if defined(__HIP_DEVICE_COMPILE__)
+template <class T>
+using gp = __attribute__((address_space(1))) T*;
+#else
+template <class T>
+using gp = T*;
+#endif
 
 size_t layout_solve(const GridImpl& g, int C, int nb, void* base, SolveWs& w) {
     w.C = C;
@@ -77,32 +93,34 @@ struct Vec {
 };
 
 template <int K>
-__device__ inline Vec<K> ldv(const float* __restrict__ p) {
+__device__ inline Vec<K> ldv(gp<const float> p) {
     Vec<K> o;
     if constexpr (K == 4) {
-        const float4 t = *reinterpret_cast<const float4*>(p);
+        const float4 t = *reinterpret_cast<gp<const float4>>(p);
         o.v[0] = t.x;
         o.v[1] = t.y;
         o.v[2] = t.z;
         o.v[3] = t.w;
     } else if constexpr (K == 2) {
-        const float2 t = *reinterpret_cast<const float2*>(p);
+        const float2 t = *reinterpret_cast<gp<const float2>>(p);
         o.v[0] = t.x;
         o.v[1] = t.y;
     } else {
-        o.v[0] = *p;
+#pragma unroll
+        for (int k = 0; k < K; ++k) o.v[k] = p[k];
     }
     return o;
 }
 
 template <int K>
-__device__ inline void stv(float* __restrict__ p, const Vec<K>& a) {
+__device__ inline void stv(gp<float> p, const Vec<K>& a) {
     if constexpr (K == 4) {
-        *reinterpret_cast<float4*>(p) = make_float4(a.v[0], a.v[1], a.v[2], a.v[3]);
+        *reinterpret_cast<gp<float4>>(p) = make_float4(a.v[0], a.v[1], a.v[2], a.v[3]);
     } else if constexpr (K == 2) {
-        *reinterpret_cast<float2*>(p) = make_float2(a.v[0], a.v[1]);
+        *reinterpret_cast<gp<float2>>(p) = make_float2(a.v[0], a.v[1]);
     } else {
-        *p = a.v[0];
+#pragma unroll
+        for (int k = 0; k < K; ++k) p[k] = a.v[k];
     }
 }
 
@@ -129,7 +147,7 @@ struct Lanes {
 // part[(k Cp + ch) nb + slot].
 template <int NV, int K>
 __device__ inline void lane_partials(const double (&acc)[NV][K], const Lanes& ln, int Cp,
-                                     int nb, int slot, double* __restrict__ part) {
+                                     int nb, int slot, gp<double> part) {
     const int t = threadIdx.x;
     if (ln.Lv == 1) {
         // one lane per vertex: shuffle trees per wave, then one pass over the waves
@@ -184,7 +202,7 @@ struct PartialSums {
     double v[kMax];
     int pairs, q, pair, seg, G;
     bool held;
-    const double* pre;   // sums already reduced by pcg_reduce, or nullptr
+    gp<const double> pre;   // sums already reduced by pcg_reduce, or nullptr
 
     // Lanes per pair for `pairs` sums over G partials, and whether each lane's
     // share fits in registers (the host uses the same rule to decide when to
@@ -200,8 +218,8 @@ struct PartialSums {
         return pairs * q <= kRedBlock && G / q <= kMax;
     }
 
-    __device__ void load(const double* __restrict__ part, int nv_c, int grid,
-                         const double* __restrict__ sums = nullptr) {
+    __device__ void load(gp<const double> part, int nv_c, int grid,
+                         gp<const double> sums = nullptr) {
         pre = sums;
         pairs = nv_c;
         G = grid;
@@ -220,7 +238,7 @@ struct PartialSums {
         }
     }
 
-    __device__ void sum(const double* __restrict__ part, double* out) {
+    __device__ void sum(gp<const double> part, double* out) {
         if (pre) {
             if ((int)threadIdx.x < pairs) out[threadIdx.x] = v[0];
         } else if (held) {
@@ -245,8 +263,8 @@ struct PartialSums {
 };
 
 template <int NV>
-__device__ inline void reduce_partials(const double* __restrict__ part, int Cp, int G,
-                                       double* out, const double* __restrict__ sums = nullptr) {
+__device__ inline void reduce_partials(gp<const double> part, int Cp, int G, double* out,
+                                       gp<const double> sums = nullptr) {
     PartialSums ps;
     ps.load(part, NV * Cp, G, sums);
     ps.sum(part, out);
@@ -278,6 +296,32 @@ __device__ inline void store_state(ChanState& d, const ChanState& s) {
     d.iters = s.iters;
     d.reason = s.reason;
     d.phase = s.phase;
+}
+
+__device__ inline ChanState load_state(gp<const ChanRec> p) {
+    ChanState s;
+    s.rho = p->s.rho;
+    s.alpha = p->s.alpha;
+    s.beta = p->s.beta;
+    s.bnorm = p->s.bnorm;
+    s.res = p->s.res;
+    s.active = p->s.active;
+    s.iters = p->s.iters;
+    s.reason = p->s.reason;
+    s.phase = p->s.phase;
+    return s;
+}
+
+__device__ inline void store_state(gp<ChanRec> p, const ChanState& s) {
+    p->s.rho = s.rho;
+    p->s.alpha = s.alpha;
+    p->s.beta = s.beta;
+    p->s.bnorm = s.bnorm;
+    p->s.res = s.res;
+    p->s.active = s.active;
+    p->s.iters = s.iters;
+    p->s.reason = s.reason;
+    p->s.phase = s.phase;
 }
 
 __device__ inline ChanState zero_state() {
@@ -630,16 +674,75 @@ __device__ inline const PcgImage& block_image(const PcgArgs& a, int& jb) {
     }
 }
 
+// The kernels' view of one image: the descriptor's fields as separate
+// scalars (run-time indices into its two-slot arrays would keep a copy in
+// private memory), with every pointer typed global.
+struct ImgView {
+    gp<const int32_t> nbr;
+    gp<const float2> nfm;
+    gp<const float> sc;
+    gp<const float> b;
+    gp<float> y;
+    gp<float> r;
+    gp<float> d0;
+    gp<float> d1;
+    gp<float> q;
+    gp<const int32_t> counts;
+    gp<ChanRec> cs0;
+    gp<ChanRec> cs1;
+    gp<double> part0;
+    gp<double> part1;
+    gp<const double> sums0;
+    gp<const double> sums1;
+    gp<double> wsums0;
+    gp<double> wsums1;
+    gp<int32_t> active;
+    gp<bs_chan_stats> stats;
+    int64_t vcap;
+    float lam;
+    int C, Cp, nb;
+};
+
+__device__ inline ImgView view_of(const PcgImage& s) {
+    ImgView I;
+    I.nbr = (gp<const int32_t>)s.nbr;
+    I.nfm = (gp<const float2>)s.nfm;
+    I.sc = (gp<const float>)s.sc;
+    I.b = (gp<const float>)s.b;
+    I.y = (gp<float>)s.y;
+    I.r = (gp<float>)s.r;
+    I.d0 = (gp<float>)s.d[0];
+    I.d1 = (gp<float>)s.d[1];
+    I.q = (gp<float>)s.q;
+    I.counts = (gp<const int32_t>)s.counts;
+    I.cs0 = (gp<ChanRec>)s.cs[0];
+    I.cs1 = (gp<ChanRec>)s.cs[1];
+    I.part0 = (gp<double>)s.part[0];
+    I.part1 = (gp<double>)s.part[1];
+    I.wsums0 = (gp<double>)s.sums[0];
+    I.wsums1 = (gp<double>)s.sums[1];
+    I.sums0 = I.wsums0;
+    I.sums1 = I.wsums1;
+    I.active = (gp<int32_t>)s.active;
+    I.stats = (gp<bs_chan_stats>)s.stats;
+    I.vcap = s.vcap;
+    I.lam = s.lam;
+    I.C = s.C;
+    I.Cp = s.Cp;
+    I.nb = s.nb;
+    return I;
+}
+
 // Clears the channel state; the image is active until its first stop test.
 template <bool MULTI>
 __global__ void __launch_bounds__(kRedBlock) pcg_prologue(PcgArgs a) {
     int jb;
-    const PcgImage& I = block_image<MULTI>(a, jb);
+    const ImgView I = view_of(block_image<MULTI>(a, jb));
     const int t = threadIdx.x;
     if (t < I.Cp) {
         const ChanState z = zero_state();
-        store_state(I.cs[0][(int64_t)jb * I.Cp + t].s, z);
-        store_state(I.cs[1][(int64_t)jb * I.Cp + t].s, z);
+        store_state(I.cs0 + (int64_t)jb * I.Cp + t, z);
+        store_state(I.cs1 + (int64_t)jb * I.Cp + t, z);
     }
     if (jb == 0 && t == 0) *I.active = 1;
 }
@@ -648,7 +751,7 @@ __global__ void __launch_bounds__(kRedBlock) pcg_prologue(PcgArgs a) {
 template <int K, bool MULTI>
 __global__ void __launch_bounds__(kRedBlock) pcg_start(PcgArgs a) {
     int jb;
-    const PcgImage& I = block_image<MULTI>(a, jb);
+    const ImgView I = view_of(block_image<MULTI>(a, jb));
     const int V = I.counts[CNT_V];
     const int Cp = I.Cp, nb = I.nb;
     const Lanes ln(Cp, K);
@@ -689,7 +792,7 @@ __global__ void __launch_bounds__(kRedBlock) pcg_start(PcgArgs a) {
         }
         stv<K>(I.r + e, rv);
     }
-    lane_partials<3, K>(acc, ln, Cp, nb, partial_slot(jb, nb), I.part[0]);
+    lane_partials<3, K>(acc, ln, Cp, nb, partial_slot(jb, nb), I.part0);
 }
 
 // Operands of one lane of pcg_matvec.  Loading them does not depend on the
@@ -707,7 +810,7 @@ struct MatOps {
 };
 
 // Neighbour indices of vertex v (phase 1 of a tile's loads).
-__device__ inline void load_nbr(int (&nb)[10], int v, const PcgImage& I) {
+__device__ inline void load_nbr(int (&nb)[10], int v, const ImgView& I) {
 #pragma unroll
     for (int j = 0; j < 10; ++j) nb[j] = I.nbr[j * I.vcap + v];
 }
@@ -715,7 +818,7 @@ __device__ inline void load_nbr(int (&nb)[10], int v, const PcgImage& I) {
 // The gathers and per-vertex operands of vertex v (phase 2).
 template <int K>
 __device__ inline void load_ops(MatOps<K>& o, int v, const int (&nb)[10], const Lanes& ln,
-                                const PcgImage& I, const float* __restrict__ dold) {
+                                const ImgView& I, gp<const float> dold) {
     o.v = v;
     const int Cp = I.Cp;
     // Missing neighbours (about half of the slots) load nothing: the lanes
@@ -753,7 +856,7 @@ __global__ void __launch_bounds__(kRedBlock) pcg_matvec(PcgArgs a, int it) {
     __shared__ double fin[3 * BS_MAX_CHANNELS];
     __shared__ int n_active;
     int jb;
-    const PcgImage& I = block_image<MULTI>(a, jb);
+    const ImgView I = view_of(block_image<MULTI>(a, jb));
     if constexpr (MULTI) {
         if (*I.active == 0) return;   // stopped image
     }
@@ -761,16 +864,16 @@ __global__ void __launch_bounds__(kRedBlock) pcg_matvec(PcgArgs a, int it) {
     const int V = I.counts[CNT_V];
     const int Cp = I.Cp, nb = I.nb;
     const Lanes ln(Cp, K);
-    const float* dold = I.d[(it + 1) & 1];
-    float* dnew = I.d[it & 1];
+    gp<const float> dold = (it & 1) ? I.d0 : I.d1;
+    gp<float> dnew = (it & 1) ? I.d1 : I.d0;
     const XcdTiles tl((V + ln.vpb - 1) / ln.vpb, jb, nb);
     // Loads complete in issue order: partials and state first, then the first
     // tile's operands, which stay in flight during the reduction.
     PartialSums ps;
-    ps.load(I.part[0], 3 * Cp, nb, I.sums[0]);
+    ps.load(I.part0, 3 * Cp, nb, I.sums0);
     // every lane loads a record (lanes >= Cp a duplicate): a conditional load
     // merged with a default would be waited for before the operand loads
-    ChanState st0 = load_state(I.cs[0][(int64_t)jb * Cp + min(t, Cp - 1)].s);
+    ChanState st0 = load_state(I.cs0 + (int64_t)jb * Cp + min(t, Cp - 1));
     MatOps<K> o;
     int nbn[10];
     int v = (int)(tl.first * ln.vpb) + ln.vl;
@@ -779,14 +882,14 @@ __global__ void __launch_bounds__(kRedBlock) pcg_matvec(PcgArgs a, int it) {
         load_nbr(nbn, v, I);
         load_ops<K>(o, v, nbn, ln, I, dold);
     }
-    ps.sum(I.part[0], fin);
+    ps.sum(I.part0, fin);
     if (t == 0) n_active = 0;
     __syncthreads();
     if (t < Cp) {
         st0 = advance_state(st0, fin[t], fin[Cp + t], fin[2 * Cp + t], a.max_iters, a.tol);
         store_state(S[t], st0);
         if (st0.active) atomicAdd(&n_active, 1);
-        store_state(I.cs[1][(int64_t)jb * Cp + t].s, st0);
+        store_state(I.cs1 + (int64_t)jb * Cp + t, st0);
     }
     __syncthreads();
     if (jb == 0 && t == 0) *I.active = n_active;
@@ -843,7 +946,7 @@ __global__ void __launch_bounds__(kRedBlock) pcg_matvec(PcgArgs a, int it) {
         if (hn) load_ops<K>(o, vn, nbn, ln, I, dold);
         have = hn;
     }
-    lane_partials<1, K>(acc, ln, Cp, nb, partial_slot(jb, nb), I.part[1]);
+    lane_partials<1, K>(acc, ln, Cp, nb, partial_slot(jb, nb), I.part1);
 }
 
 // Prologue: alpha = r^T M^-1 r / d^T q from the slot-1 partials (a channel
@@ -855,7 +958,7 @@ __global__ void __launch_bounds__(kRedBlock) pcg_update(PcgArgs a, int it) {
     __shared__ double fin[BS_MAX_CHANNELS];
     __shared__ int n_active;
     int jb;
-    const PcgImage& I = block_image<MULTI>(a, jb);
+    const ImgView I = view_of(block_image<MULTI>(a, jb));
     if constexpr (MULTI) {
         if (*I.active == 0) return;
     }
@@ -863,11 +966,11 @@ __global__ void __launch_bounds__(kRedBlock) pcg_update(PcgArgs a, int it) {
     const int V = I.counts[CNT_V];
     const int Cp = I.Cp, nb = I.nb;
     const Lanes ln(Cp, K);
-    const float* d = I.d[it & 1];
+    gp<const float> d = (it & 1) ? I.d1 : I.d0;
     const XcdTiles tl((V + ln.vpb - 1) / ln.vpb, jb, nb);
     PartialSums ps;
-    ps.load(I.part[1], Cp, nb, I.sums[1]);
-    ChanState st0 = load_state(I.cs[1][(int64_t)jb * Cp + min(t, Cp - 1)].s);
+    ps.load(I.part1, Cp, nb, I.sums1);
+    ChanState st0 = load_state(I.cs1 + (int64_t)jb * Cp + min(t, Cp - 1));
     // first tile's operands in flight during the reduction
     int v = (int)(tl.first * ln.vpb) + ln.vl;
     bool have = ln.ok && tl.first < tl.end && v < V;
@@ -881,7 +984,7 @@ __global__ void __launch_bounds__(kRedBlock) pcg_update(PcgArgs a, int it) {
         qv = ldv<K>(I.q + e);
         miv = I.nfm[v].y;
     }
-    ps.sum(I.part[1], fin);
+    ps.sum(I.part1, fin);
     if (t == 0) n_active = 0;
     __syncthreads();
     if (t < Cp) {
@@ -896,7 +999,7 @@ __global__ void __launch_bounds__(kRedBlock) pcg_update(PcgArgs a, int it) {
         }
         store_state(S[t], st0);
         if (st0.active) atomicAdd(&n_active, 1);
-        store_state(I.cs[0][(int64_t)jb * Cp + t].s, st0);
+        store_state(I.cs0 + (int64_t)jb * Cp + t, st0);
     }
     __syncthreads();
     if (jb == 0 && t == 0) *I.active = n_active;
@@ -956,7 +1059,7 @@ __global__ void __launch_bounds__(kRedBlock) pcg_update(PcgArgs a, int it) {
         qv = qn;
         miv = min_;
     }
-    lane_partials<3, K>(acc, ln, Cp, nb, partial_slot(jb, nb), I.part[0]);
+    lane_partials<3, K>(acc, ln, Cp, nb, partial_slot(jb, nb), I.part0);
 }
 
 // With many channels the per-block partials are reduced once, by one block
@@ -964,13 +1067,13 @@ __global__ void __launch_bounds__(kRedBlock) pcg_update(PcgArgs a, int it) {
 // Block (pair, image); `mult` values per channel in slot `which`.
 template <bool MULTI>
 __global__ void __launch_bounds__(kRedBlock) pcg_reduce(PcgArgs a, int which, int mult) {
-    const PcgImage& I = MULTI ? a.imgs[blockIdx.y] : a.one;
-    double* sums = I.sums[which];
+    const ImgView I = view_of(MULTI ? a.imgs[blockIdx.y] : a.one);
+    gp<double> sums = which ? I.wsums1 : I.wsums0;
     if (!sums || (int)blockIdx.x >= mult * I.Cp) return;
     if constexpr (MULTI) {
         if (*I.active == 0) return;
     }
-    const double* part = I.part[which];
+    gp<const double> part = which ? I.part1 : I.part0;
     const int G = I.nb;
     double v = 0.0;
     for (int i = threadIdx.x; i < G; i += kRedBlock) v += part[(int64_t)blockIdx.x * G + i];
@@ -983,11 +1086,11 @@ __global__ void __launch_bounds__(kRedBlock) pcg_reduce(PcgArgs a, int which, in
 template <bool MULTI>
 __global__ void __launch_bounds__(kRedBlock) pcg_finish(PcgArgs a) {
     __shared__ double fin[3 * BS_MAX_CHANNELS];
-    const PcgImage& I = MULTI ? a.imgs[blockIdx.x] : a.one;
+    const ImgView I = view_of(MULTI ? a.imgs[blockIdx.x] : a.one);
     const int t = threadIdx.x;
-    reduce_partials<3>(I.part[0], I.Cp, I.nb, fin, I.sums[0]);
+    reduce_partials<3>(I.part0, I.Cp, I.nb, fin, I.sums0);
     if (t < I.C && I.stats) {
-        ChanState st = load_state(I.cs[0][t].s);
+        ChanState st = load_state(I.cs0 + t);
         st = advance_state(st, fin[t], fin[I.Cp + t], fin[2 * I.Cp + t], a.max_iters, a.tol);
         bs_chan_stats o;
         o.iters = st.iters;
@@ -1217,6 +1320,9 @@ bs_status run_pcg(int K, const PcgImage* imgs, int n, const PcgImage* dev_imgs,
         case 2:
             return multi ? run_pcg_k<2, true>(a, n, G, max_cp, sep, p, act, s)
                          : run_pcg_k<2, false>(a, n, G, max_cp, sep, p, act, s);
+        case 3:
+            return multi ? run_pcg_k<3, true>(a, n, G, max_cp, sep, p, act, s)
+                         : run_pcg_k<3, false>(a, n, G, max_cp, sep, p, act, s);
         case 4:
             return multi ? run_pcg_k<4, true>(a, n, G, max_cp, sep, p, act, s)
                          : run_pcg_k<4, false>(a, n, G, max_cp, sep, p, act, s);

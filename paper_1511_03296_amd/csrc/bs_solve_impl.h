@@ -22,10 +22,20 @@ struct alignas(128) ChanRec {
 };
 static_assert(sizeof(ChanRec) == 128, "one record per cache line");
 
-// Channels per lane of the vertex kernels (1, 2 or 4: float, float2, float4
-// accesses) and the padded channel stride of the bilateral-space vectors.
-inline int lane_width(int C) { return C == 1 ? 1 : (C == 2 ? 2 : 4); }
-inline int padded_channels(int C) { return C <= 2 ? C : (C + 3) & ~3; }
+// Channels per lane of the vertex kernels (1, 2, 3 or 4: one float, float2,
+// 3-float or float4 access) and the channel stride of the bilateral-space
+// vectors, C rounded up to a multiple of the lane width (C = 21 = 7 x 3
+// needs no padding).
+inline int lane_width(int C) {
+    if (C <= 2) return C;
+    if (C % 4 == 0) return 4;
+    if (C % 3 == 0) return 3;
+    return 4;
+}
+inline int padded_channels(int C) {
+    const int K = lane_width(C);
+    return (C + K - 1) / K * K;
+}
 
 // One image of a PCG launch.  In a launch over several images, blocks
 // [block0, block0 + nb) work on this image; block0 and nb are multiples of 8,
