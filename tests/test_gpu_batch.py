@@ -118,3 +118,53 @@ def test_batch_rejects_bad_items():
     with pytest.raises(ValueError):
         BatchState([to_dev(p.ref)], [to_dev(p.target)], [to_dev(p.conf)],
                    [(8, 4, 4)], 17)
+
+
+def test_batched_autograd_fd_crop_21_channels():
+    """The segmentation workload's gradient check: on a 16x12 crop with 21
+    channels, the gradients of loss = sum (x - onehot)^2 through the batched
+    autograd form match FP64 central differences of the oracle's loss at
+    sampled target and confidence entries."""
+    from paper_1511_03296_amd import bilateral_solve_batch
+    p = WL.crop(WL.segmentation(seed=2), 100, 200, 12, 16)
+    onehot = p.extra["onehot"].astype(np.float64)
+    say("batched autograd FD 16x12 c21")
+    t_dev = to_dev(p.target).requires_grad_(True)
+    c_dev = to_dev(p.conf).requires_grad_(True)
+    xs = bilateral_solve_batch([to_dev(p.ref)], [t_dev], [c_dev],
+                               [(p.sigma_xy, p.sigma_l, p.sigma_uv)], p.lam, max_iters=5000,
+                               rel_tol=1e-7)
+    loss = ((xs[0] - torch.from_numpy(onehot.astype(np.float32)).cuda()) ** 2).sum()
+    loss.backward()
+    torch.cuda.synchronize()
+    gt = t_dev.grad.cpu().numpy().astype(np.float64)
+    gc = c_dev.grad.cpu().numpy().astype(np.float64)
+
+    prm = params(p, rel_tol=1e-13, max_iters=20000)
+    prepared = O.prepare(p.ref, prm)
+
+    def loss64(t, c):
+        sol = O.solve(p.ref, t, c, prm, prepared=prepared)
+        return float(np.sum((sol.x - onehot) ** 2))
+
+    t0 = p.target.astype(np.float64)
+    c0 = p.conf.astype(np.float64)
+    rng = np.random.default_rng(7)
+    fd_t, an_t, fd_c, an_c = [], [], [], []
+    for _ in range(12):
+        ch, y, x = rng.integers(0, p.C), rng.integers(0, p.H), rng.integers(0, p.W)
+        h = 1e-3
+        tp, tm = t0.copy(), t0.copy()
+        tp[ch, y, x] += h
+        tm[ch, y, x] -= h
+        fd_t.append((loss64(tp, c0) - loss64(tm, c0)) / (2 * h))
+        an_t.append(gt[ch, y, x])
+        y, x = rng.integers(0, p.H), rng.integers(0, p.W)
+        h = 1e-4
+        cp, cm = c0.copy(), c0.copy()
+        cp[y, x] += h
+        cm[y, x] -= h
+        fd_c.append((loss64(t0, cp) - loss64(t0, cm)) / (2 * h))
+        an_c.append(gc[y, x])
+    assert rel_l2(an_t, fd_t) <= TOL, (an_t, fd_t)
+    assert rel_l2(an_c, fd_c) <= TOL, (an_c, fd_c)
