@@ -245,12 +245,43 @@ bs_status batched_pcg(const bs_batch_item* items, int n, const bs_grid* grids,
                               hipMemcpyHostToDevice, cs));
     // the host vectors must outlive the copies
     BS_TRY_HIP(hipStreamSynchronize(cs));
-    for (const Group& gr : groups) {
-        const bs_status st =
-            run_pcg(gr.K, imgs.data() + gr.first, gr.count, d_imgs + gr.first,
-                    d_blk + gr.blk_first, gr.G, gr.max_cp, p, d_act + gr.first, cs);
-        if (st != BS_OK) return st;
+    // The groups are independent: each runs on its own library stream and host
+    // thread, so the small images' latency-bound launches overlap the large
+    // images' bandwidth-bound ones.
+    const int ng = (int)groups.size();
+    if (ng == 1) {
+        const Group& gr = groups[0];
+        return run_pcg(gr.K, imgs.data() + gr.first, gr.count, d_imgs + gr.first,
+                       d_blk + gr.blk_first, gr.G, gr.max_cp, p, d_act + gr.first, cs);
     }
+    int device = 0;
+    BS_TRY_HIP(hipGetDevice(&device));
+    StreamPool& sp = pool();
+    std::lock_guard<std::mutex> lock(sp.mu);
+    bs_status st = ensure_pool(ng, device);
+    if (st != BS_OK) return st;
+    BS_TRY_HIP(hipEventRecord(sp.start, cs));
+    for (int g = 0; g < ng; ++g) BS_TRY_HIP(hipStreamWaitEvent(sp.streams[g], sp.start, 0));
+    std::vector<bs_status> res(ng, BS_OK);
+    std::vector<std::string> msg(ng);
+    auto work = [&](int g) {
+        hipSetDevice(device);
+        const Group& gr = groups[g];
+        res[g] = run_pcg(gr.K, imgs.data() + gr.first, gr.count, d_imgs + gr.first,
+                         d_blk + gr.blk_first, gr.G, gr.max_cp, p, d_act + gr.first,
+                         sp.streams[g]);
+        if (res[g] != BS_OK) msg[g] = bs_last_error();
+    };
+    std::vector<std::thread> threads;
+    for (int g = 1; g < ng; ++g) threads.emplace_back(work, g);
+    work(0);
+    for (auto& t : threads) t.join();
+    for (int g = 0; g < ng; ++g) {
+        BS_TRY_HIP(hipEventRecord(sp.done[g], sp.streams[g]));
+        BS_TRY_HIP(hipStreamWaitEvent(cs, sp.done[g], 0));
+    }
+    for (int g = 0; g < ng; ++g)
+        if (res[g] != BS_OK) return fail(res[g], msg[g]);
     return BS_OK;
 }
 
