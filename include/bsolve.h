@@ -309,7 +309,10 @@ bs_status bs_solve_ws_view(const bs_grid* grid, int32_t C, void* ws, size_t ws_b
  * returns the summed elapsed milliseconds and launch count of one kernel:
  * "level_count", "level_scan", "level_write", "neighbour_table", "bist_step",
  * "bist_other", "splat", "init", "pcg_start", "pcg_matvec", "pcg_update",
- * "pcg_reduce", "slice" or "grad_scatter".  bs_timing_reset clears the sums. */
+ * "pcg_reduce", "slice" or "grad_scatter".  bs_timing_reset clears the sums.
+ * While enabled, the batch calls run their PCG groups one after another
+ * instead of concurrently, so that every timed launch has the device to
+ * itself. */
 bs_status bs_timing_enable(int32_t on);
 bs_status bs_timing_reset(void);
 bs_status bs_timing_read(const char* kernel, double* total_ms, int64_t* launches);

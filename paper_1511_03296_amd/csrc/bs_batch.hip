@@ -247,12 +247,17 @@ bs_status batched_pcg(const bs_batch_item* items, int n, const bs_grid* grids,
     BS_TRY_HIP(hipStreamSynchronize(cs));
     // The groups are independent: each runs on its own library stream and host
     // thread, so the small images' latency-bound launches overlap the large
-    // images' bandwidth-bound ones.
+    // images' bandwidth-bound ones.  With kernel timing enabled they run one
+    // after another, so that each timed launch has the device to itself.
     const int ng = (int)groups.size();
-    if (ng == 1) {
-        const Group& gr = groups[0];
-        return run_pcg(gr.K, imgs.data() + gr.first, gr.count, d_imgs + gr.first,
-                       d_blk + gr.blk_first, gr.G, gr.max_cp, p, d_act + gr.first, cs);
+    if (ng == 1 || timing_enabled()) {
+        for (const Group& gr : groups) {
+            const bs_status st =
+                run_pcg(gr.K, imgs.data() + gr.first, gr.count, d_imgs + gr.first,
+                        d_blk + gr.blk_first, gr.G, gr.max_cp, p, d_act + gr.first, cs);
+            if (st != BS_OK) return st;
+        }
+        return BS_OK;
     }
     int device = 0;
     BS_TRY_HIP(hipGetDevice(&device));

@@ -45,6 +45,7 @@ enum KernelId : int {
     K_COUNT
 };
 void timing_begin(hipStream_t s, int id);
+bool timing_enabled();
 void timing_end(hipStream_t s, int id);
 
 // Enqueues `launch` on `stream`, bracketed by timing events when enabled, and

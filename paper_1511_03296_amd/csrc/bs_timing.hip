@@ -60,6 +60,8 @@ bs_status drain(Timing& t) {
 thread_local hipEvent_t t_open[K_COUNT] = {};
 }  // namespace
 
+bool timing_enabled() { return T().on.load(std::memory_order_relaxed); }
+
 void timing_begin(hipStream_t s, int id) {
     Timing& t = T();
     if (!t.on.load(std::memory_order_relaxed)) return;
