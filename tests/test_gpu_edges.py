@@ -1,0 +1,95 @@
+"""GPU edge cases of the solve: every lane width and channel padding (C = 4,
+5, 6, 9, 64), degenerate images (one pixel, one row, one column), the
+largest grid scale, a batch mixing them, and invalid inputs rejected on the
+host before anything is launched."""
+import numpy as np
+import pytest
+import torch
+
+import workloads as WL
+from oracle import bilateral as O
+from tests.gpu_helpers import gpu_grid, params, rel_l2, say, to_dev
+
+pytestmark = pytest.mark.gpu
+
+TOL_X = 1e-4
+
+
+def _solve_vs_oracle(p, init="hier", rel_tol=1e-6, max_iters=3000):
+    G = gpu_grid(p)
+    t, c = to_dev(p.target), to_dev(p.conf)
+    y, st = G.solve(t, c, p.lam, max_iters=max_iters, rel_tol=rel_tol, init=init)
+    x = G.slice(y, p.C)
+    torch.cuda.synchronize()
+    exact = O.solve(p.ref, p.target, p.conf, params(p, rel_tol=1e-12, max_iters=20000,
+                                                   init=init))
+    return x.cpu().numpy(), exact, st
+
+
+@pytest.mark.parametrize("C", [4, 5, 6, 9, 64])
+def test_channel_counts(C):
+    # 4: float4 lanes, no padding; 5: float4 lanes padded to 8; 6, 9: 3-float
+    # lanes; 64: 16 lanes per vertex (the widest)
+    p = WL.segmentation(H=40, W=56, regions=10, C=C, rel_tol=1e-6)
+    say(f"edge: channels C={C}")
+    x, exact, st = _solve_vs_oracle(p)
+    assert rel_l2(x, exact.x) <= TOL_X
+    from paper_1511_03296_amd import read_stats
+    s = read_stats(st)
+    assert len(s) == C and np.all(s["reason"] == 1)
+
+
+@pytest.mark.parametrize("H,W", [(1, 1), (1, 50), (50, 1), (2, 3)])
+def test_degenerate_images(H, W):
+    p = WL.tiny_ramp(seed=21, H=H, W=W, regions=min(3, H * W), channels=2)
+    say(f"edge: image {W}x{H}")
+    x, exact, _ = _solve_vs_oracle(p)
+    assert np.all(np.isfinite(x))
+    assert rel_l2(x, exact.x) <= TOL_X
+
+
+def test_largest_grid_scale():
+    # sigma_xy = 128 and colour scales 255: a handful of vertices in one cell
+    p = WL.tiny_ramp(seed=22, H=90, W=120, regions=8, sigma=(128, 255, 255))
+    say("edge: sigma (128, 255, 255)")
+    x, exact, _ = _solve_vs_oracle(p, init="flat")
+    assert rel_l2(x, exact.x) <= TOL_X
+
+
+def test_batch_of_extremes():
+    from paper_1511_03296_amd import BatchState, SolveOptions
+    probs = [WL.tiny_ramp(seed=23, H=1, W=1, regions=1),
+             WL.segmentation(seed=24, H=30, W=44, regions=6, C=64, rel_tol=1e-6),
+             WL.tiny_ramp(seed=25, H=50, W=1, regions=3, channels=2),
+             WL.segmentation(seed=26, H=33, W=47, regions=6, C=5, rel_tol=1e-6)]
+    say("edge: batch of extremes")
+    refs = [to_dev(p.ref) for p in probs]
+    ts = [to_dev(p.target) for p in probs]
+    cs = [to_dev(p.conf) for p in probs]
+    sig = [(p.sigma_xy, p.sigma_l, p.sigma_uv) for p in probs]
+    st = BatchState(refs, ts, cs, sig, 2)
+    xs, _ = st.forward(SolveOptions(128.0, 3000, 1e-6))
+    torch.cuda.synchronize()
+    for i, p in enumerate(probs):
+        exact = O.solve(p.ref, p.target, p.conf,
+                        params(p, lam=128.0, rel_tol=1e-12, max_iters=20000))
+        assert rel_l2(xs[i].cpu().numpy(), exact.x) <= TOL_X, i
+
+
+def test_invalid_inputs_rejected():
+    from paper_1511_03296_amd import BilateralGrid
+    from paper_1511_03296_amd import _lib as L
+    say("edge: invalid inputs")
+    p = WL.tiny_ramp(seed=27)
+    ref = to_dev(p.ref)
+    with pytest.raises(ValueError):
+        BilateralGrid(ref[:, :0, :], 8, 4, 4)        # empty image
+    with pytest.raises(ValueError):
+        BilateralGrid(ref, 0, 4, 4)                  # zero grid scale
+    G = BilateralGrid(ref, 8, 4, 4)
+    t65 = torch.zeros((65, p.H, p.W), device="cuda")
+    with pytest.raises(ValueError):
+        G.solve(t65, to_dev(p.conf), 128.0)          # more than 64 channels
+    with pytest.raises(ValueError):
+        G.solve(to_dev(p.target), to_dev(p.conf), -1.0)   # negative lambda
+    assert L.lib.bs_solve_workspace_bytes(None, 1) == 0
