@@ -1,0 +1,64 @@
+"""Full-size parity of the default benchmark workload, in the launch
+configuration bench.py times: the 64-image mixed batch (43 Mpix, C in
+{1, 2, 21}) through the batch engine on 4 streams, forward and backward to a
+relative residual of 1e-5 with the bench's upstream gradients.  Every image's
+channels must stop on the tolerance; the smallest image of each channel
+count is compared with the oracle (forward and backward), which is too slow
+for the whole batch."""
+import numpy as np
+import pytest
+import torch
+
+import bench
+import workloads as WL
+from oracle import bilateral as O
+from tests.gpu_helpers import rel_l2, say
+
+pytestmark = [pytest.mark.gpu, pytest.mark.slow]
+
+TOL = 1e-4
+
+
+def test_mixed64_batch_in_bench_configuration():
+    from paper_1511_03296_amd import BatchState, SolveOptions, read_stats
+    spec = bench.WORKLOADS["mixed64"]
+    probs = bench.make_problems("mixed64")
+    say(f"full size mixed64: {len(probs)} images, {sum(p.pixels for p in probs)} pixels")
+    inputs = bench.gpu_inputs(probs, spec, torch.device("cuda:0"))
+    (fi, ft), (bi, bt) = spec["fwd"], spec["bwd"]
+    lam = probs[0].lam
+    state = BatchState([d["ref"] for d in inputs], [d["t"] for d in inputs],
+                       [d["c"] for d in inputs],
+                       [(p.sigma_xy, p.sigma_l, p.sigma_uv) for p in probs], 4)
+    xs, fst = state.forward(SolveOptions(lam, fi, ft, check_every=8), stats=True)
+    gts, gcs, bst = state.backward([d["gx"] for d in inputs],
+                                   SolveOptions(lam, bi, bt, check_every=8), stats=True)
+    torch.cuda.synchronize()
+    for i in range(len(probs)):
+        f, b = read_stats(fst[i]), read_stats(bst[i])
+        assert np.all(f["reason"] == 1) and np.all(f["rel_residual"] <= ft), i
+        assert np.all(b["reason"] == 1) and np.all(b["rel_residual"] <= bt), i
+        assert torch.isfinite(xs[i]).all() and torch.isfinite(gts[i]).all(), i
+    by_c = {}
+    for i, p in enumerate(probs):
+        if p.C not in by_c or p.pixels < probs[by_c[p.C]].pixels:
+            by_c[p.C] = i
+    for C, i in sorted(by_c.items()):
+        p = probs[i]
+        say(f"  oracle check image {i}: {p.W}x{p.H} C={C} sigma_xy={p.sigma_xy}")
+        prm = O.Params(p.sigma_xy, p.sigma_l, p.sigma_uv, lam, max_iters=fi, rel_tol=ft)
+        sol = O.solve(p.ref, p.target, p.conf, prm)
+        gx = inputs[i]["gx"].cpu().numpy()
+        prmb = O.Params(p.sigma_xy, p.sigma_l, p.sigma_uv, lam, max_iters=bi, rel_tol=bt)
+        og = O.solve_backward(sol, p.target, p.conf, gx, prmb)
+        assert rel_l2(xs[i].cpu().numpy(), sol.x) <= TOL, i
+        assert rel_l2(gts[i].cpu().numpy(), og.grad_t) <= TOL, i
+        # dL/dc = sum_ch g[idx] (t - y[idx]) cancels where the solution follows
+        # the target, so its error is bounded against the size of its terms,
+        # sum_ch |g[idx]| (|t| + |y[idx]|), at the same relative tolerance
+        idx = sol.grid.idx
+        terms = sum(np.abs(og.gb[idx, ch]) * (np.abs(p.target[ch].reshape(-1)) +
+                                               np.abs(sol.y[idx, ch]))
+                    for ch in range(p.C))
+        err = np.linalg.norm(gcs[i].cpu().numpy().reshape(-1) - og.grad_c.reshape(-1))
+        assert err <= TOL * np.linalg.norm(terms), (i, err / np.linalg.norm(terms))
