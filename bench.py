@@ -52,6 +52,12 @@ WORKLOADS = {
 }
 
 
+def matvec_bytes(C: int, iters: int) -> int:
+    """Algorithmic bytes per vertex of `iters` pcg_matvec iterations."""
+    exact = iters if C <= 2 else iters // 4
+    return exact * (52 + 16 * C) + (iters - exact) * (52 + 20 * C)
+
+
 def _histogram(values) -> dict:
     out = {}
     for v in values:
@@ -276,10 +282,12 @@ def main() -> int:
     sec_inst, kt = kernel_times(inputs, spec, args.steps, streams)
     mv_ms, mv_launches = kt["pcg_matvec"]
     # pcg_matvec reads the neighbour table (40 B), n, S c and M^-1 (4 B each)
-    # and r, d (4C B each), and writes the new d and q (4C B each): algorithmic
-    # bytes of one step's launches over their summed durations.  Launches past
-    # convergence (between stop polls) return at once and count as time only.
-    step_bytes = sum(v * (52 + 16 * p.C) * (fi + bi) for v, p, fi, bi in
+    # and r, d (4C B each), and writes the new d and q (4C B each); on the
+    # iterations that take q by its recurrence (3 of every 4 for C >= 3) it
+    # also reads the old q (4C B).  Algorithmic bytes of one step's launches
+    # over their summed durations.  Launches past convergence (between stop
+    # polls) return at once and count as time only.
+    step_bytes = sum(v * matvec_bytes(p.C, fi + bi) for v, p, fi, bi in
                      zip(V, problems, fwd_iters, bwd_iters))
     avg_us = mv_ms / mv_launches * 1e3 if mv_launches else float("nan")
     bytes_per_launch = step_bytes / mv_launches if mv_launches else 0.0

@@ -12,9 +12,12 @@
 //
 // PCG (supplement Algorithm 2) runs one independent PCG per channel.  One
 // iteration is two kernels, each with one grid-wide reduction:
-//   pcg_matvec:  d = M^-1 r + beta d  (fused: the neighbours' new d values are
-//                recomputed from their gathered r and old d),  q = A d, d^T q;
+//   pcg_matvec:  z = M^-1 r,  d = z + beta d,  q = A d,  d^T q;
 //   pcg_update:  y += alpha d,  r -= alpha q,  r^T r,  r^T M^-1 r.
+// The new d is not stored before the reduction that yields beta, so the
+// matvec either recomputes the neighbours' new d from their gathered r and
+// old d (two gathered vectors), or, for lanes of 3 or 4 channels on most
+// iterations, takes q = A z + beta q by linearity and gathers r alone.
 // A z is evaluated in Laplacian form,
 //   (A z)_v = (S c)_v z_v + lam n_v sum_u n_u (z_v - z_u),
 // which equals diag(A) z - lam n o N(n o z) with diag(A) = lam n o N n + S c,
@@ -798,13 +801,14 @@ __global__ void __launch_bounds__(kRedBlock) pcg_start(PcgArgs a) {
 // Operands of one lane of pcg_matvec.  Loading them does not depend on the
 // iteration's scalars, so the first tile's loads are issued before the
 // prologue and overlap its reduction.
-template <int K>
+template <int K, bool EXACT>
 struct MatOps {
     int v;
     int nb[10];
-    Vec<K> r[10], d[10];
+    Vec<K> r[10];
+    Vec<K> d[EXACT ? 10 : 1];
     float2 nm[10];
-    Vec<K> rv, dv;
+    Vec<K> rv, dv, qv;
     float2 nmv;
     float scv;
 };
@@ -815,10 +819,11 @@ __device__ inline void load_nbr(int (&nb)[10], int v, const ImgView& I) {
     for (int j = 0; j < 10; ++j) nb[j] = I.nbr[j * I.vcap + v];
 }
 
-// The gathers and per-vertex operands of vertex v (phase 2).
-template <int K>
-__device__ inline void load_ops(MatOps<K>& o, int v, const int (&nb)[10], const Lanes& ln,
-                                const ImgView& I, gp<const float> dold) {
+// The gathers and per-vertex operands of vertex v (phase 2): the neighbours'
+// r and {n, M^-1} (and old d when EXACT), the vertex's own r, d and q.
+template <int K, bool EXACT>
+__device__ inline void load_ops(MatOps<K, EXACT>& o, int v, const int (&nb)[10], const Lanes& ln,
+                                const ImgView& I, gp<const float> din) {
     o.v = v;
     const int Cp = I.Cp;
     // Missing neighbours (about half of the slots) load nothing: the lanes
@@ -830,28 +835,35 @@ __device__ inline void load_ops(MatOps<K>& o, int v, const int (&nb)[10], const 
         if (u >= 0) {
             const int64_t eu = (int64_t)u * Cp + ln.g * K;
             o.r[j] = ldv<K>(I.r + eu);
-            o.d[j] = ldv<K>(dold + eu);
+            if constexpr (EXACT) o.d[j] = ldv<K>(din + eu);
             o.nm[j] = I.nfm[u];
         }
     }
     const int64_t e = (int64_t)v * Cp + ln.g * K;
     o.rv = ldv<K>(I.r + e);
-    o.dv = ldv<K>(dold + e);
+    o.dv = ldv<K>(din + e);
+    if constexpr (!EXACT) o.qv = ldv<K>(I.q + e);
     o.nmv = I.nfm[v];
     o.scv = I.sc[v];
 }
 
-// New search direction of one element: M^-1 r + beta d_old (M^-1 r first).
-__device__ inline float pcg_dir(float r, float d_old, float mi, float beta, bool first) {
-    const float s = mi * r;
-    return first ? s : fmaf(beta, d_old, s);
+// New search direction of one element: z + beta d_old.
+__device__ inline float pcg_dir(float z, float d_old, float beta, bool first) {
+    return first ? z : fmaf(beta, d_old, z);
 }
 
 // Prologue: finish the previous step (stopping rule, beta) from the slot-0
-// partials.  Then d = M^-1 r + beta d_old, q = A d and partials of d^T q.
-// Iteration `it` writes d[it % 2] and reads d[(it + 1) % 2].
-template <int K, bool MULTI>
-__global__ void __launch_bounds__(kRedBlock) pcg_matvec(PcgArgs a, int it) {
+// partials.  Then, with z = M^-1 r, d = z + beta d and partials of d^T q,
+// where q = A d is either
+//   EXACT false:  A z + beta q, its recurrence.  Only r is gathered from the
+//                 neighbours; d and q are updated in place (d[src]).
+//   EXACT true:   A d itself, with the neighbours' new d recomputed from
+//                 their gathered r and old d (read from d[src], written to
+//                 d[src ^ 1]).  It resets the rounding that the recurrence
+//                 accumulates.
+// On a channel's first iteration d = z and q = A z.
+template <int K, bool MULTI, bool EXACT>
+__global__ void __launch_bounds__(kRedBlock) pcg_matvec(PcgArgs a, int src) {
     __shared__ ChanState S[BS_MAX_CHANNELS];
     __shared__ double fin[3 * BS_MAX_CHANNELS];
     __shared__ int n_active;
@@ -860,12 +872,13 @@ __global__ void __launch_bounds__(kRedBlock) pcg_matvec(PcgArgs a, int it) {
     if constexpr (MULTI) {
         if (*I.active == 0) return;   // stopped image
     }
+    const int dst = EXACT ? (src ^ 1) : src;
+    gp<const float> din = src ? I.d1 : I.d0;
+    gp<float> dout = dst ? I.d1 : I.d0;
     const int t = threadIdx.x;
     const int V = I.counts[CNT_V];
     const int Cp = I.Cp, nb = I.nb;
     const Lanes ln(Cp, K);
-    gp<const float> dold = (it & 1) ? I.d0 : I.d1;
-    gp<float> dnew = (it & 1) ? I.d1 : I.d0;
     const XcdTiles tl((V + ln.vpb - 1) / ln.vpb, jb, nb);
     // Loads complete in issue order: partials and state first, then the first
     // tile's operands, which stay in flight during the reduction.
@@ -874,13 +887,13 @@ __global__ void __launch_bounds__(kRedBlock) pcg_matvec(PcgArgs a, int it) {
     // every lane loads a record (lanes >= Cp a duplicate): a conditional load
     // merged with a default would be waited for before the operand loads
     ChanState st0 = load_state(I.cs0 + (int64_t)jb * Cp + min(t, Cp - 1));
-    MatOps<K> o;
+    MatOps<K, EXACT> o;
     int nbn[10];
     int v = (int)(tl.first * ln.vpb) + ln.vl;
     bool have = ln.ok && tl.first < tl.end && v < V;
     if (have) {
         load_nbr(nbn, v, I);
-        load_ops<K>(o, v, nbn, ln, I, dold);
+        load_ops<K, EXACT>(o, v, nbn, ln, I, din);
     }
     ps.sum(I.part0, fin);
     if (t == 0) n_active = 0;
@@ -900,9 +913,11 @@ __global__ void __launch_bounds__(kRedBlock) pcg_matvec(PcgArgs a, int it) {
 #pragma unroll
     for (int k = 0; k < K; ++k) {
         const ChanState& s = S[ln.ok ? ln.g * K + k : 0];
-        beta[k] = (float)s.beta;
-        first[k] = s.iters == 0;
         act[k] = ln.ok && s.active;
+        beta[k] = (float)s.beta;
+        // stopped channels restart their (unused) recurrences, which keeps
+        // them bounded while the other channels iterate
+        first[k] = s.iters == 0 || !act[k];
         any = any || act[k];
     }
     const float lam = I.lam;
@@ -918,42 +933,60 @@ __global__ void __launch_bounds__(kRedBlock) pcg_matvec(PcgArgs a, int it) {
         const bool hn = any && ln.ok && nt < tl.end && vn < V;
         if (hn) load_nbr(nbn, vn, I);
         if (any && have) {
+            float zv[K], ns[K];
             Vec<K> dv, qv;
 #pragma unroll
-            for (int k = 0; k < K; ++k)
-                dv.v[k] = pcg_dir(o.rv.v[k], o.dv.v[k], o.nmv.y, beta[k], first[k]);
-            float ns[K];
+            for (int k = 0; k < K; ++k) {
+                zv[k] = o.nmv.y * o.rv.v[k];
+                dv.v[k] = pcg_dir(zv[k], o.dv.v[k], beta[k], first[k]);
+                ns[k] = 0.0f;
+            }
+            if constexpr (EXACT) {
 #pragma unroll
-            for (int k = 0; k < K; ++k) ns[k] = 0.0f;
+                for (int j = 0; j < 10; ++j) {
+                    if (o.nb[j] >= 0) {
 #pragma unroll
-            for (int j = 0; j < 10; ++j) {
-                if (o.nb[j] >= 0) {
+                        for (int k = 0; k < K; ++k)
+                            ns[k] += o.nm[j].x *
+                                     (dv.v[k] - pcg_dir(o.nm[j].y * o.r[j].v[k], o.d[j].v[k],
+                                                        beta[k], first[k]));
+                    }
+                }
 #pragma unroll
-                    for (int k = 0; k < K; ++k)
-                        ns[k] += o.nm[j].x *
-                                 (dv.v[k] - pcg_dir(o.r[j].v[k], o.d[j].v[k], o.nm[j].y, beta[k], first[k]));
+                for (int k = 0; k < K; ++k) qv.v[k] = o.scv * dv.v[k] + lam * o.nmv.x * ns[k];
+            } else {
+#pragma unroll
+                for (int j = 0; j < 10; ++j) {
+                    if (o.nb[j] >= 0) {
+#pragma unroll
+                        for (int k = 0; k < K; ++k)
+                            ns[k] += o.nm[j].x * (zv[k] - o.nm[j].y * o.r[j].v[k]);
+                    }
+                }
+#pragma unroll
+                for (int k = 0; k < K; ++k) {
+                    const float az = o.scv * zv[k] + lam * o.nmv.x * ns[k];
+                    qv.v[k] = first[k] ? az : fmaf(beta[k], o.qv.v[k], az);
                 }
             }
-#pragma unroll
-            for (int k = 0; k < K; ++k) qv.v[k] = o.scv * dv.v[k] + lam * o.nmv.x * ns[k];
             const int64_t e = (int64_t)o.v * Cp + ln.g * K;
-            stv<K>(dnew + e, dv);
+            stv<K>(dout + e, dv);
             stv<K>(I.q + e, qv);
 #pragma unroll
             for (int k = 0; k < K; ++k)
                 if (act[k]) acc[0][k] += (double)dv.v[k] * (double)qv.v[k];
         }
-        if (hn) load_ops<K>(o, vn, nbn, ln, I, dold);
+        if (hn) load_ops<K, EXACT>(o, vn, nbn, ln, I, din);
         have = hn;
     }
     lane_partials<1, K>(acc, ln, Cp, nb, partial_slot(jb, nb), I.part1);
 }
 
 // Prologue: alpha = r^T M^-1 r / d^T q from the slot-1 partials (a channel
-// with d^T q <= 0 stops).  Then y += alpha d, r -= alpha q and partials of
-// r^T r and r^T M^-1 r.  Stopped channels keep their values.
+// with d^T q <= 0 stops).  Then y += alpha d (d = d[src]), r -= alpha q and
+// partials of r^T r and r^T M^-1 r.  Stopped channels keep their values.
 template <int K, bool MULTI>
-__global__ void __launch_bounds__(kRedBlock) pcg_update(PcgArgs a, int it) {
+__global__ void __launch_bounds__(kRedBlock) pcg_update(PcgArgs a, int src) {
     __shared__ ChanState S[BS_MAX_CHANNELS];
     __shared__ double fin[BS_MAX_CHANNELS];
     __shared__ int n_active;
@@ -966,7 +999,7 @@ __global__ void __launch_bounds__(kRedBlock) pcg_update(PcgArgs a, int it) {
     const int V = I.counts[CNT_V];
     const int Cp = I.Cp, nb = I.nb;
     const Lanes ln(Cp, K);
-    gp<const float> d = (it & 1) ? I.d1 : I.d0;
+    gp<const float> d = src ? I.d1 : I.d0;
     const XcdTiles tl((V + ln.vpb - 1) / ln.vpb, jb, nb);
     PartialSums ps;
     ps.load(I.part1, Cp, nb, I.sums1);
@@ -1267,6 +1300,19 @@ PcgImage make_image(const GridImpl& g, const SolveWs& w, float lam, float* yw,
     return I;
 }
 
+// Lanes of 3 or 4 channels take q by its recurrence and compute q = A d
+// directly every kExactEvery-th iteration.  The recurrence accumulates the
+// rounding of every A z it adds, while A d shrinks as d grows smooth, so near
+// the float32 floor of an ill-conditioned system (sparse confidence) q drifts
+// from A d and the iteration diverges unless the drift is reset often enough
+// (every 8 iterations sufficed on the depth workload, every 16 did not).  With
+// one or two channels per lane the matvec is bound by its own bytes rather
+// than by the gathers, the recurrence gains nothing there, and q = A d is
+// computed directly every iteration.
+constexpr int kExactEvery = 4;
+template <int K>
+constexpr bool uses_recurrence() { return K >= 3; }
+
 template <int K, bool MULTI>
 static bs_status run_pcg_k(const PcgArgs& a, int n, int G, int max_cp, bool sep,
                            const bs_solve_params& p, const int32_t* act, hipStream_t s) {
@@ -1277,12 +1323,22 @@ static bs_status run_pcg_k(const PcgArgs& a, int n, int G, int max_cp, bool sep,
         BS_LAUNCH(s, K_PCG_REDUCE, "pcg_reduce", pcg_reduce<MULTI>, dim3(3 * max_cp, n), block, 0,
                   s, a, 0, 3);
     std::vector<int32_t> poll(n);
+    int src = 0;   // the buffer holding d
     for (int it = 0; it < p.max_iters; ++it) {
-        BS_LAUNCH(s, K_PCG_MATVEC, "pcg_matvec", (pcg_matvec<K, MULTI>), grid, block, 0, s, a, it);
+        bool exact = true;
+        if constexpr (uses_recurrence<K>()) exact = (it + 1) % kExactEvery == 0;
+        if (exact) {
+            BS_LAUNCH(s, K_PCG_MATVEC, "pcg_matvec", (pcg_matvec<K, MULTI, true>), grid, block, 0,
+                      s, a, src);
+            src ^= 1;
+        } else if constexpr (uses_recurrence<K>()) {
+            BS_LAUNCH(s, K_PCG_MATVEC, "pcg_matvec", (pcg_matvec<K, MULTI, false>), grid, block, 0,
+                      s, a, src);
+        }
         if (sep)
             BS_LAUNCH(s, K_PCG_REDUCE, "pcg_reduce", pcg_reduce<MULTI>, dim3(max_cp, n), block, 0,
                       s, a, 1, 1);
-        BS_LAUNCH(s, K_PCG_UPDATE, "pcg_update", (pcg_update<K, MULTI>), grid, block, 0, s, a, it);
+        BS_LAUNCH(s, K_PCG_UPDATE, "pcg_update", (pcg_update<K, MULTI>), grid, block, 0, s, a, src);
         if (sep)
             BS_LAUNCH(s, K_PCG_REDUCE, "pcg_reduce", pcg_reduce<MULTI>, dim3(3 * max_cp, n), block,
                       0, s, a, 0, 3);

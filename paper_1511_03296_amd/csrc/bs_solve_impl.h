@@ -47,7 +47,7 @@ struct PcgImage {
     const float* b;          // right-hand side
     float* y;                // solution (initial state on entry)
     float* r;
-    float* d[2];             // search directions, ping-pong
+    float* d[2];             // search direction (two buffers for the exact matvec)
     float* q;
     const int32_t* counts;   // V = counts[CNT_V]
     ChanRec* cs[2];          // [nb][Cp] per-block channel state, ping-pong
