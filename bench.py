@@ -53,9 +53,15 @@ WORKLOADS = {
 
 
 def matvec_bytes(C: int, iters: int) -> int:
-    """Algorithmic bytes per vertex of `iters` pcg_matvec iterations."""
+    """Algorithmic bytes per vertex of `iters` pcg_matvec iterations.
+
+    The exact form reads the neighbour table (40 B), n, S c and M^-1 (4 B
+    each), r and the old d (4C B each) and writes d and q (4C B each):
+    52 + 16C.  The recurrence form (3 of every 4 iterations for C >= 3) reads
+    the table, n and M^-1, r, d and the old q and writes d and q: 48 + 20C.
+    The neighbours' gathered values are cache hits in the count."""
     exact = iters if C <= 2 else iters // 4
-    return exact * (52 + 16 * C) + (iters - exact) * (52 + 20 * C)
+    return exact * (52 + 16 * C) + (iters - exact) * (48 + 20 * C)
 
 
 def _histogram(values) -> dict:
@@ -281,11 +287,8 @@ def main() -> int:
               file=sys.stderr, flush=True)
     sec_inst, kt = kernel_times(inputs, spec, args.steps, streams)
     mv_ms, mv_launches = kt["pcg_matvec"]
-    # pcg_matvec reads the neighbour table (40 B), n, S c and M^-1 (4 B each)
-    # and r, d (4C B each), and writes the new d and q (4C B each); on the
-    # iterations that take q by its recurrence (3 of every 4 for C >= 3) it
-    # also reads the old q (4C B).  Algorithmic bytes of one step's launches
-    # over their summed durations.  Launches past convergence (between stop
+    # Algorithmic bytes of one step's pcg_matvec launches over their summed
+    # durations (matvec_bytes).  Launches past convergence (between stop
     # polls) return at once and count as time only.
     step_bytes = sum(v * matvec_bytes(p.C, fi + bi) for v, p, fi, bi in
                      zip(V, problems, fwd_iters, bwd_iters))

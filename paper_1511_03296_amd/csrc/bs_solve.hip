@@ -68,6 +68,7 @@ size_t layout_solve(const GridImpl& g, int C, int nb, void* base, SolveWs& w) {
     w.d[0] = c.take<float>(n);
     w.d[1] = c.take<float>(n);
     w.q = c.take<float>(n);
+    w.w = c.take<float>(n);
     w.yi = c.take<float>(n);
     w.up[0] = nullptr;
     for (int k = 1; k < BS_MAX_LEVELS; ++k)
@@ -660,6 +661,26 @@ __global__ void __launch_bounds__(kBlock) hier_final(const float* __restrict__ b
     }
 }
 
+// Lanes of 3 or 4 channels take q by its recurrence and compute q = A d
+// directly every kExactEvery-th iteration (iterations it with
+// (it + 1) % kExactEvery == 0).  The recurrence accumulates the
+// rounding of every A z it adds, while A d shrinks as d grows smooth, so near
+// the float32 floor of an ill-conditioned system (sparse confidence) q drifts
+// from A d and the iteration diverges unless the drift is reset often enough
+// (every 8 iterations sufficed on the depth workload, every 16 did not).  With
+// one or two channels per lane the matvec is bound by its own bytes rather
+// than by the gathers, the recurrence gains nothing there, and q = A d is
+// computed directly every iteration.
+constexpr int kExactEvery = 4;
+template <int K>
+constexpr bool uses_recurrence() { return K >= 3; }
+
+// Whether iteration `it` of a K-lane PCG computes q = A d directly.
+template <int K>
+inline bool exact_iteration(int it) {
+    return !uses_recurrence<K>() || (it + 1) % kExactEvery == 0;
+}
+
 // ---------------------------------------------------------------------------
 // PCG kernels.  Each takes one image (MULTI false, by value) or a table of
 // images with the image of every block (MULTI true).
@@ -690,6 +711,7 @@ struct ImgView {
     gp<float> d0;
     gp<float> d1;
     gp<float> q;
+    gp<float> w;
     gp<const int32_t> counts;
     gp<ChanRec> cs0;
     gp<ChanRec> cs1;
@@ -717,6 +739,7 @@ __device__ inline ImgView view_of(const PcgImage& s) {
     I.d0 = (gp<float>)s.d[0];
     I.d1 = (gp<float>)s.d[1];
     I.q = (gp<float>)s.q;
+    I.w = (gp<float>)s.w;
     I.counts = (gp<const int32_t>)s.counts;
     I.cs0 = (gp<ChanRec>)s.cs[0];
     I.cs1 = (gp<ChanRec>)s.cs[1];
@@ -750,7 +773,17 @@ __global__ void __launch_bounds__(kRedBlock) pcg_prologue(PcgArgs a) {
     if (jb == 0 && t == 0) *I.active = 1;
 }
 
-// r = b - A y0; partials r^T r, b^T b, r^T M^-1 r.
+// w = n o M^-1 r, the neighbours' share of the recurrence matvec.
+template <int K>
+__device__ inline Vec<K> scaled_residual(const Vec<K>& r, float2 nm) {
+    Vec<K> w;
+#pragma unroll
+    for (int k = 0; k < K; ++k) w.v[k] = nm.x * (nm.y * r.v[k]);
+    return w;
+}
+
+// r = b - A y0 (and w for the recurrence matvec); partials r^T r, b^T b,
+// r^T M^-1 r.
 template <int K, bool MULTI>
 __global__ void __launch_bounds__(kRedBlock) pcg_start(PcgArgs a) {
     int jb;
@@ -794,20 +827,22 @@ __global__ void __launch_bounds__(kRedBlock) pcg_start(PcgArgs a) {
             acc[2][k] += (double)rv.v[k] * (double)(nmv.y * rv.v[k]);
         }
         stv<K>(I.r + e, rv);
+        if constexpr (uses_recurrence<K>()) stv<K>(I.w + e, scaled_residual<K>(rv, nmv));
     }
     lane_partials<3, K>(acc, ln, Cp, nb, partial_slot(jb, nb), I.part0);
 }
 
 // Operands of one lane of pcg_matvec.  Loading them does not depend on the
 // iteration's scalars, so the first tile's loads are issued before the
-// prologue and overlap its reduction.
+// prologue and overlap its reduction.  The exact form gathers the
+// neighbours' r, old d and {n, M^-1}; the recurrence form their w alone.
 template <int K, bool EXACT>
 struct MatOps {
     int v;
     int nb[10];
-    Vec<K> r[10];
+    Vec<K> g[10];                  // r (EXACT) or w of the neighbours
     Vec<K> d[EXACT ? 10 : 1];
-    float2 nm[10];
+    float2 nm[EXACT ? 10 : 1];
     Vec<K> rv, dv, qv;
     float2 nmv;
     float scv;
@@ -819,8 +854,7 @@ __device__ inline void load_nbr(int (&nb)[10], int v, const ImgView& I) {
     for (int j = 0; j < 10; ++j) nb[j] = I.nbr[j * I.vcap + v];
 }
 
-// The gathers and per-vertex operands of vertex v (phase 2): the neighbours'
-// r and {n, M^-1} (and old d when EXACT), the vertex's own r, d and q.
+// The gathers and per-vertex operands of vertex v (phase 2).
 template <int K, bool EXACT>
 __device__ inline void load_ops(MatOps<K, EXACT>& o, int v, const int (&nb)[10], const Lanes& ln,
                                 const ImgView& I, gp<const float> din) {
@@ -834,17 +868,21 @@ __device__ inline void load_ops(MatOps<K, EXACT>& o, int v, const int (&nb)[10],
         const int u = nb[j];
         if (u >= 0) {
             const int64_t eu = (int64_t)u * Cp + ln.g * K;
-            o.r[j] = ldv<K>(I.r + eu);
-            if constexpr (EXACT) o.d[j] = ldv<K>(din + eu);
-            o.nm[j] = I.nfm[u];
+            if constexpr (EXACT) {
+                o.g[j] = ldv<K>(I.r + eu);
+                o.d[j] = ldv<K>(din + eu);
+                o.nm[j] = I.nfm[u];
+            } else {
+                o.g[j] = ldv<K>(I.w + eu);
+            }
         }
     }
     const int64_t e = (int64_t)v * Cp + ln.g * K;
     o.rv = ldv<K>(I.r + e);
     o.dv = ldv<K>(din + e);
-    if constexpr (!EXACT) o.qv = ldv<K>(I.q + e);
     o.nmv = I.nfm[v];
-    o.scv = I.sc[v];
+    if constexpr (EXACT) o.scv = I.sc[v];
+    else o.qv = ldv<K>(I.q + e);
 }
 
 // New search direction of one element: z + beta d_old.
@@ -855,12 +893,15 @@ __device__ inline float pcg_dir(float z, float d_old, float beta, bool first) {
 // Prologue: finish the previous step (stopping rule, beta) from the slot-0
 // partials.  Then, with z = M^-1 r, d = z + beta d and partials of d^T q,
 // where q = A d is either
-//   EXACT false:  A z + beta q, its recurrence.  Only r is gathered from the
-//                 neighbours; d and q are updated in place (d[src]).
-//   EXACT true:   A d itself, with the neighbours' new d recomputed from
-//                 their gathered r and old d (read from d[src], written to
-//                 d[src ^ 1]).  It resets the rounding that the recurrence
-//                 accumulates.
+//   EXACT false:  A z + beta q, its recurrence.  diag(A) z = r, so
+//                   (A z)_v = r_v - lam n_v sum_u w_u,  w = n o M^-1 r,
+//                 and only w is gathered from the neighbours (it is written
+//                 by the previous update); d and q are updated in place
+//                 (d[src]).  A row with diag(A) = 0 is zero: (A z)_v = 0.
+//   EXACT true:   A d itself, in Laplacian form, with the neighbours' new d
+//                 recomputed from their gathered r and old d (read from
+//                 d[src], written to d[src ^ 1]).  It resets the rounding
+//                 that the recurrence accumulates.
 // On a channel's first iteration d = z and q = A z.
 template <int K, bool MULTI, bool EXACT>
 __global__ void __launch_bounds__(kRedBlock) pcg_matvec(PcgArgs a, int src) {
@@ -948,7 +989,7 @@ __global__ void __launch_bounds__(kRedBlock) pcg_matvec(PcgArgs a, int src) {
 #pragma unroll
                         for (int k = 0; k < K; ++k)
                             ns[k] += o.nm[j].x *
-                                     (dv.v[k] - pcg_dir(o.nm[j].y * o.r[j].v[k], o.d[j].v[k],
+                                     (dv.v[k] - pcg_dir(o.nm[j].y * o.g[j].v[k], o.d[j].v[k],
                                                         beta[k], first[k]));
                     }
                 }
@@ -959,13 +1000,13 @@ __global__ void __launch_bounds__(kRedBlock) pcg_matvec(PcgArgs a, int src) {
                 for (int j = 0; j < 10; ++j) {
                     if (o.nb[j] >= 0) {
 #pragma unroll
-                        for (int k = 0; k < K; ++k)
-                            ns[k] += o.nm[j].x * (zv[k] - o.nm[j].y * o.r[j].v[k]);
+                        for (int k = 0; k < K; ++k) ns[k] += o.g[j].v[k];
                     }
                 }
+                const bool row = o.nmv.y > 0.0f;
 #pragma unroll
                 for (int k = 0; k < K; ++k) {
-                    const float az = o.scv * zv[k] + lam * o.nmv.x * ns[k];
+                    const float az = (row ? o.rv.v[k] : 0.0f) - lam * o.nmv.x * ns[k];
                     qv.v[k] = first[k] ? az : fmaf(beta[k], o.qv.v[k], az);
                 }
             }
@@ -984,9 +1025,10 @@ __global__ void __launch_bounds__(kRedBlock) pcg_matvec(PcgArgs a, int src) {
 
 // Prologue: alpha = r^T M^-1 r / d^T q from the slot-1 partials (a channel
 // with d^T q <= 0 stops).  Then y += alpha d (d = d[src]), r -= alpha q and
-// partials of r^T r and r^T M^-1 r.  Stopped channels keep their values.
+// partials of r^T r and r^T M^-1 r; with want_w, also w = n o M^-1 r for a
+// following recurrence matvec.  Stopped channels keep their values.
 template <int K, bool MULTI>
-__global__ void __launch_bounds__(kRedBlock) pcg_update(PcgArgs a, int src) {
+__global__ void __launch_bounds__(kRedBlock) pcg_update(PcgArgs a, int src, int want_w) {
     __shared__ ChanState S[BS_MAX_CHANNELS];
     __shared__ double fin[BS_MAX_CHANNELS];
     __shared__ int n_active;
@@ -1008,14 +1050,14 @@ __global__ void __launch_bounds__(kRedBlock) pcg_update(PcgArgs a, int src) {
     int v = (int)(tl.first * ln.vpb) + ln.vl;
     bool have = ln.ok && tl.first < tl.end && v < V;
     Vec<K> yv, dv, rv, qv;
-    float miv = 0.0f;
+    float2 nmv = make_float2(0.0f, 0.0f);
     if (have) {
         const int64_t e = (int64_t)v * Cp + ln.g * K;
         yv = ldv<K>(I.y + e);
         dv = ldv<K>(d + e);
         rv = ldv<K>(I.r + e);
         qv = ldv<K>(I.q + e);
-        miv = I.nfm[v].y;
+        nmv = I.nfm[v];
     }
     ps.sum(I.part1, fin);
     if (t == 0) n_active = 0;
@@ -1057,14 +1099,14 @@ __global__ void __launch_bounds__(kRedBlock) pcg_update(PcgArgs a, int src) {
         const int vn = (int)(nt * ln.vpb) + ln.vl;
         const bool hn = any && ln.ok && nt < tl.end && vn < V;
         Vec<K> yn, dn, rn, qn;
-        float min_ = 0.0f;
+        float2 nmn = make_float2(0.0f, 0.0f);
         if (hn) {
             const int64_t e = (int64_t)vn * Cp + ln.g * K;
             yn = ldv<K>(I.y + e);
             dn = ldv<K>(d + e);
             rn = ldv<K>(I.r + e);
             qn = ldv<K>(I.q + e);
-            min_ = I.nfm[vn].y;
+            nmn = I.nfm[vn];
         }
         if (any && have) {
             Vec<K> y1, r1;
@@ -1074,7 +1116,7 @@ __global__ void __launch_bounds__(kRedBlock) pcg_update(PcgArgs a, int src) {
                     y1.v[k] = fmaf(alpha[k], dv.v[k], yv.v[k]);
                     r1.v[k] = fmaf(-alpha[k], qv.v[k], rv.v[k]);
                     acc[0][k] += (double)r1.v[k] * (double)r1.v[k];
-                    acc[2][k] += (double)r1.v[k] * (double)(miv * r1.v[k]);
+                    acc[2][k] += (double)r1.v[k] * (double)(nmv.y * r1.v[k]);
                 } else {
                     y1.v[k] = yv.v[k];
                     r1.v[k] = rv.v[k];
@@ -1083,6 +1125,9 @@ __global__ void __launch_bounds__(kRedBlock) pcg_update(PcgArgs a, int src) {
             const int64_t e = (int64_t)v * Cp + ln.g * K;
             stv<K>(I.y + e, y1);
             stv<K>(I.r + e, r1);
+            if constexpr (uses_recurrence<K>()) {
+                if (want_w) stv<K>(I.w + e, scaled_residual<K>(r1, nmv));
+            }
         }
         v = vn;
         have = hn;
@@ -1090,7 +1135,7 @@ __global__ void __launch_bounds__(kRedBlock) pcg_update(PcgArgs a, int src) {
         dv = dn;
         rv = rn;
         qv = qn;
-        miv = min_;
+        nmv = nmn;
     }
     lane_partials<3, K>(acc, ln, Cp, nb, partial_slot(jb, nb), I.part0);
 }
@@ -1279,6 +1324,7 @@ PcgImage make_image(const GridImpl& g, const SolveWs& w, float lam, float* yw,
     I.d[0] = w.d[0];
     I.d[1] = w.d[1];
     I.q = w.q;
+    I.w = w.w;
     I.counts = g.counts;
     I.cs[0] = w.cs[0];
     I.cs[1] = w.cs[1];
@@ -1300,18 +1346,6 @@ PcgImage make_image(const GridImpl& g, const SolveWs& w, float lam, float* yw,
     return I;
 }
 
-// Lanes of 3 or 4 channels take q by its recurrence and compute q = A d
-// directly every kExactEvery-th iteration.  The recurrence accumulates the
-// rounding of every A z it adds, while A d shrinks as d grows smooth, so near
-// the float32 floor of an ill-conditioned system (sparse confidence) q drifts
-// from A d and the iteration diverges unless the drift is reset often enough
-// (every 8 iterations sufficed on the depth workload, every 16 did not).  With
-// one or two channels per lane the matvec is bound by its own bytes rather
-// than by the gathers, the recurrence gains nothing there, and q = A d is
-// computed directly every iteration.
-constexpr int kExactEvery = 4;
-template <int K>
-constexpr bool uses_recurrence() { return K >= 3; }
 
 template <int K, bool MULTI>
 static bs_status run_pcg_k(const PcgArgs& a, int n, int G, int max_cp, bool sep,
@@ -1325,9 +1359,7 @@ static bs_status run_pcg_k(const PcgArgs& a, int n, int G, int max_cp, bool sep,
     std::vector<int32_t> poll(n);
     int src = 0;   // the buffer holding d
     for (int it = 0; it < p.max_iters; ++it) {
-        bool exact = true;
-        if constexpr (uses_recurrence<K>()) exact = (it + 1) % kExactEvery == 0;
-        if (exact) {
+        if (exact_iteration<K>(it)) {
             BS_LAUNCH(s, K_PCG_MATVEC, "pcg_matvec", (pcg_matvec<K, MULTI, true>), grid, block, 0,
                       s, a, src);
             src ^= 1;
@@ -1338,7 +1370,9 @@ static bs_status run_pcg_k(const PcgArgs& a, int n, int G, int max_cp, bool sep,
         if (sep)
             BS_LAUNCH(s, K_PCG_REDUCE, "pcg_reduce", pcg_reduce<MULTI>, dim3(max_cp, n), block, 0,
                       s, a, 1, 1);
-        BS_LAUNCH(s, K_PCG_UPDATE, "pcg_update", (pcg_update<K, MULTI>), grid, block, 0, s, a, src);
+        const int want_w = exact_iteration<K>(it + 1) ? 0 : 1;
+        BS_LAUNCH(s, K_PCG_UPDATE, "pcg_update", (pcg_update<K, MULTI>), grid, block, 0, s, a, src,
+                  want_w);
         if (sep)
             BS_LAUNCH(s, K_PCG_REDUCE, "pcg_reduce", pcg_reduce<MULTI>, dim3(3 * max_cp, n), block,
                       0, s, a, 0, 3);
