@@ -843,7 +843,7 @@ struct MatOps {
     Vec<K> g[10];                  // r (EXACT) or w of the neighbours
     Vec<K> d[EXACT ? 10 : 1];
     float2 nm[EXACT ? 10 : 1];
-    Vec<K> rv, dv, qv;
+    Vec<K> rv, dv, qv, yv;
     float2 nmv;
     float scv;
 };
@@ -880,6 +880,7 @@ __device__ inline void load_ops(MatOps<K, EXACT>& o, int v, const int (&nb)[10],
     const int64_t e = (int64_t)v * Cp + ln.g * K;
     o.rv = ldv<K>(I.r + e);
     o.dv = ldv<K>(din + e);
+    o.yv = ldv<K>(I.y + e);
     o.nmv = I.nfm[v];
     if constexpr (EXACT) o.scv = I.sc[v];
     else o.qv = ldv<K>(I.q + e);
@@ -891,7 +892,9 @@ __device__ inline float pcg_dir(float z, float d_old, float beta, bool first) {
 }
 
 // Prologue: finish the previous step (stopping rule, beta) from the slot-0
-// partials.  Then, with z = M^-1 r, d = z + beta d and partials of d^T q,
+// partials.  Then y += alpha d_old, the previous iteration's step (deferred
+// from the update to here, where d_old is read anyway; pcg_flush applies
+// the last one), and, with z = M^-1 r, d = z + beta d and partials of d^T q,
 // where q = A d is either
 //   EXACT false:  A z + beta q, its recurrence.  diag(A) z = r, so
 //                   (A z)_v = r_v - lam n_v sum_u w_u,  w = n o M^-1 r,
@@ -907,11 +910,12 @@ template <int K, bool MULTI, bool EXACT>
 __global__ void __launch_bounds__(kRedBlock) pcg_matvec(PcgArgs a, int src) {
     __shared__ ChanState S[BS_MAX_CHANNELS];
     __shared__ double fin[3 * BS_MAX_CHANNELS];
-    __shared__ int n_active;
+    __shared__ float pend[BS_MAX_CHANNELS];
+    __shared__ int n_active, n_pend;
     int jb;
     const ImgView I = view_of(block_image<MULTI>(a, jb));
     if constexpr (MULTI) {
-        if (*I.active == 0) return;   // stopped image
+        if (*I.active == 0) return;   // stopped image (its last step applied)
     }
     const int dst = EXACT ? (src ^ 1) : src;
     gp<const float> din = src ? I.d1 : I.d0;
@@ -937,29 +941,39 @@ __global__ void __launch_bounds__(kRedBlock) pcg_matvec(PcgArgs a, int src) {
         load_ops<K, EXACT>(o, v, nbn, ln, I, din);
     }
     ps.sum(I.part0, fin);
-    if (t == 0) n_active = 0;
+    if (t == 0) n_active = n_pend = 0;
     __syncthreads();
     if (t < Cp) {
+        // a channel the update left active has its step alpha d_old pending
+        const bool p = st0.phase != 0 && st0.active;
+        pend[t] = p ? (float)st0.alpha : 0.0f;
+        if (p) atomicAdd(&n_pend, 1);
         st0 = advance_state(st0, fin[t], fin[Cp + t], fin[2 * Cp + t], a.max_iters, a.tol);
         store_state(S[t], st0);
         if (st0.active) atomicAdd(&n_active, 1);
         store_state(I.cs1 + (int64_t)jb * Cp + t, st0);
     }
     __syncthreads();
-    if (jb == 0 && t == 0) *I.active = n_active;
-    if (n_active == 0) return;
-    float beta[K];
-    bool first[K], act[K];
+    // Blocks of this launch that start later read the count and return at
+    // once when it is 0; with steps still pending it reads -1 instead (the
+    // next update stores the true count).
+    if (jb == 0 && t == 0) *I.active = n_active > 0 ? n_active : (n_pend > 0 ? -1 : 0);
+    if (n_active == 0 && n_pend == 0) return;
+    float beta[K], alpha[K];
+    bool first[K], act[K], pnd[K];
     bool any = false;
 #pragma unroll
     for (int k = 0; k < K; ++k) {
-        const ChanState& s = S[ln.ok ? ln.g * K + k : 0];
+        const int c = ln.ok ? ln.g * K + k : 0;
+        const ChanState& s = S[c];
         act[k] = ln.ok && s.active;
+        alpha[k] = pend[c];
+        pnd[k] = ln.ok && alpha[k] != 0.0f;
         beta[k] = (float)s.beta;
         // stopped channels restart their (unused) recurrences, which keeps
         // them bounded while the other channels iterate
         first[k] = s.iters == 0 || !act[k];
-        any = any || act[k];
+        any = any || act[k] || pnd[k];
     }
     const float lam = I.lam;
     double acc[1][K];
@@ -1010,7 +1024,12 @@ __global__ void __launch_bounds__(kRedBlock) pcg_matvec(PcgArgs a, int src) {
                     qv.v[k] = first[k] ? az : fmaf(beta[k], o.qv.v[k], az);
                 }
             }
+            Vec<K> yv;
+#pragma unroll
+            for (int k = 0; k < K; ++k)
+                yv.v[k] = pnd[k] ? fmaf(alpha[k], o.dv.v[k], o.yv.v[k]) : o.yv.v[k];
             const int64_t e = (int64_t)o.v * Cp + ln.g * K;
+            stv<K>(I.y + e, yv);
             stv<K>(dout + e, dv);
             stv<K>(I.q + e, qv);
 #pragma unroll
@@ -1024,11 +1043,12 @@ __global__ void __launch_bounds__(kRedBlock) pcg_matvec(PcgArgs a, int src) {
 }
 
 // Prologue: alpha = r^T M^-1 r / d^T q from the slot-1 partials (a channel
-// with d^T q <= 0 stops).  Then y += alpha d (d = d[src]), r -= alpha q and
-// partials of r^T r and r^T M^-1 r; with want_w, also w = n o M^-1 r for a
-// following recurrence matvec.  Stopped channels keep their values.
+// with d^T q <= 0 stops).  Then r -= alpha q and partials of r^T r and
+// r^T M^-1 r; with want_w, also w = n o M^-1 r for a following recurrence
+// matvec.  The step y += alpha d is left to the next matvec (or pcg_flush).
+// Stopped channels keep their values.
 template <int K, bool MULTI>
-__global__ void __launch_bounds__(kRedBlock) pcg_update(PcgArgs a, int src, int want_w) {
+__global__ void __launch_bounds__(kRedBlock) pcg_update(PcgArgs a, int want_w) {
     __shared__ ChanState S[BS_MAX_CHANNELS];
     __shared__ double fin[BS_MAX_CHANNELS];
     __shared__ int n_active;
@@ -1041,7 +1061,6 @@ __global__ void __launch_bounds__(kRedBlock) pcg_update(PcgArgs a, int src, int 
     const int V = I.counts[CNT_V];
     const int Cp = I.Cp, nb = I.nb;
     const Lanes ln(Cp, K);
-    gp<const float> d = src ? I.d1 : I.d0;
     const XcdTiles tl((V + ln.vpb - 1) / ln.vpb, jb, nb);
     PartialSums ps;
     ps.load(I.part1, Cp, nb, I.sums1);
@@ -1049,12 +1068,10 @@ __global__ void __launch_bounds__(kRedBlock) pcg_update(PcgArgs a, int src, int 
     // first tile's operands in flight during the reduction
     int v = (int)(tl.first * ln.vpb) + ln.vl;
     bool have = ln.ok && tl.first < tl.end && v < V;
-    Vec<K> yv, dv, rv, qv;
+    Vec<K> rv, qv;
     float2 nmv = make_float2(0.0f, 0.0f);
     if (have) {
         const int64_t e = (int64_t)v * Cp + ln.g * K;
-        yv = ldv<K>(I.y + e);
-        dv = ldv<K>(d + e);
         rv = ldv<K>(I.r + e);
         qv = ldv<K>(I.q + e);
         nmv = I.nfm[v];
@@ -1098,32 +1115,27 @@ __global__ void __launch_bounds__(kRedBlock) pcg_update(PcgArgs a, int src, int 
         const int64_t nt = tile + tl.step;
         const int vn = (int)(nt * ln.vpb) + ln.vl;
         const bool hn = any && ln.ok && nt < tl.end && vn < V;
-        Vec<K> yn, dn, rn, qn;
+        Vec<K> rn, qn;
         float2 nmn = make_float2(0.0f, 0.0f);
         if (hn) {
             const int64_t e = (int64_t)vn * Cp + ln.g * K;
-            yn = ldv<K>(I.y + e);
-            dn = ldv<K>(d + e);
             rn = ldv<K>(I.r + e);
             qn = ldv<K>(I.q + e);
             nmn = I.nfm[vn];
         }
         if (any && have) {
-            Vec<K> y1, r1;
+            Vec<K> r1;
 #pragma unroll
             for (int k = 0; k < K; ++k) {
                 if (act[k]) {
-                    y1.v[k] = fmaf(alpha[k], dv.v[k], yv.v[k]);
                     r1.v[k] = fmaf(-alpha[k], qv.v[k], rv.v[k]);
                     acc[0][k] += (double)r1.v[k] * (double)r1.v[k];
                     acc[2][k] += (double)r1.v[k] * (double)(nmv.y * r1.v[k]);
                 } else {
-                    y1.v[k] = yv.v[k];
                     r1.v[k] = rv.v[k];
                 }
             }
             const int64_t e = (int64_t)v * Cp + ln.g * K;
-            stv<K>(I.y + e, y1);
             stv<K>(I.r + e, r1);
             if constexpr (uses_recurrence<K>()) {
                 if (want_w) stv<K>(I.w + e, scaled_residual<K>(r1, nmv));
@@ -1131,13 +1143,59 @@ __global__ void __launch_bounds__(kRedBlock) pcg_update(PcgArgs a, int src, int 
         }
         v = vn;
         have = hn;
-        yv = yn;
-        dv = dn;
         rv = rn;
         qv = qn;
         nmv = nmn;
     }
     lane_partials<3, K>(acc, ln, Cp, nb, partial_slot(jb, nb), I.part0);
+}
+
+// After the last enqueued iteration: applies the step y += alpha d that the
+// last update left pending (d = d[src]) for the channels it left active.  An
+// image whose active count is 0 has none pending: its channels stopped in an
+// update (no step) or in a matvec, which applied the step.
+template <int K, bool MULTI>
+__global__ void __launch_bounds__(kRedBlock) pcg_flush(PcgArgs a, int src) {
+    __shared__ float pend[BS_MAX_CHANNELS];
+    __shared__ int n_pend;
+    int jb;
+    const ImgView I = view_of(block_image<MULTI>(a, jb));
+    if (*I.active == 0) return;
+    const int t = threadIdx.x;
+    const int V = I.counts[CNT_V];
+    const int Cp = I.Cp, nb = I.nb;
+    const Lanes ln(Cp, K);
+    gp<const float> d = src ? I.d1 : I.d0;
+    if (t == 0) n_pend = 0;
+    __syncthreads();
+    if (t < Cp) {
+        const ChanState st = load_state(I.cs0 + (int64_t)jb * Cp + t);
+        const bool p = st.phase != 0 && st.active;
+        pend[t] = p ? (float)st.alpha : 0.0f;
+        if (p) atomicAdd(&n_pend, 1);
+    }
+    __syncthreads();
+    if (n_pend == 0 || !ln.ok) return;
+    float alpha[K];
+    bool any = false;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        alpha[k] = pend[ln.g * K + k];
+        any = any || alpha[k] != 0.0f;
+    }
+    if (!any) return;
+    const XcdTiles tl((V + ln.vpb - 1) / ln.vpb, jb, nb);
+    for (int64_t tile = tl.first; tile < tl.end; tile += tl.step) {
+        const int v = (int)(tile * ln.vpb) + ln.vl;
+        if (v >= V) continue;
+        const int64_t e = (int64_t)v * Cp + ln.g * K;
+        const Vec<K> dv = ldv<K>(d + e);
+        Vec<K> yv = ldv<K>(I.y + e);
+#pragma unroll
+        for (int k = 0; k < K; ++k)
+            if (alpha[k] != 0.0f) yv.v[k] = fmaf(alpha[k], dv.v[k], yv.v[k]);
+        stv<K>(I.y + e, yv);
+    }
 }
 
 // With many channels the per-block partials are reduced once, by one block
@@ -1371,7 +1429,7 @@ static bs_status run_pcg_k(const PcgArgs& a, int n, int G, int max_cp, bool sep,
             BS_LAUNCH(s, K_PCG_REDUCE, "pcg_reduce", pcg_reduce<MULTI>, dim3(max_cp, n), block, 0,
                       s, a, 1, 1);
         const int want_w = exact_iteration<K>(it + 1) ? 0 : 1;
-        BS_LAUNCH(s, K_PCG_UPDATE, "pcg_update", (pcg_update<K, MULTI>), grid, block, 0, s, a, src,
+        BS_LAUNCH(s, K_PCG_UPDATE, "pcg_update", (pcg_update<K, MULTI>), grid, block, 0, s, a,
                   want_w);
         if (sep)
             BS_LAUNCH(s, K_PCG_REDUCE, "pcg_reduce", pcg_reduce<MULTI>, dim3(3 * max_cp, n), block,
@@ -1385,6 +1443,7 @@ static bs_status run_pcg_k(const PcgArgs& a, int n, int G, int max_cp, bool sep,
             if (!any) break;
         }
     }
+    BS_LAUNCH(s, K_PCG_UPDATE, "pcg_flush", (pcg_flush<K, MULTI>), grid, block, 0, s, a, src);
     BS_LAUNCH(s, K_INIT, "pcg_finish", pcg_finish<MULTI>, dim3(n), block, 0, s, a);
     return BS_OK;
 }
