@@ -32,6 +32,9 @@ in the design notes):
       operator with b replaced by u = S dL/dx; dL/dc sums the per-channel terms.
   R12 the diagonal of the smoothness term, m - 10 n^2, is evaluated as n o N n,
       its value at the bistochastization fixed point (see Operator).
+  R17 robust solver with several channels: the Geman-McClure weight of a pixel
+      takes e o e summed over the channels (the confidence is shared); with
+      one channel this is the printed weight.
 """
 from __future__ import annotations
 
@@ -484,3 +487,48 @@ def true_relative_residual(A: Operator, b: np.ndarray, y: np.ndarray) -> np.ndar
         nb = float(np.sqrt(b[:, ch] @ b[:, ch]))
         out.append(float(np.sqrt(r @ r)) / nb if nb > 0 else 0.0)
     return np.array(out)
+
+
+# ----------------------------------------------------------------------------
+# The robust bilateral solver  (supplement Section Robustness, Algorithm RBS;
+# R17)
+# ----------------------------------------------------------------------------
+
+def gm_weight(e2: np.ndarray, sigma_gm: float) -> np.ndarray:
+    """IRLS weight of the Geman-McClure loss for squared errors e2:
+    2 sigma^2 / (sigma^2 + e2)^2."""
+    s2 = float(sigma_gm) ** 2
+    return 2.0 * s2 / (s2 + np.asarray(e2, np.float64)) ** 2
+
+
+def gm_loss(e2: np.ndarray, sigma_gm: float) -> np.ndarray:
+    """Geman-McClure loss of squared errors e2: e2 / (sigma^2 + e2)."""
+    e2 = np.asarray(e2, np.float64)
+    return e2 / (float(sigma_gm) ** 2 + e2)
+
+
+@dataclass
+class RobustSolution:
+    solution: Solution            # the last solve: x_hat and its state
+    weights: list                 # the confidence of every solve, [P] each (first: c_init)
+
+
+def robust_solve(ref: np.ndarray, target: np.ndarray, conf_init: np.ndarray, p: Params,
+                 sigma_gm: float, irls_iters: int, prepared=None) -> RobustSolution:
+    """Algorithm RBS: solve with the current confidence, then replace the
+    confidence by the Geman-McClure weights of the solution's errors; repeat
+    irls_iters times (>= 1) and return the last solve."""
+    if irls_iters < 1:
+        raise ValueError("irls_iters must be >= 1")
+    prepared = prepared if prepared is not None else prepare(ref, p)
+    C = target.shape[0]
+    t = np.asarray(target, np.float64).reshape(C, -1)
+    c = np.asarray(conf_init, np.float64).reshape(-1)
+    weights = []
+    sol = None
+    for _ in range(irls_iters):
+        weights.append(c)
+        sol = solve(ref, target, c.reshape(conf_init.shape), p, prepared=prepared)
+        e2 = np.sum((sol.x.reshape(C, -1) - t) ** 2, axis=0)
+        c = gm_weight(e2, sigma_gm)
+    return RobustSolution(sol, weights)

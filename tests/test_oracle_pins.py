@@ -402,3 +402,89 @@ def test_gradients_against_finite_differences():
     delta = rng.normal(size=t.shape)
     lhs = np.sum(w * (_dense_output(p, prm, t + delta, c, pre) - _dense_output(p, prm, t, c, pre)))
     assert abs(lhs - np.sum(grads.grad_t * delta)) <= 1e-8 * max(1.0, abs(lhs))
+
+
+# --------------------------------------------------------------------------
+# Robust bilateral solver (supplement Section Robustness, Algorithm RBS)
+# --------------------------------------------------------------------------
+
+def _with_outliers(p, frac, size, seed):
+    """The target with a fraction of pixels moved by +size (gross outliers)."""
+    rng = np.random.default_rng(seed)
+    t = p.target.copy()
+    mask = rng.random(t.shape[1:]) < frac
+    t[:, mask] += size
+    return t, mask
+
+
+def test_gm_weight_is_the_irls_weight_of_the_printed_loss():
+    """IRLS weights are rho'(e) / e; checked against central differences of
+    the printed Geman-McClure loss rho(e) = e^2 / (sigma^2 + e^2)."""
+    for sigma in (0.1, 1.0, 7.5):
+        e = np.linspace(-5 * sigma, 5 * sigma, 41)
+        e = e[np.abs(e) > 1e-3 * sigma]
+        h = 1e-6 * sigma
+        drho = (O.gm_loss((e + h) ** 2, sigma) - O.gm_loss((e - h) ** 2, sigma)) / (2 * h)
+        assert np.allclose(O.gm_weight(e ** 2, sigma), drho / e, rtol=1e-6, atol=0)
+
+
+def test_robust_one_iteration_is_the_solve():
+    p = tiny(seed=3)
+    prm = params_of(p)
+    r = O.robust_solve(p.ref, p.target, p.conf, prm, sigma_gm=0.2, irls_iters=1)
+    plain = O.solve(p.ref, p.target, p.conf, prm)
+    assert np.array_equal(r.solution.x, plain.x)
+    assert np.array_equal(r.weights[0], p.conf.reshape(-1).astype(np.float64))
+
+
+def test_robust_objective_decreases():
+    """Each IRLS step minimises a quadratic majorizer of the Geman-McClure
+    objective, so with exact solves the objective never increases.  The
+    solve's data term sum c (x - t)^2 carries no 1/2, so the objective
+    majorized is (lam / 4) sum W-hat (x_i - x_j)^2 + sum rho(x - t): the
+    printed robust loss with lam / 2.  W-hat is the dense matrix of
+    Eq. equiv, independent of the matrix-free operator."""
+    p = tiny(seed=4, H=12, W=16, regions=4)
+    t, _ = _with_outliers(p, 0.08, 2.0, seed=1)
+    prm = params_of(p)
+    g, bs, _, S, B, Wh, _ = dense_problem(p, prm)
+    sigma = 0.15
+    r = O.robust_solve(p.ref, t, p.conf, prm, sigma_gm=sigma, irls_iters=8)
+    tt = t.reshape(-1).astype(np.float64)
+    F = []
+    for c in r.weights:
+        x = O.solve(p.ref, t, c.reshape(p.conf.shape), prm).x.reshape(-1)
+        smooth = 0.5 * D.pixel_loss(x, tt, np.zeros_like(x), Wh, p.lam)
+        F.append(smooth + float(np.sum(O.gm_loss((x - tt) ** 2, sigma))))
+    F = np.array(F)
+    assert np.all(np.diff(F[1:]) <= 1e-9 * np.abs(F[1:-1])), F
+    assert F[-1] < F[1]
+
+
+def test_robust_large_sigma_is_uniform_confidence():
+    """sigma_gm -> inf: every weight tends to 2 / sigma^2, so the second solve
+    tends to the plain solve with that uniform confidence (relative change
+    O(max e^2 / sigma^2))."""
+    p = tiny(seed=5)
+    prm = params_of(p)
+    sigma = 1e3
+    r = O.robust_solve(p.ref, p.target, p.conf, prm, sigma_gm=sigma, irls_iters=2)
+    uni = O.solve(p.ref, p.target, np.full(p.conf.shape, 2.0 / sigma ** 2), prm)
+    assert np.linalg.norm(r.solution.x - uni.x) <= 1e-5 * np.linalg.norm(uni.x)
+
+
+def test_robust_rejects_outliers():
+    """A piecewise ramp with 5 % gross outliers: the robust solve stays close
+    to the plain solve of the target without them, from which the plain
+    solve of the corrupted target is pulled away."""
+    p = WL.tiny_ramp(seed=6, H=32, W=40, regions=4, sigma=(4, 8, 8), lam=0.5)
+    t, mask = _with_outliers(p, 0.05, 3.0, seed=2)
+    c = np.ones_like(p.conf)
+    prm = params_of(p)
+    want = O.solve(p.ref, p.target, c, prm).x[0]
+    plain = O.solve(p.ref, t, c, prm).x[0]
+    rob = O.robust_solve(p.ref, t, c, prm, sigma_gm=0.1, irls_iters=10).solution.x[0]
+    keep = ~mask
+    err_plain = np.abs(plain[keep] - want[keep]).mean()
+    err_rob = np.abs(rob[keep] - want[keep]).mean()
+    assert err_rob < 0.2 * err_plain, (err_rob, err_plain)
