@@ -49,6 +49,11 @@ WORKLOADS = {
                           bwd=(20000, 1e-6)),
     "mixed64": dict(gen="mixed_batch", images=64, batch=True, fwd=(20000, 1e-5),
                     bwd=(20000, 1e-5)),
+    # the robust solver (Geman-McClure IRLS, sigma_gm in disparity units, 8
+    # rounds) on the stereo shape, whose targets carry 10 % outlier
+    # disparities; forward only (a step is the 8 rounds)
+    "robust_stereo1024x768": dict(gen="stereo_refine", images=1, fwd=(25, 0.0), bwd=(0, 0.0),
+                                  robust=(4.0, 8)),
 }
 
 
@@ -120,6 +125,16 @@ def run_step(inputs, spec, backward=True, keep=None, streams=0):
     bce = 0 if bt == 0.0 else 8
     if streams > 0:
         return run_batch_step(inputs, spec, backward, keep, streams)
+    if spec.get("robust"):
+        sigma_gm, rounds = spec["robust"]
+        for d in inputs:
+            p = d["p"]
+            G = BilateralGrid(d["ref"], p.sigma_xy, p.sigma_l, p.sigma_uv)
+            _, _, st = G.robust_solve(d["t"], d["c"], p.lam, sigma_gm, rounds, max_iters=fi,
+                                      rel_tol=ft, check_every=fce)
+            if keep is not None:
+                keep.append((G.vertex_count(), st, None))
+        return
     for d in inputs:
         p = d["p"]
         G = BilateralGrid(d["ref"], p.sigma_xy, p.sigma_l, p.sigma_uv)
@@ -201,13 +216,18 @@ def cpu_baseline(problems, spec, seconds):
     gx = WL.random_grad(0, p.C, p.H, p.W)
     if spec.get("grad") == "conf_weighted":
         gx = gx * p.conf[None]
+    if spec.get("robust"):
+        sample = sample.replace("forward+backward", "robust forward")
     t0 = time.perf_counter()
     n = 0
     while True:
         prm = O.Params(p.sigma_xy, p.sigma_l, p.sigma_uv, p.lam, max_iters=fi, rel_tol=ft)
-        sol = O.solve(p.ref, p.target, p.conf, prm)
-        prmb = O.Params(p.sigma_xy, p.sigma_l, p.sigma_uv, p.lam, max_iters=bi, rel_tol=bt)
-        O.solve_backward(sol, p.target, p.conf, gx, prmb)
+        if spec.get("robust"):
+            O.robust_solve(p.ref, p.target, p.conf, prm, *spec["robust"])
+        else:
+            sol = O.solve(p.ref, p.target, p.conf, prm)
+            prmb = O.Params(p.sigma_xy, p.sigma_l, p.sigma_uv, p.lam, max_iters=bi, rel_tol=bt)
+            O.solve_backward(sol, p.target, p.conf, gx, prmb)
         n += 1
         el = time.perf_counter() - t0
         if el >= seconds:
@@ -267,8 +287,10 @@ def main() -> int:
         print("bench: warmup step done", file=sys.stderr, flush=True)
     from paper_1511_03296_amd import read_stats
     V = [v for v, _, _ in keep]
-    fwd_iters = [int(read_stats(st)["iters"].max()) for _, st, _ in keep]
-    bwd_iters = [int(read_stats(bst)["iters"].max()) for _, _, bst in keep]
+    # PCG iterations per step (the robust solver's rounds each solve anew)
+    rounds = spec["robust"][1] if spec.get("robust") else 1
+    fwd_iters = [rounds * int(read_stats(st)["iters"].max()) for _, st, _ in keep]
+    bwd_iters = [0 if bst is None else int(read_stats(bst)["iters"].max()) for _, _, bst in keep]
     C = problems[0].C
 
     t0 = time.perf_counter()
@@ -328,6 +350,8 @@ def main() -> int:
                    "fwd_pcg": list(spec["fwd"]), "bwd_pcg": list(spec["bwd"]),
                    "fwd_iters": fwd_iters[0] if len(V) == 1 else _spread(fwd_iters),
                    "bwd_iters": bwd_iters[0] if len(V) == 1 else _spread(bwd_iters),
+                   **({"robust": {"sigma_gm": spec["robust"][0], "irls_rounds": rounds,
+                                  "pass": "forward only"}} if spec.get("robust") else {}),
                    "parallelism": "single-gpu",
                    "engine": f"batch, {streams} streams" if streams else "single-image"},
         "fwd_mpix_s": round(pixels / sec_f / 1e6, 3),

@@ -210,6 +210,38 @@ bs_status bs_solve_backward(const bs_grid* grid, const float* target, const floa
                             void* stream);
 
 /* ---------------------------------------------------------------------- */
+/* Robust solver: supplement Section Robustness, Algorithm RBS.            */
+/* ---------------------------------------------------------------------- */
+
+/* Bytes of device workspace bs_robust_solve needs for C channels: the solve
+ * workspace followed by the IRLS weights (float32 [H][W]).  Host, pure;
+ * 0 for invalid arguments. */
+size_t bs_robust_workspace_bytes(const bs_grid* grid, int32_t C);
+
+/* The robust bilateral solver: iteratively reweighted least squares with the
+ * Geman-McClure loss rho(e) = e^2 / (sigma_gm^2 + e^2).  Round i (of
+ * irls_iters >= 1) runs bs_solve with confidence c_i and slices its solution
+ * to x; c_0 = conf_init and c_{i+1} = 2 sigma_gm^2 / (sigma_gm^2 + e)^2 per
+ * pixel, e = sum over channels of (x - t)^2 (the printed weight for one
+ * channel), computed in float64 and stored as float32.  Each round solves
+ * from its own initial state, as bs_solve does.
+ *  target     device float32 [C][H][W];  conf_init device float32 [H][W].
+ *  y          device float32 [Vcap][C] output: the last round's solution.
+ *  x          device float32 [C][H][W] output: the last round's S^T y.
+ *  stats      device bs_chan_stats [C] output for the last round, or NULL.
+ *  ws         device workspace of bs_robust_workspace_bytes, 256-byte
+ *             aligned, owned by the caller.
+ * Errors: BS_EINVAL for sigma_gm <= 0 or not finite, irls_iters < 1, a NULL
+ * or misaligned x, and every argument error of bs_solve; BS_EWORKSPACE for a
+ * short workspace.  Checked before any work is enqueued; conf_init is not
+ * modified.  Enqueues on `stream` (synchronising it only where bs_solve does,
+ * for check_every > 0). */
+bs_status bs_robust_solve(const bs_grid* grid, const float* target, const float* conf_init,
+                          int32_t C, const bs_solve_params* params, float sigma_gm,
+                          int32_t irls_iters, float* y, float* x, void* ws, size_t ws_bytes,
+                          bs_chan_stats* stats, void* stream);
+
+/* ---------------------------------------------------------------------- */
 /* Batches: many images of uneven size and channel count (Section 3's      */
 /* forward and backward over a batch, e.g. a segmentation minibatch).      */
 /* ---------------------------------------------------------------------- */

@@ -94,6 +94,9 @@ _SIGS = {
     "bs_solve": (_i32, [ct.POINTER(Grid), _vp, _vp, _i32, ct.POINTER(SolveParams), _vp, _vp,
                         _sz, _vp, _vp]),
     "bs_slice": (_i32, [ct.POINTER(Grid), _vp, _i32, _vp, _vp]),
+    "bs_robust_workspace_bytes": (_sz, [ct.POINTER(Grid), _i32]),
+    "bs_robust_solve": (_i32, [ct.POINTER(Grid), _vp, _vp, _i32, ct.POINTER(SolveParams), ct.c_float,
+                               _i32, _vp, _vp, _vp, _sz, _vp, _vp]),
     "bs_solve_backward": (_i32, [ct.POINTER(Grid), _vp, _vp, _vp, _vp, _i32,
                                  ct.POINTER(SolveParams), _vp, _vp, _vp, _vp, _sz, _vp, _vp]),
     "bs_read_counters": (_i32, [ct.POINTER(Grid), ct.POINTER(_i32), _i32, _vp]),

@@ -151,6 +151,31 @@ class BilateralGrid:
         self._last_ws = ws
         return y, stats
 
+    def robust_solve(self, target: torch.Tensor, conf_init: torch.Tensor, lam: float,
+                     sigma_gm: float, irls_iters: int, max_iters: int = 25, rel_tol: float = 0.0,
+                     init: str = "hier", init_alpha: float = 4.0, init_beta: float = 0.0,
+                     check_every: int = 8):
+        """Robust bilateral solver (Geman-McClure IRLS): the last round's y
+        [Vcap][C], its slice x [C][H][W] and per-channel stats (device bytes)."""
+        C = int(target.shape[0])
+        target = _dev_f32(target, "target", (C, self.H, self.W))
+        conf_init = _dev_f32(conf_init, "confidence", (self.H, self.W))
+        opts = SolveOptions(lam, max_iters, rel_tol, init, init_alpha, init_beta, check_every)
+        nbytes = L.lib.bs_robust_workspace_bytes(ct.byref(self.handle), C)
+        if nbytes == 0:
+            raise ValueError("invalid channel count")
+        ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        y = torch.empty((self.vcap, C), dtype=torch.float32, device=self.device)
+        x = torch.empty((C, self.H, self.W), dtype=torch.float32, device=self.device)
+        stats = torch.empty(C * _STATS_DTYPE.itemsize, dtype=torch.uint8, device=self.device)
+        p = opts.struct()
+        L.check(L.lib.bs_robust_solve(ct.byref(self.handle), target.data_ptr(),
+                                      conf_init.data_ptr(), C, ct.byref(p), float(sigma_gm),
+                                      int(irls_iters), y.data_ptr(), x.data_ptr(), ws.data_ptr(),
+                                      ws.numel(), stats.data_ptr(), _stream()),
+                "bs_robust_solve")
+        return y, x, stats
+
     def slice(self, y: torch.Tensor, C: int | None = None, out: torch.Tensor | None = None):
         C = int(y.shape[1]) if C is None else int(C)
         if out is None:

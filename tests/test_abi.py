@@ -80,6 +80,11 @@ def test_invalid_arguments_are_rejected_before_launch():
     assert L.lib.bs_bistochastize(ct.byref(g), None, None) == L.BS_EINVAL
     assert L.lib.bs_slice(ct.byref(g), ct.c_void_p(256), 1, ct.c_void_p(256), None) == L.BS_EINVAL
     assert L.lib.bs_solve_workspace_bytes(ct.byref(g), 1) == 0
+    assert L.lib.bs_robust_workspace_bytes(ct.byref(g), 1) == 0
+    st = L.lib.bs_robust_solve(ct.byref(g), ct.c_void_p(256), ct.c_void_p(256), 1, ct.byref(sp),
+                               1.0, 4, ct.c_void_p(256), ct.c_void_p(256), ct.c_void_p(4096),
+                               1 << 30, None, None)
+    assert st == L.BS_EINVAL
     assert L.lib.bs_status_string(L.BS_EWORKSPACE) == b"workspace too small"
 
 
