@@ -35,6 +35,13 @@ in the design notes):
   R17 robust solver with several channels: the Geman-McClure weight of a pixel
       takes e o e summed over the channels (the confidence is shared); with
       one channel this is the printed weight.
+  R18 low-rank reduction, the rank t: the number of kept rows is the smallest
+      t whose mass reaches (1 - eps) of the total, so that at most eps of B's
+      squared norm is dropped (the printed inequality, read literally, keeps
+      at most (1 - eps) and contradicts the stated role of eps).
+  R19 low-rank reduction, R-tilde: the first t rows of R', which already is
+      R P^T with its rows reordered (applying P^T once more would permute the
+      columns twice).
 """
 from __future__ import annotations
 
@@ -532,3 +539,62 @@ def robust_solve(ref: np.ndarray, target: np.ndarray, conf_init: np.ndarray, p: 
         e2 = np.sum((sol.x.reshape(C, -1) - t) ** 2, axis=0)
         c = gm_weight(e2, sigma_gm)
     return RobustSolution(sol, weights)
+
+
+# ----------------------------------------------------------------------------
+# Low-rank reduction of many right-hand sides  (supplement Section Multiple
+# Output Channels; R18, R19)
+# ----------------------------------------------------------------------------
+
+@dataclass
+class LowRank:
+    Q: np.ndarray                 # [V][t] Q-tilde, orthonormal columns
+    R: np.ndarray                 # [t][C] R-tilde
+    rank: int                     # t
+    mass: np.ndarray              # row masses of R', non-increasing
+
+
+def lowrank_reduce(B: np.ndarray, eps: float) -> LowRank:
+    """B P = Q R (rank-revealing QR with column pivoting), R' = R P^T with its
+    rows sorted by non-increasing squared norm (the columns of Q alike), and
+    the smallest t whose rows hold (1 - eps) of the mass."""
+    import scipy.linalg
+    B = np.asarray(B, np.float64)
+    Q, R, piv = scipy.linalg.qr(B, mode="economic", pivoting=True)
+    RPt = np.empty_like(R)
+    RPt[:, piv] = R
+    mass = np.sum(RPt ** 2, axis=1)
+    order = np.argsort(-mass, kind="stable")
+    mass = mass[order]
+    total = float(np.sum(mass))
+    if total == 0.0:
+        return LowRank(Q[:, :0], RPt[:0], 0, mass)
+    t = int(np.searchsorted(np.cumsum(mass), (1.0 - eps) * total) + 1)
+    t = min(t, mass.shape[0])
+    return LowRank(Q[:, order[:t]], RPt[order[:t]], t, mass)
+
+
+def solve_lowrank(ref: np.ndarray, target: np.ndarray, conf: np.ndarray, p: Params,
+                  eps: float, prepared=None):
+    """Y = (A^-1 Q-tilde) R-tilde: the reduced system A Z = Q-tilde solved by
+    the same initialisation and PCG as every other right-hand side, then
+    expanded.  Returns (Y [V][C], x [C][H][W], LowRank, PCG runs of Z)."""
+    g, bs, pyr = prepared if prepared is not None else prepare(ref, p)
+    C = target.shape[0]
+    c = np.asarray(conf, np.float64).reshape(-1)
+    t = np.asarray(target, np.float64).reshape(C, -1)
+    sc = splat(g, c)
+    B = np.stack([splat(g, c * t[ch]) for ch in range(C)], axis=1)
+    lr = lowrank_reduce(B, eps)
+    A = Operator(g, bs.n, sc, p.lam)
+    minv = A.jacobi_inverse()
+    runs = []
+    Z = np.zeros((g.V, lr.rank))
+    if lr.rank:
+        Z0 = initial_state(pyr, lr.Q, sc, p)
+        runs = [pcg(A, lr.Q[:, j], Z0[:, j], minv, p.max_iters, p.rel_tol)
+                for j in range(lr.rank)]
+        Z = np.stack([r.y for r in runs], axis=1)
+    Y = Z @ lr.R if lr.rank else np.zeros((g.V, C))
+    x = np.stack([slice_(g, Y[:, ch]) for ch in range(C)]).reshape(C, g.H, g.W)
+    return Y, x, lr, runs

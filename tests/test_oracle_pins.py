@@ -488,3 +488,58 @@ def test_robust_rejects_outliers():
     err_plain = np.abs(plain[keep] - want[keep]).mean()
     err_rob = np.abs(rob[keep] - want[keep]).mean()
     assert err_rob < 0.2 * err_plain, (err_rob, err_plain)
+
+
+# --------------------------------------------------------------------------
+# Low-rank reduction of many right-hand sides (supplement Section Multiple
+# Output Channels)
+# --------------------------------------------------------------------------
+
+def _splat_b(p, prm):
+    g, bs, pyr = O.prepare(p.ref, prm)
+    c = p.conf.reshape(-1).astype(np.float64)
+    B = np.stack([O.splat(g, c * p.target[ch].reshape(-1)) for ch in range(p.C)], axis=1)
+    return g, B
+
+
+def test_lowrank_eps_zero_is_the_full_solve():
+    """eps = 0 keeps every row: A^-1 (Q-tilde R-tilde) = A^-1 B exactly."""
+    p = WL.segmentation(H=40, W=48, regions=6, C=5)
+    prm = params_of(p, rel_tol=1e-12)
+    Y, x, lr, _ = O.solve_lowrank(p.ref, p.target, p.conf, prm, 0.0)
+    full = O.solve(p.ref, p.target, p.conf, prm)
+    assert lr.rank == 5
+    assert np.linalg.norm(Y - full.y) <= 1e-9 * np.linalg.norm(full.y)
+    assert np.linalg.norm(x - full.x) <= 1e-9 * np.linalg.norm(full.x)
+
+
+def test_lowrank_exact_rank_is_found_and_solved():
+    """Six channels spanned by two: t = 2 for a small eps, and the reduced
+    solve equals the full one."""
+    p = WL.segmentation(H=40, W=48, regions=6, C=2)
+    rng = np.random.default_rng(3)
+    mix = rng.normal(size=(6, 2))
+    p.target = np.einsum("kc,chw->khw", mix, p.target).astype(np.float32)
+    prm = params_of(p, rel_tol=1e-12)
+    Y, x, lr, _ = O.solve_lowrank(p.ref, p.target, p.conf, prm, 1e-6)
+    full = O.solve(p.ref, p.target, p.conf, prm)
+    assert lr.rank == 2
+    # the float32 targets are rank 2 up to their rounding (~1e-8)
+    assert np.linalg.norm(Y - full.y) <= 1e-6 * np.linalg.norm(full.y)
+
+
+@pytest.mark.parametrize("eps", [0.01, 0.1, 0.5])
+def test_lowrank_drops_at_most_eps_and_keeps_the_fewest_rows(eps):
+    """R18: ||B - Q-tilde R-tilde||_F^2 <= eps ||B||_F^2, computed from B
+    itself, and one row fewer would drop more than eps; Q-tilde has
+    orthonormal columns."""
+    p = WL.segmentation(H=48, W=64, regions=8, C=8)
+    prm = params_of(p)
+    g, B = _splat_b(p, prm)
+    lr = O.lowrank_reduce(B, eps)
+    nb = np.sum(B ** 2)
+    assert np.sum((B - lr.Q @ lr.R) ** 2) <= eps * nb * (1 + 1e-12)
+    assert np.allclose(lr.Q.T @ lr.Q, np.eye(lr.rank), atol=1e-12)
+    if lr.rank > 0:
+        fewer = lr.Q[:, :-1] @ lr.R[:-1]
+        assert np.sum((B - fewer) ** 2) > eps * nb
