@@ -54,6 +54,12 @@ WORKLOADS = {
     # disparities; forward only (a step is the 8 rounds)
     "robust_stereo1024x768": dict(gen="stereo_refine", images=1, fwd=(25, 0.0), bwd=(0, 0.0),
                                   robust=(4.0, 8)),
+    # low-rank reduction (eps = 0.01) of 21-channel class-probability maps with
+    # three classes present per image, forward only, image after image; the
+    # same images solved with all 21 right-hand sides give the "vs plain"
+    # ratio
+    "segprob16x512x512": dict(gen="segmentation_probs", images=16, fwd=(20000, 1e-6),
+                              bwd=(0, 0.0), lowrank=0.01),
 }
 
 
@@ -125,6 +131,17 @@ def run_step(inputs, spec, backward=True, keep=None, streams=0):
     bce = 0 if bt == 0.0 else 8
     if streams > 0:
         return run_batch_step(inputs, spec, backward, keep, streams)
+    if spec.get("lowrank") is not None:
+        for d in inputs:
+            p = d["p"]
+            G = BilateralGrid(d["ref"], p.sigma_xy, p.sigma_l, p.sigma_uv)
+            y, st, rank = G.solve_lowrank(d["t"], d["c"], p.lam, spec["lowrank"], max_iters=fi,
+                                          rel_tol=ft, check_every=fce)
+            G.slice(y, p.C)
+            if keep is not None:
+                keep.append((G.vertex_count(), st, None))
+                RANKS.append(rank)
+        return
     if spec.get("robust"):
         sigma_gm, rounds = spec["robust"]
         for d in inputs:
@@ -146,6 +163,9 @@ def run_step(inputs, spec, backward=True, keep=None, streams=0):
                                         rel_tol=bt, check_every=bce, ws=ws)
         if keep is not None:
             keep.append((G.vertex_count(), st, bst if backward else None))
+
+
+RANKS = []   # reduced ranks of the low-rank workload's images (warm-up step)
 
 
 def run_batch_step(inputs, spec, backward, keep, streams):
@@ -218,12 +238,16 @@ def cpu_baseline(problems, spec, seconds):
         gx = gx * p.conf[None]
     if spec.get("robust"):
         sample = sample.replace("forward+backward", "robust forward")
+    if spec.get("lowrank") is not None:
+        sample = sample.replace("forward+backward", "low-rank forward")
     t0 = time.perf_counter()
     n = 0
     while True:
         prm = O.Params(p.sigma_xy, p.sigma_l, p.sigma_uv, p.lam, max_iters=fi, rel_tol=ft)
         if spec.get("robust"):
             O.robust_solve(p.ref, p.target, p.conf, prm, *spec["robust"])
+        elif spec.get("lowrank") is not None:
+            O.solve_lowrank(p.ref, p.target, p.conf, prm, spec["lowrank"])
         else:
             sol = O.solve(p.ref, p.target, p.conf, prm)
             prmb = O.Params(p.sigma_xy, p.sigma_l, p.sigma_uv, p.lam, max_iters=bi, rel_tol=bt)
@@ -282,6 +306,7 @@ def main() -> int:
     keep = []
     for _ in range(max(1, args.warmup)):
         keep.clear()
+        RANKS.clear()
         run_step(inputs, spec, True, keep, streams)
         torch.cuda.synchronize()
         print("bench: warmup step done", file=sys.stderr, flush=True)
@@ -303,6 +328,12 @@ def main() -> int:
     print(f"bench: fwd+bwd {sec_fb * 1e3:.3f} ms/step, fwd {sec_f * 1e3:.3f} ms/step",
           file=sys.stderr, flush=True)
     plain = None
+    if spec.get("lowrank") is not None and not args.no_plain:
+        full = {k: v for k, v in spec.items() if k != "lowrank"}
+        sec_plain = timed(inputs, full, args.steps, backward=False, streams=0)
+        plain = pixels / sec_plain / 1e6
+        print(f"bench: full-rank single-image path fwd {sec_plain * 1e3:.3f} ms/step",
+              file=sys.stderr, flush=True)
     if streams and not args.no_plain:
         sec_plain = timed(inputs, spec, args.steps, backward=True, streams=0)
         plain = pixels / sec_plain / 1e6
@@ -313,8 +344,9 @@ def main() -> int:
     # Algorithmic bytes of one step's pcg_matvec launches over their summed
     # durations (matvec_bytes).  Launches past convergence (between stop
     # polls) return at once and count as time only.
-    step_bytes = sum(v * matvec_bytes(p.C, fi + bi) for v, p, fi, bi in
-                     zip(V, problems, fwd_iters, bwd_iters))
+    solved_c = RANKS if RANKS else [p.C for p in problems]   # right-hand sides solved
+    step_bytes = sum(v * matvec_bytes(c, fi + bi) for v, c, fi, bi in
+                     zip(V, solved_c, fwd_iters, bwd_iters))
     avg_us = mv_ms / mv_launches * 1e3 if mv_launches else float("nan")
     bytes_per_launch = step_bytes / mv_launches if mv_launches else 0.0
     achieved = step_bytes / (mv_ms * 1e-3) / 1e9 if mv_launches else 0.0
@@ -352,6 +384,9 @@ def main() -> int:
                    "bwd_iters": bwd_iters[0] if len(V) == 1 else _spread(bwd_iters),
                    **({"robust": {"sigma_gm": spec["robust"][0], "irls_rounds": rounds,
                                   "pass": "forward only"}} if spec.get("robust") else {}),
+                   **({"lowrank": {"eps": spec["lowrank"], "ranks": _histogram(RANKS),
+                                   "pass": "forward only"}}
+                      if spec.get("lowrank") is not None else {}),
                    "parallelism": "single-gpu",
                    "engine": f"batch, {streams} streams" if streams else "single-image"},
         "fwd_mpix_s": round(pixels / sec_f / 1e6, 3),

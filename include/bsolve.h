@@ -242,6 +242,46 @@ bs_status bs_robust_solve(const bs_grid* grid, const float* target, const float*
                           bs_chan_stats* stats, void* stream);
 
 /* ---------------------------------------------------------------------- */
+/* Low-rank reduction of many right-hand sides: supplement Section         */
+/* Multiple Output Channels.                                               */
+/* ---------------------------------------------------------------------- */
+
+/* Bytes of device workspace bs_solve_lowrank needs for C channels (host,
+ * pure; 0 for invalid arguments). */
+size_t bs_lowrank_workspace_bytes(const bs_grid* grid, int32_t C);
+
+/* Solves A Y = B, B = S(c o t) [V][C], through a low-rank reduction of B:
+ * B P = Q R with column pivoting, the rows of R P^T ordered by non-increasing
+ * mass (squared norm) with the columns of Q alike, and the fewest rows t whose
+ * mass reaches (1 - eps) of the total, so that at most eps of B's squared
+ * norm is dropped; then A Z = Q~ (t right-hand sides, each by the same
+ * initialisation and PCG as bs_solve) and Y = Z R~.  R is computed from the
+ * Gram matrix B^T B, summed in float64 in a fixed order, by bs_lowrank_factor.
+ *  target  device float32 [C][H][W];  conf device float32 [H][W], >= 0.
+ *  eps     in [0, 1): 0 keeps every independent row.
+ *  y       device float32 [Vcap][C] output (all zero when B = 0).
+ *  stats   device bs_chan_stats [C] or NULL: entries 0..t-1 describe the
+ *          reduced systems; the rest are not written.
+ *  rank    host int32 output: t.
+ * Synchronises `stream` (the factorisation runs on the host, between the
+ * splat and the reduced solve).  Errors as bs_solve, plus BS_EINVAL for eps
+ * outside [0, 1) or a NULL rank. */
+bs_status bs_solve_lowrank(const bs_grid* grid, const float* target, const float* conf,
+                           int32_t C, const bs_solve_params* params, double eps, float* y,
+                           void* ws, size_t ws_bytes, bs_chan_stats* stats, int32_t* rank,
+                           void* stream);
+
+/* The factorisation step of bs_solve_lowrank on the host (pure, no device
+ * work): from the Gram matrix G = B^T B (float64 [C][C], row-major,
+ * symmetric), a Cholesky factorisation with diagonal pivoting gives R of
+ * B P = Q R (the largest remaining diagonal is the largest remaining column
+ * norm); pivots at or below 1e-13 of the largest diagonal end it.  Writes
+ * t, M (float32 [C][t], Q~ = B M) and R~ (float32 [t][C], the kept rows of
+ * R P^T in order of mass).  M and Rt must hold C*C floats. */
+bs_status bs_lowrank_factor(const double* gram, int32_t C, double eps, float* M, float* Rt,
+                            int32_t* rank);
+
+/* ---------------------------------------------------------------------- */
 /* Batches: many images of uneven size and channel count (Section 3's      */
 /* forward and backward over a batch, e.g. a segmentation minibatch).      */
 /* ---------------------------------------------------------------------- */

@@ -95,6 +95,10 @@ _SIGS = {
                         _sz, _vp, _vp]),
     "bs_slice": (_i32, [ct.POINTER(Grid), _vp, _i32, _vp, _vp]),
     "bs_robust_workspace_bytes": (_sz, [ct.POINTER(Grid), _i32]),
+    "bs_lowrank_workspace_bytes": (_sz, [ct.POINTER(Grid), _i32]),
+    "bs_solve_lowrank": (_i32, [ct.POINTER(Grid), _vp, _vp, _i32, ct.POINTER(SolveParams),
+                                ct.c_double, _vp, _vp, _sz, _vp, ct.POINTER(_i32), _vp]),
+    "bs_lowrank_factor": (_i32, [_vp, _i32, ct.c_double, _vp, _vp, ct.POINTER(_i32)]),
     "bs_robust_solve": (_i32, [ct.POINTER(Grid), _vp, _vp, _i32, ct.POINTER(SolveParams), ct.c_float,
                                _i32, _vp, _vp, _vp, _sz, _vp, _vp]),
     "bs_solve_backward": (_i32, [ct.POINTER(Grid), _vp, _vp, _vp, _vp, _i32,

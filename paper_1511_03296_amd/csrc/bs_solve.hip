@@ -1292,7 +1292,7 @@ __global__ void __launch_bounds__(kBlock) grad_scatter(const int32_t* __restrict
 // ---------------------------------------------------------------------------
 // Host sequencing.
 // ---------------------------------------------------------------------------
-static bs_status validate_solve(const bs_grid* grid, int C, const bs_solve_params* p) {
+bs_status validate_solve(const bs_grid* grid, int C, const bs_solve_params* p) {
     if (!grid || impl(grid)->magic != kGridMagic) return fail(BS_EINVAL, "grid was not built");
     if (!impl(grid)->bistochastized) return fail(BS_EINVAL, "grid was not bistochastized");
     if (C < 1 || C > BS_MAX_CHANNELS) return fail(BS_EINVAL, "channel count must be in 1..64");
@@ -1361,10 +1361,20 @@ static bs_status run_init(const GridImpl& g, const SolveWs& w, const bs_solve_pa
     return BS_OK;
 }
 
+bs_status splat_setup(const GridImpl& g, const SolveWs& w, const float* conf, const float* vals,
+                      bool weighted, double lambda, hipStream_t s) {
+    return weighted ? launch_splat<true>(g, w, conf, vals, lambda, s)
+                    : launch_splat<false>(g, w, conf, vals, lambda, s);
+}
+
+bs_status init_state(const GridImpl& g, const SolveWs& w, const bs_solve_params& p, float* yw,
+                     hipStream_t s) {
+    return run_init(g, w, p, yw, s);
+}
+
 bs_status solve_setup(const GridImpl& g, const SolveWs& w, const float* conf, const float* vals,
                       bool weighted, const bs_solve_params& p, float* yw, hipStream_t s) {
-    const bs_status st = weighted ? launch_splat<true>(g, w, conf, vals, (double)p.lambda, s)
-                                  : launch_splat<false>(g, w, conf, vals, (double)p.lambda, s);
+    const bs_status st = splat_setup(g, w, conf, vals, weighted, (double)p.lambda, s);
     if (st != BS_OK) return st;
     return run_init(g, w, p, yw, s);
 }

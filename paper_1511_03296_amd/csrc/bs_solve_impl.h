@@ -98,6 +98,19 @@ size_t layout_solve(const GridImpl& g, int C, int nb, void* base, SolveWs& w);
 // Reducing blocks of a single-image solve.
 int solve_blocks(const GridImpl& g, int C);
 
+// Argument checks shared by the solve entry points (grid built and
+// bistochastized, channel count, parameters).
+bs_status validate_solve(const bs_grid* grid, int C, const bs_solve_params* p);
+
+// Splat alone: S c, diag(A), its Jacobi inverse, {n, M^-1} and b (weighted:
+// b = S(c o t), else b = S t).
+bs_status splat_setup(const GridImpl& g, const SolveWs& w, const float* conf, const float* vals,
+                      bool weighted, double lambda, hipStream_t s);
+
+// Initial state of w's right-hand side w.b into yw (flat or hierarchical).
+bs_status init_state(const GridImpl& g, const SolveWs& w, const bs_solve_params& p, float* yw,
+                     hipStream_t s);
+
 // Splat (weighted: b = S(c o t), else b = S t) and initial state into yw.
 bs_status solve_setup(const GridImpl& g, const SolveWs& w, const float* conf, const float* vals,
                       bool weighted, const bs_solve_params& p, float* yw, hipStream_t s);

@@ -176,6 +176,32 @@ class BilateralGrid:
                 "bs_robust_solve")
         return y, x, stats
 
+    def solve_lowrank(self, target: torch.Tensor, conf: torch.Tensor, lam: float,
+                      eps: float = 0.01, max_iters: int = 25, rel_tol: float = 0.0,
+                      init: str = "hier", init_alpha: float = 4.0, init_beta: float = 0.0,
+                      check_every: int = 8, ws: torch.Tensor | None = None):
+        """A Y = B through the low-rank reduction of B: y [Vcap][C], the
+        reduced systems' stats (device bytes, first `rank` entries) and the
+        rank.  Synchronises the current stream."""
+        C = int(target.shape[0])
+        target = _dev_f32(target, "target", (C, self.H, self.W))
+        conf = _dev_f32(conf, "confidence", (self.H, self.W))
+        opts = SolveOptions(lam, max_iters, rel_tol, init, init_alpha, init_beta, check_every)
+        if ws is None:
+            nbytes = L.lib.bs_lowrank_workspace_bytes(ct.byref(self.handle), C)
+            if nbytes == 0:
+                raise ValueError("invalid channel count")
+            ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        y = torch.empty((self.vcap, C), dtype=torch.float32, device=self.device)
+        stats = torch.zeros(C * _STATS_DTYPE.itemsize, dtype=torch.uint8, device=self.device)
+        rank = ct.c_int32(0)
+        p = opts.struct()
+        L.check(L.lib.bs_solve_lowrank(ct.byref(self.handle), target.data_ptr(), conf.data_ptr(),
+                                       C, ct.byref(p), float(eps), y.data_ptr(), ws.data_ptr(),
+                                       ws.numel(), stats.data_ptr(), ct.byref(rank), _stream()),
+                "bs_solve_lowrank")
+        return y, stats, int(rank.value)
+
     def slice(self, y: torch.Tensor, C: int | None = None, out: torch.Tensor | None = None):
         C = int(y.shape[1]) if C is None else int(C)
         if out is None:

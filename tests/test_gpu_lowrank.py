@@ -1,0 +1,62 @@
+"""GPU parity of the low-rank reduction of many right-hand sides
+(supplement Section Multiple Output Channels) through the C ABI against the
+FP64 oracle: the same rank, and the reduced solution to the solver's
+tolerance."""
+import numpy as np
+import pytest
+import torch
+
+import workloads as WL
+from oracle import bilateral as O
+from tests.gpu_helpers import gpu_grid, params, rel_l2, say, to_dev
+
+pytestmark = pytest.mark.gpu
+
+TOL_X = 1e-4
+
+
+def test_lowrank_class_probabilities():
+    p = WL.segmentation_probs(H=192, W=256, regions=30)
+    say("lowrank segprob256x192 C=21 eps=0.01")
+    prm = params(p)
+    G = gpu_grid(p)
+    y, st, t = G.solve_lowrank(to_dev(p.target), to_dev(p.conf), p.lam, 0.01,
+                               max_iters=prm.max_iters, rel_tol=prm.rel_tol)
+    x = G.slice(y, p.C)
+    torch.cuda.synchronize()
+    Y, xo, lr, runs = O.solve_lowrank(p.ref, p.target, p.conf, prm, 0.01)
+    say(f"  rank {t} (oracle {lr.rank})")
+    assert t == lr.rank and 1 <= t <= 5
+    from paper_1511_03296_amd import read_stats
+    s = read_stats(st)[:t]
+    assert np.all(s["reason"] == 1)
+    V = Y.shape[0]
+    assert rel_l2(y.cpu().numpy()[:V], Y) <= TOL_X
+    assert rel_l2(x.cpu().numpy(), xo) <= TOL_X
+    # what the reduction drops: small next to the full solve
+    full = O.solve(p.ref, p.target, p.conf, prm)
+    assert rel_l2(x.cpu().numpy(), full.x) <= 0.1
+
+
+def test_lowrank_eps_zero_is_the_full_solve():
+    p = WL.segmentation(H=96, W=128, regions=20, C=5, rel_tol=1e-6)
+    say("lowrank eps=0 seg128x96 C=5")
+    G = gpu_grid(p)
+    t_, c_ = to_dev(p.target), to_dev(p.conf)
+    y, st, t = G.solve_lowrank(t_, c_, p.lam, 0.0, max_iters=p.max_iters, rel_tol=p.rel_tol)
+    yf, _ = G.solve(t_, c_, p.lam, max_iters=p.max_iters, rel_tol=p.rel_tol)
+    torch.cuda.synchronize()
+    V = G.vertex_count()
+    assert t == 5
+    assert rel_l2(y.cpu().numpy()[:V], yf.cpu().numpy()[:V]) <= TOL_X
+
+
+def test_lowrank_zero_target_and_invalid_eps():
+    p = WL.segmentation(H=40, W=48, regions=6, C=4)
+    G = gpu_grid(p)
+    z = torch.zeros((4, p.H, p.W), device="cuda")
+    y, _, t = G.solve_lowrank(z, to_dev(p.conf), p.lam, 0.01)
+    torch.cuda.synchronize()
+    assert t == 0 and torch.count_nonzero(y) == 0
+    with pytest.raises(ValueError):
+        G.solve_lowrank(to_dev(p.target), to_dev(p.conf), p.lam, 1.0)

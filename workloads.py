@@ -178,6 +178,28 @@ def segmentation(seed: int = 0, H: int = 512, W: int = 512, regions: int = 100,
                    sigma[2], lam, max_iters, rel_tol, extra={"onehot": onehot})
 
 
+def segmentation_probs(seed: int = 0, H: int = 512, W: int = 512, regions: int = 100,
+                       C: int = 21, present: int = 3, sharpness: float = 5.0,
+                       sigma=(8, 4, 4), lam: float = 128.0, rel_tol: float = 1e-6,
+                       max_iters: int = 20000) -> Problem:
+    """Class-probability shape: each region belongs to one of `present` of
+    the C classes, and the target is the softmax over classes of
+    sharpness * onehot(region class) + box-smoothed N(0,1) logits, the form
+    of a segmentation network's output in which few classes carry mass.
+    Confidence U[0.2,1]."""
+    rng = np.random.default_rng(seed)
+    ref, lab = voronoi_reference(rng, H, W, regions)
+    classes = rng.choice(C, present, replace=False)
+    region_class = classes[rng.integers(0, present, regions)]
+    logits = smoothed_logits(rng, C, H, W)
+    logits += sharpness * (np.arange(C)[:, None, None] == region_class[lab][None])
+    e = np.exp(logits - logits.max(axis=0, keepdims=True))
+    t = (e / e.sum(axis=0, keepdims=True)).astype(np.float32)
+    conf = rng.uniform(0.2, 1.0, size=(H, W)).astype(np.float32)
+    return Problem("segprob_%dx%d_c%d" % (W, H, C), ref, t, conf, sigma[0], sigma[1],
+                   sigma[2], lam, max_iters, rel_tol)
+
+
 def mixed_batch(seed: int = 0, count: int = 64, wmin=320, wmax=1920, hmin=240,
                 hmax=1080, lam: float = 128.0, rel_tol: float = 1e-5,
                 max_iters: int = 20000) -> list[Problem]:
