@@ -55,11 +55,11 @@ WORKLOADS = {
     "robust_stereo1024x768": dict(gen="stereo_refine", images=1, fwd=(25, 0.0), bwd=(0, 0.0),
                                   robust=(4.0, 8)),
     # low-rank reduction (eps = 0.01) of 21-channel class-probability maps with
-    # three classes present per image, forward only, image after image; the
-    # same images solved with all 21 right-hand sides give the "vs plain"
-    # ratio
-    "segprob16x512x512": dict(gen="segmentation_probs", images=16, fwd=(20000, 1e-6),
-                              bwd=(0, 0.0), lowrank=0.01),
+    # three classes present per image, forward only, through the batch engine;
+    # the same images solved one after another with all 21 right-hand sides
+    # give the "vs plain" ratio
+    "segprob16x512x512": dict(gen="segmentation_probs", images=16, batch=True,
+                              fwd=(20000, 1e-6), bwd=(0, 0.0), lowrank=0.01),
 }
 
 
@@ -180,6 +180,14 @@ def run_batch_step(inputs, spec, backward, keep, streams):
     want = keep is not None
     fwd = SolveOptions(lam, fi, ft, check_every=0 if ft == 0.0 else 8)
     bwd = SolveOptions(lam, bi, bt, check_every=0 if bt == 0.0 else 8)
+    if spec.get("lowrank") is not None:
+        _, fst, ranks = state.forward_lowrank(fwd, spec["lowrank"], stats=want)
+        if want:
+            V = state.vertex_counts()
+            for i in range(len(inputs)):
+                keep.append((V[i], fst[i], None))
+            RANKS.extend(ranks)
+        return
     _, fst = state.forward(fwd, stats=want)
     bst = None
     if backward:
@@ -334,7 +342,7 @@ def main() -> int:
         plain = pixels / sec_plain / 1e6
         print(f"bench: full-rank single-image path fwd {sec_plain * 1e3:.3f} ms/step",
               file=sys.stderr, flush=True)
-    if streams and not args.no_plain:
+    elif streams and not args.no_plain:
         sec_plain = timed(inputs, spec, args.steps, backward=True, streams=0)
         plain = pixels / sec_plain / 1e6
         print(f"bench: plain single-image path fwd+bwd {sec_plain * 1e3:.3f} ms/step",

@@ -346,6 +346,27 @@ bs_status bs_batch_backward(const bs_batch_item* items, int32_t n, const bs_grid
                             const bs_solve_params* params, int32_t n_streams, void* ws,
                             size_t ws_bytes, void* stream);
 
+/* Scratch bytes of bs_batch_forward_lowrank: every image's solve workspace
+ * and reduced system, plus the batched PCG's tables (0 for an invalid
+ * batch). */
+size_t bs_batch_lowrank_workspace_bytes(const bs_batch_item* items, int32_t n,
+                                        int32_t n_streams);
+
+/* Forward pass of every image through the low-rank reduction of its
+ * right-hand sides (as bs_solve_lowrank, with the same eps for all images):
+ * grid, bistochastization, splat and reduction per image on the library
+ * streams (each image's factorisation synchronises its stream), then the
+ * reduced systems of rank > 0 through the batched PCG (grouped by lane width
+ * of their rank), then Y = Z R~ into y and the slice into x.  ranks: host
+ * int32 [n] output.  stats [C] of an item: entries 0..t-1 describe its
+ * reduced systems.  Errors as bs_batch_forward, plus BS_EINVAL for eps
+ * outside [0, 1) or a NULL rank array.  Returns after enqueuing; the stream
+ * has been synchronised by the set-up. */
+bs_status bs_batch_forward_lowrank(const bs_batch_item* items, int32_t n,
+                                   const bs_solve_params* params, const bs_bistoch_params* bist,
+                                   bs_grid* grids, int32_t n_streams, double eps, int32_t* ranks,
+                                   void* ws, size_t ws_bytes, void* stream);
+
 /* ---------------------------------------------------------------------- */
 /* Queries and diagnostics.                                                */
 /* ---------------------------------------------------------------------- */

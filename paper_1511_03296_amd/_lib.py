@@ -114,6 +114,10 @@ _SIGS = {
                                 ct.POINTER(BistochParams), ct.POINTER(Grid), _i32, _vp, _sz, _vp]),
     "bs_batch_backward": (_i32, [ct.POINTER(BatchItem), _i32, ct.POINTER(Grid),
                                  ct.POINTER(SolveParams), _i32, _vp, _sz, _vp]),
+    "bs_batch_lowrank_workspace_bytes": (_sz, [ct.POINTER(BatchItem), _i32, _i32]),
+    "bs_batch_forward_lowrank": (_i32, [ct.POINTER(BatchItem), _i32, ct.POINTER(SolveParams),
+                                        ct.POINTER(BistochParams), ct.POINTER(Grid), _i32,
+                                        ct.c_double, ct.POINTER(_i32), _vp, _sz, _vp]),
     "bs_timing_enable": (_i32, [_i32]),
     "bs_timing_reset": (_i32, []),
     "bs_timing_read": (_i32, [ct.c_char_p, ct.POINTER(ct.c_double), ct.POINTER(ct.c_int64)]),

@@ -400,3 +400,90 @@ extern "C" bs_status bs_batch_backward(const bs_batch_item* items, int32_t n,
     }
     return BS_OK;
 }
+
+// Bytes of one image's part of a low-rank batch: its solve workspace, then
+// the reduced system, Gram partials and factors.
+static size_t lowrank_item_bytes(const bs_batch_item& it) {
+    const GridImpl g = sized_grid(it);
+    return item_solve_bytes(it) + align_up(lowrank_extra_bytes(g, it.C, kRedGridMax), 256);
+}
+
+extern "C" size_t bs_batch_lowrank_workspace_bytes(const bs_batch_item* items, int32_t n,
+                                                   int32_t n_streams) {
+    if (validate_items(items, n, n_streams, false) != BS_OK) return 0;
+    size_t total = table_bytes(n);
+    for (int i = 0; i < n; ++i) total += lowrank_item_bytes(items[i]);
+    return total;
+}
+
+extern "C" bs_status bs_batch_forward_lowrank(const bs_batch_item* items, int32_t n,
+                                              const bs_solve_params* params,
+                                              const bs_bistoch_params* bist, bs_grid* grids,
+                                              int32_t n_streams, double eps, int32_t* ranks,
+                                              void* ws, size_t ws_bytes, void* stream) {
+    bs_status st = validate_items(items, n, n_streams, false);
+    if (st != BS_OK) return st;
+    st = check_params(params);
+    if (st != BS_OK) return st;
+    if (!grids || !ranks) return fail(BS_EINVAL, "NULL grid or rank array");
+    if (!(eps >= 0.0 && eps < 1.0)) return fail(BS_EINVAL, "eps must be in [0, 1)");
+    if (((uintptr_t)ws & 255) != 0) return fail(BS_EINVAL, "workspace must be 256-byte aligned");
+    const size_t need = bs_batch_lowrank_workspace_bytes(items, n, n_streams);
+    if (!ws || ws_bytes < need)
+        return fail(BS_EWORKSPACE, "batch workspace needs " + std::to_string(need) + " bytes");
+    const bs_solve_params& p = *params;
+    hipStream_t cs = (hipStream_t)stream;
+    // every image: its full-channel solve workspace, then its reduced system
+    std::vector<SolveWs> full(n);
+    std::vector<char*> extra(n);
+    std::vector<LowRankPlan> lr(n);
+    size_t off = table_bytes(n);
+    for (int i = 0; i < n; ++i) {
+        const GridImpl g = sized_grid(items[i]);
+        layout_solve(g, items[i].C, kRedGridMax, (char*)ws + off, full[i]);
+        extra[i] = (char*)ws + off + item_solve_bytes(items[i]);
+        off += lowrank_item_bytes(items[i]);
+    }
+    // set-up per image: grid, bistochastization, splat, reduction (the host
+    // factorisation synchronises the image's library stream) and the reduced
+    // system's initial state
+    st = for_each_item(items, n, n_streams, cs, [&](int i, hipStream_t s) -> bs_status {
+        const bs_batch_item& it = items[i];
+        bs_status r = bs_build_grid(it.ref, it.H, it.W, &it.sigma, it.grid_ws, it.grid_ws_bytes, s,
+                                    &grids[i]);
+        if (r != BS_OK) return r;
+        r = bs_bistochastize(&grids[i], bist, s);
+        if (r != BS_OK) return r;
+        const GridImpl& g = *impl(&grids[i]);
+        r = splat_setup(g, full[i], it.conf, it.target, true, (double)p.lambda, s);
+        if (r != BS_OK) return r;
+        return lowrank_prepare(g, full[i], extra[i], kRedGridMax, eps, p, s, lr[i]);
+    });
+    if (st != BS_OK) return st;
+    // the reduced systems of rank > 0 through the batched PCG
+    std::vector<bs_batch_item> items_c;
+    std::vector<bs_grid> grids_c;
+    std::vector<Plan> plans_c;
+    for (int i = 0; i < n; ++i) {
+        ranks[i] = lr[i].t;
+        if (lr[i].t == 0) continue;
+        items_c.push_back(items[i]);
+        grids_c.push_back(grids[i]);
+        plans_c.push_back(Plan{lr[i].w, lr[i].w.yi});
+    }
+    if (!plans_c.empty()) {
+        st = batched_pcg(items_c.data(), (int)items_c.size(), grids_c.data(), plans_c, p, ws, cs);
+        if (st != BS_OK) return st;
+    }
+    for (int i = 0; i < n; ++i) {
+        const bs_batch_item& it = items[i];
+        const GridImpl& g = *impl(&grids[i]);
+        st = lowrank_finish(g, lr[i], it.C, it.y, cs);
+        if (st != BS_OK) return st;
+        if (it.x) {
+            st = bs_slice(&grids[i], it.y, it.C, it.x, cs);
+            if (st != BS_OK) return st;
+        }
+    }
+    return BS_OK;
+}

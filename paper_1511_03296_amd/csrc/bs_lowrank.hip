@@ -196,14 +196,79 @@ Reduction reduce_gram(const std::vector<double>& G, int C, double eps) {
     return out;
 }
 
-size_t reduced_bytes(const GridImpl& g, int C) {
+size_t reduced_bytes(const GridImpl& g, int C, int nb) {
     SolveWs w;
     size_t r = 0;
-    for (int t = 1; t <= C; ++t) r = std::max(r, layout_solve(g, t, 0, nullptr, w));
+    for (int t = 1; t <= C; ++t) r = std::max(r, layout_solve(g, t, nb, nullptr, w));
     return r;
 }
 
 }  // namespace
+
+size_t lowrank_extra_bytes(const GridImpl& g, int C, int nb) {
+    return align_up(reduced_bytes(g, C, nb), 256) +
+           align_up((size_t)kGramBlocks * pair_count(C) * sizeof(double), 256) +
+           align_up((size_t)2 * C * C * sizeof(float), 256);
+}
+
+bs_status lowrank_prepare(const GridImpl& g, const SolveWs& w1, char* extra, int nb, double eps,
+                          const bs_solve_params& p, hipStream_t s, LowRankPlan& out) {
+    const int C = w1.C;
+    const int np = pair_count(C);
+    double* part = (double*)(extra + align_up(reduced_bytes(g, C, nb), 256));
+    float* dmat = (float*)((char*)part + align_up((size_t)kGramBlocks * np * sizeof(double), 256));
+    BS_LAUNCH(s, K_SPLAT, "gram_partials", gram_partials, dim3(kGramBlocks), dim3(kBlock), 0, s,
+              w1.b, w1.Cp, C, g.counts, part);
+    std::vector<double> hp((size_t)kGramBlocks * np);
+    BS_TRY_HIP(hipMemcpyAsync(hp.data(), part, hp.size() * sizeof(double), hipMemcpyDeviceToHost,
+                              s));
+    BS_TRY_HIP(hipStreamSynchronize(s));
+    std::vector<double> G((size_t)C * C, 0.0);
+    for (int q = 0, i = 0, k = 0; q < np; ++q) {
+        double acc = 0.0;
+        for (int j = 0; j < kGramBlocks; ++j) acc += hp[(size_t)j * np + q];
+        G[(size_t)i * C + k] = G[(size_t)k * C + i] = acc;
+        if (++k == C) k = ++i;
+    }
+    const Reduction rd = reduce_gram(G, C, eps);
+    out.t = rd.t;
+    out.Rt = nullptr;
+    if (rd.t == 0) return BS_OK;
+    std::vector<float> mats(rd.M);
+    mats.insert(mats.end(), rd.Rt.begin(), rd.Rt.end());
+    BS_TRY_HIP(hipMemcpyAsync(dmat, mats.data(), mats.size() * sizeof(float),
+                              hipMemcpyHostToDevice, s));
+    out.Rt = dmat + (size_t)C * rd.t;
+    SolveWs& w2 = out.w;
+    layout_solve(g, rd.t, nb, extra, w2);
+    // the reduced system shares A: S c, diag(A), M^-1 and {n, M^-1}
+    w2.sc = w1.sc;
+    w2.diag = w1.diag;
+    w2.minv = w1.minv;
+    w2.nfm = w1.nfm;
+    const int pblocks = grid_blocks(ceil_div(g.vcap * w2.Cp, kBlock));
+    BS_LAUNCH(s, K_SPLAT, "lowrank_project", lowrank_project, dim3(pblocks), dim3(kBlock), 0, s,
+              w1.b, w1.Cp, C, (const float*)dmat, rd.t, w2.b, w2.Cp, g.counts);
+    bs_status st = init_state(g, w2, p, w2.yi, s);
+    if (st != BS_OK) return st;
+    // the host copy of the factors must outlive its transfer
+    BS_TRY_HIP(hipStreamSynchronize(s));
+    return BS_OK;
+}
+
+bs_status lowrank_finish(const GridImpl& g, const LowRankPlan& lr, int C, float* y,
+                         hipStream_t s) {
+    if (lr.t == 0) {
+        // B = 0: Y = 0 (the solve's b = 0 case)
+        BS_TRY_HIP(hipMemsetAsync(y, 0, (size_t)g.vcap * C * sizeof(float), s));
+        return BS_OK;
+    }
+    const int eblocks = grid_blocks(ceil_div(g.vcap * C, kBlock));
+    BS_LAUNCH(s, K_SLICE, "lowrank_expand", lowrank_expand, dim3(eblocks), dim3(kBlock), 0, s,
+              lr.w.yi, lr.w.Cp, lr.t, lr.Rt, C, y, g.counts);
+    return BS_OK;
+}
+
 }  // namespace bs
 
 using namespace bs;
@@ -226,10 +291,7 @@ extern "C" bs_status bs_lowrank_factor(const double* gram, int32_t C, double eps
 extern "C" size_t bs_lowrank_workspace_bytes(const bs_grid* grid, int32_t C) {
     const size_t full = bs_solve_workspace_bytes(grid, C);
     if (full == 0) return 0;
-    const GridImpl& g = *impl(grid);
-    return full + reduced_bytes(g, C) +
-           align_up((size_t)kGramBlocks * pair_count(C) * sizeof(double), 256) +
-           align_up((size_t)2 * C * C * sizeof(float), 256);
+    return full + lowrank_extra_bytes(*impl(grid), C, 0);
 }
 
 extern "C" bs_status bs_solve_lowrank(const bs_grid* grid, const float* target, const float* conf,
@@ -249,61 +311,18 @@ extern "C" bs_status bs_solve_lowrank(const bs_grid* grid, const float* target, 
     const GridImpl& g = *impl(grid);
     const bs_solve_params& p = *params;
     hipStream_t s = (hipStream_t)stream;
-    char* base = (char*)ws;
     SolveWs w1;
-    const size_t full = layout_solve(g, C, 0, base, w1);
-    char* red = base + full;
-    const size_t redb = reduced_bytes(g, C);
-    double* part = (double*)(red + redb);
-    const int np = pair_count(C);
-    float* dmat = (float*)((char*)part + align_up((size_t)kGramBlocks * np * sizeof(double), 256));
+    const size_t full = layout_solve(g, C, 0, ws, w1);
     st = splat_setup(g, w1, conf, target, true, (double)p.lambda, s);
     if (st != BS_OK) return st;
-    BS_LAUNCH(s, K_SPLAT, "gram_partials", gram_partials, dim3(kGramBlocks), dim3(kBlock), 0, s,
-              w1.b, w1.Cp, C, g.counts, part);
-    std::vector<double> hp((size_t)kGramBlocks * np);
-    BS_TRY_HIP(hipMemcpyAsync(hp.data(), part, hp.size() * sizeof(double), hipMemcpyDeviceToHost,
-                              s));
-    BS_TRY_HIP(hipStreamSynchronize(s));
-    std::vector<double> G((size_t)C * C, 0.0);
-    for (int q = 0, i = 0, k = 0; q < np; ++q) {
-        double acc = 0.0;
-        for (int j = 0; j < kGramBlocks; ++j) acc += hp[(size_t)j * np + q];
-        G[(size_t)i * C + k] = G[(size_t)k * C + i] = acc;
-        if (++k == C) k = ++i;
-    }
-    const Reduction rd = reduce_gram(G, C, eps);
-    *rank = rd.t;
-    if (rd.t == 0) {
-        // B = 0: Y = 0 (the solve's b = 0 case)
-        BS_TRY_HIP(hipMemsetAsync(y, 0, (size_t)g.vcap * C * sizeof(float), s));
-        return BS_OK;
-    }
-    std::vector<float> mats(rd.M);
-    mats.insert(mats.end(), rd.Rt.begin(), rd.Rt.end());
-    BS_TRY_HIP(hipMemcpyAsync(dmat, mats.data(), mats.size() * sizeof(float),
-                              hipMemcpyHostToDevice, s));
-    const float* dM = dmat;
-    const float* dRt = dmat + (size_t)C * rd.t;
-    SolveWs w2;
-    layout_solve(g, rd.t, 0, red, w2);
-    // the reduced system shares A: S c, diag(A), M^-1 and {n, M^-1}
-    w2.sc = w1.sc;
-    w2.diag = w1.diag;
-    w2.minv = w1.minv;
-    w2.nfm = w1.nfm;
-    const int pblocks = grid_blocks(ceil_div(g.vcap * w2.Cp, kBlock));
-    BS_LAUNCH(s, K_SPLAT, "lowrank_project", lowrank_project, dim3(pblocks), dim3(kBlock), 0, s,
-              w1.b, w1.Cp, C, dM, rd.t, w2.b, w2.Cp, g.counts);
-    st = init_state(g, w2, p, w2.yi, s);
+    LowRankPlan lr;
+    st = lowrank_prepare(g, w1, (char*)ws + full, 0, eps, p, s, lr);
     if (st != BS_OK) return st;
-    const PcgImage I = make_image(g, w2, p.lambda, w2.yi, stats);
-    st = run_pcg(w2.K, &I, 1, nullptr, nullptr, w2.nb, w2.Cp, p, w2.act, s);
-    if (st != BS_OK) return st;
-    const int eblocks = grid_blocks(ceil_div(g.vcap * C, kBlock));
-    BS_LAUNCH(s, K_SLICE, "lowrank_expand", lowrank_expand, dim3(eblocks), dim3(kBlock), 0, s,
-              w2.yi, w2.Cp, rd.t, dRt, C, y, g.counts);
-    // the host copy of the factors must outlive its transfer
-    BS_TRY_HIP(hipStreamSynchronize(s));
-    return BS_OK;
+    *rank = lr.t;
+    if (lr.t > 0) {
+        const PcgImage I = make_image(g, lr.w, p.lambda, lr.w.yi, stats);
+        st = run_pcg(lr.w.K, &I, 1, nullptr, nullptr, lr.w.nb, lr.w.Cp, p, lr.w.act, s);
+        if (st != BS_OK) return st;
+    }
+    return lowrank_finish(g, lr, C, y, s);
 }

@@ -138,4 +138,22 @@ bs_status grad_scatter_launch(const GridImpl& g, const float* gb, int Cp, const 
                               const float* target, const float* conf, int C, float* grad_t,
                               float* grad_c, hipStream_t s);
 
+// Low-rank reduction of many right-hand sides (the part after the splat and
+// before the expansion).  The reduced system of t channels shares A's arrays
+// with w1 and keeps its own vectors in `extra` (lowrank_extra_bytes, laid
+// out for nb reducing blocks, 0: the single-image default).
+struct LowRankPlan {
+    SolveWs w;                 // the reduced system (t channels)
+    int t = 0;
+    const float* Rt = nullptr; // device [t][C]
+};
+size_t lowrank_extra_bytes(const GridImpl& g, int C, int nb);
+// Gram matrix, host factorisation (synchronises s), projection of w1.b onto
+// Q~ and the reduced system's initial state in out.w.yi.
+bs_status lowrank_prepare(const GridImpl& g, const SolveWs& w1, char* extra, int nb, double eps,
+                          const bs_solve_params& p, hipStream_t s, LowRankPlan& out);
+// y [Vcap][C] = Z R~ (0 when t = 0).
+bs_status lowrank_finish(const GridImpl& g, const LowRankPlan& lr, int C, float* y,
+                         hipStream_t s);
+
 }  // namespace bs

@@ -356,6 +356,33 @@ class BatchState:
             self.items[i].x = None
         return xs, st
 
+    def forward_lowrank(self, opts: SolveOptions, eps: float, bist_tol=1e-10,
+                        bist_max_iters=200, stats=False):
+        """Forward pass through the low-rank reduction of every image's
+        right-hand sides: outputs, stats (first rank entries) and ranks."""
+        nbytes = L.lib.bs_batch_lowrank_workspace_bytes(self.items, self.n, self.n_streams)
+        if nbytes == 0:
+            raise ValueError("invalid batch")
+        if getattr(self, "ws_lowrank", None) is None or self.ws_lowrank.numel() < nbytes:
+            self.ws_lowrank = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        xs = [torch.empty(s, dtype=torch.float32, device=self.device) for s in self.shapes]
+        st = [torch.zeros(s[0] * _STATS_DTYPE.itemsize, dtype=torch.uint8, device=self.device)
+              for s in self.shapes] if stats else None
+        for i, x in enumerate(xs):
+            self.items[i].x = x.data_ptr()
+            self.items[i].stats = st[i].data_ptr() if stats else None
+        ranks = (ct.c_int32 * self.n)()
+        p = opts.struct()
+        b = L.BistochParams(int(bist_max_iters), 8, float(bist_tol))
+        L.check(L.lib.bs_batch_forward_lowrank(self.items, self.n, ct.byref(p), ct.byref(b),
+                                               self.grids, self.n_streams, float(eps), ranks,
+                                               self.ws_lowrank.data_ptr(),
+                                               self.ws_lowrank.numel(), _stream()),
+                "bs_batch_forward_lowrank")
+        for i in range(self.n):
+            self.items[i].x = None
+        return xs, st, [int(r) for r in ranks]
+
     def backward(self, grad_xs, opts: SolveOptions, stats=False):
         gts = [torch.empty(s, dtype=torch.float32, device=self.device) for s in self.shapes]
         gcs = [torch.empty(s[1:], dtype=torch.float32, device=self.device) for s in self.shapes]

@@ -60,3 +60,58 @@ def test_lowrank_zero_target_and_invalid_eps():
     assert t == 0 and torch.count_nonzero(y) == 0
     with pytest.raises(ValueError):
         G.solve_lowrank(to_dev(p.target), to_dev(p.conf), p.lam, 1.0)
+
+
+@pytest.mark.slow
+def test_lowrank_full_size_in_bench_configuration():
+    """One image of segprob16x512x512 as bench.py runs it (eps = 0.01, PCG to
+    1e-6): the rank and the solution against the oracle."""
+    p = WL.segmentation_probs(seed=0)
+    say("lowrank full size segprob512x512")
+    prm = params(p)
+    G = gpu_grid(p)
+    y, st, t = G.solve_lowrank(to_dev(p.target), to_dev(p.conf), p.lam, 0.01,
+                               max_iters=prm.max_iters, rel_tol=prm.rel_tol)
+    x = G.slice(y, p.C)
+    torch.cuda.synchronize()
+    Y, xo, lr, _ = O.solve_lowrank(p.ref, p.target, p.conf, prm, 0.01)
+    say(f"  rank {t} (oracle {lr.rank})")
+    assert t == lr.rank
+    assert rel_l2(x.cpu().numpy(), xo) <= TOL_X
+
+
+def test_batch_lowrank_matches_single_image():
+    """The batched low-rank forward against the single-image one on a batch
+    of class-probability maps of different sizes, a full-rank five-channel
+    image and a zero target (rank 0)."""
+    from paper_1511_03296_amd import BatchState, SolveOptions
+    probs = [WL.segmentation_probs(seed=s, H=h, W=w, regions=20)
+             for s, (h, w) in enumerate([(120, 160), (192, 256), (300, 200)])]
+    five = WL.segmentation(H=96, W=128, regions=20, C=5, rel_tol=1e-6)
+    zero = WL.segmentation_probs(seed=9, H=64, W=80, regions=8)
+    zero.target = np.zeros_like(zero.target)
+    batch = probs + [five, zero]
+    say("batch lowrank: 5 images")
+    st = BatchState([to_dev(p.ref) for p in batch], [to_dev(p.target) for p in batch],
+                    [to_dev(p.conf) for p in batch],
+                    [(p.sigma_xy, p.sigma_l, p.sigma_uv) for p in batch], 3)
+    opts = SolveOptions(128.0, 20000, 1e-6)
+    xs, _, ranks = st.forward_lowrank(opts, 0.01)
+    torch.cuda.synchronize()
+    for i, p in enumerate(batch):
+        G = gpu_grid(p)
+        y, _, t = G.solve_lowrank(to_dev(p.target), to_dev(p.conf), 128.0, 0.01,
+                                  max_iters=20000, rel_tol=1e-6)
+        x = G.slice(y, p.C)
+        torch.cuda.synchronize()
+        say(f"  image {i}: rank {ranks[i]} (single image {t})")
+        assert ranks[i] == t
+        if t == 0:
+            assert torch.count_nonzero(xs[i]) == 0
+        else:
+            assert rel_l2(xs[i].cpu().numpy(), x.cpu().numpy()) <= TOL_X
+    assert ranks[-1] == 0 and ranks[3] == 5
+    p = probs[1]
+    prm = params(p, max_iters=20000, rel_tol=1e-6)
+    _, xo, lr, _ = O.solve_lowrank(p.ref, p.target, p.conf, prm, 0.01)
+    assert ranks[1] == lr.rank and rel_l2(xs[1].cpu().numpy(), xo) <= TOL_X

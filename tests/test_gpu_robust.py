@@ -75,3 +75,15 @@ def test_robust_rejects_invalid_arguments():
     for sigma, n in ((0.0, 4), (float("nan"), 4), (1.0, 0)):
         with pytest.raises(ValueError):
             G.robust_solve(t, c, p.lam, sigma, n)
+
+
+@pytest.mark.slow
+def test_robust_full_size_in_bench_configuration():
+    """robust_stereo1024x768 as bench.py runs it: 8 rounds of 25 iterations,
+    sigma_gm = 4, on the full stereo input with its outliers."""
+    p = WL.stereo_refine()
+    say("robust full size stereo1024x768 n=8")
+    G, y, x, st, o, prm = _both(p, p.target, p.conf, 4.0, 8)
+    err = rel_l2(x.cpu().numpy(), o.solution.x)
+    say(f"  rel-L2 vs oracle {err:.2e}")
+    assert err <= TOL_X
