@@ -279,6 +279,9 @@ def main() -> int:
                     help="library streams of the batch engine (batched workloads)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="batched workloads: keep the default tiles per block instead of "
+                         "tuning them on the batch first")
     ap.add_argument("--no-plain", action="store_true",
                     help="batched workloads: skip the single-image comparison (counter runs)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -318,6 +321,15 @@ def main() -> int:
         run_step(inputs, spec, True, keep, streams)
         torch.cuda.synchronize()
         print("bench: warmup step done", file=sys.stderr, flush=True)
+    tuned = None
+    if streams and not args.no_autotune:
+        from paper_1511_03296_amd import autotune
+        # lane widths of the systems the batched PCG runs: the reduced ranks
+        # of a low-rank workload, else the channel counts
+        channels = list(RANKS) if RANKS else [p.C for p in problems]
+        tuned = autotune.tune_batch(lambda: run_step(inputs, spec, True, streams=streams),
+                                    channels)
+        print(f"bench: autotuned tiles per block {tuned}", file=sys.stderr, flush=True)
     from paper_1511_03296_amd import read_stats
     V = [v for v, _, _ in keep]
     # PCG iterations per step (the robust solver's rounds each solve anew)
@@ -395,6 +407,8 @@ def main() -> int:
                    **({"lowrank": {"eps": spec["lowrank"], "ranks": _histogram(RANKS),
                                    "pass": "forward only"}}
                       if spec.get("lowrank") is not None else {}),
+                   **({"tiles_per_block": {str(K): v["tiles"] for K, v in tuned.items()}}
+                      if tuned else {}),
                    "parallelism": "single-gpu",
                    "engine": f"batch, {streams} streams" if streams else "single-image"},
         "fwd_mpix_s": round(pixels / sec_f / 1e6, 3),

@@ -346,6 +346,18 @@ bs_status bs_batch_backward(const bs_batch_item* items, int32_t n, const bs_grid
                             const bs_solve_params* params, int32_t n_streams, void* ws,
                             size_t ws_bytes, void* stream);
 
+/* Tuning of the batched PCG: vertex tiles per block for lanes of K channels
+ * (K in 1..4; a lane is K consecutive channels of one vertex, K =
+ * bs_lane_width(C)), 1..64, or 0 for the default (16 for K >= 3, 8
+ * otherwise).  Fewer tiles per block means more, shorter blocks.
+ * Process-wide; read by the next batch call; BS_EINVAL out of range.  For
+ * the autotuner, which times candidates on the caller's own batch. */
+bs_status bs_batch_set_tiles_per_block(int32_t K, int32_t tiles);
+/* The tiles per block in effect for lane width K (0 for K outside 1..4). */
+int32_t bs_batch_tiles_per_block(int32_t K);
+/* The lane width of C channels (host, pure; 0 outside 1..64). */
+int32_t bs_lane_width(int32_t C);
+
 /* Scratch bytes of bs_batch_forward_lowrank: every image's solve workspace
  * and reduced system, plus the batched PCG's tables (0 for an invalid
  * batch). */

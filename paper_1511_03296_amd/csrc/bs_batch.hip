@@ -27,9 +27,16 @@ namespace bs {
 namespace {
 
 constexpr int kMaxStreams = 16;
-// PCG tiles per block of a batched launch: fewer, longer-running blocks
-// measured faster (16 tiles for 3- and 4-channel lanes, 8 otherwise).
-inline int tiles_per_block(int K) { return K >= 3 ? 16 : 8; }
+constexpr int kMaxTilesPerBlock = 64;
+// PCG tiles per block of a batched launch, per lane width (index K; 0: the
+// default, where fewer, longer-running blocks measured faster: 16 tiles for
+// 3- and 4-channel lanes, 8 otherwise).  Set by bs_batch_set_tiles_per_block.
+std::atomic<int> g_tiles[5] = {{0}, {0}, {0}, {0}, {0}};
+inline int default_tiles_per_block(int K) { return K >= 3 ? 16 : 8; }
+inline int tiles_per_block(int K) {
+    const int t = g_tiles[K].load(std::memory_order_relaxed);
+    return t > 0 ? t : default_tiles_per_block(K);
+}
 
 struct StreamPool {
     std::mutex mu;
@@ -486,4 +493,20 @@ extern "C" bs_status bs_batch_forward_lowrank(const bs_batch_item* items, int32_
         }
     }
     return BS_OK;
+}
+
+extern "C" bs_status bs_batch_set_tiles_per_block(int32_t K, int32_t tiles) {
+    if (K < 1 || K > 4) return fail(BS_EINVAL, "lane width must be in 1..4");
+    if (tiles < 0 || tiles > kMaxTilesPerBlock)
+        return fail(BS_EINVAL, "tiles per block must be in 0..64");
+    g_tiles[K].store(tiles, std::memory_order_relaxed);
+    return BS_OK;
+}
+
+extern "C" int32_t bs_batch_tiles_per_block(int32_t K) {
+    return (K < 1 || K > 4) ? 0 : tiles_per_block(K);
+}
+
+extern "C" int32_t bs_lane_width(int32_t C) {
+    return (C < 1 || C > BS_MAX_CHANNELS) ? 0 : lane_width(C);
 }

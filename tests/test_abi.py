@@ -95,3 +95,17 @@ def test_python_errors_map_statuses():
         L.check(L.BS_EINVAL, "x")
     with pytest.raises(L.BsError):
         L.check(L.BS_EDEVICE, "x")
+
+
+def test_batch_tuning_setters():
+    from paper_1511_03296_amd import _lib as L
+    assert [L.lib.bs_lane_width(c) for c in (1, 2, 3, 4, 5, 6, 21, 64, 0, 65)] == \
+        [1, 2, 3, 4, 4, 3, 3, 4, 0, 0]
+    assert L.lib.bs_batch_tiles_per_block(3) == 16 and L.lib.bs_batch_tiles_per_block(1) == 8
+    assert L.lib.bs_batch_set_tiles_per_block(3, 4) == L.BS_OK
+    assert L.lib.bs_batch_tiles_per_block(3) == 4
+    assert L.lib.bs_batch_set_tiles_per_block(3, 0) == L.BS_OK
+    assert L.lib.bs_batch_tiles_per_block(3) == 16
+    assert L.lib.bs_batch_set_tiles_per_block(5, 4) == L.BS_EINVAL
+    assert L.lib.bs_batch_set_tiles_per_block(2, 65) == L.BS_EINVAL
+    assert L.lib.bs_batch_tiles_per_block(0) == 0

@@ -168,3 +168,32 @@ def test_batched_autograd_fd_crop_21_channels():
         an_c.append(gc[y, x])
     assert rel_l2(an_t, fd_t) <= TOL, (an_t, fd_t)
     assert rel_l2(an_c, fd_c) <= TOL, (an_c, fd_c)
+
+
+def test_autotuned_tiles_keep_the_results():
+    """Other tiles per block change only the reduction grid: the batch's
+    results agree with the default shape to the solver's tolerance, and the
+    autotuner leaves a valid choice in effect."""
+    from paper_1511_03296_amd import BatchState, SolveOptions, autotune
+    batch = [WL.segmentation(seed=s, H=96, W=128, regions=20, C=C, rel_tol=1e-6)
+             for s, C in enumerate((21, 2, 1))]
+    say("autotune: 3 images, C = 21, 2, 1")
+    st = BatchState([to_dev(p.ref) for p in batch], [to_dev(p.target) for p in batch],
+                    [to_dev(p.conf) for p in batch],
+                    [(p.sigma_xy, p.sigma_l, p.sigma_uv) for p in batch], 2)
+    opts = SolveOptions(128.0, 20000, 1e-6)
+    try:
+        autotune.reset()
+        base, _ = st.forward(opts)
+        for K in (1, 2, 3):
+            autotune.set_tiles(K, 4)
+        other, _ = st.forward(opts)
+        torch.cuda.synchronize()
+        for a, b in zip(base, other):
+            assert rel_l2(b.cpu().numpy(), a.cpu().numpy()) <= 1e-4
+        tuned = autotune.tune_batch(lambda: st.forward(opts), [p.C for p in batch],
+                                    candidates=(8, 16), repeats=1)
+        assert set(tuned) == {3, 2, 1}
+        assert all(autotune.current()[K] == v["tiles"] for K, v in tuned.items())
+    finally:
+        autotune.reset()
