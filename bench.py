@@ -66,13 +66,13 @@ WORKLOADS = {
 def matvec_bytes(C: int, iters: int) -> int:
     """Algorithmic bytes per vertex of `iters` pcg_matvec iterations.
 
-    The exact form reads the neighbour table (40 B), n, S c and M^-1 (4 B
-    each), r, the old d and y (4C B each) and writes y, d and q (4C B each):
-    52 + 24C.  The recurrence form (3 of every 4 iterations for C >= 3) reads
-    the table, n and M^-1, r, d, the old q and y and writes y, d and q:
-    48 + 28C.  (y += alpha d of the previous iteration is applied here.)  The
-    neighbours' gathered values are cache hits in the count."""
-    exact = iters if C <= 2 else iters // 4
+    The exact form (every 4th iteration) reads the neighbour table (40 B),
+    n, S c and M^-1 (4 B each), r, the old d and y (4C B each) and writes y,
+    d and q (4C B each): 52 + 24C.  The recurrence form (the other three)
+    reads the table, n and M^-1, r, d, the old q and y and writes y, d and
+    q: 48 + 28C.  (y += alpha d of the previous iteration is applied here.)
+    The neighbours' gathered values are cache hits in the count."""
+    exact = iters // 4
     return exact * (52 + 24 * C) + (iters - exact) * (48 + 28 * C)
 
 

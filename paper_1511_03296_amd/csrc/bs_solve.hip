@@ -16,8 +16,8 @@
 //   pcg_update:  y += alpha d,  r -= alpha q,  r^T r,  r^T M^-1 r.
 // The new d is not stored before the reduction that yields beta, so the
 // matvec either recomputes the neighbours' new d from their gathered r and
-// old d (two gathered vectors), or, for lanes of 3 or 4 channels on most
-// iterations, takes q = A z + beta q by linearity and gathers r alone.
+// old d (two gathered vectors), or, on 3 of every 4 iterations, takes
+// q = A z + beta q by linearity and gathers w = n o M^-1 r alone.
 // A z is evaluated in Laplacian form,
 //   (A z)_v = (S c)_v z_v + lam n_v sum_u n_u (z_v - z_u),
 // which equals diag(A) z - lam n o N(n o z) with diag(A) = lam n o N n + S c,
@@ -661,19 +661,21 @@ __global__ void __launch_bounds__(kBlock) hier_final(const float* __restrict__ b
     }
 }
 
-// Lanes of 3 or 4 channels take q by its recurrence and compute q = A d
-// directly every kExactEvery-th iteration (iterations it with
-// (it + 1) % kExactEvery == 0).  The recurrence accumulates the
-// rounding of every A z it adds, while A d shrinks as d grows smooth, so near
-// the float32 floor of an ill-conditioned system (sparse confidence) q drifts
-// from A d and the iteration diverges unless the drift is reset often enough
-// (every 8 iterations sufficed on the depth workload, every 16 did not).  With
-// one or two channels per lane the matvec is bound by its own bytes rather
-// than by the gathers, the recurrence gains nothing there, and q = A d is
-// computed directly every iteration.
+// Every lane width takes q by its recurrence and computes q = A d directly
+// every kExactEvery-th iteration (iterations it with
+// (it + 1) % kExactEvery == 0).  The recurrence accumulates the rounding of
+// every A z it adds, while A d shrinks as d grows smooth, so near the float32
+// floor of an ill-conditioned system (sparse confidence) q drifts from A d
+// and the iteration diverges unless the drift is reset often enough (on a
+// 2048x1536 depth super-resolution backward pass every 8 iterations sufficed
+// and every 16 did not; every 4 costs 765 iterations against 730 without the
+// recurrence).  The recurrence form gathers one vector per neighbour instead
+// of three, and its matvec is the faster for every lane width (a depth
+// launch averages 31.5 us with it against 35.4 without; with 3 channels per
+// lane a 16-image launch takes 384 us against 565 for the exact form).
 constexpr int kExactEvery = 4;
 template <int K>
-constexpr bool uses_recurrence() { return K >= 3; }
+constexpr bool uses_recurrence() { return K >= 1; }
 
 // Whether iteration `it` of a K-lane PCG computes q = A d directly.
 template <int K>
