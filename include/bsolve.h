@@ -9,16 +9,22 @@
  * by preconditioned conjugate gradients (supplement Algorithm 2) with the
  * Jacobi preconditioner and flat or hierarchical initialisation (Section 4,
  * supplement Section 2), slice y back to pixels (Eq. solution), and
- * back-propagate onto the target and confidence (Section 3).
+ * back-propagate onto the target and confidence (Section 3).  On top of the
+ * solve: batches of images of uneven size and channel count, the robust
+ * solver (supplement Algorithm RBS) and the low-rank reduction of many
+ * right-hand sides (supplement Section Multiple Output Channels).
  *
  * Conventions shared by every entry point:
  *  - Pointers named as device pointers must point to device memory of the
  *    GPU current on the calling thread; the caller allocates and owns all of
  *    it.  No entry point allocates device memory.  Buffers must be 4-byte
  *    aligned, workspaces 256-byte aligned.
- *  - `stream` is a hipStream_t (NULL = the default stream).  Every entry point
- *    except bs_grid_vertex_count and bs_read_counters only enqueues work on
- *    `stream` and returns; results are ready when the stream reaches them.
+ *  - `stream` is a hipStream_t (NULL = the default stream).  Entry points
+ *    enqueue work on `stream` and return; results are ready when the stream
+ *    reaches them.  The exceptions synchronise `stream` while they run and
+ *    say so: bs_grid_vertex_count and bs_read_counters, solves with
+ *    convergence polls (check_every > 0), the batch calls and the low-rank
+ *    solves.
  *  - Arguments are validated on the host before anything is enqueued.  On an
  *    error nothing is launched, outputs are untouched and bs_last_error()
  *    returns a description (thread-local).

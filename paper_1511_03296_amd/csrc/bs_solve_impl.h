@@ -49,7 +49,7 @@ struct PcgImage {
     float* r;
     float* d[2];             // search direction (two buffers for the exact matvec)
     float* q;
-    float* w;                // n o M^-1 r for the recurrence matvec (lanes of 3-4)
+    float* w;                // n o M^-1 r, gathered by the recurrence matvec
     const int32_t* counts;   // V = counts[CNT_V]
     ChanRec* cs[2];          // [nb][Cp] per-block channel state, ping-pong
     double* part[2];         // [3][Cp][nb] per-block partials: 0 start/update, 1 matvec
