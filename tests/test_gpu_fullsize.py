@@ -1,10 +1,10 @@
-"""Full-size parity of the default benchmark workload, in the launch
+"""Full-size parity of the batched benchmark workloads, in the launch
 configuration bench.py times: the 64-image mixed batch (43 Mpix, C in
-{1, 2, 21}) through the batch engine on 4 streams, forward and backward to a
-relative residual of 1e-5 with the bench's upstream gradients.  Every image's
-channels must stop on the tolerance; the smallest image of each channel
-count is compared with the oracle (forward and backward), which is too slow
-for the whole batch."""
+{1, 2, 21}) and the 16-image 21-channel segmentation batch, through the
+batch engine on 4 streams, forward and backward with the bench's tolerances
+and upstream gradients.  Every image's channels must stop on the tolerance;
+images the oracle can solve in seconds (the smallest of each channel count,
+or the first) are compared with it, forward and backward."""
 import numpy as np
 import pytest
 import torch
@@ -62,3 +62,42 @@ def test_mixed64_batch_in_bench_configuration():
                     for ch in range(p.C))
         err = np.linalg.norm(gcs[i].cpu().numpy().reshape(-1) - og.grad_c.reshape(-1))
         assert err <= TOL * np.linalg.norm(terms), (i, err / np.linalg.norm(terms))
+
+
+def test_seg16_batch_in_bench_configuration():
+    """The 16-image 21-channel segmentation batch (512x512 each) as bench.py
+    runs it: batch engine on 4 streams, forward and adjoint PCG to 1e-6,
+    upstream gradient 2 (x - onehot label).  Every channel must stop on the
+    tolerance; image 0 is compared with the oracle, forward and backward."""
+    from paper_1511_03296_amd import BatchState, SolveOptions, read_stats
+    spec = bench.WORKLOADS["seg16x512x512"]
+    probs = bench.make_problems("seg16x512x512")
+    say(f"full size seg16x512x512: {len(probs)} images")
+    inputs = bench.gpu_inputs(probs, spec, torch.device("cuda:0"))
+    (fi, ft), (bi, bt) = spec["fwd"], spec["bwd"]
+    lam = probs[0].lam
+    state = BatchState([d["ref"] for d in inputs], [d["t"] for d in inputs],
+                       [d["c"] for d in inputs],
+                       [(p.sigma_xy, p.sigma_l, p.sigma_uv) for p in probs], 4)
+    xs, fst = state.forward(SolveOptions(lam, fi, ft, check_every=8), stats=True)
+    gts, gcs, bst = state.backward([d["gx"] for d in inputs],
+                                   SolveOptions(lam, bi, bt, check_every=8), stats=True)
+    torch.cuda.synchronize()
+    for i in range(len(probs)):
+        f, b = read_stats(fst[i]), read_stats(bst[i])
+        assert np.all(f["reason"] == 1) and np.all(f["rel_residual"] <= ft), i
+        assert np.all(b["reason"] == 1) and np.all(b["rel_residual"] <= bt), i
+    p = probs[0]
+    say("  oracle check image 0 (21 channels, forward and backward)")
+    prm = O.Params(p.sigma_xy, p.sigma_l, p.sigma_uv, lam, max_iters=fi, rel_tol=ft)
+    sol = O.solve(p.ref, p.target, p.conf, prm)
+    gx = inputs[0]["gx"].cpu().numpy()
+    prmb = O.Params(p.sigma_xy, p.sigma_l, p.sigma_uv, lam, max_iters=bi, rel_tol=bt)
+    og = O.solve_backward(sol, p.target, p.conf, gx, prmb)
+    assert rel_l2(xs[0].cpu().numpy(), sol.x) <= TOL
+    assert rel_l2(gts[0].cpu().numpy(), og.grad_t) <= TOL
+    idx = sol.grid.idx
+    terms = sum(np.abs(og.gb[idx, ch]) * (np.abs(p.target[ch].reshape(-1)) +
+                                          np.abs(sol.y[idx, ch])) for ch in range(p.C))
+    err = np.linalg.norm(gcs[0].cpu().numpy().reshape(-1) - og.grad_c.reshape(-1))
+    assert err <= TOL * np.linalg.norm(terms), err / np.linalg.norm(terms)
