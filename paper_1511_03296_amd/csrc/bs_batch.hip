@@ -145,7 +145,15 @@ bs_status for_each_item(const bs_batch_item* items, int n, int n_streams, hipStr
     bs_status first_err = BS_OK;
     std::string first_msg;
     auto worker = [&](int s) {
-        hipSetDevice(device);
+        if (hipSetDevice(device) != hipSuccess) {
+            std::lock_guard<std::mutex> g(err_mu);
+            if (first_err == BS_OK) {
+                first_err = BS_EDEVICE;
+                first_msg = "hipSetDevice failed on a worker thread";
+            }
+            failed.store(1);
+            return;
+        }
         for (;;) {
             if (failed.load()) return;
             const int k = next.fetch_add(1);
@@ -277,7 +285,11 @@ bs_status batched_pcg(const bs_batch_item* items, int n, const bs_grid* grids,
     std::vector<bs_status> res(ng, BS_OK);
     std::vector<std::string> msg(ng);
     auto work = [&](int g) {
-        hipSetDevice(device);
+        if (hipSetDevice(device) != hipSuccess) {
+            res[g] = BS_EDEVICE;
+            msg[g] = "hipSetDevice failed on a group thread";
+            return;
+        }
         const Group& gr = groups[g];
         res[g] = run_pcg(gr.K, imgs.data() + gr.first, gr.count, d_imgs + gr.first,
                          d_blk + gr.blk_first, gr.G, gr.max_cp, p, d_act + gr.first,
