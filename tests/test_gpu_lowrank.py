@@ -115,3 +115,33 @@ def test_batch_lowrank_matches_single_image():
     prm = params(p, max_iters=20000, rel_tol=1e-6)
     _, xo, lr, _ = O.solve_lowrank(p.ref, p.target, p.conf, prm, 0.01)
     assert ranks[1] == lr.rank and rel_l2(xs[1].cpu().numpy(), xo) <= TOL_X
+
+
+@pytest.mark.parametrize("case", ["C1", "C64", "rank2of8"])
+def test_lowrank_edge_channel_counts(case):
+    """One channel (t = 1), the largest channel count (64, lanes of 4) and
+    an exactly rank-2 B of 8 channels: rank and solution against the
+    oracle."""
+    if case == "C1":
+        p = WL.tiny_ramp(seed=21, H=60, W=80, regions=8)
+    elif case == "C64":
+        p = WL.segmentation(seed=22, H=48, W=64, regions=8, C=64, rel_tol=1e-6)
+    else:
+        p = WL.segmentation(seed=23, H=60, W=80, regions=8, C=2, rel_tol=1e-6)
+        mix = np.random.default_rng(5).normal(size=(8, 2))
+        p.target = np.einsum("kc,chw->khw", mix, p.target).astype(np.float32)
+    say(f"lowrank edge {case}: C={p.C}")
+    prm = params(p, max_iters=5000, rel_tol=1e-6)
+    G = gpu_grid(p)
+    y, st, t = G.solve_lowrank(to_dev(p.target), to_dev(p.conf), p.lam, 0.01,
+                               max_iters=prm.max_iters, rel_tol=prm.rel_tol)
+    x = G.slice(y, p.C)
+    torch.cuda.synchronize()
+    Y, xo, lr, _ = O.solve_lowrank(p.ref, p.target, p.conf, prm, 0.01)
+    say(f"  rank {t} (oracle {lr.rank})")
+    assert t == lr.rank
+    if case == "C1":
+        assert t == 1
+    if case == "rank2of8":
+        assert t == 2
+    assert rel_l2(x.cpu().numpy(), xo) <= TOL_X
