@@ -53,9 +53,24 @@ def build(verbose: bool = False) -> str:
     if res.returncode != 0:
         raise RuntimeError(f"link failed:\n{res.stdout}\n{res.stderr}")
     os.replace(tmp, LIB)
+    _build_example()
     if verbose:
         print("built", LIB)
     return LIB
+
+
+EXAMPLE = os.path.join(PKG, "examples", "solve_c")
+
+
+def _build_example() -> None:
+    """The C-ABI example program, linked against the library next to it."""
+    src = EXAMPLE + ".cpp"
+    cmd = [HIPCC, "-O2", "-std=c++17", "-I" + INCLUDE, src, "-L" + PKG, "-lbsolve",
+           "-Wl,-rpath,$ORIGIN/..", "-o", EXAMPLE + ".tmp"]
+    res = subprocess.run(cmd, capture_output=True, text=True)
+    if res.returncode != 0:
+        raise RuntimeError(f"example build failed:\n{res.stdout}\n{res.stderr}")
+    os.replace(EXAMPLE + ".tmp", EXAMPLE)
 
 
 if __name__ == "__main__":
