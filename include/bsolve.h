@@ -117,7 +117,8 @@ typedef struct bs_grid {
 /* Device pointers to a built grid's arrays, for inspection and tests.
  * counts (int32, device): [0] V, [1] K, [2] bistochastization updates,
  * [3] bistochastization done flag, [4] ping-pong buffer of the final n,
- * [8 + k] V_k for k < levels (0 for levels above K). */
+ * [5] 1 when some neighbour lies more than 32767 ids from its vertex (never
+ * on grids with nb_packed), [8 + k] V_k for k < levels (0 for levels above K). */
 typedef struct bs_grid_view {
     int32_t H, W, P, levels;           /* levels = capacity of the pyramid (K <= levels - 1) */
     int32_t ncells_x, ncells_y;        /* spatial cells of level 0                          */
@@ -138,6 +139,13 @@ typedef struct bs_grid_view {
     const uint64_t* level_key[BS_MAX_LEVELS];   /* [k >= 1] keys of level k                  */
     const int32_t* parent[BS_MAX_LEVELS];       /* [k < levels-1] level-k vertex -> level k+1 */
     const int32_t* ones[BS_MAX_LEVELS];         /* [k >= 1] level-0 vertices under each vertex (P(1)) */
+    const uint32_t* nb16;              /* [5][vcap] nbr packed: word i holds slots 2i (low half)
+                                          and 2i+1 (high half) as signed 16-bit u - v, 0 for -1;
+                                          exact where counts[5] == 0                          */
+    int32_t nb_packed;                 /* 1: every offset fits by construction (at most one row
+                                          of cells plus one cell apart; checked on the host from
+                                          the image width and the scales), and the stencil
+                                          passes read nb16; 0: they read nbr                  */
 } bs_grid_view;
 
 /* ---------------------------------------------------------------------- */

@@ -58,6 +58,7 @@ class GridView(ct.Structure):
         ("level_key", ct.c_void_p * BS_MAX_LEVELS),
         ("parent", ct.c_void_p * BS_MAX_LEVELS),
         ("ones", ct.c_void_p * BS_MAX_LEVELS),
+        ("nb16", ct.c_void_p), ("nb_packed", ct.c_int32),
     ]
 
 

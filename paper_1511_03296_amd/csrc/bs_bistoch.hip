@@ -61,13 +61,14 @@ __device__ inline bool bist_stop(double R, int s, int max_iters, double tol) {
 }
 
 __global__ void __launch_bounds__(kRedBlock) bist_step(const int32_t* __restrict__ nbr,
+                                                        const uint32_t* __restrict__ nb16,
                                                         const int32_t* __restrict__ m,
                                                         const double* __restrict__ src,
                                                         double* __restrict__ dst, int64_t vcap,
                                                         int32_t* __restrict__ counts,
                                                         double* __restrict__ part,
                                                         double* __restrict__ res_out, int step,
-                                                        int max_iters, double tol) {
+                                                        int max_iters, double tol, int packed) {
 #pragma clang fp contract(off)
     const int G = gridDim.x;
     if (counts[CNT_BIST_DONE]) return;
@@ -84,15 +85,13 @@ __global__ void __launch_bounds__(kRedBlock) bist_step(const int32_t* __restrict
     int v = (int)(tl.first * kRedBlock) + threadIdx.x;
     bool have = tl.first < tl.end && v < V;
     double n = 0.0, nbv[10];
-    int mv = 1;
+    int mv = 1, nbi[10];
     if (have) {
         n = src[v];
         mv = m[v];
+        load_neighbours(nbi, v, vcap, packed, nbr, nb16);
 #pragma unroll
-        for (int j = 0; j < 10; ++j) {
-            const int u = nbr[j * vcap + v];
-            nbv[j] = (u >= 0) ? src[u] : 0.0;
-        }
+        for (int j = 0; j < 10; ++j) nbv[j] = (nbi[j] >= 0) ? src[nbi[j]] : 0.0;
     }
     if (step >= 1) {
         const double R = block_max<kRedBlock>(prevmax);
@@ -114,11 +113,9 @@ __global__ void __launch_bounds__(kRedBlock) bist_step(const int32_t* __restrict
             if (have) {
                 n = src[v];
                 mv = m[v];
+                load_neighbours(nbi, v, vcap, packed, nbr, nb16);
 #pragma unroll
-                for (int j = 0; j < 10; ++j) {
-                    const int u = nbr[j * vcap + v];
-                    nbv[j] = (u >= 0) ? src[u] : 0.0;
-                }
+                for (int j = 0; j < 10; ++j) nbv[j] = (nbi[j] >= 0) ? src[nbi[j]] : 0.0;
             }
         }
         if (!have) continue;
@@ -159,12 +156,14 @@ __global__ void __launch_bounds__(kRedBlock) bist_decide(int32_t* __restrict__ c
 // Copies the final n, its float rounding and n o (N n) (the smoothness
 // diagonal divided by lambda at the fixed point) into the grid.
 __global__ void __launch_bounds__(kBlock) bist_finalize(const int32_t* __restrict__ nbr,
+                                                         const uint32_t* __restrict__ nb16,
                                                          const double* __restrict__ b0,
                                                          const double* __restrict__ b1,
                                                          int64_t vcap, double* __restrict__ n64,
                                                          float* __restrict__ nf,
                                                          double* __restrict__ nn,
-                                                         const int32_t* __restrict__ counts) {
+                                                         const int32_t* __restrict__ counts,
+                                                         int packed) {
 #pragma clang fp contract(off)
     const int V = counts[CNT_V];
     const double* src = counts[CNT_BIST_SRC] ? b1 : b0;
@@ -173,12 +172,11 @@ __global__ void __launch_bounds__(kBlock) bist_finalize(const int32_t* __restric
         const int v = (int)(tile * kBlock) + threadIdx.x;
         if (v >= V) continue;
         const double n = src[v];
+        int nbi[10];
+        load_neighbours(nbi, v, vcap, packed, nbr, nb16);
         double ns = 0.0;
 #pragma unroll
-        for (int j = 0; j < 10; ++j) {
-            const int u = nbr[j * vcap + v];
-            ns += (u >= 0) ? src[u] : 0.0;
-        }
+        for (int j = 0; j < 10; ++j) ns += (nbi[j] >= 0) ? src[nbi[j]] : 0.0;
         n64[v] = n;
         nf[v] = (float)n;
         nn[v] = n * ns;
@@ -221,8 +219,9 @@ extern "C" bs_status bs_bistochastize(bs_grid* grid, const bs_bistoch_params* pa
     int last = 0;
     for (int step = 0; step <= p.max_iters; ++step) {
         BS_LAUNCH(s, K_BIST_STEP, "bist_step", bist_step, dim3(G), dim3(kRedBlock), 0, s,
-                  g.nbr, g.lv[0].mult, g.nbuf[step & 1], g.nbuf[(step + 1) & 1], g.vcap,
-                  g.counts, g.bist_part, g.bist_res, step, p.max_iters, p.tol);
+                  g.nbr, g.nb16, g.lv[0].mult, g.nbuf[step & 1], g.nbuf[(step + 1) & 1], g.vcap,
+                  g.counts, g.bist_part, g.bist_res, step, p.max_iters, p.tol,
+                  g.nb_packed);
         last = step;
         if (p.check_every > 0 && (step + 1) % p.check_every == 0 && step < p.max_iters) {
             int32_t done = 0;
@@ -235,7 +234,8 @@ extern "C" bs_status bs_bistochastize(bs_grid* grid, const bs_bistoch_params* pa
     BS_LAUNCH(s, K_BIST_OTHER, "bist_decide", bist_decide, dim3(1), dim3(kRedBlock), 0, s,
               g.counts, g.bist_part, g.bist_res, last, G);
     BS_LAUNCH(s, K_BIST_OTHER, "bist_finalize", bist_finalize, dim3(blocks), dim3(kBlock), 0, s,
-              g.nbr, g.nbuf[0], g.nbuf[1], g.vcap, g.n64, g.nf, g.nn, g.counts);
+              g.nbr, g.nb16, g.nbuf[0], g.nbuf[1], g.vcap, g.n64, g.nf, g.nn, g.counts,
+              g.nb_packed);
     if (join) {
         BS_TRY_HIP(hipStreamWaitEvent(s, join, 0));
         BS_TRY_HIP(hipEventDestroy(fork));

@@ -76,6 +76,11 @@ size_t layout_grid(GridImpl& g, int H, int W, const bs_grid_params& sp, void* ba
     }
     g.vcap = g.lv[0].cap;
     g.max_cells = max_cells;
+    {
+        const int64_t colours = (int64_t)(cl + 1) * (cu + 1) * (cu + 1);
+        const int64_t cell_max = std::min<int64_t>((int64_t)sp.sigma_xy * sp.sigma_xy, colours);
+        g.nb_packed = packed_table_fits(ncx0, cell_max) ? 1 : 0;
+    }
 
     Carver c(base);
     g.counts = c.take<int32_t>(CNT_SIZE);
@@ -97,6 +102,7 @@ size_t layout_grid(GridImpl& g, int H, int W, const bs_grid_params& sp, void* ba
         L.item_parent = c.take<int32_t>(L.item_cap);
     }
     g.nbr = c.take<int32_t>(10 * g.vcap);
+    g.nb16 = c.take<uint32_t>(5 * g.vcap);
     g.nbuf[0] = c.take<double>(g.vcap);
     g.nbuf[1] = c.take<double>(g.vcap);
     g.n64 = c.take<double>(g.vcap);
@@ -530,12 +536,16 @@ __device__ inline int find_key(const uint64_t* __restrict__ key, int s, int e, u
 // Neighbour table of level 0: for each vertex and unit step along each of
 // (y, x, l, u, v), the neighbour's id or -1.  Colour neighbours share the
 // vertex's spatial cell; spatial neighbours lie in the adjacent cell; both are
-// looked up in that cell's key range.
+// looked up in that cell's key range.  The table is written twice: as 32-bit
+// ids, and packed as 16-bit offsets from the vertex (half the bytes for the
+// stencil passes of grids whose offsets provably fit); a vertex whose offset
+// does not fit sets CNT_NB_WIDE.
 __global__ void __launch_bounds__(kBlock) neighbour_table(const uint64_t* __restrict__ key,
                                                            const int32_t* __restrict__ vbase,
-                                                           const int32_t* __restrict__ counts,
+                                                           int32_t* __restrict__ counts,
                                                            int ncx, int ncy, int64_t vcap,
-                                                           int32_t* __restrict__ nbr) {
+                                                           int32_t* __restrict__ nbr,
+                                                           uint32_t* __restrict__ nb16) {
     const int V = counts[CNT_V];
     const XcdTiles tl((V + kBlock - 1) / kBlock);
     for (int64_t tile = tl.first; tile < tl.end; tile += tl.step) {
@@ -545,38 +555,38 @@ __global__ void __launch_bounds__(kBlock) neighbour_table(const uint64_t* __rest
         const int cy = (int)(k >> 40), cx = (int)((k >> 24) & 0xffff);
         const int cell = cy * ncx + cx;
         const int s = vbase[cell], e = vbase[cell + 1];
+        int rr[10];
         // y
-        int r = -1;
+        rr[0] = rr[1] = -1;
         if (cy > 0) {
             const int cc = cell - ncx;
-            r = find_key(key, vbase[cc], vbase[cc + 1], k - (1ull << 40));
+            rr[0] = find_key(key, vbase[cc], vbase[cc + 1], k - (1ull << 40));
         }
-        nbr[0 * vcap + v] = r;
-        r = -1;
         if (cy + 1 < ncy) {
             const int cc = cell + ncx;
-            r = find_key(key, vbase[cc], vbase[cc + 1], k + (1ull << 40));
+            rr[1] = find_key(key, vbase[cc], vbase[cc + 1], k + (1ull << 40));
         }
-        nbr[1 * vcap + v] = r;
         // x
-        r = -1;
-        if (cx > 0) r = find_key(key, vbase[cell - 1], vbase[cell], k - (1ull << 24));
-        nbr[2 * vcap + v] = r;
-        r = -1;
-        if (cx + 1 < ncx) r = find_key(key, vbase[cell + 1], vbase[cell + 2], k + (1ull << 24));
-        nbr[3 * vcap + v] = r;
+        rr[2] = rr[3] = -1;
+        if (cx > 0) rr[2] = find_key(key, vbase[cell - 1], vbase[cell], k - (1ull << 24));
+        if (cx + 1 < ncx) rr[3] = find_key(key, vbase[cell + 1], vbase[cell + 2], k + (1ull << 24));
         // l, u, v within the cell
 #pragma unroll
         for (int d = 0; d < 3; ++d) {
             const int sh = 16 - 8 * d;
             const int f = (int)((k >> sh) & 0xff);
-            r = -1;
-            if (f > 0) r = find_key(key, s, e, k - (1ull << sh));
-            nbr[(4 + 2 * d) * vcap + v] = r;
-            r = -1;
-            if (f < 255) r = find_key(key, s, e, k + (1ull << sh));
-            nbr[(5 + 2 * d) * vcap + v] = r;
+            rr[4 + 2 * d] = f > 0 ? find_key(key, s, e, k - (1ull << sh)) : -1;
+            rr[5 + 2 * d] = f < 255 ? find_key(key, s, e, k + (1ull << sh)) : -1;
         }
+        bool fits = true;
+#pragma unroll
+        for (int j = 0; j < 10; ++j) {
+            nbr[j * vcap + v] = rr[j];
+            if (rr[j] >= 0) fits = fits && rr[j] - v >= -kNbOffsetMax && rr[j] - v <= kNbOffsetMax;
+        }
+#pragma unroll
+        for (int i = 0; i < 5; ++i) nb16[i * vcap + v] = pack_offsets(v, rr[2 * i], rr[2 * i + 1]);
+        if (!fits) counts[CNT_NB_WIDE] = 1;
     }
 }
 
@@ -664,7 +674,7 @@ extern "C" bs_status bs_build_grid(const float* ref, int32_t H, int32_t W,
 
     const int blocks = grid_blocks(ceil_div(g.vcap, kBlock));
     BS_LAUNCH(s, K_NEIGHBOURS, "neighbour_table", neighbour_table, dim3(blocks), dim3(kBlock), 0, s, g.lv[0].key,
-                       g.lv[0].cell_vbase, g.counts, g.lv[0].ncx, g.lv[0].ncy, g.vcap, g.nbr);
+                       g.lv[0].cell_vbase, g.counts, g.lv[0].ncx, g.lv[0].ncy, g.vcap, g.nbr, g.nb16);
     std::memcpy(out->opaque, &g, sizeof(g));
     return BS_OK;
 }
@@ -709,6 +719,8 @@ extern "C" bs_status bs_grid_get_view(const bs_grid* grid, bs_grid_view* v) {
     v->idx = g.lv[0].item_parent;
     v->m = g.lv[0].mult;
     v->nbr = g.nbr;
+    v->nb16 = g.nb16;
+    v->nb_packed = g.nb_packed;
     v->pix_ptr = g.lv[0].ptr;
     v->pix_list = g.lv[0].list;
     v->n = g.n64;

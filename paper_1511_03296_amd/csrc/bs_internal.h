@@ -89,6 +89,8 @@ enum Counter : int {
     CNT_BIST_ITERS = 2,   // bistochastization updates applied
     CNT_BIST_DONE = 3,    // 1 once bistochastization has stopped
     CNT_BIST_SRC = 4,     // ping-pong buffer holding the final n
+    CNT_NB_WIDE = 5,      // 1 when some neighbour lies more than 32767 ids away
+                          // (a diagnostic: nb_packed grids never set it)
     CNT_LEVEL0 = 8,       // V_k at CNT_LEVEL0 + k
     CNT_SIZE = 64
 };
@@ -164,6 +166,10 @@ struct GridImpl {
     int32_t max_cells;
     Level lv[BS_MAX_LEVELS];
     int32_t* nbr;            // [10][vcap]
+    uint32_t* nb16;          // [5][vcap] the same table as signed 16-bit offsets u - v
+                             // (0: no neighbour), slots 2i and 2i+1 in word i
+    int32_t nb_packed;       // 1 when every offset provably fits 16 bits (the stencil
+                             // passes read nb16), else they read nbr
     double* nbuf[2];         // bistochastization ping-pong
     double* n64;             // [vcap] final n
     float* nf;               // [vcap]
@@ -261,6 +267,48 @@ __device__ inline double block_max(double v) {
 #pragma unroll
     for (int w = 1; w < B / 64; ++w) s = fmax(s, red[w]);
     return s;
+}
+
+// Packed neighbour table: signed 16-bit offsets u - v, 0 for a missing
+// neighbour (a vertex is never its own neighbour), slots 2i and 2i+1 in word
+// i.  Vertices are ordered by (cell row, cell column, colour), so a neighbour
+// is at most one row of cells plus one cell away: |u - v| < (ncx + 1) * the
+// most vertices a cell can hold.  Grids where that bound exceeds 32767 keep
+// the 32-bit table for the stencil passes.
+constexpr int kNbOffsetMax = 32767;
+
+inline bool packed_table_fits(int64_t ncx, int64_t cell_max) {
+    return (ncx + 1) * cell_max <= (int64_t)kNbOffsetMax + 1;
+}
+
+__host__ __device__ inline uint32_t pack_offsets(int v, int lo, int hi) {
+    const uint32_t a = lo < 0 ? 0u : (uint32_t)(lo - v) & 0xffffu;
+    const uint32_t b = hi < 0 ? 0u : (uint32_t)(hi - v) & 0xffffu;
+    return a | (b << 16);
+}
+
+__device__ inline int unpack_offset(int v, uint32_t half) {
+    const int o = (int)(int16_t)(uint16_t)half;
+    return o != 0 ? v + o : -1;
+}
+
+// The ten neighbour ids of vertex v (slot 2d: -1 step, 2d+1: +1 step along
+// dim d of (y, x, l, u, v); -1 if absent): five packed words, or ten 32-bit
+// ids.  `packed` is uniform over the launch.
+template <class P32, class P16>
+__device__ inline void load_neighbours(int (&nb)[10], int v, int64_t vcap, bool packed, P32 nbr,
+                                       P16 nb16) {
+    if (packed) {
+#pragma unroll
+        for (int i = 0; i < 5; ++i) {
+            const uint32_t p = nb16[i * vcap + v];
+            nb[2 * i] = unpack_offset(v, p & 0xffffu);
+            nb[2 * i + 1] = unpack_offset(v, p >> 16);
+        }
+    } else {
+#pragma unroll
+        for (int j = 0; j < 10; ++j) nb[j] = nbr[j * vcap + v];
+    }
 }
 
 }  // namespace bs

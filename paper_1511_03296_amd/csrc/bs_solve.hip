@@ -32,6 +32,7 @@
 // on one image (a per-block image table), each image with its own channel
 // state, partials and stopping rule.
 #include "bs_solve_impl.h"
+#include <type_traits>
 
 namespace bs {
 
@@ -705,6 +706,7 @@ __device__ inline const PcgImage& block_image(const PcgArgs& a, int& jb) {
 // private memory), with every pointer typed global.
 struct ImgView {
     gp<const int32_t> nbr;
+    gp<const uint32_t> nb16;
     gp<const float2> nfm;
     gp<const float> sc;
     gp<const float> b;
@@ -733,6 +735,7 @@ struct ImgView {
 __device__ inline ImgView view_of(const PcgImage& s) {
     ImgView I;
     I.nbr = (gp<const int32_t>)s.nbr;
+    I.nb16 = (gp<const uint32_t>)s.nb16;
     I.nfm = (gp<const float2>)s.nfm;
     I.sc = (gp<const float>)s.sc;
     I.b = (gp<const float>)s.b;
@@ -761,6 +764,13 @@ __device__ inline ImgView view_of(const PcgImage& s) {
     return I;
 }
 
+// Neighbour indices of vertex v (phase 1 of a tile's loads): five packed
+// words when every image of the launch has a packed table, else ten ids.
+template <bool PACKED>
+__device__ inline void load_nbr(int (&nb)[10], int v, const ImgView& I) {
+    load_neighbours(nb, v, I.vcap, PACKED, I.nbr, I.nb16);
+}
+
 // Clears the channel state; the image is active until its first stop test.
 template <bool MULTI>
 __global__ void __launch_bounds__(kRedBlock) pcg_prologue(PcgArgs a) {
@@ -786,7 +796,7 @@ __device__ inline Vec<K> scaled_residual(const Vec<K>& r, float2 nm) {
 
 // r = b - A y0 (and w for the recurrence matvec); partials r^T r, b^T b,
 // r^T M^-1 r.
-template <int K, bool MULTI>
+template <int K, bool MULTI, bool PACKED>
 __global__ void __launch_bounds__(kRedBlock) pcg_start(PcgArgs a) {
     int jb;
     const ImgView I = view_of(block_image<MULTI>(a, jb));
@@ -806,9 +816,11 @@ __global__ void __launch_bounds__(kRedBlock) pcg_start(PcgArgs a) {
         float ns[K];
 #pragma unroll
         for (int k = 0; k < K; ++k) ns[k] = 0.0f;
+        int nbv[10];
+        load_nbr<PACKED>(nbv, v, I);
 #pragma unroll
         for (int j = 0; j < 10; ++j) {
-            const int u = I.nbr[j * I.vcap + v];
+            const int u = nbv[j];
             if (u >= 0) {
                 const float nu = I.nfm[u].x;
                 const Vec<K> yu = ldv<K>(I.y + (int64_t)u * Cp + ln.g * K);
@@ -849,12 +861,6 @@ struct MatOps {
     float2 nmv;
     float scv;
 };
-
-// Neighbour indices of vertex v (phase 1 of a tile's loads).
-__device__ inline void load_nbr(int (&nb)[10], int v, const ImgView& I) {
-#pragma unroll
-    for (int j = 0; j < 10; ++j) nb[j] = I.nbr[j * I.vcap + v];
-}
 
 // The gathers and per-vertex operands of vertex v (phase 2).
 template <int K, bool EXACT>
@@ -908,7 +914,7 @@ __device__ inline float pcg_dir(float z, float d_old, float beta, bool first) {
 //                 d[src], written to d[src ^ 1]).  It resets the rounding
 //                 that the recurrence accumulates.
 // On a channel's first iteration d = z and q = A z.
-template <int K, bool MULTI, bool EXACT>
+template <int K, bool MULTI, bool EXACT, bool PACKED>
 __global__ void __launch_bounds__(kRedBlock) pcg_matvec(PcgArgs a, int src) {
     __shared__ ChanState S[BS_MAX_CHANNELS];
     __shared__ double fin[3 * BS_MAX_CHANNELS];
@@ -939,7 +945,7 @@ __global__ void __launch_bounds__(kRedBlock) pcg_matvec(PcgArgs a, int src) {
     int v = (int)(tl.first * ln.vpb) + ln.vl;
     bool have = ln.ok && tl.first < tl.end && v < V;
     if (have) {
-        load_nbr(nbn, v, I);
+        load_nbr<PACKED>(nbn, v, I);
         load_ops<K, EXACT>(o, v, nbn, ln, I, din);
     }
     ps.sum(I.part0, fin);
@@ -988,7 +994,7 @@ __global__ void __launch_bounds__(kRedBlock) pcg_matvec(PcgArgs a, int src) {
         const int64_t nt = tile + tl.step;
         const int vn = (int)(nt * ln.vpb) + ln.vl;
         const bool hn = any && ln.ok && nt < tl.end && vn < V;
-        if (hn) load_nbr(nbn, vn, I);
+        if (hn) load_nbr<PACKED>(nbn, vn, I);
         if (any && have) {
             float zv[K], ns[K];
             Vec<K> dv, qv;
@@ -1386,6 +1392,7 @@ PcgImage make_image(const GridImpl& g, const SolveWs& w, float lam, float* yw,
     PcgImage I;
     std::memset(&I, 0, sizeof(I));
     I.nbr = g.nbr;
+    I.nb16 = g.nb_packed ? g.nb16 : nullptr;
     I.nfm = w.nfm;
     I.sc = w.sc;
     I.b = w.b;
@@ -1417,12 +1424,12 @@ PcgImage make_image(const GridImpl& g, const SolveWs& w, float lam, float* yw,
 }
 
 
-template <int K, bool MULTI>
+template <int K, bool MULTI, bool PACKED>
 static bs_status run_pcg_k(const PcgArgs& a, int n, int G, int max_cp, bool sep,
                            const bs_solve_params& p, const int32_t* act, hipStream_t s) {
     const dim3 grid(G), block(kRedBlock);
     BS_LAUNCH(s, K_INIT, "pcg_prologue", pcg_prologue<MULTI>, grid, block, 0, s, a);
-    BS_LAUNCH(s, K_PCG_START, "pcg_start", (pcg_start<K, MULTI>), grid, block, 0, s, a);
+    BS_LAUNCH(s, K_PCG_START, "pcg_start", (pcg_start<K, MULTI, PACKED>), grid, block, 0, s, a);
     if (sep)
         BS_LAUNCH(s, K_PCG_REDUCE, "pcg_reduce", pcg_reduce<MULTI>, dim3(3 * max_cp, n), block, 0,
                   s, a, 0, 3);
@@ -1430,11 +1437,11 @@ static bs_status run_pcg_k(const PcgArgs& a, int n, int G, int max_cp, bool sep,
     int src = 0;   // the buffer holding d
     for (int it = 0; it < p.max_iters; ++it) {
         if (exact_iteration<K>(it)) {
-            BS_LAUNCH(s, K_PCG_MATVEC, "pcg_matvec", (pcg_matvec<K, MULTI, true>), grid, block, 0,
+            BS_LAUNCH(s, K_PCG_MATVEC, "pcg_matvec", (pcg_matvec<K, MULTI, true, PACKED>), grid, block, 0,
                       s, a, src);
             src ^= 1;
         } else if constexpr (uses_recurrence<K>()) {
-            BS_LAUNCH(s, K_PCG_MATVEC, "pcg_matvec", (pcg_matvec<K, MULTI, false>), grid, block, 0,
+            BS_LAUNCH(s, K_PCG_MATVEC, "pcg_matvec", (pcg_matvec<K, MULTI, false, PACKED>), grid, block, 0,
                       s, a, src);
         }
         if (sep)
@@ -1474,21 +1481,25 @@ bs_status run_pcg(int K, const PcgImage* imgs, int n, const PcgImage* dev_imgs,
     for (int i = 0; i < n; ++i) sep = sep || imgs[i].sums[0] != nullptr;
     const bool multi = n > 1;
     if (multi && (!dev_imgs || !blk2img)) return fail(BS_EINVAL, "image tables missing");
+    // the packed neighbour table when every image has one
+    bool packed = true;
+    for (int i = 0; i < n; ++i) packed = packed && imgs[i].nb16 != nullptr;
+    const int mode = (multi ? 1 : 0) | (packed ? 2 : 0);
+    auto go = [&](auto k) -> bs_status {
+        constexpr int Kc = decltype(k)::value;
+        switch (mode) {
+            case 0: return run_pcg_k<Kc, false, false>(a, n, G, max_cp, sep, p, act, s);
+            case 1: return run_pcg_k<Kc, true, false>(a, n, G, max_cp, sep, p, act, s);
+            case 2: return run_pcg_k<Kc, false, true>(a, n, G, max_cp, sep, p, act, s);
+            default: return run_pcg_k<Kc, true, true>(a, n, G, max_cp, sep, p, act, s);
+        }
+    };
     switch (K) {
-        case 1:
-            return multi ? run_pcg_k<1, true>(a, n, G, max_cp, sep, p, act, s)
-                         : run_pcg_k<1, false>(a, n, G, max_cp, sep, p, act, s);
-        case 2:
-            return multi ? run_pcg_k<2, true>(a, n, G, max_cp, sep, p, act, s)
-                         : run_pcg_k<2, false>(a, n, G, max_cp, sep, p, act, s);
-        case 3:
-            return multi ? run_pcg_k<3, true>(a, n, G, max_cp, sep, p, act, s)
-                         : run_pcg_k<3, false>(a, n, G, max_cp, sep, p, act, s);
-        case 4:
-            return multi ? run_pcg_k<4, true>(a, n, G, max_cp, sep, p, act, s)
-                         : run_pcg_k<4, false>(a, n, G, max_cp, sep, p, act, s);
-        default:
-            return fail(BS_EINVAL, "unsupported lane width");
+        case 1: return go(std::integral_constant<int, 1>{});
+        case 2: return go(std::integral_constant<int, 2>{});
+        case 3: return go(std::integral_constant<int, 3>{});
+        case 4: return go(std::integral_constant<int, 4>{});
+        default: return fail(BS_EINVAL, "unsupported lane width");
     }
 }
 

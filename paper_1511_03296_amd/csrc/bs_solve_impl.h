@@ -42,6 +42,8 @@ inline int padded_channels(int C) {
 // so the image's local block j runs on die j % 8.  Vectors are [V][Cp].
 struct PcgImage {
     const int32_t* nbr;      // [10][vcap] neighbour table
+    const uint32_t* nb16;    // [5][vcap] the table as packed 16-bit offsets (read unless
+                             // counts[CNT_NB_WIDE])
     const float2* nfm;       // [V] {n, 1 / diag(A)}
     const float* sc;         // [V] S c
     const float* b;          // right-hand side

@@ -50,6 +50,14 @@ def grid_arrays(G) -> dict:
     out["m"] = G.array(v.m, V, torch.int32).cpu().numpy().astype(np.int64)
     nbr = G.array(v.nbr, 10 * vcap, torch.int32).view(10, vcap)[:, :V]
     out["nbr"] = nbr.cpu().numpy().astype(np.int64)
+    # the packed table: word i holds slots 2i, 2i+1 as signed 16-bit u - v
+    words = G.array(v.nb16, 5 * vcap, torch.int32).view(5, vcap)[:, :V].cpu().numpy()
+    words = words.astype(np.int64) & 0xFFFFFFFF
+    halves = np.stack([words & 0xFFFF, words >> 16], axis=1).reshape(10, V)
+    off = np.where(halves >= 0x8000, halves - 0x10000, halves)
+    out["nb16"] = np.where(off != 0, np.arange(V)[None, :] + off, -1)
+    out["nb_wide"] = int(cnt[5])
+    out["nb_packed"] = int(v.nb_packed)
     out["pix_ptr"] = G.array(v.pix_ptr, V + 1, torch.int32).cpu().numpy().astype(np.int64)
     out["pix_list"] = G.array(v.pix_list, P, torch.int32).cpu().numpy().astype(np.int64)
     out["n"] = G.array(v.n, V, torch.float64).cpu().numpy()

@@ -1,6 +1,7 @@
 """GPU edge cases of the solve: every lane width and channel padding (C = 4,
 5, 6, 9, 64), degenerate images (one pixel, one row, one column), the
-largest grid scale, a batch mixing them, and invalid inputs rejected on the
+largest grid scale, neighbour offsets at the limit of the packed 16-bit
+table and beyond it, a batch mixing them, and invalid inputs rejected on the
 host before anything is launched."""
 import numpy as np
 import pytest
@@ -8,7 +9,7 @@ import torch
 
 import workloads as WL
 from oracle import bilateral as O
-from tests.gpu_helpers import gpu_grid, params, rel_l2, say, to_dev
+from tests.gpu_helpers import grid_arrays, gpu_grid, params, rel_l2, say, to_dev
 
 pytestmark = pytest.mark.gpu
 
@@ -54,6 +55,59 @@ def test_largest_grid_scale():
     say("edge: sigma (128, 255, 255)")
     x, exact, _ = _solve_vs_oracle(p, init="flat")
     assert rel_l2(x, exact.x) <= TOL_X
+
+
+@pytest.mark.parametrize("W,packed,wide", [(32767, 1, 0), (32800, 0, 1)])
+def test_neighbour_offsets_at_16_bit_limit(W, packed, wide):
+    # sigma_xy = 1 and a reference constant down each column: every pixel is a
+    # vertex and its neighbour one row down is W ids away.  W = 32767 is the
+    # widest strip the packed table holds (the host bound admits it exactly);
+    # at 32800 the host keeps the 32-bit table and the grid reports the
+    # offset that does not fit.  Forward and backward against the oracle.
+    p = WL.strip(seed=27, H=3, W=W)
+    say(f"edge: strip {W}x3, sigma_xy 1 (packed table {packed})")
+    G = gpu_grid(p)
+    t, c = to_dev(p.target), to_dev(p.conf)
+    y, st = G.solve(t, c, p.lam, max_iters=p.max_iters, rel_tol=p.rel_tol)
+    x = G.slice(y, 1)
+    gx = WL.random_grad(28, 1, 3, W)
+    gt, gc, _, _ = G.backward(t, c, y, to_dev(gx), p.lam, max_iters=p.max_iters,
+                           rel_tol=p.rel_tol)
+    torch.cuda.synchronize()
+    got = grid_arrays(G)
+    g = O.build_grid(p.ref, p.sigma_xy, p.sigma_l, p.sigma_uv)
+    assert got["V"] == g.V == 3 * W
+    assert got["nb_packed"] == packed and got["nb_wide"] == wide
+    assert np.array_equal(got["nbr"], g.nbr)
+    assert int(np.max(np.abs(np.where(g.nbr >= 0, g.nbr - np.arange(g.V), 0)))) == W
+    if packed:
+        assert np.array_equal(got["nb16"], g.nbr)
+    bs = O.bistochastize(g, 1e-10, 200)
+    assert got["bist_iters"] == bs.iters
+    assert np.max(np.abs(got["n"] - bs.n) / bs.n) <= 1e-12
+    prm = params(p, rel_tol=1e-12, max_iters=20000)
+    sol = O.solve(p.ref, p.target, p.conf, prm)
+    og = O.solve_backward(sol, p.target, p.conf, gx, prm)
+    assert rel_l2(x.cpu().numpy(), sol.x) <= TOL_X
+    assert rel_l2(gt.cpu().numpy(), og.grad_t) <= TOL_X
+
+
+def test_batch_mixing_packed_and_wide_tables():
+    # one launch group (C = 1) holding a grid with the packed table and one
+    # without: the group reads the 32-bit ids of both
+    from paper_1511_03296_amd import BatchState, SolveOptions
+    probs = [WL.strip(seed=29, H=3, W=32800),
+             WL.tiny_ramp(seed=30, H=48, W=64, regions=6)]
+    say("edge: batch of a wide strip and a packed image")
+    st = BatchState([to_dev(p.ref) for p in probs], [to_dev(p.target) for p in probs],
+                    [to_dev(p.conf) for p in probs],
+                    [(p.sigma_xy, p.sigma_l, p.sigma_uv) for p in probs], 2)
+    xs, _ = st.forward(SolveOptions(128.0, 3000, 1e-6))
+    torch.cuda.synchronize()
+    for i, p in enumerate(probs):
+        exact = O.solve(p.ref, p.target, p.conf,
+                        params(p, lam=128.0, rel_tol=1e-12, max_iters=20000))
+        assert rel_l2(xs[i].cpu().numpy(), exact.x) <= TOL_X, i
 
 
 def test_batch_of_extremes():

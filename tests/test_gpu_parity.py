@@ -56,6 +56,7 @@ def test_grid_bit_exact(name, make):
     assert np.array_equal(got["idx"], g.idx)
     assert np.array_equal(got["m"], g.m)
     assert np.array_equal(got["nbr"], g.nbr)
+    assert got["nb_packed"] == 1 and got["nb_wide"] == 0 and np.array_equal(got["nb16"], g.nbr)
     ptr = np.concatenate([[0], np.cumsum(g.m)])
     assert np.array_equal(got["pix_ptr"], ptr)
     assert np.array_equal(got["pix_list"], np.argsort(g.idx, kind="stable"))
@@ -221,6 +222,7 @@ def test_full_size_stereo_1024x768():
     got = grid_arrays(G)
     assert got["V"] == sol.grid.V and np.array_equal(got["idx"], sol.grid.idx)
     assert np.array_equal(got["nbr"], sol.grid.nbr)
+    assert got["nb_packed"] == 1 and got["nb_wide"] == 0 and np.array_equal(got["nb16"], sol.grid.nbr)
     assert rel_l2(x.cpu().numpy(), sol.x) <= TOL_X
 
 
@@ -258,6 +260,7 @@ def test_full_size_depth_2048x1536():
     g = O.build_grid(p.ref, p.sigma_xy, p.sigma_l, p.sigma_uv)
     assert got["V"] == g.V == gold["V"] and np.array_equal(got["key"], g.keys)
     assert np.array_equal(got["idx"], g.idx) and np.array_equal(got["nbr"], g.nbr)
+    assert got["nb_packed"] == 1 and got["nb_wide"] == 0 and np.array_equal(got["nb16"], g.nbr)
     pyr = O.build_pyramid(g)
     assert got["K"] == pyr.K and got["sizes"][: pyr.K + 1] == pyr.sizes == gold["pyramid_sizes"]
     bs = O.bistochastize(g, 1e-10, 200)

@@ -108,6 +108,23 @@ def tiny_ramp(seed: int = 0, H: int = 48, W: int = 64, regions: int = 12,
                    lam, max_iters, rel_tol)
 
 
+def strip(seed: int = 0, H: int = 3, W: int = 32800, sigma=(1, 8, 8), lam: float = 128.0,
+          rel_tol: float = 1e-6, max_iters: int = 20000) -> Problem:
+    """A wide strip whose reference is constant down each column (random
+    column colours), so at sigma_xy = 1 every pixel is a vertex whose
+    neighbour one row down lies W vertex ids away.  Ramp target with noise,
+    confidence U[0.2, 1]."""
+    rng = np.random.default_rng(seed)
+    cols = rng.uniform(0.0, 1.0, size=(3, 1, W)).astype(np.float32)
+    ref = np.ascontiguousarray(np.broadcast_to(cols, (3, H, W)))
+    x = np.arange(W, dtype=np.float64)[None, :] / W
+    y = np.arange(H, dtype=np.float64)[:, None] / max(H, 1)
+    t = (0.3 + 0.4 * x + 0.2 * y + rng.normal(0.0, 0.05, size=(H, W)))[None].astype(np.float32)
+    conf = rng.uniform(0.2, 1.0, size=(H, W)).astype(np.float32)
+    return Problem("strip_%dx%d" % (W, H), ref, t, conf, sigma[0], sigma[1], sigma[2],
+                   lam, max_iters, rel_tol)
+
+
 def stereo_refine(seed: int = 0, H: int = 768, W: int = 1024, regions: int = 300,
                   sigma=(16, 8, 8), lam: float = 128.0, iters: int = 25) -> Problem:
     """Stereo-refinement shape: piecewise-planar disparity in [0,256], 10% outliers."""
