@@ -8,8 +8,7 @@ to check against the paper by eye.  Library primitives used as single steps:
 ``np.unique`` (sorted vertex set), ``np.searchsorted`` (key lookup),
 ``np.bincount`` (splat sums).  No blocking, fusion or reordering.
 
-Readings of passages where the paper is silent or ambiguous (each also listed
-in the design notes):
+Readings of passages where the paper is silent or ambiguous:
   R1  colour space: quantise each channel to 8 bits, then JFIF (BT.601 full
       range) YCbCr in 16.16 fixed point; luma l = Y, chroma (u, v) = (Cb, Cr).
   R2  grid coordinate of a value v at scale s: round half up of v/s, computed

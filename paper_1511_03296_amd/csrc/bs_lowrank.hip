@@ -121,7 +121,10 @@ struct Reduction {
 };
 
 // Pivoted Cholesky of the Gram matrix G (C x C, float64), the row masses of
-// R P^T, the rank t and the factors M and R~ (R18, R19 of the design notes).
+// R P^T, the rank t and the factors M and R~.  t is the fewest rows, taken
+// by decreasing mass, whose mass reaches (1 - eps) of the total, so at most
+// eps of B's squared norm is dropped; R~ is those rows of R P^T (rows of R
+// with their pivoted columns put back in channel order).
 Reduction reduce_gram(const std::vector<double>& G, int C, double eps) {
     std::vector<int> perm(C);
     for (int i = 0; i < C; ++i) perm[i] = i;
