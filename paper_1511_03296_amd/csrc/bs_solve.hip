@@ -764,38 +764,12 @@ __device__ inline ImgView view_of(const PcgImage& s) {
     return I;
 }
 
-// Neighbour words of vertex v (phase 1 of a tile's loads).  With the packed
-// table and DEFER, the five words as loaded (raw[0..4]), decoded by nbr_id
-// where the gathers are formed; otherwise the ten ids.  Decoding late keeps
-// the wait for the words out of the previous tile's arithmetic.  Measured per
-// form: the one-channel recurrence matvec runs 21 % faster with it, while the
-// one-channel exact form (+8 %), the two-channel recurrence (+4 %) and the
-// 21-channel matvec (+6 %) run slower, their live ranges across the tile loop
-// growing instead.
-template <bool PACKED, bool DEFER>
-__device__ inline void load_nbr(int (&raw)[10], int v, const ImgView& I) {
-    if constexpr (PACKED && DEFER) {
-#pragma unroll
-        for (int i = 0; i < 5; ++i) raw[i] = (int)I.nb16[i * I.vcap + v];
-    } else {
-        load_neighbours(raw, v, I.vcap, PACKED, I.nbr, I.nb16);
-    }
+// Neighbour indices of vertex v (phase 1 of a tile's loads): five packed
+// words when every image of the launch has a packed table, else ten ids.
+template <bool PACKED>
+__device__ inline void load_nbr(int (&nb)[10], int v, const ImgView& I) {
+    load_neighbours(nb, v, I.vcap, PACKED, I.nbr, I.nb16);
 }
-
-// Neighbour j of vertex v from its loaded words (-1 if absent).
-template <bool PACKED, bool DEFER>
-__device__ inline int nbr_id(const int (&raw)[10], int v, int j) {
-    if constexpr (PACKED && DEFER) {
-        const uint32_t wd = (uint32_t)raw[j >> 1];
-        return unpack_offset(v, (j & 1) ? wd >> 16 : wd & 0xffffu);
-    } else {
-        return raw[j];
-    }
-}
-
-// Late decoding of the packed words, by lane width and matvec form.
-template <int K, bool EXACT>
-constexpr bool defer_decode() { return K == 1 && !EXACT; }
 
 // Clears the channel state; the image is active until its first stop test.
 template <bool MULTI>
@@ -843,10 +817,10 @@ __global__ void __launch_bounds__(kRedBlock) pcg_start(PcgArgs a) {
 #pragma unroll
         for (int k = 0; k < K; ++k) ns[k] = 0.0f;
         int nbv[10];
-        load_nbr<PACKED, false>(nbv, v, I);
+        load_nbr<PACKED>(nbv, v, I);
 #pragma unroll
         for (int j = 0; j < 10; ++j) {
-            const int u = nbr_id<PACKED, false>(nbv, v, j);
+            const int u = nbv[j];
             if (u >= 0) {
                 const float nu = I.nfm[u].x;
                 const Vec<K> yu = ldv<K>(I.y + (int64_t)u * Cp + ln.g * K);
@@ -888,10 +862,9 @@ struct MatOps {
     float scv;
 };
 
-// The gathers and per-vertex operands of vertex v (phase 2), from its
-// neighbour words.
-template <int K, bool EXACT, bool PACKED, bool DEFER>
-__device__ inline void load_ops(MatOps<K, EXACT>& o, int v, const int (&raw)[10], const Lanes& ln,
+// The gathers and per-vertex operands of vertex v (phase 2).
+template <int K, bool EXACT>
+__device__ inline void load_ops(MatOps<K, EXACT>& o, int v, const int (&nb)[10], const Lanes& ln,
                                 const ImgView& I, gp<const float> din) {
     o.v = v;
     const int Cp = I.Cp;
@@ -899,8 +872,8 @@ __device__ inline void load_ops(MatOps<K, EXACT>& o, int v, const int (&raw)[10]
     // are masked off, which halves the bytes the texture path delivers.
 #pragma unroll
     for (int j = 0; j < 10; ++j) {
-        const int u = nbr_id<PACKED, DEFER>(raw, v, j);
-        o.nb[j] = u;
+        o.nb[j] = nb[j];
+        const int u = nb[j];
         if (u >= 0) {
             const int64_t eu = (int64_t)u * Cp + ln.g * K;
             if constexpr (EXACT) {
@@ -952,7 +925,6 @@ __global__ void __launch_bounds__(kRedBlock) pcg_matvec(PcgArgs a, int src) {
     if constexpr (MULTI) {
         if (*I.active == 0) return;   // stopped image (its last step applied)
     }
-    constexpr bool kDefer = defer_decode<K, EXACT>();
     const int dst = EXACT ? (src ^ 1) : src;
     gp<const float> din = src ? I.d1 : I.d0;
     gp<float> dout = dst ? I.d1 : I.d0;
@@ -973,8 +945,8 @@ __global__ void __launch_bounds__(kRedBlock) pcg_matvec(PcgArgs a, int src) {
     int v = (int)(tl.first * ln.vpb) + ln.vl;
     bool have = ln.ok && tl.first < tl.end && v < V;
     if (have) {
-        load_nbr<PACKED, kDefer>(nbn, v, I);
-        load_ops<K, EXACT, PACKED, kDefer>(o, v, nbn, ln, I, din);
+        load_nbr<PACKED>(nbn, v, I);
+        load_ops<K, EXACT>(o, v, nbn, ln, I, din);
     }
     ps.sum(I.part0, fin);
     if (t == 0) n_active = n_pend = 0;
@@ -1022,7 +994,7 @@ __global__ void __launch_bounds__(kRedBlock) pcg_matvec(PcgArgs a, int src) {
         const int64_t nt = tile + tl.step;
         const int vn = (int)(nt * ln.vpb) + ln.vl;
         const bool hn = any && ln.ok && nt < tl.end && vn < V;
-        if (hn) load_nbr<PACKED, kDefer>(nbn, vn, I);
+        if (hn) load_nbr<PACKED>(nbn, vn, I);
         if (any && have) {
             float zv[K], ns[K];
             Vec<K> dv, qv;
@@ -1072,7 +1044,7 @@ __global__ void __launch_bounds__(kRedBlock) pcg_matvec(PcgArgs a, int src) {
             for (int k = 0; k < K; ++k)
                 if (act[k]) acc[0][k] += (double)dv.v[k] * (double)qv.v[k];
         }
-        if (hn) load_ops<K, EXACT, PACKED, kDefer>(o, vn, nbn, ln, I, din);
+        if (hn) load_ops<K, EXACT>(o, vn, nbn, ln, I, din);
         have = hn;
     }
     lane_partials<1, K>(acc, ln, Cp, nb, partial_slot(jb, nb), I.part1);
