@@ -109,3 +109,50 @@ def test_batch_tuning_setters():
     assert L.lib.bs_batch_set_tiles_per_block(5, 4) == L.BS_EINVAL
     assert L.lib.bs_batch_set_tiles_per_block(2, 65) == L.BS_EINVAL
     assert L.lib.bs_batch_tiles_per_block(0) == 0
+
+
+def test_ctypes_mirrors_match_the_c_layout(tmp_path):
+    """Every struct the binding mirrors has the header's size and field offsets,
+    as a C compiler lays them out (the library fills some of them, so a short
+    mirror would be overrun)."""
+    from paper_1511_03296_amd import _lib as L
+    mirrors = {"bs_grid_params": L.GridParams, "bs_bistoch_params": L.BistochParams,
+               "bs_solve_params": L.SolveParams, "bs_chan_stats": L.ChanStats,
+               "bs_grid": L.Grid, "bs_grid_view": L.GridView, "bs_batch_item": L.BatchItem}
+    c_name = {"lambda_": "lambda"}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "bsolve.h"',
+             'int main(void) {']
+    for cs, py in mirrors.items():
+        lines.append(f'printf("{cs} size %zu\\n", sizeof({cs}));')
+        for f in py._fields_:
+            n = c_name.get(f[0], f[0])
+            lines.append(f'printf("{cs} {f[0]} %zu\\n", offsetof({cs}, {n}));')
+    lines += ["return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), str(src), "-o",
+                    str(exe)], check=True, capture_output=True)
+    got = {}
+    for line in subprocess.run([str(exe)], check=True, capture_output=True,
+                               text=True).stdout.splitlines():
+        cs, field, val = line.split()
+        got[(cs, field)] = int(val)
+    for cs, py in mirrors.items():
+        assert got[(cs, "size")] == ct.sizeof(py), cs
+        for f in py._fields_:
+            assert got[(cs, f[0])] == getattr(py, f[0]).offset, (cs, f[0])
+
+
+def test_image_size_limits():
+    """Sides up to 65535 (16-bit key fields) and up to 2^30 pixels are sized;
+    larger images are rejected by the pure workspace query."""
+    from paper_1511_03296_amd import _lib as L
+    p = L.GridParams(8, 4, 4)
+    q = ct.byref(p)
+    assert L.lib.bs_grid_workspace_bytes(1, 65535, q) > 0
+    assert L.lib.bs_grid_workspace_bytes(65535, 1, q) > 0
+    assert L.lib.bs_grid_workspace_bytes(1, 65536, q) == 0
+    assert L.lib.bs_grid_workspace_bytes(65536, 1, q) == 0
+    assert L.lib.bs_grid_workspace_bytes(32768, 32768, q) > 0      # exactly 2^30 pixels
+    assert L.lib.bs_grid_workspace_bytes(32768, 32769, q) == 0

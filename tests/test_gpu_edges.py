@@ -92,6 +92,26 @@ def test_neighbour_offsets_at_16_bit_limit(W, packed, wide):
     assert rel_l2(gt.cpu().numpy(), og.grad_t) <= TOL_X
 
 
+@pytest.mark.parametrize("H,W", [(1, 65535), (65535, 1)])
+def test_largest_image_side(H, W):
+    # the longest side the 16-bit key fields hold; at sigma_xy = 1 every pixel
+    # has its own cell, so the cell coordinate reaches 65534
+    p = WL.tiny_ramp(seed=31, H=H, W=W, regions=40, sigma=(1, 8, 8))
+    say(f"edge: image {W}x{H}, sigma_xy 1")
+    G = gpu_grid(p)
+    t, c = to_dev(p.target), to_dev(p.conf)
+    y, _ = G.solve(t, c, p.lam, max_iters=3000, rel_tol=1e-6)
+    x = G.slice(y, 1)
+    torch.cuda.synchronize()
+    got = grid_arrays(G)
+    g = O.build_grid(p.ref, p.sigma_xy, p.sigma_l, p.sigma_uv)
+    assert got["V"] == g.V and np.array_equal(got["key"], g.keys)
+    assert np.array_equal(got["idx"], g.idx) and np.array_equal(got["nbr"], g.nbr)
+    assert int(np.max(g.coords[:, 0 if H > 1 else 1])) == max(H, W) - 1
+    exact = O.solve(p.ref, p.target, p.conf, params(p, rel_tol=1e-12, max_iters=20000))
+    assert rel_l2(x.cpu().numpy(), exact.x) <= TOL_X
+
+
 def test_batch_mixing_packed_and_wide_tables():
     # one launch group (C = 1) holding a grid with the packed table and one
     # without: the group reads the 32-bit ids of both
