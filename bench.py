@@ -20,7 +20,6 @@ solved one after another by the single-image path as the "plain" reference.
 from __future__ import annotations
 
 import argparse
-import hashlib
 import json
 import os
 import sys
@@ -88,11 +87,24 @@ def _spread(values) -> dict:
     return {"min": v[0], "median": v[len(v) // 2], "max": v[-1]}
 
 
-def _source_digest() -> str:
-    h = hashlib.sha256()
-    with open(os.path.join(ROOT, "paper_1511_03296_amd", "csrc", "bs_solve.hip"), "rb") as f:
-        h.update(f.read())
-    return h.hexdigest()
+KERNEL_CODE = os.path.join(ROOT, "paper_1511_03296_amd", "kernel_code.json")
+
+
+def _measured_traffic(workload: str):
+    """HBM bytes per pcg_matvec launch from the committed counter runs, if
+    every pcg_matvec kernel they covered still has the machine code it had
+    then (digests written by the build), else None."""
+    if not (os.path.exists(TRAFFIC_FILE) and os.path.exists(KERNEL_CODE)):
+        return None
+    with open(TRAFFIC_FILE) as f:
+        wl = json.load(f).get("workloads", {}).get(workload)
+    with open(KERNEL_CODE) as f:
+        code = json.load(f)
+    if not wl or not wl.get("kernels"):
+        return None
+    if any(code.get(k) != d for k, d in wl["kernels"].items()):
+        return None
+    return wl.get("bytes_per_launch")
 
 
 def make_problems(name: str):
@@ -371,13 +383,7 @@ def main() -> int:
     bytes_per_launch = step_bytes / mv_launches if mv_launches else 0.0
     achieved = step_bytes / (mv_ms * 1e-3) / 1e9 if mv_launches else 0.0
 
-    traffic = None
-    if os.path.exists(TRAFFIC_FILE):
-        with open(TRAFFIC_FILE) as f:
-            tr = json.load(f)
-        wl = tr.get("workloads", {}).get(args.workload)
-        if tr.get("source_sha256") == _source_digest() and wl:
-            traffic = wl.get("bytes_per_launch")
+    traffic = _measured_traffic(args.workload)
 
     line = {
         "metric": METRIC,
