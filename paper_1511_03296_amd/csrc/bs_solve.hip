@@ -773,18 +773,20 @@ __device__ inline void load_nbr(int (&nb)[10], int v, const ImgView& I) {
 
 // The packed words of vertex v as loaded (raw[0..4]), decoded only where the
 // gathers are formed (load_ops_late), which keeps the wait for them out of
-// the previous tile's arithmetic.  Measured per form, it speeds the
-// one-channel recurrence matvec by a fifth, and slows the one-channel exact
-// form (8 %), the two-channel recurrence (4 %) and 21-channel lanes (6 %),
-// whose live ranges across the tile loop grow instead; it is used for the
-// one-channel recurrence matvec of a single image.
+// the previous tile's arithmetic.  Measured on one-channel single images,
+// both matvec forms gain (the 1.58 M-vertex depth matvec: 30.8 us per launch
+// on average, 25.7 with the recurrence form decoding late, 24.7 with both).
+// In launches over an image table it sped the one-channel recurrence form by
+// a fifth but slowed the one-channel exact form (8 %), the two-channel
+// recurrence (4 %) and 21-channel lanes (6 %), whose live ranges across the
+// tile loop grow instead; those launches decode early.
 __device__ inline void load_nbr_words(int (&raw)[10], int v, const ImgView& I) {
 #pragma unroll
     for (int i = 0; i < 5; ++i) raw[i] = (int)I.nb16[i * I.vcap + v];
 }
 
 template <int K, bool EXACT, bool PACKED, bool MULTI>
-constexpr bool late_decode() { return K == 1 && !EXACT && PACKED && !MULTI; }
+constexpr bool late_decode() { return K == 1 && PACKED && !MULTI; }
 
 // Clears the channel state; the image is active until its first stop test.
 template <bool MULTI>
@@ -909,10 +911,20 @@ __device__ inline void load_ops(MatOps<K, EXACT>& o, int v, const int (&nb)[10],
     else o.qv = ldv<K>(I.q + e);
 }
 
-// load_ops of the recurrence form from the packed words of load_nbr_words.
-template <int K>
-__device__ inline void load_ops_late(MatOps<K, false>& o, int v, const int (&raw)[10],
+// load_ops from the packed words of load_nbr_words.
+template <int K, bool EXACT>
+__device__ inline void load_ops_late(MatOps<K, EXACT>& o, int v, const int (&raw)[10],
                                      const Lanes& ln, const ImgView& I, gp<const float> din) {
+    if constexpr (EXACT) {
+        int nb[10];
+#pragma unroll
+        for (int j = 0; j < 10; ++j) {
+            const uint32_t wd = (uint32_t)raw[j >> 1];
+            nb[j] = unpack_offset(v, (j & 1) ? wd >> 16 : wd & 0xffffu);
+        }
+        load_ops<K, true>(o, v, nb, ln, I, din);
+        return;
+    } else {
     o.v = v;
     const int Cp = I.Cp;
 #pragma unroll
@@ -928,6 +940,7 @@ __device__ inline void load_ops_late(MatOps<K, false>& o, int v, const int (&raw
     o.yv = ldv<K>(I.y + e);
     o.nmv = I.nfm[v];
     o.qv = ldv<K>(I.q + e);
+    }
 }
 
 // New search direction of one element: z + beta d_old.
@@ -984,7 +997,7 @@ __global__ void __launch_bounds__(kRedBlock) pcg_matvec(PcgArgs a, int src) {
     if (have) {
         if constexpr (kLate) {
             load_nbr_words(nbn, v, I);
-            load_ops_late<K>(o, v, nbn, ln, I, din);
+            load_ops_late<K, EXACT>(o, v, nbn, ln, I, din);
         } else {
             load_nbr<PACKED>(nbn, v, I);
             load_ops<K, EXACT>(o, v, nbn, ln, I, din);
@@ -1090,7 +1103,7 @@ __global__ void __launch_bounds__(kRedBlock) pcg_matvec(PcgArgs a, int src) {
                 if (act[k]) acc[0][k] += (double)dv.v[k] * (double)qv.v[k];
         }
         if (hn) {
-            if constexpr (kLate) load_ops_late<K>(o, vn, nbn, ln, I, din);
+            if constexpr (kLate) load_ops_late<K, EXACT>(o, vn, nbn, ln, I, din);
             else load_ops<K, EXACT>(o, vn, nbn, ln, I, din);
         }
         have = hn;
