@@ -2,6 +2,8 @@
 
 Argument marshalling only: every step of the solver runs in the HIP library.
 Importing this module loads the library and fails loudly if it is missing.
+BSOLVE_LIB, if set, names another build of the same library to load (the
+host-sanitizer build of the tests).
 """
 from __future__ import annotations
 
@@ -9,7 +11,7 @@ import ctypes as ct
 import os
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libbsolve.so")
+LIB_PATH = os.environ.get("BSOLVE_LIB") or os.path.join(_HERE, "libbsolve.so")
 
 BS_OK, BS_EINVAL, BS_EWORKSPACE, BS_EDEVICE, BS_EUNSUPPORTED = 0, -1, -2, -3, -4
 BS_MAX_CHANNELS = 64
