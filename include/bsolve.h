@@ -31,7 +31,15 @@
  *  - Images are planar float32: reference [3][H][W] (R, G, B in [0, 1]),
  *    target [C][H][W], confidence [H][W].  Bilateral-space vectors are
  *    vertex-major float32 [V][C] (channels contiguous per vertex) with
- *    room for Vcap = H*W vertices.
+ *    room for Vcap vertices (bs_grid_view.vcap; Vcap <= H*W, so H*W rows
+ *    always suffice).
+ *  - Device data are not scanned: targets and confidences are expected to be
+ *    finite, confidences >= 0.  A non-finite value reaches the channels whose
+ *    arithmetic it enters (all of them, for a confidence): they stop after
+ *    their first iteration with reason 4 and a non-finite rel_residual in
+ *    bs_chan_stats, and their output is not finite; other channels are
+ *    unaffected.  A negative confidence can make A indefinite, which stops a
+ *    channel with reason 4 once d^T A d <= 0.
  *  - Readings of passages the paper leaves open (colour space, rounding,
  *    vertex order, blur form, stopping rules) are documented with the
  *    operation they affect below.

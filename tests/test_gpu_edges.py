@@ -150,6 +150,32 @@ def test_batch_of_extremes():
         assert rel_l2(xs[i].cpu().numpy(), exact.x) <= TOL_X, i
 
 
+def test_non_finite_input_stops_only_its_channels():
+    # device data are not scanned: a NaN target value stops its own channel
+    # after one iteration (reason 4, non-finite residual); the other channel
+    # is solved as if alone.  A NaN confidence stops every channel.
+    from paper_1511_03296_amd import read_stats
+    p = WL.tiny_ramp(seed=32, H=40, W=56, regions=6, channels=2)
+    say("edge: NaN target in channel 0, NaN confidence")
+    G = gpu_grid(p)
+    t = p.target.copy()
+    t[0, 7, 9] = np.nan
+    y, st = G.solve(to_dev(t), to_dev(p.conf), p.lam, max_iters=3000, rel_tol=1e-6)
+    x = G.slice(y, 2)
+    torch.cuda.synchronize()
+    s = read_stats(st)
+    assert s["reason"][0] == 4 and s["iters"][0] <= 1 and not np.isfinite(s["rel_residual"][0])
+    assert s["reason"][1] == 1
+    one = O.solve(p.ref, p.target[1:2], p.conf, params(p, rel_tol=1e-12, max_iters=20000))
+    assert rel_l2(x[1:2].cpu().numpy(), one.x) <= TOL_X
+    c = p.conf.copy()
+    c[3, 4] = np.nan
+    y, st = G.solve(to_dev(p.target), to_dev(c), p.lam, max_iters=3000, rel_tol=1e-6)
+    torch.cuda.synchronize()
+    s = read_stats(st)
+    assert np.all(s["reason"] == 4) and np.all(s["iters"] <= 1)
+
+
 def test_invalid_inputs_rejected():
     from paper_1511_03296_amd import BilateralGrid
     from paper_1511_03296_amd import _lib as L
