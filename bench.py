@@ -302,8 +302,8 @@ def main() -> int:
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
-              "(images or row slabs would shard across GPUs, see the design notes)",
-              file=sys.stderr)
+              "(a batch would shard by images across GPUs, one large image by slabs of "
+              "cell rows with a halo exchange per PCG iteration)", file=sys.stderr)
         return 2
 
     import torch
