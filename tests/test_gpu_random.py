@@ -1,0 +1,54 @@
+"""Parity on seeded random configurations (workloads.random_case): image
+sides 1..160, sigma_xy from 1 to 64, colour scales 1..64, 1 to 21 channels,
+lambda from 0.1 to 1000, a quarter of the confidences zero.  Each case is
+solved alone (its own lambda) and the first twenty together through the batch
+engine (lambda 128); the grid must be bit-exact and the solution within the
+parity bar of the oracle's, every channel stopping on the tolerance."""
+import numpy as np
+import pytest
+import torch
+
+import workloads as WL
+from oracle import bilateral as O
+from tests.gpu_helpers import grid_arrays, gpu_grid, params, rel_l2, say, to_dev
+
+pytestmark = pytest.mark.gpu
+
+TOL_X = 1e-4
+SEEDS = range(40)
+
+
+@pytest.mark.parametrize("seed", SEEDS)
+def test_random_case(seed):
+    from paper_1511_03296_amd import read_stats
+    p = WL.random_case(seed)
+    say(f"random case {seed}: {p.name} sigma ({p.sigma_xy}, {p.sigma_l}, {p.sigma_uv}) "
+        f"lambda {p.lam:.3g}")
+    G = gpu_grid(p)
+    y, st = G.solve(to_dev(p.target), to_dev(p.conf), p.lam, max_iters=20000, rel_tol=1e-6)
+    x = G.slice(y, p.C)
+    torch.cuda.synchronize()
+    got = grid_arrays(G)
+    sol = O.solve(p.ref, p.target, p.conf, params(p, rel_tol=1e-12, max_iters=20000))
+    assert got["V"] == sol.grid.V and np.array_equal(got["key"], sol.grid.keys)
+    assert np.array_equal(got["idx"], sol.grid.idx) and np.array_equal(got["nbr"], sol.grid.nbr)
+    if got["nb_packed"]:
+        assert np.array_equal(got["nb16"], sol.grid.nbr)
+    s = read_stats(st)
+    assert np.all(np.isin(s["reason"], (1, 5))), s["reason"]
+    assert rel_l2(x.cpu().numpy(), sol.x) <= TOL_X
+
+
+def test_random_cases_as_one_batch():
+    from paper_1511_03296_amd import BatchState, SolveOptions
+    probs = [WL.random_case(s) for s in range(20)]
+    say("random cases 0..19 as one batch, lambda 128")
+    st = BatchState([to_dev(p.ref) for p in probs], [to_dev(p.target) for p in probs],
+                    [to_dev(p.conf) for p in probs],
+                    [(p.sigma_xy, p.sigma_l, p.sigma_uv) for p in probs], 3)
+    xs, _ = st.forward(SolveOptions(128.0, 20000, 1e-6))
+    torch.cuda.synchronize()
+    for i, p in enumerate(probs):
+        exact = O.solve(p.ref, p.target, p.conf,
+                        params(p, lam=128.0, rel_tol=1e-12, max_iters=20000))
+        assert rel_l2(xs[i].cpu().numpy(), exact.x) <= TOL_X, (i, p.name)

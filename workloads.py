@@ -240,6 +240,27 @@ def mixed_batch(seed: int = 0, count: int = 64, wmin=320, wmax=1920, hmin=240,
     return out
 
 
+def random_case(seed: int) -> Problem:
+    """One seeded random configuration for parity sweeps: image 1..160 pixels a
+    side, sigma_xy in {1, 2, 4, 8, 16, 32, 64}, colour scales in 1..64, C in
+    {1, 2, 3, 4, 5, 7, 21}, lambda log-uniform in [0.1, 1000], Voronoi
+    reference (1..30 regions) with colour noise 0..0.1, targets N(0, 1)
+    box-smoothed, confidence U[0, 1] with a quarter of the pixels at 0."""
+    rng = np.random.default_rng(seed + 104729)
+    H, W = (int(v) for v in rng.integers(1, 161, size=2))
+    regions = int(rng.integers(1, 31))
+    sxy = int(rng.choice([1, 2, 4, 8, 16, 32, 64]))
+    sl, suv = (int(v) for v in rng.integers(1, 65, size=2))
+    C = int(rng.choice([1, 2, 3, 4, 5, 7, 21]))
+    lam = float(10.0 ** rng.uniform(-1.0, 3.0))
+    ref, _ = voronoi_reference(rng, H, W, min(regions, H * W), noise=float(rng.uniform(0.0, 0.1)))
+    t = smoothed_logits(rng, C, H, W, k=int(rng.choice([1, 3, 5])))
+    conf = rng.uniform(0.0, 1.0, size=(H, W)).astype(np.float32)
+    conf[rng.uniform(size=(H, W)) < 0.25] = 0.0
+    return Problem("random%d_%dx%d_c%d" % (seed, W, H, C), ref, t, conf, sxy, sl, suv, lam,
+                   20000, 1e-6)
+
+
 def random_grad(seed: int, C: int, H: int, W: int) -> np.ndarray:
     """A seeded upstream gradient d(loss)/d(output) of shape [C][H][W]."""
     rng = np.random.default_rng(seed + 7919)
