@@ -41,6 +41,10 @@ Readings of passages where the paper is silent or ambiguous:
   R19 low-rank reduction, R-tilde: the first t rows of R', which already is
       R P^T with its rows reordered (applying P^T once more would permute the
       columns twice).
+  R21 the backward pass needs A invertible, i.e. every connected component
+      of the grid with positive total confidence: on a component without, A
+      is a singular graph Laplacian, A g = S dL/dx has no solution and the
+      printed gradient is not defined (the forward solve is: b = 0 there).
 """
 from __future__ import annotations
 
@@ -462,7 +466,9 @@ def solve_backward(sol: Solution, target: np.ndarray, conf: np.ndarray,
                    ) -> Gradients:
     """(dL/dt, dL/dc) from dL/dx (Section 3):
     dL/db = A^{-1} S dL/dx,  dL/ddiag(A) = -dL/db o y_hat,
-    dL/dt = c o S^T dL/db,   dL/dc = S^T dL/ddiag(A) + (S^T dL/db) o t."""
+    dL/dt = c o S^T dL/db,   dL/dc = S^T dL/ddiag(A) + (S^T dL/db) o t.
+    Defined only where A is invertible (R21): every connected component of
+    the grid needs positive total confidence."""
     g = sol.grid
     C = target.shape[0]
     gx = np.asarray(grad_x, np.float64).reshape(C, -1)

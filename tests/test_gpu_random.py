@@ -3,7 +3,8 @@ sides 1..160, sigma_xy from 1 to 64, colour scales 1..64, 1 to 21 channels,
 lambda from 0.1 to 1000, a quarter of the confidences zero.  Each case is
 solved alone (its own lambda) and the first twenty together through the batch
 engine (lambda 128); the grid must be bit-exact and the solution within the
-parity bar of the oracle's, every channel stopping on the tolerance."""
+parity bar of the oracle's, every channel stopping on the tolerance.  The
+backward pass runs on the same cases with every confidence positive."""
 import numpy as np
 import pytest
 import torch
@@ -52,3 +53,30 @@ def test_random_cases_as_one_batch():
         exact = O.solve(p.ref, p.target, p.conf,
                         params(p, lam=128.0, rel_tol=1e-12, max_iters=20000))
         assert rel_l2(xs[i].cpu().numpy(), exact.x) <= TOL_X, (i, p.name)
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_random_case_backward(seed):
+    # the adjoint solve and gradient scatter on the same random configurations,
+    # with the zero confidences raised to 0.05: the gradient needs every grid
+    # component to carry some confidence (A invertible).  dL/dc cancels where
+    # the solution follows the target, so its error is bounded against the
+    # size of its terms
+    p = WL.random_case(seed)
+    p.conf = np.where(p.conf == 0, np.float32(0.05), p.conf).astype(np.float32)
+    say(f"random case {seed} backward: {p.name}")
+    G = gpu_grid(p)
+    t, c = to_dev(p.target), to_dev(p.conf)
+    y, _ = G.solve(t, c, p.lam, max_iters=20000, rel_tol=1e-6)
+    gx = WL.random_grad(seed, p.C, p.H, p.W)
+    gt, gc, _, _ = G.backward(t, c, y, to_dev(gx), p.lam, max_iters=20000, rel_tol=1e-6)
+    torch.cuda.synchronize()
+    prm = params(p, rel_tol=1e-12, max_iters=20000)
+    sol = O.solve(p.ref, p.target, p.conf, prm)
+    og = O.solve_backward(sol, p.target, p.conf, gx, prm)
+    assert rel_l2(gt.cpu().numpy(), og.grad_t) <= TOL_X
+    idx = sol.grid.idx
+    terms = sum(np.abs(og.gb[idx, ch]) * (np.abs(p.target[ch].reshape(-1)) +
+                                          np.abs(sol.y[idx, ch])) for ch in range(p.C))
+    err = np.linalg.norm(gc.cpu().numpy().reshape(-1) - og.grad_c.reshape(-1))
+    assert err <= TOL_X * max(np.linalg.norm(terms), 1e-30), err / np.linalg.norm(terms)
