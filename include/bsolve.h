@@ -226,7 +226,7 @@ bs_status bs_slice(const bs_grid* grid, const float* y, int32_t C, float* x, voi
  * component without one, A is singular and A g = u has no solution; the
  * adjoint PCG then cannot meet its tolerance (bs_chan_stats reports it) and
  * the gradients are not defined, as in the paper's formula.  The forward
- * solve is defined there (b = 0 on such a component). */
+ * solve is defined there (b = 0 on such a component).
  *  y_hat   device float32 [Vcap][C], the forward solution from bs_solve.
  *  grad_x  device float32 [C][H][W].
  *  grad_t  device float32 [C][H][W] output;  grad_c device float32 [H][W] output.
