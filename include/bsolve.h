@@ -221,12 +221,13 @@ bs_status bs_slice(const bs_grid* grid, const float* y, int32_t C, float* x, voi
  *  u = S dL/dx,  g = A^{-1} u  (same A, preconditioner and init operator),
  *  dL/dt[c][p] = conf[p] g[idx[p]][c],
  *  dL/dconf[p] = sum_c g[idx[p]][c] (t[c][p] - y_hat[idx[p]][c]).
- * A must be invertible: every connected component of the grid (vertices
- * joined by blur neighbours) needs a pixel of positive confidence.  On a
- * component without one, A is singular and A g = u has no solution; the
- * adjoint PCG then cannot meet its tolerance (bs_chan_stats reports it) and
- * the gradients are not defined, as in the paper's formula.  The forward
- * solve is defined there (b = 0 on such a component).
+ * A connected component of the grid (vertices joined by blur neighbours)
+ * without any confidence makes A singular.  If dL/dx does not vanish on it,
+ * A g = u has no solution: the adjoint PCG cannot meet its tolerance
+ * (bs_chan_stats reports it) and the gradients are not defined, as with the
+ * paper's formula.  If it vanishes there (a confidence-weighted dL/dx does),
+ * g on that component is what PCG keeps of its initial state.  The forward
+ * solve is always defined (b = 0 on such a component).
  *  y_hat   device float32 [Vcap][C], the forward solution from bs_solve.
  *  grad_x  device float32 [C][H][W].
  *  grad_t  device float32 [C][H][W] output;  grad_c device float32 [H][W] output.

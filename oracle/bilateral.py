@@ -41,10 +41,13 @@ Readings of passages where the paper is silent or ambiguous:
   R19 low-rank reduction, R-tilde: the first t rows of R', which already is
       R P^T with its rows reordered (applying P^T once more would permute the
       columns twice).
-  R21 the backward pass needs A invertible, i.e. every connected component
-      of the grid with positive total confidence: on a component without, A
-      is a singular graph Laplacian, A g = S dL/dx has no solution and the
-      printed gradient is not defined (the forward solve is: b = 0 there).
+  R21 the backward pass on a grid with a connected component of zero total
+      confidence: A restricted to it is a singular graph Laplacian.  If dL/dx
+      does not vanish on the component, A g = S dL/dx has no solution and the
+      printed gradient is not defined (solve_backward raises); if it does
+      (e.g. a confidence-weighted upstream gradient), g there is what PCG
+      keeps of its initial state.  The forward solve is always defined
+      (b = 0 there).
 """
 from __future__ import annotations
 
@@ -461,14 +464,40 @@ class Gradients:
     runs: list
 
 
+def unconfident_components(g: Grid, sc: np.ndarray, u: np.ndarray | None = None) -> int:
+    """Number of connected components of the grid (vertices joined by blur
+    neighbours) whose total confidence S c is zero, where A restricted to the
+    component is a singular graph Laplacian (R21); with u [V][C], only those
+    on which u does not vanish, where A g = u has no solution.  Labels by
+    scipy's connected components."""
+    from scipy.sparse import coo_matrix
+    from scipy.sparse.csgraph import connected_components
+    rows, cols = [], []
+    for j in range(10):
+        ok = g.nbr[j] >= 0
+        rows.append(np.nonzero(ok)[0])
+        cols.append(g.nbr[j][ok])
+    r = np.concatenate(rows)
+    adj = coo_matrix((np.ones(r.size), (r, np.concatenate(cols))), shape=(g.V, g.V))
+    n, lab = connected_components(adj, directed=False)
+    bad = np.bincount(lab, weights=np.asarray(sc, np.float64), minlength=n) == 0.0
+    if u is not None:
+        mass = np.bincount(lab, weights=np.abs(np.asarray(u, np.float64)).reshape(g.V, -1)
+                           .sum(axis=1), minlength=n)
+        bad &= mass > 0.0
+    return int(np.count_nonzero(bad))
+
+
 def solve_backward(sol: Solution, target: np.ndarray, conf: np.ndarray,
                    grad_x: np.ndarray, p: Params, y_hat: np.ndarray | None = None
                    ) -> Gradients:
     """(dL/dt, dL/dc) from dL/dx (Section 3):
     dL/db = A^{-1} S dL/dx,  dL/ddiag(A) = -dL/db o y_hat,
     dL/dt = c o S^T dL/db,   dL/dc = S^T dL/ddiag(A) + (S^T dL/db) o t.
-    Defined only where A is invertible (R21): every connected component of
-    the grid needs positive total confidence."""
+    A component of the grid without confidence makes A singular (R21): the
+    adjoint system is solvable only if dL/dx vanishes on it (a confidence-
+    weighted upstream gradient does), and dL/db there is then fixed by the
+    initial state; otherwise this raises ValueError."""
     g = sol.grid
     C = target.shape[0]
     gx = np.asarray(grad_x, np.float64).reshape(C, -1)
@@ -476,6 +505,9 @@ def solve_backward(sol: Solution, target: np.ndarray, conf: np.ndarray,
     c = np.asarray(conf, np.float64).reshape(-1)
     yh = sol.y if y_hat is None else np.asarray(y_hat, np.float64)
     u = np.stack([splat(g, gx[ch]) for ch in range(C)], axis=1)
+    if unconfident_components(g, sol.sc, u):
+        raise ValueError("A g = S dL/dx has no solution: dL/dx does not vanish on a connected "
+                         "component of the grid without confidence (R21)")
     u0 = initial_state(sol.pyr, u, sol.sc, p)
     runs = [pcg(sol.A, u[:, ch], u0[:, ch], sol.minv, p.max_iters, p.rel_tol)
             for ch in range(C)]

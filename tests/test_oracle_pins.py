@@ -543,3 +543,26 @@ def test_lowrank_drops_at_most_eps_and_keeps_the_fewest_rows(eps):
     if lr.rank > 0:
         fewer = lr.Q[:, :-1] @ lr.R[:-1]
         assert np.sum((B - fewer) ** 2) > eps * nb
+
+
+def test_unconfident_components_and_the_inconsistent_adjoint():
+    """R21: a grid component without confidence.  Three pixels of unrelated
+    colours at sigma_xy = 1 are three isolated vertices; with confidence only
+    on the first, two components have none.  The adjoint system is solvable
+    only where dL/dx vanishes on them, which a confidence-weighted gradient
+    does; otherwise solve_backward refuses."""
+    ref = np.array([[[0.0, 1.0, 0.0]], [[0.0, 0.0, 1.0]], [[1.0, 0.0, 0.0]]], np.float32)
+    conf = np.array([[1.0, 0.0, 0.0]], np.float32)
+    t = np.array([[[0.3, 0.7, 0.9]]], np.float32)
+    prm = O.Params(1, 8, 8, 10.0, max_iters=100, rel_tol=1e-12)
+    sol = O.solve(ref, t, conf, prm)
+    g = sol.grid
+    assert g.V == 3 and np.all(g.nbr < 0)
+    assert O.unconfident_components(g, sol.sc) == 2
+    gx = np.ones((1, 1, 3), np.float32)
+    assert O.unconfident_components(g, sol.sc, O.splat(g, gx.reshape(-1))[:, None]) == 2
+    with pytest.raises(ValueError):
+        O.solve_backward(sol, t, conf, gx, prm)
+    og = O.solve_backward(sol, t, conf, gx * conf[None], prm)
+    # the one confident isolated vertex: x = t there, so dL/dt = 1 and dL/dc = 0
+    assert abs(og.grad_t[0, 0, 0] - 1.0) < 1e-12 and abs(og.grad_c[0, 0]) < 1e-12
