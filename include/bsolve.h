@@ -239,6 +239,37 @@ bs_status bs_solve_backward(const bs_grid* grid, const float* target, const floa
                             void* stream);
 
 /* ---------------------------------------------------------------------- */
+/* The solve without a workspace argument.                                 */
+/* ---------------------------------------------------------------------- */
+
+/* Size of the library's static device scratch array (64 MiB per GPU). */
+#define BS_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+
+/* For callers that cannot allocate device memory around a solve: code under
+ * HIP graph capture, tight serving loops, harnesses that forbid allocation.
+ * Does what bs_solve does, with the same kernels and results, but the solve
+ * workspace is a static device array of the library (BS_NOALLOC_SCRATCH_BYTES
+ * on every GPU that loads the library, held until the process ends) instead
+ * of a buffer of the caller.  The caller still passes the grid (built in its
+ * own workspace), the inputs and the outputs y and stats.  The call allocates
+ * nothing (no hipMalloc, hipFree or allocating library routine): the array's
+ * device address is looked up once per device, on the first call there.
+ *  - params->check_every must be 0: the call only enqueues and never waits
+ *    (BS_EINVAL otherwise);
+ *  - BS_EUNSUPPORTED when bs_solve_workspace_bytes(grid, C) exceeds
+ *    BS_NOALLOC_SCRATCH_BYTES (e.g. 64 MiB holds one channel of a 1024 x 768
+ *    image, or three of a 512 x 512 one), and while kernel timing is enabled
+ *    (timing records events);
+ *  - every call on one GPU uses that GPU's one array, which keeps the last
+ *    call's contents.  Nothing in it needs clearing (a solve writes every
+ *    workspace byte before reading it), but calls whose work overlaps on one
+ *    GPU (several streams, or several host threads) race on it and give
+ *    undefined results: order them on one stream, or with events. */
+bs_status bs_solve_noalloc(const bs_grid* grid, const float* target, const float* conf,
+                           int32_t C, const bs_solve_params* params, float* y,
+                           bs_chan_stats* stats, void* stream);
+
+/* ---------------------------------------------------------------------- */
 /* Robust solver: supplement Section Robustness, Algorithm RBS.            */
 /* ---------------------------------------------------------------------- */
 

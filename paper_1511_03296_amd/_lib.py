@@ -18,6 +18,7 @@ BS_MAX_CHANNELS = 64
 BS_MAX_LEVELS = 24
 BS_GRID_BYTES = 4096
 BS_INIT_FLAT, BS_INIT_HIER = 0, 1
+BS_NOALLOC_SCRATCH_BYTES = 64 << 20
 
 # Slots of the device counter array.
 CNT_V, CNT_K, CNT_BIST_ITERS, CNT_BIST_DONE, CNT_BIST_SRC, CNT_LEVEL0 = 0, 1, 2, 3, 4, 8
@@ -96,6 +97,8 @@ _SIGS = {
     "bs_solve_workspace_bytes": (_sz, [ct.POINTER(Grid), _i32]),
     "bs_solve": (_i32, [ct.POINTER(Grid), _vp, _vp, _i32, ct.POINTER(SolveParams), _vp, _vp,
                         _sz, _vp, _vp]),
+    "bs_solve_noalloc": (_i32, [ct.POINTER(Grid), _vp, _vp, _i32, ct.POINTER(SolveParams), _vp,
+                                _vp, _vp]),
     "bs_slice": (_i32, [ct.POINTER(Grid), _vp, _i32, _vp, _vp]),
     "bs_robust_workspace_bytes": (_sz, [ct.POINTER(Grid), _i32]),
     "bs_lowrank_workspace_bytes": (_sz, [ct.POINTER(Grid), _i32]),

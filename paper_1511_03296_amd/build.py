@@ -20,7 +20,7 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libbsolve.so")
 SOURCES = ["bs_grid.hip", "bs_bistoch.hip", "bs_solve.hip", "bs_batch.hip", "bs_robust.hip",
-           "bs_lowrank.hip", "bs_timing.hip"]
+           "bs_lowrank.hip", "bs_timing.hip", "bs_noalloc.hip"]
 
 ARCH = "gfx950"
 HIPCC = os.environ.get("HIPCC", shutil.which("hipcc") or "/opt/rocm/bin/hipcc")
