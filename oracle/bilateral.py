@@ -48,6 +48,9 @@ Readings of passages where the paper is silent or ambiguous:
       (e.g. a confidence-weighted upstream gradient), g there is what PCG
       keeps of its initial state.  The forward solve is always defined
       (b = 0 there).
+  R22 hierarchical preconditioner: a pyramid coefficient whose P(diag A) is 0
+      (every level-0 vertex below it has a zero diagonal: no neighbours and no
+      confidence) contributes 0, as the Jacobi inverse does where diag(A) = 0.
 """
 from __future__ import annotations
 
@@ -314,6 +317,27 @@ def level_weights(pyr: Pyramid, alpha: float, beta: float) -> list:
     return [1.0] + [float(alpha) ** (-(beta + k)) for k in range(1, pyr.K + 1)]
 
 
+class HierPrecond:
+    """M_hier^-1(r) = P^T(w o P(1) o P(r) / P(diag A))  (Section 4,
+    Eq. hier_precond): lift r into pyramid space, scale every coefficient by
+    its level weight times the number of vertices under it over the sum of
+    diag(A) under it, collapse.  At level 0 the scaling is 1 / diag(A), so
+    large alpha or beta leave the Jacobi preconditioner.  A coefficient with
+    P(diag A) = 0 contributes 0 (R22).  P^T D P with D >= 0 diagonal:
+    symmetric positive semi-definite."""
+
+    def __init__(self, pyr: Pyramid, diag: np.ndarray, alpha: float = 2.0, beta: float = 5.0):
+        self.pyr = pyr
+        w = level_weights(pyr, alpha, beta)
+        self.scale = []
+        for k, (pd, o) in enumerate(zip(lift(pyr, diag), pyr.ones)):
+            self.scale.append(np.where(pd > 0, w[k] * o / np.where(pd > 0, pd, 1.0), 0.0))
+
+    def __call__(self, r: np.ndarray) -> np.ndarray:
+        z = [s * pr for s, pr in zip(self.scale, lift(self.pyr, r))]
+        return collapse(self.pyr, z)
+
+
 def hier_init(pyr: Pyramid, b: np.ndarray, sc: np.ndarray, alpha: float = 4.0,
               beta: float = 0.0) -> np.ndarray:
     """Push-pull init  P^T(w P(b) / P(1)) / P^T(w P(Sc) / P(1))  (Section 4)."""
@@ -343,16 +367,19 @@ class PCGResult:
     energy: list = field(default_factory=list)     # 1/2 y^T A y - b^T y per iterate
 
 
-def pcg(A, b: np.ndarray, y0: np.ndarray, minv: np.ndarray, max_iters: int,
+def pcg(A, b: np.ndarray, y0: np.ndarray, minv, max_iters: int,
         rel_tol: float, track_energy: bool = False) -> PCGResult:
-    """Shewchuk's PCG (B3) on one right-hand side, with the stopping rule R10."""
+    """Shewchuk's PCG (B3) on one right-hand side, with the stopping rule R10.
+    `minv` is the Jacobi inverse (a vector, applied element-wise) or a
+    preconditioner applied as a function (HierPrecond)."""
+    apply_m = minv if callable(minv) else (lambda r: minv * r)
     y = np.array(y0, np.float64)
     b = np.asarray(b, np.float64)
     bnorm = float(np.sqrt(b @ b))
     if bnorm == 0.0:
         return PCGResult(y, 0, 0.0, 0.0)
     r = b - A(y)
-    d = minv * r
+    d = apply_m(r)
     rho = float(r @ d)
     res = float(np.sqrt(r @ r)) / bnorm
     out = PCGResult(y, 0, res, 0.0, [res])
@@ -367,7 +394,7 @@ def pcg(A, b: np.ndarray, y0: np.ndarray, minv: np.ndarray, max_iters: int,
         alpha = rho / dq
         y = y + alpha * d
         r = r - alpha * q
-        s = minv * r
+        s = apply_m(r)
         rho_old, rho = rho, float(r @ s)
         beta = rho / rho_old
         d = s + beta * d
@@ -399,6 +426,9 @@ class Params:
     init: str = "hier"            # "hier" | "flat"
     init_alpha: float = 4.0
     init_beta: float = 0.0
+    precond: str = "jacobi"       # "jacobi" | "hier"
+    pre_alpha: float = 2.0
+    pre_beta: float = 5.0
     bist_tol: float = 1e-10
     bist_max_iters: int = 200
 
@@ -416,6 +446,7 @@ class Solution:
     y: np.ndarray                 # [V][C]
     x: np.ndarray                 # [C][H][W]
     runs: list                    # PCGResult per channel
+    pre: object = None            # the preconditioner PCG applied (minv or a HierPrecond)
 
 
 def initial_state(sol_pyr: Pyramid, b: np.ndarray, sc: np.ndarray, p: Params) -> np.ndarray:
@@ -447,12 +478,22 @@ def solve(ref: np.ndarray, target: np.ndarray, conf: np.ndarray, p: Params,
     b = np.stack([splat(g, c * t[ch]) for ch in range(C)], axis=1)
     A = Operator(g, bs.n, sc, p.lam)
     minv = A.jacobi_inverse()
+    pre = preconditioner(pyr, A, minv, p)
     y0 = initial_state(pyr, b, sc, p)
-    runs = [pcg(A, b[:, ch], y0[:, ch], minv, p.max_iters, p.rel_tol, track_energy)
+    runs = [pcg(A, b[:, ch], y0[:, ch], pre, p.max_iters, p.rel_tol, track_energy)
             for ch in range(C)]
     y = np.stack([r.y for r in runs], axis=1)
     x = np.stack([slice_(g, y[:, ch]) for ch in range(C)]).reshape(C, g.H, g.W)
-    return Solution(g, bs, pyr, A, minv, sc, b, y0, y, x, runs)
+    return Solution(g, bs, pyr, A, minv, sc, b, y0, y, x, runs, pre)
+
+
+def preconditioner(pyr: Pyramid, A: Operator, minv: np.ndarray, p: Params):
+    """The Jacobi inverse, or M_hier^-1 with (pre_alpha, pre_beta) (Section 4)."""
+    if p.precond == "jacobi":
+        return minv
+    if p.precond == "hier":
+        return HierPrecond(pyr, A.diag(), p.pre_alpha, p.pre_beta)
+    raise ValueError("precond must be 'jacobi' or 'hier'")
 
 
 @dataclass
@@ -509,7 +550,8 @@ def solve_backward(sol: Solution, target: np.ndarray, conf: np.ndarray,
         raise ValueError("A g = S dL/dx has no solution: dL/dx does not vanish on a connected "
                          "component of the grid without confidence (R21)")
     u0 = initial_state(sol.pyr, u, sol.sc, p)
-    runs = [pcg(sol.A, u[:, ch], u0[:, ch], sol.minv, p.max_iters, p.rel_tol)
+    pre = preconditioner(sol.pyr, sol.A, sol.minv, p)
+    runs = [pcg(sol.A, u[:, ch], u0[:, ch], pre, p.max_iters, p.rel_tol)
             for ch in range(C)]
     gb = np.stack([r.y for r in runs], axis=1)
     grad_t = np.empty_like(t)
@@ -624,12 +666,12 @@ def solve_lowrank(ref: np.ndarray, target: np.ndarray, conf: np.ndarray, p: Para
     B = np.stack([splat(g, c * t[ch]) for ch in range(C)], axis=1)
     lr = lowrank_reduce(B, eps)
     A = Operator(g, bs.n, sc, p.lam)
-    minv = A.jacobi_inverse()
+    pre = preconditioner(pyr, A, A.jacobi_inverse(), p)
     runs = []
     Z = np.zeros((g.V, lr.rank))
     if lr.rank:
         Z0 = initial_state(pyr, lr.Q, sc, p)
-        runs = [pcg(A, lr.Q[:, j], Z0[:, j], minv, p.max_iters, p.rel_tol)
+        runs = [pcg(A, lr.Q[:, j], Z0[:, j], pre, p.max_iters, p.rel_tol)
                 for j in range(lr.rank)]
         Z = np.stack([r.y for r in runs], axis=1)
     Y = Z @ lr.R if lr.rank else np.zeros((g.V, C))

@@ -58,3 +58,69 @@ def a_literal(m: np.ndarray, n: np.ndarray, B: np.ndarray, sc: np.ndarray, lam: 
 def solve_dense(A: np.ndarray, b: np.ndarray) -> np.ndarray:
     """Minimum-norm least-squares solution of A y = b (exact for invertible A)."""
     return np.linalg.lstsq(A, b, rcond=None)[0]
+
+
+# ----------------------------------------------------------------------------
+# Bilateral pyramid (supplement Section 2) as explicit matrices
+# ----------------------------------------------------------------------------
+
+def pyramid_splat_matrices(coords: np.ndarray) -> list:
+    """[S_0, S_1, ..., S_{K-1}]: S_k maps level-k vertices to level k+1, where
+    level k+1's vertices are the distinct coordinates of level k halved (floor),
+    until a single vertex remains.  Built by brute force: every level-k vertex
+    is compared with every distinct halved coordinate.  The order of a level's
+    vertices is that of Python's sorted tuples, unrelated to any other code."""
+    level = [tuple(int(x) for x in c) for c in coords]
+    mats = []
+    while len(level) > 1:
+        halves = [tuple(x >> 1 for x in c) for c in level]
+        nxt = sorted(set(halves))
+        S = np.zeros((len(nxt), len(level)))
+        for j, h in enumerate(halves):
+            for i, u in enumerate(nxt):
+                if u == h:
+                    S[i, j] = 1.0
+        mats.append(S)
+        level = nxt
+    return mats
+
+
+def pyramid_lift_matrices(coords: np.ndarray) -> list:
+    """[M_0 = I, M_1 = S_0, M_2 = S_1 S_0, ...]: block k of the stacked P."""
+    V = coords.shape[0]
+    out = [np.eye(V)]
+    for S in pyramid_splat_matrices(coords):
+        out.append(S @ out[-1])
+    return out
+
+
+def hier_init_dense(coords: np.ndarray, b: np.ndarray, sc: np.ndarray, alpha: float,
+                    beta: float) -> np.ndarray:
+    """y_hier = P^T(w o P(b) / P(1)) / P^T(w o P(S c) / P(1)) (Section 4) with
+    the stacked P of pyramid_lift_matrices and w = 1 at k = 0, alpha^-(beta+k)
+    at k >= 1."""
+    Ms = pyramid_lift_matrices(coords)
+    ones = np.ones(coords.shape[0])
+    num = np.zeros(coords.shape[0])
+    den = np.zeros(coords.shape[0])
+    for k, M in enumerate(Ms):
+        w = 1.0 if k == 0 else float(alpha) ** (-(beta + k))
+        cnt = M @ ones
+        num += M.T @ (w * (M @ b) / cnt)
+        den += M.T @ (w * (M @ sc) / cnt)
+    return num / den
+
+
+def hier_precond_dense(coords: np.ndarray, diag: np.ndarray, alpha: float,
+                       beta: float) -> np.ndarray:
+    """M_hier^-1 = P^T D P as a dense V x V matrix (Section 4, Eq. hier_precond),
+    D = diag(w o P(1) / P(diag A)), with a zero weight where P(diag A) = 0."""
+    Ms = pyramid_lift_matrices(coords)
+    ones = np.ones(coords.shape[0])
+    out = np.zeros((coords.shape[0], coords.shape[0]))
+    for k, M in enumerate(Ms):
+        w = 1.0 if k == 0 else float(alpha) ** (-(beta + k))
+        pd = M @ diag
+        scale = np.where(pd > 0, w * (M @ ones) / np.where(pd > 0, pd, 1.0), 0.0)
+        out += M.T @ (scale[:, None] * M)
+    return out

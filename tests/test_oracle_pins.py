@@ -322,6 +322,139 @@ def test_hier_init_reduces_iterations():
     assert its["hier"] < its["flat"]
 
 
+def _hand_grid(coords):
+    """A grid whose level-0 vertices have the given (y, x, l, u, v) coordinates
+    (ascending key order), one pixel each."""
+    coords = np.asarray(coords, np.int64)
+    keys = O.pack_key(coords)
+    assert np.all(np.diff(keys) > 0)
+    V = coords.shape[0]
+    return O.Grid(1, V, keys, coords, np.arange(V), np.ones(V, np.int64),
+                  O.neighbours(keys, coords))
+
+
+def test_hier_init_hand_computed_two_levels():
+    """Two vertices under one coarse vertex (K = 1), alpha = 4, beta = 0, by hand
+    from the Section 4 formula: w_1 = 4^-1, P(1) = (1, 1 | 2),
+    y_v = (b_v + w_1 (b_0 + b_1) / 2) / (s_v + w_1 (s_0 + s_1) / 2)."""
+    g = _hand_grid([(0, 0, 0, 0, 0), (0, 1, 0, 0, 0)])
+    pyr = O.build_pyramid(g)
+    assert pyr.sizes == [2, 1]
+    b, sc = np.array([2.0, 3.0]), np.array([1.0, 0.5])
+    y = O.hier_init(pyr, b, sc, alpha=4.0, beta=0.0)
+    # 2 + 5/8 over 1 + 3/16, and 3 + 5/8 over 1/2 + 3/16
+    want = [Fraction(21, 8) / Fraction(19, 16), Fraction(29, 8) / Fraction(11, 16)]
+    assert np.allclose(y, [float(w) for w in want], rtol=1e-15, atol=0)
+
+
+def test_hier_init_hand_computed_three_levels():
+    """Three vertices: v0, v1 share a level-1 vertex, v2 has its own; level 2
+    is the top (K = 2).  alpha = 2, beta = 0: w = (1, 1/2, 1/4); P(1) at level 1
+    is (2, 1), at level 2 it is 3.  b = (1, 0, 4), S c = (1, 0, 2), by hand:
+    y_0 = (1 + 1/4 + 5/12) / (1 + 1/4 + 1/4)   = 10/9,
+    y_1 = (0 + 1/4 + 5/12) / (0 + 1/4 + 1/4)   = 4/3,
+    y_2 = (4 + 2 + 5/12)   / (2 + 1 + 1/4)     = 77/39."""
+    g = _hand_grid([(0, 0, 0, 0, 0), (0, 1, 0, 0, 0), (0, 2, 0, 0, 0)])
+    pyr = O.build_pyramid(g)
+    assert pyr.sizes == [3, 2, 1]
+    assert pyr.ones[1].tolist() == [2.0, 1.0] and pyr.ones[2].tolist() == [3.0]
+    y = O.hier_init(pyr, np.array([1.0, 0.0, 4.0]), np.array([1.0, 0.0, 2.0]), alpha=2.0,
+                    beta=0.0)
+    want = [Fraction(10, 9), Fraction(4, 3), Fraction(77, 39)]
+    assert np.allclose(y, [float(w) for w in want], rtol=1e-15, atol=0)
+
+
+@pytest.mark.parametrize("seed,alpha,beta", [(0, 4.0, 0.0), (1, 2.0, 1.0), (2, 1.5, 0.0)])
+def test_hier_init_equals_the_dense_pyramid_formula(seed, alpha, beta):
+    """hier_init (lift and collapse by parent maps) against the Section 4 formula
+    evaluated with explicit pyramid matrices built by brute-force halving of
+    the vertex coordinates (supplement Section 2), at finite alpha."""
+    p = tiny(seed=seed, H=12, W=16, regions=4, sigma=(3, 40, 40))
+    g = O.build_grid(p.ref, p.sigma_xy, p.sigma_l, p.sigma_uv)
+    pyr = O.build_pyramid(g)
+    assert pyr.K >= 3
+    c = p.conf.reshape(-1).astype(float)
+    c[::5] = 0.0
+    t = p.target[0].reshape(-1).astype(float)
+    sc, b = O.splat(g, c), O.splat(g, c * t)
+    want = D.hier_init_dense(g.coords, b, sc, alpha, beta)
+    got = O.hier_init(pyr, b, sc, alpha=alpha, beta=beta)
+    assert np.allclose(got, want, rtol=1e-12, atol=0)
+
+
+def test_hier_precond_hand_computed_and_limits():
+    """M_hier^-1 (Section 4, Eq. hier_precond) on the three-vertex pyramid, by
+    hand with alpha = 2, beta = 0 (w = 1, 1/2, 1/4), diag(A) = (1, 2, 4),
+    r = (1, 1, 1): the level-1 scalings are w_1 P(1)/P(diag) = (1/2)(2/3),
+    (1/2)(1/4) and the top's (1/4)(3/7), so
+    z_0 = 1 + 2/3 * 2 ... written out below; large alpha gives Jacobi."""
+    g = _hand_grid([(0, 0, 0, 0, 0), (0, 1, 0, 0, 0), (0, 2, 0, 0, 0)])
+    pyr = O.build_pyramid(g)
+    diag = np.array([1.0, 2.0, 4.0])
+    r = np.array([1.0, 1.0, 1.0])
+    M = O.HierPrecond(pyr, diag, alpha=2.0, beta=0.0)
+    s1 = [Fraction(1, 2) * Fraction(2, 3), Fraction(1, 2) * Fraction(1, 4)]
+    s2 = Fraction(1, 4) * Fraction(3, 7)
+    top = s2 * 3                      # P(r) at the top is 3
+    z = [1 + s1[0] * 2 + top,         # P(r) at v0's level-1 vertex is 2
+         Fraction(1, 2) + s1[0] * 2 + top,
+         Fraction(1, 4) + s1[1] * 1 + top]
+    assert np.allclose(M(r), [float(v) for v in z], rtol=1e-15, atol=0)
+    big = O.HierPrecond(pyr, diag, alpha=1e30, beta=0.0)
+    assert np.allclose(big(np.array([3.0, -1.0, 2.0])), [3.0, -0.5, 0.5], rtol=1e-14)
+    # a zero diagonal gives a zero coefficient, not a division by zero (R22)
+    Mz = O.HierPrecond(pyr, np.array([0.0, 0.0, 4.0]), alpha=2.0, beta=0.0)
+    assert np.all(np.isfinite(Mz(r)))
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_hier_precond_equals_dense_and_is_spd(seed):
+    """The matrix-free M_hier^-1 equals P^T D P built from brute-force pyramid
+    matrices; it is symmetric positive definite where diag(A) > 0, and PCG with
+    it reaches the dense solution."""
+    p = tiny(seed=seed, H=12, W=16, regions=4, sigma=(3, 40, 40), C=1)
+    prm = params_of(p, precond="hier", pre_alpha=2.0, pre_beta=1.0)
+    g, bs, pyr, S, B, Wh, Alit = dense_problem(p, prm)
+    sol = O.solve(p.ref, p.target, p.conf, prm, prepared=(g, bs, pyr))
+    Md = D.hier_precond_dense(g.coords, sol.A.diag(), 2.0, 1.0)
+    rng = np.random.default_rng(seed)
+    for _ in range(3):
+        r = rng.normal(size=g.V)
+        assert np.allclose(sol.pre(r), Md @ r, rtol=1e-12, atol=1e-14)
+    assert np.allclose(Md, Md.T, rtol=0, atol=1e-14)
+    assert np.linalg.eigvalsh(Md).min() > 0
+    y = D.solve_dense(Alit, sol.b[:, 0])
+    assert np.linalg.norm(sol.y[:, 0] - y) <= 1e-9 * np.linalg.norm(y)
+
+
+def test_hier_precond_reduces_iterations():
+    """The hierarchical preconditioner (alpha = 2, beta = 5) reaches 1e-5 in
+    fewer PCG iterations than Jacobi on a sparse-confidence interpolation
+    problem (Section 4, Fig. precon_init), to the same solution."""
+    p = WL.depth_superres(H=192, W=256, regions=30)
+    its, ys = {}, {}
+    for pre in ("jacobi", "hier"):
+        prm = O.Params(p.sigma_xy, p.sigma_l, p.sigma_uv, p.lam, max_iters=20000,
+                       rel_tol=1e-8, precond=pre)
+        sol = O.solve(p.ref, p.target, p.conf, prm)
+        its[pre] = sol.runs[0].iters
+        ys[pre] = sol.y[:, 0]
+    assert its["hier"] < its["jacobi"]
+    # the solution is unique on the grid components that carry confidence
+    from scipy.sparse import coo_matrix
+    from scipy.sparse.csgraph import connected_components
+    g = sol.grid
+    ok = g.nbr >= 0
+    rows = np.concatenate([np.nonzero(ok[j])[0] for j in range(10)])
+    cols = np.concatenate([g.nbr[j][ok[j]] for j in range(10)])
+    _, lab = connected_components(coo_matrix((np.ones(rows.size), (rows, cols)),
+                                             shape=(g.V, g.V)), directed=False)
+    live = (np.bincount(lab, weights=sol.sc) > 0)[lab]
+    assert live.sum() > 0.5 * g.V
+    d = ys["hier"][live] - ys["jacobi"][live]
+    assert np.linalg.norm(d) <= 1e-5 * np.linalg.norm(ys["jacobi"][live])
+
+
 # --------------------------------------------------------------------------
 # PCG behaviour (supplement Algorithm 2)
 # --------------------------------------------------------------------------
