@@ -231,6 +231,37 @@ __device__ inline int partial_slot(int j, int nb) {
 }
 __device__ inline int partial_slot() { return partial_slot(blockIdx.x, gridDim.x); }
 
+// ---------------------------------------------------------------------------
+// Launches over one image or over a table of images.
+//
+// A kernel body is an Op: a struct with its per-image arguments Args, its
+// block size kThreads and run(args, j, nb, arg), which does block j of the
+// nb blocks working on one image (`arg`: a scalar of the launch, the same for
+// every image, e.g. an iteration number).  one_launch runs an Op over one
+// image (j = blockIdx.x, nb = gridDim.x); multi_launch runs it over a table
+// of images, every block finding its image and its place among that image's
+// blocks in a schedule.  So the single-image calls and the batch engine run
+// the same code.
+// ---------------------------------------------------------------------------
+struct Sched {
+    const int32_t* blk2img;   // [G] table index of each block's image, -1: idle block
+    const int32_t* block0;    // [n] first block of each image
+    const int32_t* nb;        // [n] blocks of each image
+};
+
+template <class Op>
+__global__ void __launch_bounds__(Op::kThreads) one_launch(typename Op::Args a, int arg) {
+    Op::run(a, (int)blockIdx.x, (int)gridDim.x, arg);
+}
+
+template <class Op>
+__global__ void __launch_bounds__(Op::kThreads)
+    multi_launch(const typename Op::Args* __restrict__ tab, Sched s, int arg) {
+    const int i = s.blk2img[blockIdx.x];
+    if (i < 0) return;
+    Op::run(tab[i], (int)blockIdx.x - s.block0[i], s.nb[i], arg);
+}
+
 __device__ inline double wave_sum(double v) {
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
     return v;

@@ -1,0 +1,563 @@
+// Kernel bodies of the per-image stages around the PCG: the splat of the
+// right-hand side with diag(A) and its Jacobi inverse (Eq. quad_min, the
+// Jacobi preconditioner of Section 4), the flat and hierarchical initial
+// states (Section 4, supplement Section 2), the slice (Eq. solution) and the
+// gradient scatter (Section 3).  They are Ops: the single-image entry points
+// run them through one_launch, the batch engine through multi_launch.
+#pragma once
+
+#include "bs_solve_impl.h"
+
+namespace bs {
+
+// ---------------------------------------------------------------------------
+// Splat.
+// ---------------------------------------------------------------------------
+
+// Output arrays of the splat of one image.
+struct SplatOut {
+    float* sc;       // [V] S c
+    float* diag;     // [V] diag(A)
+    float* minv;     // [V] 1 / diag(A), 0 where diag(A) <= 0
+    float2* nfm;     // [V] {n, 1 / diag(A)}
+    float* b;        // [V][Cp] right-hand side
+};
+
+// S c, b = S (c o t) (or S t when `weighted` is false) as ascending-pixel sums
+// in float64, diag(A) = lam n o (N n) + S c with its Jacobi inverse, and the
+// packed per-vertex scalars {n, 1 / diag(A)} of the PCG kernels.  b has
+// stride Cp; channels C..Cp-1 are zero.  One thread per vertex.
+template <bool WEIGHTED>
+struct SplatVertex {
+    static constexpr int kThreads = kBlock;
+    struct Args {
+        const int32_t* ptr;
+        const int32_t* list;
+        const float* conf;
+        const float* vals;
+        const double* nn;
+        const float* nf;
+        const int32_t* counts;
+        SplatOut o;
+        double lam;
+        int C, Cp, P;
+    };
+    __device__ static void run(const Args& a, int jb, int nb, int) {
+        const int32_t* __restrict__ ptr = a.ptr;
+        const int32_t* __restrict__ list = a.list;
+        const float* __restrict__ conf = a.conf;
+        const float* __restrict__ vals = a.vals;
+        float* __restrict__ b = a.o.b;
+        const int C = a.C, Cp = a.Cp, P = a.P;
+        const int V = a.counts[CNT_V];
+        const XcdTiles tl((V + kBlock - 1) / kBlock, jb, nb);
+        for (int64_t tile = tl.first; tile < tl.end; tile += tl.step) {
+            const int v = (int)(tile * kBlock) + threadIdx.x;
+            if (v >= V) continue;
+            const int s = ptr[v], e = ptr[v + 1];
+            double sc = 0.0;
+            for (int j = s; j < e; ++j) sc += (double)conf[list[j]];
+            for (int c0 = 0; c0 < C; c0 += 8) {
+                double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+                const int cn = min(8, C - c0);
+                for (int j = s; j < e; ++j) {
+                    const int p = list[j];
+                    const double w = WEIGHTED ? (double)conf[p] : 1.0;
+#pragma unroll
+                    for (int k = 0; k < 8; ++k)
+                        if (k < cn) acc[k] += w * (double)vals[(int64_t)(c0 + k) * P + p];
+                }
+#pragma unroll
+                for (int k = 0; k < 8; ++k)
+                    if (k < cn) b[(int64_t)v * Cp + c0 + k] = (float)acc[k];
+            }
+            for (int c = C; c < Cp; ++c) b[(int64_t)v * Cp + c] = 0.0f;
+            const double d = a.lam * a.nn[v] + sc;
+            const float mi = d > 0.0 ? (float)(1.0 / d) : 0.0f;
+            a.o.sc[v] = (float)sc;
+            a.o.diag[v] = (float)d;
+            a.o.minv[v] = mi;
+            a.o.nfm[v] = make_float2(a.nf[v], mi);
+        }
+    }
+};
+
+// The same sums computed per spatial cell of the grid (block c: cell c):
+// every pixel of a cell lies on one of the cell's vertices, so a block stages
+// the cell's pixels in LDS with coalesced row loads and each (vertex,
+// channel) thread sums its own pixels, in ascending pixel order, from LDS.
+// CAP bounds the cell's pixels.
+constexpr int kSplatVals = 4096;   // floats of staged values per channel chunk
+
+template <int B, int CAP, bool WEIGHTED>
+struct SplatCells {
+    static constexpr int kThreads = B;
+    struct Args {
+        const int32_t* cell_vbase;
+        const int32_t* cell_ibase;
+        const int32_t* ptr;
+        const int32_t* list;
+        const float* conf;
+        const float* vals;
+        const double* nn;
+        const float* nf;
+        SplatOut o;
+        double lam;
+        int H, W, sxy, ncx, C, Cp, P;
+    };
+    __device__ static void run(const Args& a, int c, int, int) {
+        __shared__ float cv[CAP];
+        __shared__ int32_t lst[CAP];
+        __shared__ float tv[kSplatVals];
+        const int32_t* __restrict__ ptr = a.ptr;
+        const float* __restrict__ vals = a.vals;
+        float* __restrict__ b = a.o.b;
+        const int H = a.H, W = a.W, sxy = a.sxy, ncx = a.ncx, C = a.C, Cp = a.Cp, P = a.P;
+        const int cy = c / ncx, cx = c - cy * ncx;
+        const int y0 = cell_lo(cy, sxy), y1 = min(cell_lo(cy + 1, sxy), H);
+        const int x0 = cell_lo(cx, sxy), x1 = min(cell_lo(cx + 1, sxy), W);
+        const int wx = x1 - x0, n = (y1 - y0) * wx;
+        const int vbase = a.cell_vbase[c], cnt = a.cell_vbase[c + 1] - vbase;
+        const int ibase = a.cell_ibase[c];
+        for (int j = threadIdx.x; j < n; j += B) {
+            const int r = j / wx;
+            cv[j] = a.conf[(y0 + r) * W + x0 + (j - r * wx)];
+            const int pq = a.list[ibase + j];
+            const int py = pq / W;
+            lst[j] = (py - y0) * wx + (pq - py * W - x0);
+        }
+        __syncthreads();
+        for (int k = threadIdx.x; k < cnt; k += B) {
+            const int s0 = ptr[vbase + k] - ibase, s1 = ptr[vbase + k + 1] - ibase;
+            double sc = 0.0;
+            for (int q = s0; q < s1; ++q) sc += (double)cv[lst[q]];
+            const double d = a.lam * a.nn[vbase + k] + sc;
+            const float mi = d > 0.0 ? (float)(1.0 / d) : 0.0f;
+            a.o.sc[vbase + k] = (float)sc;
+            a.o.diag[vbase + k] = (float)d;
+            a.o.minv[vbase + k] = mi;
+            a.o.nfm[vbase + k] = make_float2(a.nf[vbase + k], mi);
+        }
+        const int CH = max(1, min(C, kSplatVals / max(n, 1)));
+        for (int c0 = 0; c0 < C; c0 += CH) {
+            const int cn = min(CH, C - c0);
+            __syncthreads();
+            for (int e = threadIdx.x; e < cn * n; e += B) {
+                const int cc = e / n, j = e - cc * n;
+                const int r = j / wx;
+                tv[cc * n + j] = vals[(int64_t)(c0 + cc) * P + (y0 + r) * W + x0 + (j - r * wx)];
+            }
+            __syncthreads();
+            for (int e = threadIdx.x; e < cnt * cn; e += B) {
+                const int k = e / cn, cc = e - k * cn;
+                const int s0 = ptr[vbase + k] - ibase, s1 = ptr[vbase + k + 1] - ibase;
+                double acc = 0.0;
+                for (int q = s0; q < s1; ++q) {
+                    const int jl = lst[q];
+                    acc += WEIGHTED ? (double)cv[jl] * (double)tv[cc * n + jl]
+                                    : (double)tv[cc * n + jl];
+                }
+                b[(int64_t)(vbase + k) * Cp + c0 + cc] = (float)acc;
+            }
+        }
+        const int pad = Cp - C;
+        for (int e = threadIdx.x; e < cnt * pad; e += B) {
+            const int k = e / pad, cc = e - k * pad;
+            b[(int64_t)(vbase + k) * Cp + C + cc] = 0.0f;
+        }
+    }
+};
+
+// Which splat form an image takes: per cell while a cell's pixels (at most
+// sigma_xy^2) fit the LDS staging (kind 0, 1, 2: 64, 256, 1024 pixels), else
+// per vertex (kind 3).
+inline int splat_kind(int sigma_xy) {
+    const int items = sigma_xy * sigma_xy;
+    return items <= 64 ? 0 : (items <= 256 ? 1 : (items <= 1024 ? 2 : 3));
+}
+
+// ---------------------------------------------------------------------------
+// Initial state.
+// ---------------------------------------------------------------------------
+
+// Flat init: y = b / S c, 0 where S c = 0.
+struct FlatInit {
+    static constexpr int kThreads = kBlock;
+    struct Args {
+        const float* b;
+        const float* sc;
+        const int32_t* counts;
+        float* y;
+        int C;
+    };
+    __device__ static void run(const Args& a, int jb, int nb, int) {
+        const int C = a.C;
+        const int64_t n = (int64_t)a.counts[CNT_V] * C;
+        const XcdTiles tl((n + kBlock - 1) / kBlock, jb, nb);
+        for (int64_t tile = tl.first; tile < tl.end; tile += tl.step) {
+            const int64_t e = tile * kBlock + threadIdx.x;
+            if (e >= n) continue;
+            const float s = a.sc[e / C];
+            a.y[e] = s > 0.0f ? a.b[e] / s : 0.0f;
+        }
+    }
+};
+
+// Pyramid lift, level k >= 1: child sums of level k-1 for C channels of b and
+// S c (channel C).  up_k[u][ch] = sum over children of the child's value.
+struct PyrUp {
+    static constexpr int kThreads = kBlock;
+    struct Args {
+        const int32_t* cptr;
+        const int32_t* clist;
+        const float* b;
+        const float* sc;
+        const float* prev;   // level k-1's sums, nullptr at k = 1 (read b and S c)
+        float* up;
+        const int32_t* counts;
+        int C, level;
+    };
+    __device__ static void run(const Args& a, int jb, int nb, int) {
+        const int32_t* __restrict__ counts = a.counts;
+        const int level = a.level, C = a.C;
+        if (counts[CNT_K] < level) return;
+        const int Vk = counts[CNT_LEVEL0 + level];
+        const int C1 = C + 1;
+        const int64_t n = (int64_t)Vk * C1;
+        const float* __restrict__ prev = a.prev;
+        const XcdTiles tl((n + kBlock - 1) / kBlock, jb, nb);
+        for (int64_t tile = tl.first; tile < tl.end; tile += tl.step) {
+            const int64_t e = tile * kBlock + threadIdx.x;
+            if (e >= n) continue;
+            const int u = (int)(e / C1), ch = (int)(e - (int64_t)u * C1);
+            double s = 0.0;
+            for (int j = a.cptr[u]; j < a.cptr[u + 1]; ++j) {
+                const int c = a.clist[j];
+                if (prev) s += (double)prev[(int64_t)c * C1 + ch];
+                else s += (double)(ch < C ? a.b[(int64_t)c * C + ch] : a.sc[c]);
+            }
+            a.up[e] = (float)s;
+        }
+    }
+};
+
+// Pyramid collapse, level k >= 1 (top-down): acc_k = w_k P_k / P(1)_k + acc_{k+1}[parent].
+struct PyrDown {
+    static constexpr int kThreads = kBlock;
+    struct Args {
+        float* up;
+        const float* up_parent;
+        const int32_t* parent;
+        const int32_t* ones;
+        const int32_t* counts;
+        float wk;
+        int C, level;
+    };
+    __device__ static void run(const Args& a, int jb, int nb, int) {
+        const int K = a.counts[CNT_K];
+        const int level = a.level;
+        if (K < level) return;
+        const int Vk = a.counts[CNT_LEVEL0 + level];
+        const int C1 = a.C + 1;
+        const int64_t n = (int64_t)Vk * C1;
+        float* __restrict__ up = a.up;
+        const XcdTiles tl((n + kBlock - 1) / kBlock, jb, nb);
+        for (int64_t tile = tl.first; tile < tl.end; tile += tl.step) {
+            const int64_t e = tile * kBlock + threadIdx.x;
+            if (e >= n) continue;
+            const int u = (int)(e / C1), ch = (int)(e - (int64_t)u * C1);
+            float v = a.wk * up[e] / (float)a.ones[u];
+            if (level < K) v += a.up_parent[(int64_t)a.parent[u] * C1 + ch];
+            up[e] = v;
+        }
+    }
+};
+
+// The small top of the pyramid, levels k0 .. levels-1, in one block: the lift
+// bottom-up, then the collapse top-down, with the arithmetic of PyrUp and
+// PyrDown (the coarse levels would otherwise cost two launches each).
+constexpr int kSmallPyrElems = 16384;   // cap_k x (C + 1) of a level done in one block
+
+struct PyrLevels {
+    int k0, levels;
+    const int32_t* cptr[BS_MAX_LEVELS];    // level k: CSR of children (level k-1 vertices)
+    const int32_t* clist[BS_MAX_LEVELS];
+    const int32_t* ones[BS_MAX_LEVELS];
+    const int32_t* parent[BS_MAX_LEVELS];  // level k vertex -> level k+1 vertex
+    float* up[BS_MAX_LEVELS];
+    float wk[BS_MAX_LEVELS];
+};
+
+struct PyrSmall {
+    static constexpr int kThreads = 1024;
+    struct Args {
+        PyrLevels lv;
+        const float* b;
+        const float* sc;
+        const int32_t* counts;
+        int C;
+    };
+    __device__ static void run(const Args& A, int, int, int) {
+        const PyrLevels& a = A.lv;
+        const int K = A.counts[CNT_K];
+        const int C = A.C;
+        const int C1 = C + 1;
+        for (int k = a.k0; k < a.levels && k <= K; ++k) {
+            const int Vk = A.counts[CNT_LEVEL0 + k];
+            const float* prev = k >= 2 ? a.up[k - 1] : nullptr;
+            const int32_t* cptr = a.cptr[k];
+            const int32_t* clist = a.clist[k];
+            float* up = a.up[k];
+            const int64_t n = (int64_t)Vk * C1;
+            for (int64_t e = threadIdx.x; e < n; e += kThreads) {
+                const int u = (int)(e / C1), ch = (int)(e - (int64_t)u * C1);
+                double s = 0.0;
+                for (int j = cptr[u]; j < cptr[u + 1]; ++j) {
+                    const int c = clist[j];
+                    if (prev) s += (double)prev[(int64_t)c * C1 + ch];
+                    else s += (double)(ch < C ? A.b[(int64_t)c * C + ch] : A.sc[c]);
+                }
+                up[e] = (float)s;
+            }
+            __syncthreads();
+        }
+        for (int k = a.levels - 1; k >= a.k0; --k) {
+            if (K < k) continue;
+            const int Vk = A.counts[CNT_LEVEL0 + k];
+            float* up = a.up[k];
+            const float* upp = (k < K) ? a.up[k + 1] : nullptr;
+            const int32_t* parent = a.parent[k];
+            const int32_t* ones = a.ones[k];
+            const float wk = a.wk[k];
+            const int64_t n = (int64_t)Vk * C1;
+            for (int64_t e = threadIdx.x; e < n; e += kThreads) {
+                const int u = (int)(e / C1), ch = (int)(e - (int64_t)u * C1);
+                float v = wk * up[e] / (float)ones[u];
+                if (upp) v += upp[(int64_t)parent[u] * C1 + ch];
+                up[e] = v;
+            }
+            __syncthreads();
+        }
+    }
+};
+
+// Level 0 of the collapse and the ratio of the two push-pull filters:
+// y0 = (b + acc_1[parent]) / (S c + acc_1[parent][C]), 0 where the
+// denominator is 0 (zero total confidence).
+struct HierFinal {
+    static constexpr int kThreads = kBlock;
+    struct Args {
+        const float* b;
+        const float* sc;
+        const float* up1;
+        const int32_t* parent0;
+        const int32_t* counts;
+        float* y;
+        int C;
+    };
+    __device__ static void run(const Args& a, int jb, int nb, int) {
+        const int K = a.counts[CNT_K];
+        const int C = a.C;
+        const int64_t n = (int64_t)a.counts[CNT_V] * C;
+        const int C1 = C + 1;
+        const XcdTiles tl((n + kBlock - 1) / kBlock, jb, nb);
+        for (int64_t tile = tl.first; tile < tl.end; tile += tl.step) {
+            const int64_t e = tile * kBlock + threadIdx.x;
+            if (e >= n) continue;
+            const int v = (int)(e / C), ch = (int)(e - (int64_t)v * C);
+            float num = a.b[e], den = a.sc[v];
+            if (K >= 1) {
+                const int64_t p = (int64_t)a.parent0[v] * C1;
+                num += a.up1[p + ch];
+                den += a.up1[p + C];
+            }
+            a.y[e] = den > 0.0f ? num / den : 0.0f;
+        }
+    }
+};
+
+// ---------------------------------------------------------------------------
+// Output.
+// ---------------------------------------------------------------------------
+
+// dst[v][c] = src[v][c] for c < C, src with stride Cp.
+struct Unpad {
+    static constexpr int kThreads = kBlock;
+    struct Args {
+        const float* src;
+        const int32_t* counts;
+        float* dst;
+        int Cp, C;
+    };
+    __device__ static void run(const Args& a, int jb, int nb, int) {
+        const int C = a.C;
+        const int64_t n = (int64_t)a.counts[CNT_V] * C;
+        const XcdTiles tl((n + kBlock - 1) / kBlock, jb, nb);
+        for (int64_t tile = tl.first; tile < tl.end; tile += tl.step) {
+            const int64_t e = tile * kBlock + threadIdx.x;
+            if (e >= n) continue;
+            const int64_t v = e / C;
+            a.dst[e] = a.src[v * a.Cp + (e - v * C)];
+        }
+    }
+};
+
+// x[c][p] = y[idx[p]][c].
+struct Slice {
+    static constexpr int kThreads = kBlock;
+    struct Args {
+        const int32_t* idx;
+        const float* y;
+        float* x;
+        int C, P;
+    };
+    __device__ static void run(const Args& a, int jb, int nb, int) {
+        const int C = a.C, P = a.P;
+        const XcdTiles tl((P + kBlock - 1) / kBlock, jb, nb);
+        for (int64_t tile = tl.first; tile < tl.end; tile += tl.step) {
+            const int p = (int)(tile * kBlock) + threadIdx.x;
+            if (p >= P) continue;
+            const int64_t v = a.idx[p];
+            for (int c = 0; c < C; ++c) a.x[(int64_t)c * P + p] = a.y[v * C + c];
+        }
+    }
+};
+
+// dL/dt[c][p] = conf[p] g[idx[p]][c];  dL/dconf[p] = sum_c g[idx][c] (t[c][p] - y[idx][c]).
+// g has stride Cg, y stride C.
+struct GradScatter {
+    static constexpr int kThreads = kBlock;
+    struct Args {
+        const int32_t* idx;
+        const float* g;
+        const float* yhat;
+        const float* target;
+        const float* conf;
+        float* gt;
+        float* gc;
+        int Cg, C, P;
+    };
+    __device__ static void run(const Args& a, int jb, int nb, int) {
+        const int C = a.C, P = a.P, Cg = a.Cg;
+        const XcdTiles tl((P + kBlock - 1) / kBlock, jb, nb);
+        for (int64_t tile = tl.first; tile < tl.end; tile += tl.step) {
+            const int p = (int)(tile * kBlock) + threadIdx.x;
+            if (p >= P) continue;
+            const int64_t v = a.idx[p];
+            const float cp = a.conf[p];
+            float s = 0.0f;
+            for (int c = 0; c < C; ++c) {
+                const float gv = a.g[v * Cg + c];
+                a.gt[(int64_t)c * P + p] = cp * gv;
+                s += gv * (a.target[(int64_t)c * P + p] - a.yhat[v * C + c]);
+            }
+            a.gc[p] = s;
+        }
+    }
+};
+
+// ---------------------------------------------------------------------------
+// Arguments of one image's launches.
+// ---------------------------------------------------------------------------
+// Arguments of the splat of image g into workspace w.
+template <bool WEIGHTED>
+typename SplatVertex<WEIGHTED>::Args splat_vertex_args(const GridImpl& g, const SolveWs& w,
+                                                       const float* conf, const float* vals,
+                                                       double lam) {
+    typename SplatVertex<WEIGHTED>::Args a;
+    a.ptr = g.lv[0].ptr;
+    a.list = g.lv[0].list;
+    a.conf = conf;
+    a.vals = vals;
+    a.nn = g.nn;
+    a.nf = g.nf;
+    a.counts = g.counts;
+    a.o = SplatOut{w.sc, w.diag, w.minv, w.nfm, w.b};
+    a.lam = lam;
+    a.C = w.C;
+    a.Cp = w.Cp;
+    a.P = g.P;
+    return a;
+}
+
+template <int B, int CAP, bool WEIGHTED>
+typename SplatCells<B, CAP, WEIGHTED>::Args splat_cells_args(const GridImpl& g, const SolveWs& w,
+                                                             const float* conf, const float* vals,
+                                                             double lam) {
+    const Level& L = g.lv[0];
+    typename SplatCells<B, CAP, WEIGHTED>::Args a;
+    a.cell_vbase = L.cell_vbase;
+    a.cell_ibase = L.cell_ibase;
+    a.ptr = L.ptr;
+    a.list = L.list;
+    a.conf = conf;
+    a.vals = vals;
+    a.nn = g.nn;
+    a.nf = g.nf;
+    a.o = SplatOut{w.sc, w.diag, w.minv, w.nfm, w.b};
+    a.lam = lam;
+    a.H = g.H;
+    a.W = g.W;
+    a.sxy = g.sg.sigma_xy;
+    a.ncx = L.ncx;
+    a.C = w.C;
+    a.Cp = w.Cp;
+    a.P = g.P;
+    return a;
+}
+
+// Arguments of the initial-state kernels of image g, workspace w (into y,
+// stride Cp), with the init level weights of p (alpha, beta).
+inline FlatInit::Args flat_init_args(const GridImpl& g, const SolveWs& w, float* y) {
+    return {w.b, w.sc, g.counts, y, w.Cp};
+}
+
+inline float level_weight(const bs_solve_params& p, int k) {
+    return (float)std::pow((double)p.init_alpha, -((double)p.init_beta + k));
+}
+
+inline PyrUp::Args pyr_up_args(const GridImpl& g, const SolveWs& w, int k) {
+    return {g.lv[k].ptr, g.lv[k].list, w.b, w.sc, k >= 2 ? w.up[k - 1] : nullptr, w.up[k],
+            g.counts, w.Cp, k};
+}
+
+inline PyrDown::Args pyr_down_args(const GridImpl& g, const SolveWs& w, const bs_solve_params& p, int k) {
+    const float* upp = (k + 1 < g.levels) ? w.up[k + 1] : nullptr;
+    const int32_t* par = (k + 1 < g.levels) ? g.lv[k + 1].item_parent : nullptr;
+    return {w.up[k], upp, par, g.lv[k].ones, g.counts, level_weight(p, k), w.Cp, k};
+}
+
+inline int small_pyr_level(const GridImpl& g, int C) {
+    int k0 = 1;
+    while (k0 < g.levels && g.lv[k0].cap * (C + 1) > kSmallPyrElems) ++k0;
+    return k0;
+}
+
+inline PyrSmall::Args pyr_small_args(const GridImpl& g, const SolveWs& w, const bs_solve_params& p,
+                              int k0) {
+    PyrSmall::Args A;
+    std::memset(&A, 0, sizeof(A));
+    PyrLevels& a = A.lv;
+    a.k0 = k0;
+    a.levels = g.levels;
+    for (int k = 1; k < g.levels; ++k) {
+        a.cptr[k] = g.lv[k].ptr;
+        a.clist[k] = g.lv[k].list;
+        a.ones[k] = g.lv[k].ones;
+        a.parent[k] = (k + 1 < g.levels) ? g.lv[k + 1].item_parent : nullptr;
+        a.up[k] = w.up[k];
+        a.wk[k] = level_weight(p, k);
+    }
+    A.b = w.b;
+    A.sc = w.sc;
+    A.counts = g.counts;
+    A.C = w.Cp;
+    return A;
+}
+
+inline HierFinal::Args hier_final_args(const GridImpl& g, const SolveWs& w, float* y) {
+    return {w.b, w.sc, g.levels > 1 ? w.up[1] : nullptr,
+            g.levels > 1 ? g.lv[1].item_parent : nullptr, g.counts, y, w.Cp};
+}
+
+}  // namespace bs

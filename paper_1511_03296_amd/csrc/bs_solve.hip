@@ -31,6 +31,7 @@
 // images of any sizes runs each PCG phase as one launch, every block working
 // on one image (a per-block image table), each image with its own channel
 // state, partials and stopping rule.
+#include "bs_setup_ops.h"
 #include "bs_solve_impl.h"
 #include <type_traits>
 
@@ -373,293 +374,30 @@ __device__ inline ChanState advance_state(const ChanState& st, double rr, double
 // Splat and initialisation (per image).
 // ---------------------------------------------------------------------------
 
-// S c, b = S (v o t) (or S t when `weighted` is false) as ascending-pixel sums
-// in float64, diag(A) = lam n o (N n) + S c with its Jacobi inverse, and the
-// packed per-vertex scalars {n, 1 / diag(A)} of the PCG kernels.  b has
-// stride Cp; channels C..Cp-1 are zero.
-template <bool WEIGHTED>
-__global__ void __launch_bounds__(kBlock) splat_kernel(
-    const int32_t* __restrict__ ptr, const int32_t* __restrict__ list,
-    const float* __restrict__ conf, const float* __restrict__ vals, int C, int Cp, int P,
-    const double* __restrict__ nn, const float* __restrict__ nf, double lam,
-    const int32_t* __restrict__ counts, float* __restrict__ sc_out, float* __restrict__ diag_out,
-    float* __restrict__ minv_out, float2* __restrict__ nfm, float* __restrict__ b) {
-    const int V = counts[CNT_V];
-    const XcdTiles tl((V + kBlock - 1) / kBlock);
-    for (int64_t tile = tl.first; tile < tl.end; tile += tl.step) {
-        const int v = (int)(tile * kBlock) + threadIdx.x;
-        if (v >= V) continue;
-        const int s = ptr[v], e = ptr[v + 1];
-        double sc = 0.0;
-        for (int j = s; j < e; ++j) sc += (double)conf[list[j]];
-        for (int c0 = 0; c0 < C; c0 += 8) {
-            double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-            const int cn = min(8, C - c0);
-            for (int j = s; j < e; ++j) {
-                const int p = list[j];
-                const double w = WEIGHTED ? (double)conf[p] : 1.0;
-#pragma unroll
-                for (int k = 0; k < 8; ++k)
-                    if (k < cn) acc[k] += w * (double)vals[(int64_t)(c0 + k) * P + p];
-            }
-#pragma unroll
-            for (int k = 0; k < 8; ++k)
-                if (k < cn) b[(int64_t)v * Cp + c0 + k] = (float)acc[k];
-        }
-        for (int c = C; c < Cp; ++c) b[(int64_t)v * Cp + c] = 0.0f;
-        const double d = lam * nn[v] + sc;
-        const float mi = d > 0.0 ? (float)(1.0 / d) : 0.0f;
-        sc_out[v] = (float)sc;
-        diag_out[v] = (float)d;
-        minv_out[v] = mi;
-        nfm[v] = make_float2(nf[v], mi);
-    }
-}
-
-// The same sums computed per spatial cell of the grid: every pixel of a cell
-// lies on one of the cell's vertices, so a block stages the cell's pixels in
-// LDS with coalesced row loads and each (vertex, channel) thread sums its own
-// pixels, in ascending pixel order, from LDS.  CAP bounds the cell's pixels.
-constexpr int kSplatVals = 4096;   // floats of staged values per channel chunk
-
-template <int B, int CAP, bool WEIGHTED>
-__global__ void __launch_bounds__(B) splat_cells(
-    int H, int W, int sxy, int ncx, const int32_t* __restrict__ cell_vbase,
-    const int32_t* __restrict__ cell_ibase, const int32_t* __restrict__ ptr,
-    const int32_t* __restrict__ list, const float* __restrict__ conf,
-    const float* __restrict__ vals, int C, int Cp, int P, const double* __restrict__ nn,
-    const float* __restrict__ nf, double lam, float* __restrict__ sc_out,
-    float* __restrict__ diag_out, float* __restrict__ minv_out, float2* __restrict__ nfm,
-    float* __restrict__ b) {
-    __shared__ float cv[CAP];
-    __shared__ int32_t lst[CAP];
-    __shared__ float tv[kSplatVals];
-    const int c = blockIdx.x;
-    const int cy = c / ncx, cx = c - cy * ncx;
-    const int y0 = cell_lo(cy, sxy), y1 = min(cell_lo(cy + 1, sxy), H);
-    const int x0 = cell_lo(cx, sxy), x1 = min(cell_lo(cx + 1, sxy), W);
-    const int wx = x1 - x0, n = (y1 - y0) * wx;
-    const int vbase = cell_vbase[c], cnt = cell_vbase[c + 1] - vbase, ibase = cell_ibase[c];
-    for (int j = threadIdx.x; j < n; j += B) {
-        const int r = j / wx;
-        cv[j] = conf[(y0 + r) * W + x0 + (j - r * wx)];
-        const int pq = list[ibase + j];
-        const int py = pq / W;
-        lst[j] = (py - y0) * wx + (pq - py * W - x0);
-    }
-    __syncthreads();
-    for (int k = threadIdx.x; k < cnt; k += B) {
-        const int s0 = ptr[vbase + k] - ibase, s1 = ptr[vbase + k + 1] - ibase;
-        double sc = 0.0;
-        for (int q = s0; q < s1; ++q) sc += (double)cv[lst[q]];
-        const double d = lam * nn[vbase + k] + sc;
-        const float mi = d > 0.0 ? (float)(1.0 / d) : 0.0f;
-        sc_out[vbase + k] = (float)sc;
-        diag_out[vbase + k] = (float)d;
-        minv_out[vbase + k] = mi;
-        nfm[vbase + k] = make_float2(nf[vbase + k], mi);
-    }
-    const int CH = max(1, min(C, kSplatVals / max(n, 1)));
-    for (int c0 = 0; c0 < C; c0 += CH) {
-        const int cn = min(CH, C - c0);
-        __syncthreads();
-        for (int e = threadIdx.x; e < cn * n; e += B) {
-            const int cc = e / n, j = e - cc * n;
-            const int r = j / wx;
-            tv[cc * n + j] = vals[(int64_t)(c0 + cc) * P + (y0 + r) * W + x0 + (j - r * wx)];
-        }
-        __syncthreads();
-        for (int e = threadIdx.x; e < cnt * cn; e += B) {
-            const int k = e / cn, cc = e - k * cn;
-            const int s0 = ptr[vbase + k] - ibase, s1 = ptr[vbase + k + 1] - ibase;
-            double acc = 0.0;
-            for (int q = s0; q < s1; ++q) {
-                const int jl = lst[q];
-                acc += WEIGHTED ? (double)cv[jl] * (double)tv[cc * n + jl] : (double)tv[cc * n + jl];
-            }
-            b[(int64_t)(vbase + k) * Cp + c0 + cc] = (float)acc;
-        }
-    }
-    const int pad = Cp - C;
-    for (int e = threadIdx.x; e < cnt * pad; e += B) {
-        const int k = e / pad, cc = e - k * pad;
-        b[(int64_t)(vbase + k) * Cp + C + cc] = 0.0f;
-    }
-}
-
 // Launches the splat: per cell when a cell's pixels fit the LDS staging,
 // otherwise per vertex.
 template <bool WEIGHTED>
 static bs_status launch_splat(const GridImpl& g, const SolveWs& w, const float* conf,
                               const float* vals, double lam, hipStream_t s) {
     const Level& L = g.lv[0];
-    const int items = g.sg.sigma_xy * g.sg.sigma_xy;
     const int ncells = L.ncx * L.ncy;
-#define BS_SPLAT_CELLS(B, CAP)                                                                  \
-    BS_LAUNCH(s, K_SPLAT, "splat_cells", (splat_cells<B, CAP, WEIGHTED>), dim3(ncells), dim3(B), \
-              0, s, g.H, g.W, g.sg.sigma_xy, L.ncx, L.cell_vbase, L.cell_ibase, L.ptr, L.list,   \
-              conf, vals, w.C, w.Cp, g.P, g.nn, g.nf, lam, w.sc, w.diag, w.minv, w.nfm, w.b)
-    if (items <= 64) BS_SPLAT_CELLS(64, 64);
-    else if (items <= 256) BS_SPLAT_CELLS(256, 256);
-    else if (items <= 1024) BS_SPLAT_CELLS(256, 1024);
-    else {
-        const int vblocks = grid_blocks(ceil_div(g.vcap, kBlock));
-        BS_LAUNCH(s, K_SPLAT, "splat", splat_kernel<WEIGHTED>, dim3(vblocks), dim3(kBlock), 0, s,
-                  L.ptr, L.list, conf, vals, w.C, w.Cp, g.P, g.nn, g.nf, lam, g.counts, w.sc,
-                  w.diag, w.minv, w.nfm, w.b);
+#define BS_SPLAT_CELLS(B, CAP)                                                                 \
+    BS_LAUNCH(s, K_SPLAT, "splat_cells", (one_launch<SplatCells<B, CAP, WEIGHTED>>),            \
+              dim3(ncells), dim3(B), 0, s,                                                      \
+              (splat_cells_args<B, CAP, WEIGHTED>(g, w, conf, vals, lam)), 0)
+    switch (splat_kind(g.sg.sigma_xy)) {
+        case 0: BS_SPLAT_CELLS(64, 64); break;
+        case 1: BS_SPLAT_CELLS(256, 256); break;
+        case 2: BS_SPLAT_CELLS(256, 1024); break;
+        default: {
+            const int vblocks = grid_blocks(ceil_div(g.vcap, kBlock));
+            BS_LAUNCH(s, K_SPLAT, "splat", one_launch<SplatVertex<WEIGHTED>>, dim3(vblocks),
+                      dim3(kBlock), 0, s, (splat_vertex_args<WEIGHTED>(g, w, conf, vals, lam)),
+                      0);
+        }
     }
 #undef BS_SPLAT_CELLS
     return BS_OK;
-}
-
-// Flat init: y = b / S c, 0 where S c = 0.
-__global__ void __launch_bounds__(kBlock) flat_init_kernel(const float* __restrict__ b,
-                                                            const float* __restrict__ sc, int C,
-                                                            const int32_t* __restrict__ counts,
-                                                            float* __restrict__ y) {
-    const int64_t n = (int64_t)counts[CNT_V] * C;
-    const XcdTiles tl((n + kBlock - 1) / kBlock);
-    for (int64_t tile = tl.first; tile < tl.end; tile += tl.step) {
-        const int64_t e = tile * kBlock + threadIdx.x;
-        if (e >= n) continue;
-        const float s = sc[e / C];
-        y[e] = s > 0.0f ? b[e] / s : 0.0f;
-    }
-}
-
-// Pyramid lift, level k >= 1: child sums of level k-1 for C channels of b and
-// S c (channel C).  up_k[u][ch] = sum over children of the child's value.
-__global__ void __launch_bounds__(kBlock) pyr_up(const int32_t* __restrict__ cptr,
-                                                  const int32_t* __restrict__ clist,
-                                                  const float* __restrict__ b,
-                                                  const float* __restrict__ sc,
-                                                  const float* __restrict__ prev, float* __restrict__ up,
-                                                  int C, int level, const int32_t* __restrict__ counts) {
-    if (counts[CNT_K] < level) return;
-    const int Vk = counts[CNT_LEVEL0 + level];
-    const int C1 = C + 1;
-    const int64_t n = (int64_t)Vk * C1;
-    const XcdTiles tl((n + kBlock - 1) / kBlock);
-    for (int64_t tile = tl.first; tile < tl.end; tile += tl.step) {
-        const int64_t e = tile * kBlock + threadIdx.x;
-        if (e >= n) continue;
-        const int u = (int)(e / C1), ch = (int)(e - (int64_t)u * C1);
-        double s = 0.0;
-        for (int j = cptr[u]; j < cptr[u + 1]; ++j) {
-            const int c = clist[j];
-            if (prev) s += (double)prev[(int64_t)c * C1 + ch];
-            else s += (double)(ch < C ? b[(int64_t)c * C + ch] : sc[c]);
-        }
-        up[e] = (float)s;
-    }
-}
-
-// Pyramid collapse, level k >= 1 (top-down): acc_k = w_k P_k / P(1)_k + acc_{k+1}[parent].
-__global__ void __launch_bounds__(kBlock) pyr_down(float* __restrict__ up,
-                                                    const float* __restrict__ up_parent,
-                                                    const int32_t* __restrict__ parent,
-                                                    const int32_t* __restrict__ ones, float wk,
-                                                    int C, int level,
-                                                    const int32_t* __restrict__ counts) {
-    const int K = counts[CNT_K];
-    if (K < level) return;
-    const int Vk = counts[CNT_LEVEL0 + level];
-    const int C1 = C + 1;
-    const int64_t n = (int64_t)Vk * C1;
-    const XcdTiles tl((n + kBlock - 1) / kBlock);
-    for (int64_t tile = tl.first; tile < tl.end; tile += tl.step) {
-        const int64_t e = tile * kBlock + threadIdx.x;
-        if (e >= n) continue;
-        const int u = (int)(e / C1), ch = (int)(e - (int64_t)u * C1);
-        float v = wk * up[e] / (float)ones[u];
-        if (level < K) v += up_parent[(int64_t)parent[u] * C1 + ch];
-        up[e] = v;
-    }
-}
-
-// The small top of the pyramid, levels k0 .. levels-1, in one block: the lift
-// bottom-up, then the collapse top-down, with the arithmetic of pyr_up and
-// pyr_down (the coarse levels would otherwise cost two launches each).
-constexpr int kSmallPyrElems = 16384;   // cap_k x (C + 1) of a level done in one block
-
-struct PyrLevels {
-    int k0, levels;
-    const int32_t* cptr[BS_MAX_LEVELS];    // level k: CSR of children (level k-1 vertices)
-    const int32_t* clist[BS_MAX_LEVELS];
-    const int32_t* ones[BS_MAX_LEVELS];
-    const int32_t* parent[BS_MAX_LEVELS];  // level k vertex -> level k+1 vertex
-    float* up[BS_MAX_LEVELS];
-    float wk[BS_MAX_LEVELS];
-};
-
-__global__ void __launch_bounds__(1024) pyr_small(PyrLevels a, const float* __restrict__ b,
-                                                   const float* __restrict__ sc, int C,
-                                                   const int32_t* __restrict__ counts) {
-    const int K = counts[CNT_K];
-    const int C1 = C + 1;
-    for (int k = a.k0; k < a.levels && k <= K; ++k) {
-        const int Vk = counts[CNT_LEVEL0 + k];
-        const float* prev = k >= 2 ? a.up[k - 1] : nullptr;
-        const int32_t* cptr = a.cptr[k];
-        const int32_t* clist = a.clist[k];
-        float* up = a.up[k];
-        const int64_t n = (int64_t)Vk * C1;
-        for (int64_t e = threadIdx.x; e < n; e += blockDim.x) {
-            const int u = (int)(e / C1), ch = (int)(e - (int64_t)u * C1);
-            double s = 0.0;
-            for (int j = cptr[u]; j < cptr[u + 1]; ++j) {
-                const int c = clist[j];
-                if (prev) s += (double)prev[(int64_t)c * C1 + ch];
-                else s += (double)(ch < C ? b[(int64_t)c * C + ch] : sc[c]);
-            }
-            up[e] = (float)s;
-        }
-        __syncthreads();
-    }
-    for (int k = a.levels - 1; k >= a.k0; --k) {
-        if (K < k) continue;
-        const int Vk = counts[CNT_LEVEL0 + k];
-        float* up = a.up[k];
-        const float* upp = (k < K) ? a.up[k + 1] : nullptr;
-        const int32_t* parent = a.parent[k];
-        const int32_t* ones = a.ones[k];
-        const float wk = a.wk[k];
-        const int64_t n = (int64_t)Vk * C1;
-        for (int64_t e = threadIdx.x; e < n; e += blockDim.x) {
-            const int u = (int)(e / C1), ch = (int)(e - (int64_t)u * C1);
-            float v = wk * up[e] / (float)ones[u];
-            if (upp) v += upp[(int64_t)parent[u] * C1 + ch];
-            up[e] = v;
-        }
-        __syncthreads();
-    }
-}
-
-// Level 0 of the collapse and the ratio of the two push-pull filters:
-// y0 = (b + acc_1[parent]) / (S c + acc_1[parent][C]), 0 where the
-// denominator is 0 (zero total confidence).
-__global__ void __launch_bounds__(kBlock) hier_final(const float* __restrict__ b,
-                                                      const float* __restrict__ sc,
-                                                      const float* __restrict__ up1,
-                                                      const int32_t* __restrict__ parent0, int C,
-                                                      const int32_t* __restrict__ counts,
-                                                      float* __restrict__ y) {
-    const int K = counts[CNT_K];
-    const int64_t n = (int64_t)counts[CNT_V] * C;
-    const int C1 = C + 1;
-    const XcdTiles tl((n + kBlock - 1) / kBlock);
-    for (int64_t tile = tl.first; tile < tl.end; tile += tl.step) {
-        const int64_t e = tile * kBlock + threadIdx.x;
-        if (e >= n) continue;
-        const int v = (int)(e / C), ch = (int)(e - (int64_t)v * C);
-        float num = b[e], den = sc[v];
-        if (K >= 1) {
-            const int64_t p = (int64_t)parent0[v] * C1;
-            num += up1[p + ch];
-            den += up1[p + C];
-        }
-        y[e] = den > 0.0f ? num / den : 0.0f;
-    }
 }
 
 // Every lane width takes q by its recurrence and computes q = A d directly
@@ -688,6 +426,14 @@ inline bool exact_iteration(int it) {
 // PCG kernels.  Each takes one image (MULTI false, by value) or a table of
 // images with the image of every block (MULTI true).
 // ---------------------------------------------------------------------------
+
+// In a launch over an image table, blocks past the images' blocks (a
+// schedule of fewer blocks than the launch's) have no image and return.
+template <bool MULTI>
+__device__ inline bool idle_block(const PcgArgs& a) {
+    if constexpr (MULTI) return a.blk2img[blockIdx.x] < 0;
+    else return false;
+}
 
 template <bool MULTI>
 __device__ inline const PcgImage& block_image(const PcgArgs& a, int& jb) {
@@ -792,6 +538,7 @@ constexpr bool late_decode() { return K == 1 && PACKED && !MULTI; }
 template <bool MULTI>
 __global__ void __launch_bounds__(kRedBlock) pcg_prologue(PcgArgs a) {
     int jb;
+    if (idle_block<MULTI>(a)) return;
     const ImgView I = view_of(block_image<MULTI>(a, jb));
     const int t = threadIdx.x;
     if (t < I.Cp) {
@@ -816,6 +563,7 @@ __device__ inline Vec<K> scaled_residual(const Vec<K>& r, float2 nm) {
 template <int K, bool MULTI, bool PACKED>
 __global__ void __launch_bounds__(kRedBlock) pcg_start(PcgArgs a) {
     int jb;
+    if (idle_block<MULTI>(a)) return;
     const ImgView I = view_of(block_image<MULTI>(a, jb));
     const int V = I.counts[CNT_V];
     const int Cp = I.Cp, nb = I.nb;
@@ -970,6 +718,7 @@ __global__ void __launch_bounds__(kRedBlock) pcg_matvec(PcgArgs a, int src) {
     __shared__ float pend[BS_MAX_CHANNELS];
     __shared__ int n_active, n_pend;
     int jb;
+    if (idle_block<MULTI>(a)) return;
     const ImgView I = view_of(block_image<MULTI>(a, jb));
     if constexpr (MULTI) {
         if (*I.active == 0) return;   // stopped image (its last step applied)
@@ -1122,6 +871,7 @@ __global__ void __launch_bounds__(kRedBlock) pcg_update(PcgArgs a, int want_w) {
     __shared__ double fin[BS_MAX_CHANNELS];
     __shared__ int n_active;
     int jb;
+    if (idle_block<MULTI>(a)) return;
     const ImgView I = view_of(block_image<MULTI>(a, jb));
     if constexpr (MULTI) {
         if (*I.active == 0) return;
@@ -1228,6 +978,7 @@ __global__ void __launch_bounds__(kRedBlock) pcg_flush(PcgArgs a, int src) {
     __shared__ float pend[BS_MAX_CHANNELS];
     __shared__ int n_pend;
     int jb;
+    if (idle_block<MULTI>(a)) return;
     const ImgView I = view_of(block_image<MULTI>(a, jb));
     if (*I.active == 0) return;
     const int t = threadIdx.x;
@@ -1306,58 +1057,6 @@ __global__ void __launch_bounds__(kRedBlock) pcg_finish(PcgArgs a) {
     }
 }
 
-// y[v][c] = src[v][c] for c < C, src with stride Cp.
-__global__ void __launch_bounds__(kBlock) unpad_kernel(const float* __restrict__ src, int Cp,
-                                                        int C, const int32_t* __restrict__ counts,
-                                                        float* __restrict__ dst) {
-    const int64_t n = (int64_t)counts[CNT_V] * C;
-    const XcdTiles tl((n + kBlock - 1) / kBlock);
-    for (int64_t tile = tl.first; tile < tl.end; tile += tl.step) {
-        const int64_t e = tile * kBlock + threadIdx.x;
-        if (e >= n) continue;
-        const int64_t v = e / C;
-        dst[e] = src[v * Cp + (e - v * C)];
-    }
-}
-
-// x[c][p] = y[idx[p]][c].
-__global__ void __launch_bounds__(kBlock) slice_kernel(const int32_t* __restrict__ idx,
-                                                        const float* __restrict__ y, int C, int P,
-                                                        float* __restrict__ x) {
-    const XcdTiles tl((P + kBlock - 1) / kBlock);
-    for (int64_t tile = tl.first; tile < tl.end; tile += tl.step) {
-        const int p = (int)(tile * kBlock) + threadIdx.x;
-        if (p >= P) continue;
-        const int64_t v = idx[p];
-        for (int c = 0; c < C; ++c) x[(int64_t)c * P + p] = y[v * C + c];
-    }
-}
-
-// dL/dt[c][p] = conf[p] g[idx[p]][c];  dL/dconf[p] = sum_c g[idx][c] (t[c][p] - y[idx][c]).
-// g has stride Cg, y stride C.
-__global__ void __launch_bounds__(kBlock) grad_scatter(const int32_t* __restrict__ idx,
-                                                        const float* __restrict__ g, int Cg,
-                                                        const float* __restrict__ yhat,
-                                                        const float* __restrict__ target,
-                                                        const float* __restrict__ conf, int C,
-                                                        int P, float* __restrict__ gt,
-                                                        float* __restrict__ gc) {
-    const XcdTiles tl((P + kBlock - 1) / kBlock);
-    for (int64_t tile = tl.first; tile < tl.end; tile += tl.step) {
-        const int p = (int)(tile * kBlock) + threadIdx.x;
-        if (p >= P) continue;
-        const int64_t v = idx[p];
-        const float cp = conf[p];
-        float s = 0.0f;
-        for (int c = 0; c < C; ++c) {
-            const float gv = g[v * Cg + c];
-            gt[(int64_t)c * P + p] = cp * gv;
-            s += gv * (target[(int64_t)c * P + p] - yhat[v * C + c]);
-        }
-        gc[p] = s;
-    }
-}
-
 // ---------------------------------------------------------------------------
 // Host sequencing.
 // ---------------------------------------------------------------------------
@@ -1386,47 +1085,27 @@ static bs_status run_init(const GridImpl& g, const SolveWs& w, const bs_solve_pa
     const int C = w.Cp;
     const int blocks = grid_blocks(ceil_div(g.vcap * C, kBlock));
     if (p.init == BS_INIT_FLAT) {
-        BS_LAUNCH(s, K_INIT, "flat_init", flat_init_kernel, dim3(blocks), dim3(kBlock), 0, s, w.b,
-                  w.sc, C, g.counts, y);
+        BS_LAUNCH(s, K_INIT, "flat_init", one_launch<FlatInit>, dim3(blocks), dim3(kBlock), 0, s,
+                  flat_init_args(g, w, y), 0);
         return BS_OK;
     }
     // levels k0.. are small enough for one block (capacities decrease with k)
-    int k0 = 1;
-    while (k0 < g.levels && g.lv[k0].cap * (C + 1) > kSmallPyrElems) ++k0;
+    const int k0 = small_pyr_level(g, C);
     for (int k = 1; k < k0; ++k) {
         const int bk = grid_blocks(ceil_div(g.lv[k].cap * (C + 1), kBlock));
-        BS_LAUNCH(s, K_INIT, "pyr_up", pyr_up, dim3(bk), dim3(kBlock), 0, s, g.lv[k].ptr,
-                  g.lv[k].list, w.b, w.sc, (const float*)(k >= 2 ? w.up[k - 1] : nullptr),
-                  w.up[k], C, k, g.counts);
+        BS_LAUNCH(s, K_INIT, "pyr_up", one_launch<PyrUp>, dim3(bk), dim3(kBlock), 0, s,
+                  pyr_up_args(g, w, k), 0);
     }
-    if (k0 < g.levels) {
-        PyrLevels a;
-        std::memset(&a, 0, sizeof(a));
-        a.k0 = k0;
-        a.levels = g.levels;
-        for (int k = 1; k < g.levels; ++k) {
-            a.cptr[k] = g.lv[k].ptr;
-            a.clist[k] = g.lv[k].list;
-            a.ones[k] = g.lv[k].ones;
-            a.parent[k] = (k + 1 < g.levels) ? g.lv[k + 1].item_parent : nullptr;
-            a.up[k] = w.up[k];
-            a.wk[k] = (float)std::pow((double)p.init_alpha, -((double)p.init_beta + k));
-        }
-        BS_LAUNCH(s, K_INIT, "pyr_small", pyr_small, dim3(1), dim3(1024), 0, s, a, w.b, w.sc, C,
-                  g.counts);
-    }
+    if (k0 < g.levels)
+        BS_LAUNCH(s, K_INIT, "pyr_small", one_launch<PyrSmall>, dim3(1), dim3(1024), 0, s,
+                  pyr_small_args(g, w, p, k0), 0);
     for (int k = k0 - 1; k >= 1; --k) {
         const int bk = grid_blocks(ceil_div(g.lv[k].cap * (C + 1), kBlock));
-        const float wk = (float)std::pow((double)p.init_alpha, -((double)p.init_beta + k));
-        const float* upp = (k + 1 < g.levels) ? w.up[k + 1] : nullptr;
-        const int32_t* par = (k + 1 < g.levels) ? g.lv[k + 1].item_parent : nullptr;
-        BS_LAUNCH(s, K_INIT, "pyr_down", pyr_down, dim3(bk), dim3(kBlock), 0, s, w.up[k], upp,
-                  par, g.lv[k].ones, wk, C, k, g.counts);
+        BS_LAUNCH(s, K_INIT, "pyr_down", one_launch<PyrDown>, dim3(bk), dim3(kBlock), 0, s,
+                  pyr_down_args(g, w, p, k), 0);
     }
-    const int32_t* par0 = g.levels > 1 ? g.lv[1].item_parent : nullptr;
-    const float* up1 = g.levels > 1 ? w.up[1] : nullptr;
-    BS_LAUNCH(s, K_INIT, "hier_final", hier_final, dim3(blocks), dim3(kBlock), 0, s, w.b, w.sc,
-              up1, par0, C, g.counts, y);
+    BS_LAUNCH(s, K_INIT, "hier_final", one_launch<HierFinal>, dim3(blocks), dim3(kBlock), 0, s,
+              hier_final_args(g, w, y), 0);
     return BS_OK;
 }
 
@@ -1447,6 +1126,8 @@ bs_status solve_setup(const GridImpl& g, const SolveWs& w, const float* conf, co
     if (st != BS_OK) return st;
     return run_init(g, w, p, yw, s);
 }
+
+bool pcg_partials_fit(int Cp, int nb) { return PartialSums::fits(3 * Cp, nb); }
 
 PcgImage make_image(const GridImpl& g, const SolveWs& w, float lam, float* yw,
                     bs_chan_stats* stats) {
@@ -1540,8 +1221,8 @@ bs_status run_pcg(int K, const PcgImage* imgs, int n, const PcgImage* dev_imgs,
     a.tol = p.rel_tol;
     bool sep = false;
     for (int i = 0; i < n; ++i) sep = sep || imgs[i].sums[0] != nullptr;
-    const bool multi = n > 1;
-    if (multi && (!dev_imgs || !blk2img)) return fail(BS_EINVAL, "image tables missing");
+    const bool multi = dev_imgs != nullptr;
+    if (multi && !blk2img) return fail(BS_EINVAL, "image tables missing");
     // the packed neighbour table when every image has one
     bool packed = true;
     for (int i = 0; i < n; ++i) packed = packed && imgs[i].nb16 != nullptr;
@@ -1567,8 +1248,8 @@ bs_status run_pcg(int K, const PcgImage* imgs, int n, const PcgImage* dev_imgs,
 bs_status copy_unpadded(const GridImpl& g, const float* yw, int C, int Cp, float* y,
                         hipStream_t s) {
     const int blocks = grid_blocks(ceil_div(g.vcap * C, kBlock));
-    BS_LAUNCH(s, K_INIT, "unpad", unpad_kernel, dim3(blocks), dim3(kBlock), 0, s, yw, Cp, C,
-              g.counts, y);
+    BS_LAUNCH(s, K_INIT, "unpad", one_launch<Unpad>, dim3(blocks), dim3(kBlock), 0, s,
+              (Unpad::Args{yw, g.counts, y, Cp, C}), 0);
     return BS_OK;
 }
 
@@ -1576,8 +1257,11 @@ bs_status grad_scatter_launch(const GridImpl& g, const float* gb, int Cp, const 
                               const float* target, const float* conf, int C, float* grad_t,
                               float* grad_c, hipStream_t s) {
     const int pblocks = grid_blocks(ceil_div(g.P, kBlock));
-    BS_LAUNCH(s, K_GRAD_SCATTER, "grad_scatter", grad_scatter, dim3(pblocks), dim3(kBlock), 0, s,
-              g.lv[0].item_parent, gb, Cp, y_hat, target, conf, C, g.P, grad_t, grad_c);
+    BS_LAUNCH(s, K_GRAD_SCATTER, "grad_scatter", one_launch<GradScatter>, dim3(pblocks),
+              dim3(kBlock), 0, s,
+              (GradScatter::Args{g.lv[0].item_parent, gb, y_hat, target, conf, grad_t, grad_c, Cp,
+                                 C, g.P}),
+              0);
     return BS_OK;
 }
 
@@ -1647,8 +1331,8 @@ extern "C" bs_status bs_slice(const bs_grid* grid, const float* y, int32_t C, fl
     const GridImpl& g = *impl(grid);
     hipStream_t s = (hipStream_t)stream;
     const int blocks = grid_blocks(ceil_div(g.P, kBlock));
-    BS_LAUNCH(s, K_SLICE, "slice", slice_kernel, dim3(blocks), dim3(kBlock), 0, s,
-              g.lv[0].item_parent, y, C, g.P, x);
+    BS_LAUNCH(s, K_SLICE, "slice", one_launch<Slice>, dim3(blocks), dim3(kBlock), 0, s,
+              (Slice::Args{g.lv[0].item_parent, y, x, C, g.P}), 0);
     return BS_OK;
 }
 

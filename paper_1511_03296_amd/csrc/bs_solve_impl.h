@@ -117,13 +117,19 @@ bs_status init_state(const GridImpl& g, const SolveWs& w, const bs_solve_params&
 bs_status solve_setup(const GridImpl& g, const SolveWs& w, const float* conf, const float* vals,
                       bool weighted, const bs_solve_params& p, float* yw, hipStream_t s);
 
+// Whether the consumers of a Cp-channel image's per-block partials over nb
+// blocks sum them in registers (else make_image points the image at sums
+// that a pcg_reduce launch computes once).
+bool pcg_partials_fit(int Cp, int nb);
+
 // The descriptor of one image's PCG (block0 = 0).
 PcgImage make_image(const GridImpl& g, const SolveWs& w, float lam, float* yw,
                     bs_chan_stats* stats);
 
 // PCG over n images sharing lane width K.  `dev_imgs` / `blk2img` are device
-// copies of `imgs` and of the block-to-image map (ignored for n == 1, which
-// passes the image by value, with block0 = 0); G is the launch's block count,
+// copies of `imgs` and of the block-to-image map (-1: an idle block); with
+// dev_imgs NULL the one image is passed by value, with block0 = 0, and runs
+// on G = its nb blocks.  G is the launch's block count,
 // max_cp the largest Cp; `act` is the device array the images' active
 // counters point into (contiguous, n entries), polled every check_every
 // iterations.
