@@ -22,9 +22,9 @@
  *  - `stream` is a hipStream_t (NULL = the default stream).  Entry points
  *    enqueue work on `stream` and return; results are ready when the stream
  *    reaches them.  The exceptions synchronise `stream` while they run and
- *    say so: bs_grid_vertex_count and bs_read_counters, solves with
- *    convergence polls (check_every > 0), the batch calls and the low-rank
- *    solves.
+ *    say so: bs_grid_vertex_count and bs_read_counters, solves and batch
+ *    runs with convergence polls (check_every > 0), bs_batch_plan_create,
+ *    the synchronous batch calls and the low-rank solves.
  *  - Arguments are validated on the host before anything is enqueued.  On an
  *    error nothing is launched, outputs are untouched and bs_last_error()
  *    returns a description (thread-local).
@@ -372,36 +372,83 @@ typedef struct bs_batch_item {
     bs_chan_stats* stats;
 } bs_batch_item;
 
-/* Scratch bytes of the batch calls: every image's solve workspace plus the
- * batched PCG's tables (independent of n_streams, which must be in 1..16);
- * 0 for invalid arguments (host, pure).  One workspace serves a forward call
- * and the backward call that follows it. */
+/* A batch plan (opaque, host memory): the layout of every image's grid and
+ * solve workspace inside one device workspace, and the device tables of
+ * every launch of a forward and a backward run.  Made on the host from the
+ * images' sizes, grid scales and channel counts alone. */
+typedef struct bs_batch_plan bs_batch_plan;
+
+/* Device workspace bytes of a plan over `items` (host, pure; 0 for an invalid
+ * batch).  Items with grid_ws NULL get their grid inside the workspace; the
+ * others keep theirs in grid_ws.  Only H, W, C, sigma and grid_ws are read. */
+size_t bs_batch_plan_workspace_bytes(const bs_batch_item* items, int32_t n);
+
+/* Makes a plan over n <= 4096 images (Section 3's minibatch: many images of
+ * uneven size and channel count, solved forward and backward together).  The
+ * items' device pointers are bound into the plan: runs read and write those
+ * buffers, whose contents the caller may change between runs.
+ *  fwd  parameters of the forward solves (one set for every image);
+ *  bwd  parameters of the adjoint solves, with fwd's lambda and init; NULL
+ *       makes a forward-only plan (grad_x, grad_t, grad_c may then be NULL);
+ *  bist bistochastization parameters (NULL: 200 updates, tol 1e-10, no polls);
+ *  ws   device workspace of bs_batch_plan_workspace_bytes bytes, 256-byte
+ *       aligned, owned by the caller and used by every run of the plan.
+ * Uploads the plan's tables on `stream` and synchronises it (not capturable).
+ *  out  receives the plan; free it with bs_batch_plan_destroy.
+ * Errors: BS_EINVAL for a bad item or parameter (the message names the item),
+ * BS_EWORKSPACE for a short workspace, BS_EUNSUPPORTED above 4096 images. */
+bs_status bs_batch_plan_create(const bs_batch_item* items, int32_t n, const bs_solve_params* fwd,
+                               const bs_solve_params* bwd, const bs_bistoch_params* bist,
+                               void* ws, size_t ws_bytes, void* stream, bs_batch_plan** out);
+
+/* Forward run of a plan: every image's grid and pyramid, bistochastization,
+ * splat, initial state, PCG and slice (into x where the item has one; y
+ * receives the solution).  Each stage is one launch over all images; the PCG
+ * runs one launch per phase for each lane width (1, 2, 3 or 4 channels per
+ * lane, see bs_solve_channel_stride), each image with its own per-channel
+ * stopping rule; launches over vertices share their blocks among the images
+ * by a schedule computed on the device from the vertex counts.  With
+ * check_every = 0 in fwd and in bist the run only enqueues kernels on
+ * `stream` (no host synchronisation): exactly max_iters PCG iterations and
+ * max_iters + 1 bistochastization updates, which do nothing for an image
+ * once it has stopped, so a run can be captured into a HIP graph and
+ * replayed.  With check_every > 0 the run polls the stop flags and
+ * synchronises `stream`.  Results match bs_solve per image to the solver's
+ * tolerance (block partial sums run in another order) and are deterministic
+ * for a given batch. */
+bs_status bs_batch_run_forward(bs_batch_plan* plan, void* stream);
+
+/* Backward run (as bs_solve_backward per image: splat of grad_x, adjoint
+ * PCG, gradient scatter into grad_t and grad_c), after a forward run of the
+ * same plan; y must hold the forward solutions.  Enqueue-only and
+ * capturable under the same conditions as the forward run (bwd's
+ * check_every). */
+bs_status bs_batch_run_backward(bs_batch_plan* plan, void* stream);
+
+/* The grid handle of image i of a plan (valid after a forward run). */
+bs_status bs_batch_plan_grid(const bs_batch_plan* plan, int32_t i, bs_grid* out);
+
+/* Frees a plan (host memory only; NULL is allowed). */
+void bs_batch_plan_destroy(bs_batch_plan* plan);
+
+/* Scratch bytes of the synchronous batch calls below (n_streams must be in
+ * 1..16 and is otherwise unused); 0 for invalid arguments (host, pure).  One
+ * workspace serves a forward call and the backward call that follows it. */
 size_t bs_batch_workspace_bytes(const bs_batch_item* items, int32_t n, int32_t n_streams);
 
-/* Forward pass of every image: grid, bistochastization, solve, slice, with
- * the same params for all images.  The per-image set-up (grid,
- * bistochastization, splat, initial state) runs on `n_streams` library-owned
- * streams driven by as many host threads, largest images first.  The PCG
- * then runs over all images together: images with the same lane width
- * (channels per lane: 1, 2, 3 or 4, see bs_solve_channel_stride) share one
- * launch per PCG phase, each image keeping
- * its own per-channel stopping rule.  Everything is ordered after the work
- * already enqueued on `stream`, and the PCG, slices and copies run on
- * `stream`.  Returns after enqueueing the slices; the call synchronises
- * `stream` while it runs (vertex counts, convergence polls).  Results match
- * bs_solve per image to the solver's tolerance (the block-partial sums run in
- * another order) and are deterministic for a given batch.
+/* A forward run on a plan made for this call over items that each bring
+ * their grid workspace (grid_ws): grid, bistochastization, solve, slice,
+ * with the same params for all images, polling as params->check_every and
+ * bist->check_every say.  The plan's table upload synchronises `stream`.
  *  grids  host array [n] receiving the grid handles, for bs_batch_backward.
- * Errors: BS_EINVAL for a bad item or parameter (the message names the item),
- * BS_EWORKSPACE for a short or misaligned (256 bytes) workspace. */
+ * Errors as bs_batch_plan_create. */
 bs_status bs_batch_forward(const bs_batch_item* items, int32_t n, const bs_solve_params* params,
                            const bs_bistoch_params* bist, bs_grid* grids, int32_t n_streams,
                            void* ws, size_t ws_bytes, void* stream);
 
-/* Backward pass of every image (as bs_solve_backward: splat of grad_x,
- * adjoint PCG, gradient scatter) on the grids of a previous bs_batch_forward
- * with the same items, y holding the forward solutions; batched as the
- * forward call. */
+/* Backward run on a plan made for this call, on the grids of a previous
+ * bs_batch_forward with the same items (each grid in its item's grid_ws), y
+ * holding the forward solutions. */
 bs_status bs_batch_backward(const bs_batch_item* items, int32_t n, const bs_grid* grids,
                             const bs_solve_params* params, int32_t n_streams, void* ws,
                             size_t ws_bytes, void* stream);
@@ -426,10 +473,10 @@ size_t bs_batch_lowrank_workspace_bytes(const bs_batch_item* items, int32_t n,
 
 /* Forward pass of every image through the low-rank reduction of its
  * right-hand sides (as bs_solve_lowrank, with the same eps for all images):
- * grid, bistochastization, splat and reduction per image on the library
- * streams (each image's factorisation synchronises its stream), then the
- * reduced systems of rank > 0 through the batched PCG (grouped by lane width
- * of their rank), then Y = Z R~ into y and the slice into x.  ranks: host
+ * grid, bistochastization and splat of every image as in a batch run, the
+ * reduction image by image (each factorisation synchronises `stream`), then
+ * the reduced systems of rank > 0 through the batched PCG (grouped by lane
+ * width of their rank), then Y = Z R~ into y and the slice into x.  ranks: host
  * int32 [n] output.  stats [C] of an item: entries 0..t-1 describe its
  * reduced systems.  Errors as bs_batch_forward, plus BS_EINVAL for eps
  * outside [0, 1) or a NULL rank array.  Returns after enqueuing; the stream
@@ -475,9 +522,8 @@ bs_status bs_solve_ws_view(const bs_grid* grid, int32_t C, void* ws, size_t ws_b
  * "level_count", "level_scan", "level_write", "neighbour_table", "bist_step",
  * "bist_other", "splat", "init", "pcg_start", "pcg_matvec", "pcg_update",
  * "pcg_reduce", "slice" or "grad_scatter".  bs_timing_reset clears the sums.
- * While enabled, the batch calls run their PCG groups one after another
- * instead of concurrently, so that every timed launch has the device to
- * itself. */
+ * Every call enqueues its launches on one stream, one after another, so each
+ * timed launch has the device to itself. */
 bs_status bs_timing_enable(int32_t on);
 bs_status bs_timing_reset(void);
 bs_status bs_timing_read(const char* kernel, double* total_ms, int64_t* launches);

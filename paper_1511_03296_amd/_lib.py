@@ -115,6 +115,14 @@ _SIGS = {
     "bs_solve_channel_stride": (_i32, [_i32]),
     "bs_solve_ws_view": (_i32, [ct.POINTER(Grid), _i32, _vp, _sz, ct.POINTER(_vp),
                                 ct.POINTER(_vp), ct.POINTER(_vp), ct.POINTER(_vp)]),
+    "bs_batch_plan_workspace_bytes": (_sz, [ct.POINTER(BatchItem), _i32]),
+    "bs_batch_plan_create": (_i32, [ct.POINTER(BatchItem), _i32, ct.POINTER(SolveParams),
+                                    ct.POINTER(SolveParams), ct.POINTER(BistochParams), _vp, _sz,
+                                    _vp, ct.POINTER(_vp)]),
+    "bs_batch_run_forward": (_i32, [_vp, _vp]),
+    "bs_batch_run_backward": (_i32, [_vp, _vp]),
+    "bs_batch_plan_grid": (_i32, [_vp, _i32, ct.POINTER(Grid)]),
+    "bs_batch_plan_destroy": (None, [_vp]),
     "bs_batch_workspace_bytes": (_sz, [ct.POINTER(BatchItem), _i32, _i32]),
     "bs_batch_forward": (_i32, [ct.POINTER(BatchItem), _i32, ct.POINTER(SolveParams),
                                 ct.POINTER(BistochParams), ct.POINTER(Grid), _i32, _vp, _sz, _vp]),
