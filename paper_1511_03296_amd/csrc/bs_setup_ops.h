@@ -424,7 +424,11 @@ struct Slice {
 };
 
 // dL/dt[c][p] = conf[p] g[idx[p]][c];  dL/dconf[p] = sum_c g[idx][c] (t[c][p] - y[idx][c]).
-// g has stride Cg, y stride C.
+// g has stride Cg, y stride C.  The sum over channels is formed in float64
+// from the float32 operands (each product and difference exact), so the
+// only rounding is the final one: the channels' terms cancel where the
+// solution follows the target, and float32 partial sums would add errors
+// of the size of the terms.
 struct GradScatter {
     static constexpr int kThreads = kBlock;
     struct Args {
@@ -445,13 +449,14 @@ struct GradScatter {
             if (p >= P) continue;
             const int64_t v = a.idx[p];
             const float cp = a.conf[p];
-            float s = 0.0f;
+            double s = 0.0;
             for (int c = 0; c < C; ++c) {
                 const float gv = a.g[v * Cg + c];
                 a.gt[(int64_t)c * P + p] = cp * gv;
-                s += gv * (a.target[(int64_t)c * P + p] - a.yhat[v * C + c]);
+                s = fma((double)gv,
+                        (double)a.target[(int64_t)c * P + p] - (double)a.yhat[v * C + c], s);
             }
-            a.gc[p] = s;
+            a.gc[p] = (float)s;
         }
     }
 };

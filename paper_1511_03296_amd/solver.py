@@ -402,6 +402,124 @@ class BatchState:
         return gts, gcs, st
 
 
+class BatchPlan:
+    """A batch laid out once (``bs_batch_plan_create``): many images of uneven
+    size and channel count, with their inputs, outputs and workspace bound.
+
+    ``forward()`` and ``backward()`` run the whole path over every image;
+    with ``check_every = 0`` in the options (and ``bist_check_every = 0``)
+    they only enqueue kernels on the current stream, so ``capture()`` can
+    record them into one graph, replayed with fixed iteration counts.  Write
+    new inputs into ``targets``, ``confs`` and ``grad_xs`` (in place) between
+    runs; ``xs``, ``ys``, ``grad_ts`` and ``grad_cs`` receive the outputs."""
+
+    def __init__(self, refs, targets, confs, sigmas, fwd: SolveOptions,
+                 bwd: SolveOptions | None = None, bist_tol: float = 1e-10,
+                 bist_max_iters: int = 200, bist_check_every: int = 0, slice_out: bool = True):
+        n = len(refs)
+        if not (len(targets) == len(confs) == len(sigmas) == n) or n == 0:
+            raise ValueError("refs, targets, confs and sigmas must have the same non-zero length")
+        self.n = n
+        dev = refs[0].device
+        self.device = dev
+        self.shapes = []
+        self.refs, self.targets, self.confs = [], [], []
+        self.ys, self.xs, self.stats = [], [], []
+        self.grad_xs, self.grad_ts, self.grad_cs = [], [], []
+        self.items = (L.BatchItem * n)()
+        for i, (ref, t, c, sg) in enumerate(zip(refs, targets, confs, sigmas)):
+            H, W, C = int(ref.shape[1]), int(ref.shape[2]), int(t.shape[0])
+            self.shapes.append((C, H, W))
+            ref = _dev_f32(ref, f"refs[{i}]", (3, H, W))
+            t = _dev_f32(t, f"targets[{i}]", (C, H, W))
+            c = _dev_f32(c, f"confs[{i}]", (H, W))
+            self.refs.append(ref)
+            self.targets.append(t)
+            self.confs.append(c)
+            y = torch.empty((H * W, C), dtype=torch.float32, device=dev)
+            x = torch.empty((C, H, W), dtype=torch.float32, device=dev) if slice_out else None
+            st = torch.zeros(C * _STATS_DTYPE.itemsize, dtype=torch.uint8, device=dev)
+            self.ys.append(y)
+            self.xs.append(x)
+            self.stats.append(st)
+            it = self.items[i]
+            it.ref, it.target, it.conf = ref.data_ptr(), t.data_ptr(), c.data_ptr()
+            it.H, it.W, it.C = H, W, C
+            it.sigma = L.GridParams(*[int(v) for v in sg])
+            it.grid_ws, it.grid_ws_bytes = None, 0
+            it.y, it.x = y.data_ptr(), (x.data_ptr() if x is not None else None)
+            it.stats = st.data_ptr()
+            if bwd is not None:
+                gx = torch.zeros((C, H, W), dtype=torch.float32, device=dev)
+                gt = torch.empty((C, H, W), dtype=torch.float32, device=dev)
+                gc = torch.empty((H, W), dtype=torch.float32, device=dev)
+                self.grad_xs.append(gx)
+                self.grad_ts.append(gt)
+                self.grad_cs.append(gc)
+                it.grad_x, it.grad_t, it.grad_c = gx.data_ptr(), gt.data_ptr(), gc.data_ptr()
+        nbytes = L.lib.bs_batch_plan_workspace_bytes(self.items, n)
+        if nbytes == 0:
+            raise ValueError("invalid batch")
+        self.ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+        self.fwd, self.bwd = fwd, bwd
+        pf = fwd.struct()
+        pb = bwd.struct() if bwd is not None else None
+        bp = L.BistochParams(int(bist_max_iters), int(bist_check_every), float(bist_tol))
+        plan = ct.c_void_p()
+        L.check(L.lib.bs_batch_plan_create(self.items, n, ct.byref(pf),
+                                           ct.byref(pb) if pb is not None else None, ct.byref(bp),
+                                           self.ws.data_ptr(), self.ws.numel(), _stream(),
+                                           ct.byref(plan)), "bs_batch_plan_create")
+        self._plan = plan
+
+    def forward(self) -> None:
+        L.check(L.lib.bs_batch_run_forward(self._plan, _stream()), "bs_batch_run_forward")
+
+    def backward(self) -> None:
+        if self.bwd is None:
+            raise ValueError("the plan was made without backward options")
+        L.check(L.lib.bs_batch_run_backward(self._plan, _stream()), "bs_batch_run_backward")
+
+    def capture(self, backward: bool = True) -> "torch.cuda.CUDAGraph":
+        """A graph of one forward (and backward) run, for replay."""
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph):
+            self.forward()
+            if backward:
+                self.backward()
+        return graph
+
+    def grid(self, i: int) -> L.Grid:
+        g = L.Grid()
+        L.check(L.lib.bs_batch_plan_grid(self._plan, int(i), ct.byref(g)), "bs_batch_plan_grid")
+        return g
+
+    def vertex_counts(self) -> list[int]:
+        """V of every image's grid (after a forward run; synchronises the stream)."""
+        out = []
+        for i in range(self.n):
+            g = self.grid(i)
+            v = ct.c_int32()
+            L.check(L.lib.bs_grid_vertex_count(ct.byref(g), ct.byref(v), _stream()),
+                    "bs_grid_vertex_count")
+            out.append(int(v.value))
+        return out
+
+    def read_stats(self) -> list:
+        return [read_stats(st) for st in self.stats]
+
+    def close(self) -> None:
+        if getattr(self, "_plan", None) is not None and self._plan.value:
+            L.lib.bs_batch_plan_destroy(self._plan)
+            self._plan = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 class _BatchSolveFn(torch.autograd.Function):
     @staticmethod
     def forward(ctx, meta, *tensors):

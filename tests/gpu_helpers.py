@@ -39,6 +39,31 @@ def rel_l2(a, b) -> float:
     return float(np.linalg.norm(a - b) / (nb if nb > 0 else 1.0))
 
 
+def grad_c_errors(gc, grad_c, conf):
+    """(relative L2 error of dL/dc, relative L2 error of c o dL/dc).
+
+    c o dL/dc is the gradient with respect to log c.  At a pixel of low
+    confidence alone on its vertex, the solution equals the target and dL/dc
+    is 0, while dL/db there is about (dL/dx) / c: the float32 rounding of the
+    solution (an ulp of the target) becomes an error of about ulp / c in
+    dL/dc, larger than many exact values when c is near 0.  c o dL/dc
+    removes that 1/c; with confidences bounded away from 0 both bars hold."""
+    a = np.asarray(gc, np.float64).ravel()
+    b = np.asarray(grad_c, np.float64).ravel()
+    c = np.asarray(conf, np.float64).ravel()
+    return rel_l2(a, b), rel_l2(c * a, c * b)
+
+
+def check_grad_c(gc, grad_c, conf, tol=1e-4, plain_min_conf=0.1):
+    """dL/dc against the oracle: c o dL/dc always, dL/dc itself when every
+    confidence is at least plain_min_conf."""
+    plain, weighted = grad_c_errors(gc, grad_c, conf)
+    assert weighted <= tol, ("c o dL/dc", weighted, "dL/dc", plain)
+    if float(np.min(conf)) >= plain_min_conf:
+        assert plain <= tol, ("dL/dc", plain)
+    return plain, weighted
+
+
 def grid_arrays(G) -> dict:
     """Host copies of the level-0 grid arrays and the pyramid of a GPU grid."""
     v = G.view()

@@ -12,7 +12,7 @@ import torch
 
 import workloads as WL
 from oracle import bilateral as O
-from tests.gpu_helpers import (grid_arrays, gpu_grid, oracle_level_keys, params, rel_l2, say,
+from tests.gpu_helpers import (check_grad_c, grid_arrays, gpu_grid, oracle_level_keys, params, rel_l2, say,
                                to_dev)
 
 pytestmark = pytest.mark.gpu
@@ -185,13 +185,18 @@ def test_backward_parity():
                                  max_iters=prm.max_iters, rel_tol=prm.rel_tol, want_g=True,
                                  ws=ws)
     torch.cuda.synchronize()
-    og = O.solve_backward(sol, p.target, p.conf, gx, prm, y_hat=y.cpu().numpy()[: sol.grid.V])
     V = sol.grid.V
+    # given the kernel's own solution (the adjoint and scatter alone) ...
+    og = O.solve_backward(sol, p.target, p.conf, gx, prm, y_hat=y.cpu().numpy()[:V])
     u = G.solve_ws_arrays(ws, p.C)[0].cpu().numpy()[:V]
     assert rel_l2(u, og.u) <= 1e-6
     assert rel_l2(gb.cpu().numpy()[:V], og.gb) <= TOL_X
     assert rel_l2(gt.cpu().numpy(), og.grad_t) <= TOL_X
     assert rel_l2(gc.cpu().numpy(), og.grad_c) <= TOL_X
+    # ... and end to end, on the oracle's own solution
+    og = O.solve_backward(sol, p.target, p.conf, gx, prm)
+    assert rel_l2(gt.cpu().numpy(), og.grad_t) <= TOL_X
+    check_grad_c(gc.cpu().numpy(), og.grad_c, p.conf)
 
 
 def test_autograd_function_matches_backward():
@@ -238,6 +243,9 @@ def test_full_size_stereo_backward():
     og = O.solve_backward(sol, p.target, p.conf, gx, prm, y_hat=y.cpu().numpy()[: sol.grid.V])
     assert rel_l2(gt.cpu().numpy(), og.grad_t) <= TOL_X
     assert rel_l2(gc.cpu().numpy(), og.grad_c) <= TOL_X
+    og = O.solve_backward(sol, p.target, p.conf, gx, prm)    # end to end
+    assert rel_l2(gt.cpu().numpy(), og.grad_t) <= TOL_X
+    check_grad_c(gc.cpu().numpy(), og.grad_c, p.conf)
 
 
 def test_full_size_depth_2048x1536():
