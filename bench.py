@@ -12,8 +12,10 @@ bounded sample of the same workload.
 The default workload is the batch the metric's "solved to rel. residual
 1e-5" and "vs plain" refer to: 64 images of uneven size (320x240 to
 1920x1080) and channel count (1, 2 or 21), solved forward and backward to a
-relative residual of 1e-5 through the batch engine, with the same images
-solved one after another by the single-image path as the "plain" reference.
+relative residual of 1e-5 by a batch plan whose forward and backward runs
+are captured into one HIP graph and replayed, with the same images solved
+one after another by the single-image path as the "plain" reference.  The
+21-channel segmentation batch runs through the autograd function instead.
 
     python bench.py [--steps K] [--warmup W] [--workload NAME]
 """
@@ -21,6 +23,7 @@ from __future__ import annotations
 
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -32,47 +35,58 @@ METRIC = "Mpix/s solved to rel. residual 1e-5 (fwd and fwd+bwd), % HBM peak, vs 
 HBM_PEAK_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
 
-# name -> (generator kwargs, images, forward (max_iters, rel_tol), backward (max_iters, rel_tol))
+# name -> generator, images, form, forward (max_iters, rel_tol), backward (max_iters, rel_tol)
+#   form "single":   the single-image path (grid, bistochastize, solve, slice, backward)
+#   form "graph":    a batch plan; its forward and backward runs captured in one graph
+#   form "autograd": the batched torch.autograd.Function (eager, with convergence polls)
+#   form "lowrank":  the batched low-rank reduction (forward only)
+#   form "robust":   the robust solver's IRLS rounds (forward only)
 WORKLOADS = {
-    "stereo1024x768": dict(gen="stereo_refine", images=1, fwd=(25, 0.0), bwd=(25, 0.0)),
+    "stereo1024x768": dict(gen="stereo_refine", images=1, form="single", fwd=(25, 0.0),
+                           bwd=(25, 0.0)),
     # 255 of 256 depth pixels carry no confidence, so A is singular on their
     # grid components; the adjoint system is consistent only for upstream
     # gradients that vanish there, e.g. that of a confidence-weighted loss.
-    "depthsr2048x1536": dict(gen="depth_superres", images=1, fwd=(20000, 1e-5),
+    "depthsr2048x1536": dict(gen="depth_superres", images=1, form="single", fwd=(20000, 1e-5),
                              bwd=(20000, 1e-5), grad="conf_weighted"),
-    "ramp64x48": dict(gen="tiny_ramp", images=1, fwd=(2000, 1e-5), bwd=(2000, 1e-5)),
-    # batched forms: every image of the batch through the batch engine (images
-    # on concurrent library streams); the same images solved one after another
-    # by the single-image path give the "vs plain" ratio
-    "seg16x512x512": dict(gen="segmentation", images=16, batch=True, fwd=(20000, 1e-6),
+    "ramp64x48": dict(gen="tiny_ramp", images=1, form="single", fwd=(2000, 1e-5),
+                      bwd=(2000, 1e-5)),
+    # the differentiable 21-channel segmentation batch through the autograd
+    # function; the same images solved one after another by the single-image
+    # path give the "vs plain" ratio
+    "seg16x512x512": dict(gen="segmentation", images=16, form="autograd", fwd=(20000, 1e-6),
                           bwd=(20000, 1e-6)),
-    "mixed64": dict(gen="mixed_batch", images=64, batch=True, fwd=(20000, 1e-5),
+    # the mixed batch through a batch plan replayed from a graph
+    "mixed64": dict(gen="mixed_batch", images=64, form="graph", fwd=(20000, 1e-5),
                     bwd=(20000, 1e-5)),
     # the robust solver (Geman-McClure IRLS, sigma_gm in disparity units, 8
     # rounds) on the stereo shape, whose targets carry 10 % outlier
     # disparities; forward only (a step is the 8 rounds)
-    "robust_stereo1024x768": dict(gen="stereo_refine", images=1, fwd=(25, 0.0), bwd=(0, 0.0),
-                                  robust=(4.0, 8)),
+    "robust_stereo1024x768": dict(gen="stereo_refine", images=1, form="robust", fwd=(25, 0.0),
+                                  bwd=(0, 0.0), robust=(4.0, 8)),
     # low-rank reduction (eps = 0.01) of 21-channel class-probability maps with
     # three classes present per image, forward only, through the batch engine;
     # the same images solved one after another with all 21 right-hand sides
     # give the "vs plain" ratio
-    "segprob16x512x512": dict(gen="segmentation_probs", images=16, batch=True,
+    "segprob16x512x512": dict(gen="segmentation_probs", images=16, form="lowrank",
                               fwd=(20000, 1e-6), bwd=(0, 0.0), lowrank=0.01),
 }
 
+# Iteration caps of the graph form: the calibration run's largest count times
+# this margin, plus a few (a replayed graph runs a fixed number of launches;
+# those after an image has stopped do nothing).
+CAP_MARGIN, CAP_EXTRA = 1.2, 8
 
-def matvec_bytes(C: int, iters: int) -> int:
-    """Algorithmic bytes per vertex of `iters` pcg_matvec iterations.
 
-    The exact form (every 4th iteration) reads the neighbour table (40 B),
-    n, S c and M^-1 (4 B each), r, the old d and y (4C B each) and writes y,
-    d and q (4C B each): 52 + 24C.  The recurrence form (the other three)
-    reads the table, n and M^-1, r, d, the old q and y and writes y, d and
-    q: 48 + 28C.  (y += alpha d of the previous iteration is applied here.)
-    The neighbours' gathered values are cache hits in the count."""
-    exact = iters // 4
-    return exact * (52 + 24 * C) + (iters - exact) * (48 + 28 * C)
+def pcg_bytes(V: int, iters) -> int:
+    """Algorithmic bytes of one solve's PCG iterations: per vertex and
+    iteration 48 bytes (neighbour table 40, n 4, diag(A) or its inverse 4)
+    plus 24 per channel still iterating (y, r and d read and written once,
+    float32), summed over the channels' own iteration counts `iters`."""
+    iters = [int(i) for i in iters]
+    if not iters:
+        return 0
+    return int(V) * (48 * max(iters) + 24 * sum(iters))
 
 
 def _histogram(values) -> dict:
@@ -133,169 +147,291 @@ def gpu_inputs(problems, spec, dev):
     return out
 
 
-def run_step(inputs, spec, backward=True, keep=None, streams=0):
-    """One pass of the hot path over every image of the batch: through the
-    batch engine on `streams` library streams, or (streams=0) image after
-    image through the single-image path."""
+def _sigmas(inputs):
+    return [(d["p"].sigma_xy, d["p"].sigma_l, d["p"].sigma_uv) for d in inputs]
+
+
+def _lam(inputs):
+    lam = inputs[0]["p"].lam
+    assert all(d["p"].lam == lam for d in inputs), "one lambda per batch"
+    return lam
+
+
+# ---------------------------------------------------------------------------
+# One step of each form.  `keep` (a list) receives (V, forward stats,
+# backward stats) per image.
+# ---------------------------------------------------------------------------
+def single_step(inputs, spec, backward=True, keep=None):
+    """Image after image through the single-image path (also the "plain"
+    reference of the batched forms)."""
     from paper_1511_03296_amd import BilateralGrid
     (fi, ft), (bi, bt) = spec["fwd"], spec["bwd"]
     fce = 0 if ft == 0.0 else 8
     bce = 0 if bt == 0.0 else 8
-    if streams > 0:
-        return run_batch_step(inputs, spec, backward, keep, streams)
-    if spec.get("lowrank") is not None:
-        for d in inputs:
-            p = d["p"]
-            G = BilateralGrid(d["ref"], p.sigma_xy, p.sigma_l, p.sigma_uv)
-            y, st, rank = G.solve_lowrank(d["t"], d["c"], p.lam, spec["lowrank"], max_iters=fi,
-                                          rel_tol=ft, check_every=fce)
-            G.slice(y, p.C)
-            if keep is not None:
-                keep.append((G.vertex_count(), st, None))
-                RANKS.append(rank)
-        return
-    if spec.get("robust"):
-        sigma_gm, rounds = spec["robust"]
-        for d in inputs:
-            p = d["p"]
-            G = BilateralGrid(d["ref"], p.sigma_xy, p.sigma_l, p.sigma_uv)
+    for d in inputs:
+        p = d["p"]
+        G = BilateralGrid(d["ref"], p.sigma_xy, p.sigma_l, p.sigma_uv)
+        if spec.get("robust"):
+            sigma_gm, rounds = spec["robust"]
             _, _, st = G.robust_solve(d["t"], d["c"], p.lam, sigma_gm, rounds, max_iters=fi,
                                       rel_tol=ft, check_every=fce)
             if keep is not None:
                 keep.append((G.vertex_count(), st, None))
-        return
-    for d in inputs:
-        p = d["p"]
-        G = BilateralGrid(d["ref"], p.sigma_xy, p.sigma_l, p.sigma_uv)
+            continue
         ws = G.solve_workspace(p.C)
         y, st = G.solve(d["t"], d["c"], p.lam, max_iters=fi, rel_tol=ft, check_every=fce, ws=ws)
-        x = G.slice(y, p.C)
-        if backward:
-            gt, gc, _, bst = G.backward(d["t"], d["c"], y, d["gx"], p.lam, max_iters=bi,
-                                        rel_tol=bt, check_every=bce, ws=ws)
+        G.slice(y, p.C)
+        bst = None
+        if backward and bi > 0:
+            _, _, _, bst = G.backward(d["t"], d["c"], y, d["gx"], p.lam, max_iters=bi, rel_tol=bt,
+                                      check_every=bce, ws=ws)
         if keep is not None:
-            keep.append((G.vertex_count(), st, bst if backward else None))
+            keep.append((G.vertex_count(), st, bst))
 
 
-RANKS = []   # reduced ranks of the low-rank workload's images (warm-up step)
-
-
-def run_batch_step(inputs, spec, backward, keep, streams):
+def lowrank_step(inputs, spec, backward=False, keep=None, ranks=None):
     from paper_1511_03296_amd import BatchState, SolveOptions
-    (fi, ft), (bi, bt) = spec["fwd"], spec["bwd"]
-    lam = inputs[0]["p"].lam
-    assert all(d["p"].lam == lam for d in inputs), "one lambda per batch"
+    (fi, ft), _ = spec["fwd"], spec["bwd"]
     state = BatchState([d["ref"] for d in inputs], [d["t"] for d in inputs],
-                       [d["c"] for d in inputs],
-                       [(d["p"].sigma_xy, d["p"].sigma_l, d["p"].sigma_uv) for d in inputs],
-                       streams)
-    want = keep is not None
-    fwd = SolveOptions(lam, fi, ft, check_every=0 if ft == 0.0 else 8)
-    bwd = SolveOptions(lam, bi, bt, check_every=0 if bt == 0.0 else 8)
-    if spec.get("lowrank") is not None:
-        _, fst, ranks = state.forward_lowrank(fwd, spec["lowrank"], stats=want)
-        if want:
-            V = state.vertex_counts()
-            for i in range(len(inputs)):
-                keep.append((V[i], fst[i], None))
-            RANKS.extend(ranks)
-        return
-    _, fst = state.forward(fwd, stats=want)
-    bst = None
-    if backward:
-        _, _, bst = state.backward([d["gx"] for d in inputs], bwd, stats=want)
-    if want:
+                       [d["c"] for d in inputs], _sigmas(inputs), 1)
+    _, fst, rk = state.forward_lowrank(SolveOptions(_lam(inputs), fi, ft, check_every=8),
+                                       spec["lowrank"], stats=keep is not None)
+    if keep is not None:
         V = state.vertex_counts()
         for i in range(len(inputs)):
-            keep.append((V[i], fst[i], bst[i] if backward else None))
+            keep.append((V[i], fst[i], None))
+        if ranks is not None:
+            ranks.extend(rk)
 
 
-def timed(inputs, spec, steps, backward=True, streams=0):
+def autograd_step(inputs, spec, backward=True):
+    """The batched torch.autograd.Function: forward, then the backward pass
+    that autograd drives from the upstream gradient."""
+    import torch
+    from paper_1511_03296_amd import bilateral_solve_batch
+    (fi, ft), (bi, bt) = spec["fwd"], spec["bwd"]
+    ts = [d["t"].detach().requires_grad_(backward) for d in inputs]
+    cs = [d["c"].detach().requires_grad_(backward) for d in inputs]
+    xs = bilateral_solve_batch([d["ref"] for d in inputs], ts, cs, _sigmas(inputs),
+                               _lam(inputs), max_iters=fi, rel_tol=ft, bwd_max_iters=bi,
+                               bwd_rel_tol=bt)
+    if backward:
+        torch.autograd.backward(xs, [d["gx"] for d in inputs])
+
+
+def autograd_stats(inputs, spec, keep):
+    """Stats of the same computation as autograd_step (through BatchState,
+    the engine behind the autograd function)."""
+    from paper_1511_03296_amd import BatchState, SolveOptions
+    (fi, ft), (bi, bt) = spec["fwd"], spec["bwd"]
+    lam = _lam(inputs)
+    state = BatchState([d["ref"] for d in inputs], [d["t"] for d in inputs],
+                       [d["c"] for d in inputs], _sigmas(inputs), 1)
+    _, fst = state.forward(SolveOptions(lam, fi, ft), stats=True)
+    _, _, bst = state.backward([d["gx"] for d in inputs], SolveOptions(lam, bi, bt), stats=True)
+    V = state.vertex_counts()
+    for i in range(len(inputs)):
+        keep.append((V[i], fst[i], bst[i]))
+
+
+class GraphForm:
+    """The batch plan of the graph form: a calibration run that polls the stop
+    flags gives every image's iteration counts; the plan replayed from the
+    graph runs fixed caps above them (CAP_MARGIN), and the stats of every
+    replay say whether each channel stopped on the tolerance."""
+
+    def __init__(self, inputs, spec):
+        self.inputs, self.spec = inputs, spec
+        self.plan = None
+        self.graphs = {}
+
+    def make(self, fwd_iters, bwd_iters, check_every):
+        from paper_1511_03296_amd import BatchPlan, SolveOptions
+        (_, ft), (_, bt) = self.spec["fwd"], self.spec["bwd"]
+        lam = _lam(self.inputs)
+        plan = BatchPlan([d["ref"] for d in self.inputs], [d["t"] for d in self.inputs],
+                         [d["c"] for d in self.inputs], _sigmas(self.inputs),
+                         SolveOptions(lam, fwd_iters, ft, check_every=check_every),
+                         SolveOptions(lam, bwd_iters, bt, check_every=check_every),
+                         bist_check_every=check_every)
+        for g, d in zip(plan.grad_xs, self.inputs):
+            g.copy_(d["gx"])
+        return plan
+
+    def calibrate(self, keep):
+        import torch
+        (fi, _), (bi, _) = self.spec["fwd"], self.spec["bwd"]
+        plan = self.make(fi, bi, 8)
+        plan.forward()
+        torch.cuda.synchronize()
+        fst = [s.clone() for s in plan.stats]
+        plan.backward()
+        torch.cuda.synchronize()
+        bst = [s.clone() for s in plan.stats]
+        V = plan.vertex_counts()
+        plan.close()
+        for i in range(len(V)):
+            keep.append((V[i], fst[i], bst[i]))
+        from paper_1511_03296_amd import read_stats
+        fmax = max(int(read_stats(s)["iters"].max()) for s in fst)
+        bmax = max(int(read_stats(s)["iters"].max()) for s in bst)
+        self.caps = (int(math.ceil(fmax * CAP_MARGIN)) + CAP_EXTRA,
+                     int(math.ceil(bmax * CAP_MARGIN)) + CAP_EXTRA)
+        return self.caps
+
+    def build(self):
+        import torch
+        if self.plan is not None:
+            self.plan.close()
+        self.graphs = {}
+        self.plan = self.make(self.caps[0], self.caps[1], 0)
+        self.plan.forward()
+        self.plan.backward()
+        torch.cuda.synchronize()
+
+    def capture(self):
+        self.graphs[True] = self.plan.capture(backward=True)
+        self.graphs[False] = self.plan.capture(backward=False)
+
+    def step(self, backward=True):
+        self.graphs[backward].replay()
+
+    def eager(self, backward=True):
+        self.plan.forward()
+        if backward:
+            self.plan.backward()
+
+    def converged(self) -> bool:
+        """Whether every channel of the last run stopped on the tolerance (or
+        had a zero right-hand side)."""
+        import torch
+        torch.cuda.synchronize()
+        return all(set(s["reason"].tolist()) <= {1, 5} for s in self.plan.read_stats())
+
+
+def timed(step, steps):
     import torch
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps):
-        run_step(inputs, spec, backward, streams=streams)
+        step()
     torch.cuda.synchronize()
     return (time.perf_counter() - t0) / steps
 
 
-def kernel_times(inputs, spec, steps, streams=0):
-    """Per-kernel average launch duration (HIP events on the launch stream)."""
+KERNELS = ["level_count", "level_scan", "level_write", "neighbour_table", "bist_step",
+           "bist_other", "splat", "init", "pcg_start", "pcg_matvec", "pcg_update", "pcg_reduce",
+           "slice", "grad_scatter"]
+
+
+def kernel_times(step, steps):
+    """Per-kernel summed launch durations and launch counts per step (HIP
+    events recorded on the launch stream around every launch)."""
     from paper_1511_03296_amd import _lib as L
     import ctypes as ct
-    names = ["level_count", "level_scan", "level_write", "neighbour_table", "bist_step",
-             "bist_other", "splat", "init", "pcg_start", "pcg_matvec", "pcg_update", "pcg_reduce",
-             "slice",
-             "grad_scatter"]
     L.check(L.lib.bs_timing_reset(), "timing_reset")
     L.check(L.lib.bs_timing_enable(1), "timing_enable")
-    sec = timed(inputs, spec, steps, streams=streams)
+    sec = timed(step, steps)
     L.check(L.lib.bs_timing_enable(0), "timing_enable")
     out = {}
-    for n in names:
+    for n in KERNELS:
         ms, cnt = ct.c_double(), ct.c_int64()
         L.check(L.lib.bs_timing_read(n.encode(), ct.byref(ms), ct.byref(cnt)), "timing_read")
         out[n] = (ms.value / steps, cnt.value / steps)
     return sec, out
 
 
-def cpu_baseline(problems, spec, seconds):
-    """The FP64 oracle, as it stands, on a bounded sample of the workload."""
-    import numpy as np
+# ---------------------------------------------------------------------------
+# The oracle on the host's cores.
+# ---------------------------------------------------------------------------
+def _oracle_sample(args):
+    """One forward+backward (or the workload's own pass) of the oracle on one
+    image crop; returns its pixel count.  Runs in a worker process."""
+    import numpy as np  # noqa: F401
     from oracle import bilateral as O
     import workloads as WL
+    p, spec = args
     (fi, ft), (bi, bt) = spec["fwd"], spec["bwd"]
-    p = problems[0]
-    sample = f"{p.name}: full forward+backward of image 0"
-    if p.pixels > 1_000_000 or ft > 0:
-        # tolerance-driven workloads: a centre crop keeps the sample bounded
-        h, w = (min(p.H, 384), min(p.W, 512)) if p.C < 8 else (min(p.H, 128), min(p.W, 128))
-        p = WL.crop(p, (p.H - h) // 2, (p.W - w) // 2, h, w)
-        sample = f"{p.name} ({w}x{h} centre crop), full forward+backward"
-    gx = WL.random_grad(0, p.C, p.H, p.W)
-    if spec.get("grad") == "conf_weighted":
-        gx = gx * p.conf[None]
+    prm = O.Params(p.sigma_xy, p.sigma_l, p.sigma_uv, p.lam, max_iters=fi, rel_tol=ft)
     if spec.get("robust"):
-        sample = sample.replace("forward+backward", "robust forward")
-    if spec.get("lowrank") is not None:
-        sample = sample.replace("forward+backward", "low-rank forward")
+        O.robust_solve(p.ref, p.target, p.conf, prm, *spec["robust"])
+    elif spec.get("lowrank") is not None:
+        O.solve_lowrank(p.ref, p.target, p.conf, prm, spec["lowrank"])
+    else:
+        gx = p.extra.get("onehot")
+        gx = WL.random_grad(0, p.C, p.H, p.W) if gx is None else 2.0 * (p.target - gx)
+        if spec.get("grad") == "conf_weighted":
+            gx = gx * p.conf[None]
+        sol = O.solve(p.ref, p.target, p.conf, prm)
+        prmb = O.Params(p.sigma_xy, p.sigma_l, p.sigma_uv, p.lam, max_iters=bi, rel_tol=bt)
+        O.solve_backward(sol, p.target, p.conf, gx, prmb)
+    return p.pixels
+
+
+def _worker_init():
+    # one thread per worker process: the host's cores are shared by processes
+    os.environ["OMP_NUM_THREADS"] = "1"
+    from threadpoolctl import threadpool_limits
+    threadpool_limits(1)
+
+
+def cpu_baseline(problems, spec, seconds, cores):
+    """The FP64 oracle, as it stands, on a bounded sample of the workload: a
+    crop of each image (cycling through the images), one crop per worker
+    process, as many processes as cores, for about `seconds`."""
+    import multiprocessing as mp
+    import workloads as WL
+    crops = []
+    for p in problems:
+        if p.pixels > 200_000 or spec["fwd"][1] > 0:
+            h, w = (min(p.H, 256), min(p.W, 256)) if p.C < 8 else (min(p.H, 96), min(p.W, 96))
+            p = WL.crop(p, (p.H - h) // 2, (p.W - w) // 2, h, w)
+        crops.append(p)
+    what = {"robust": "robust forward", "lowrank": "low-rank forward"}
+    kind = next((v for k, v in what.items() if spec.get(k) is not None), "forward+backward")
+    ctx = mp.get_context("fork")
+    done_px, n = 0, 0
     t0 = time.perf_counter()
-    n = 0
-    while True:
-        prm = O.Params(p.sigma_xy, p.sigma_l, p.sigma_uv, p.lam, max_iters=fi, rel_tol=ft)
-        if spec.get("robust"):
-            O.robust_solve(p.ref, p.target, p.conf, prm, *spec["robust"])
-        elif spec.get("lowrank") is not None:
-            O.solve_lowrank(p.ref, p.target, p.conf, prm, spec["lowrank"])
-        else:
-            sol = O.solve(p.ref, p.target, p.conf, prm)
-            prmb = O.Params(p.sigma_xy, p.sigma_l, p.sigma_uv, p.lam, max_iters=bi, rel_tol=bt)
-            O.solve_backward(sol, p.target, p.conf, gx, prmb)
-        n += 1
+    with ctx.Pool(cores, initializer=_worker_init) as pool:
+        pending = []
+        k = 0
+        while time.perf_counter() - t0 < seconds or pending:
+            while len(pending) < cores and time.perf_counter() - t0 < seconds:
+                pending.append(pool.apply_async(_oracle_sample, ((crops[k % len(crops)], spec),)))
+                k += 1
+            pending[0].wait()
+            done_px += pending.pop(0).get()
+            n += 1
         el = time.perf_counter() - t0
-        if el >= seconds:
-            break
-    return {"value": round(n * p.pixels / el / 1e6, 4), "unit": "Mpix/s", "cores": 1,
-            "kind": "oracle", "sample": f"{sample}, {n} step(s) in {el:.1f} s, NumPy float64, "
-                                        "one thread"}
+    shape = f"{crops[0].W}x{crops[0].H}" if len(crops) == 1 else "crops"
+    return {"value": round(done_px / el / 1e6, 4), "unit": "Mpix/s", "cores": cores,
+            "kind": "oracle",
+            "sample": f"{n} {kind} passes of centre crops (at most 256x256, 96x96 for "
+                      f"21 channels; {shape}) cycling through the workload's images, "
+                      f"{cores} worker processes of one thread each, {el:.1f} s, "
+                      f"NumPy float64"}
 
 
+# ---------------------------------------------------------------------------
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="mixed64", choices=sorted(WORKLOADS))
-    ap.add_argument("--streams", type=int, default=4,
-                    help="library streams of the batch engine (batched workloads)")
-    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--cpu-cores", type=int, default=0,
+                    help="worker processes of the CPU baseline (0: min(16, host cores))")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true",
-                    help="batched workloads: keep the default tiles per block instead of "
-                         "tuning them on the batch first")
+                    help="graph form: keep the default tiles per block instead of tuning "
+                         "them on the batch first")
     ap.add_argument("--no-plain", action="store_true",
-                    help="batched workloads: skip the single-image comparison (counter runs)")
+                    help="batched forms: skip the single-image comparison (counter runs)")
+    ap.add_argument("--profile", action="store_true",
+                    help="the launches of forward+backward steps only, for a profiler's "
+                         "kernel trace: no autotuning, single-image comparison, "
+                         "forward-only timing or CPU baseline")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="copy a MIB-sized device buffer once (a reference kernel of known "
                          "traffic for hardware counters)")
@@ -310,13 +446,15 @@ def main() -> int:
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         return 1
+    from paper_1511_03296_amd import read_stats
     dev = torch.device("cuda:0")
     spec = WORKLOADS[args.workload]
+    form = spec["form"]
     problems = make_problems(args.workload)
     inputs = gpu_inputs(problems, spec, dev)
     pixels = sum(p.pixels for p in problems)
-    print(f"bench: {args.workload} images={len(problems)} pixels={pixels}", file=sys.stderr,
-          flush=True)
+    print(f"bench: {args.workload} images={len(problems)} pixels={pixels} form={form}",
+          file=sys.stderr, flush=True)
 
     if args.calibrate_copy > 0:
         src = torch.ones(args.calibrate_copy * (1 << 20) // 4, dtype=torch.float32, device=dev)
@@ -325,65 +463,110 @@ def main() -> int:
         torch.cuda.synchronize()
         del src, dst
 
-    streams = args.streams if spec.get("batch") else 0
-    keep = []
-    for _ in range(max(1, args.warmup)):
-        keep.clear()
-        RANKS.clear()
-        run_step(inputs, spec, True, keep, streams)
+    keep, ranks = [], []
+    tuned, caps, converged, graph_form = None, None, None, None
+    if form == "graph":
+        graph_form = GraphForm(inputs, spec)
+        caps = graph_form.calibrate(keep)
+        print(f"bench: calibration run done, iteration caps {caps}", file=sys.stderr, flush=True)
+        if not (args.no_autotune or args.profile):
+            from paper_1511_03296_amd import autotune
+
+            def trial():
+                graph_form.build()
+                return lambda: graph_form.eager(True)
+            tuned = autotune.tune_plan(trial, [p.C for p in problems])
+            print(f"bench: autotuned tiles per block {tuned}", file=sys.stderr, flush=True)
+        graph_form.build()
+        graph_form.capture()
+        for _ in range(max(1, args.warmup)):
+            graph_form.step(True)
         torch.cuda.synchronize()
-        print("bench: warmup step done", file=sys.stderr, flush=True)
-    tuned = None
-    if streams and not args.no_autotune:
-        from paper_1511_03296_amd import autotune
-        # lane widths of the systems the batched PCG runs: the reduced ranks
-        # of a low-rank workload, else the channel counts
-        channels = list(RANKS) if RANKS else [p.C for p in problems]
-        tuned = autotune.tune_batch(lambda: run_step(inputs, spec, True, streams=streams),
-                                    channels)
-        print(f"bench: autotuned tiles per block {tuned}", file=sys.stderr, flush=True)
-    from paper_1511_03296_amd import read_stats
-    V = [v for v, _, _ in keep]
-    # PCG iterations per step (the robust solver's rounds each solve anew)
-    rounds = spec["robust"][1] if spec.get("robust") else 1
-    fwd_iters = [rounds * int(read_stats(st)["iters"].max()) for _, st, _ in keep]
-    bwd_iters = [0 if bst is None else int(read_stats(bst)["iters"].max()) for _, _, bst in keep]
-    C = problems[0].C
+        step = graph_form.step
+    elif form == "autograd":
+        autograd_stats(inputs, spec, keep)
+        for _ in range(max(1, args.warmup)):
+            autograd_step(inputs, spec, True)
+        step = lambda backward=True: autograd_step(inputs, spec, backward)
+    elif form == "lowrank":
+        lowrank_step(inputs, spec, keep=keep, ranks=ranks)
+        for _ in range(max(0, args.warmup - 1)):
+            lowrank_step(inputs, spec)
+        step = lambda backward=False: lowrank_step(inputs, spec)
+    else:
+        for _ in range(max(1, args.warmup)):
+            keep.clear()
+            single_step(inputs, spec, True, keep)
+        step = lambda backward=True: single_step(inputs, spec, backward)
+    torch.cuda.synchronize()
+    print("bench: warm-up done", file=sys.stderr, flush=True)
 
     t0 = time.perf_counter()
-    run_step(inputs, spec, True, streams=streams)
+    step(True)
     host_ms = (time.perf_counter() - t0) * 1e3
     torch.cuda.synchronize()
     print(f"bench: host time of one step's calls {host_ms:.3f} ms", file=sys.stderr, flush=True)
-    sec_fb = timed(inputs, spec, args.steps, backward=True, streams=streams)
-    sec_f = timed(inputs, spec, args.steps, backward=False, streams=streams)
-    print(f"bench: fwd+bwd {sec_fb * 1e3:.3f} ms/step, fwd {sec_f * 1e3:.3f} ms/step",
-          file=sys.stderr, flush=True)
-    plain = None
-    if spec.get("lowrank") is not None and not args.no_plain:
-        full = {k: v for k, v in spec.items() if k != "lowrank"}
-        sec_plain = timed(inputs, full, args.steps, backward=False, streams=0)
-        plain = pixels / sec_plain / 1e6
-        print(f"bench: full-rank single-image path fwd {sec_plain * 1e3:.3f} ms/step",
-              file=sys.stderr, flush=True)
-    elif streams and not args.no_plain:
-        sec_plain = timed(inputs, spec, args.steps, backward=True, streams=0)
-        plain = pixels / sec_plain / 1e6
-        print(f"bench: plain single-image path fwd+bwd {sec_plain * 1e3:.3f} ms/step",
-              file=sys.stderr, flush=True)
-    sec_inst, kt = kernel_times(inputs, spec, args.steps, streams)
-    mv_ms, mv_launches = kt["pcg_matvec"]
-    # Algorithmic bytes of one step's pcg_matvec launches over their summed
-    # durations (matvec_bytes).  Launches past convergence (between stop
-    # polls) return at once and count as time only.
-    solved_c = RANKS if RANKS else [p.C for p in problems]   # right-hand sides solved
-    step_bytes = sum(v * matvec_bytes(c, fi + bi) for v, c, fi, bi in
-                     zip(V, solved_c, fwd_iters, bwd_iters))
-    avg_us = mv_ms / mv_launches * 1e3 if mv_launches else float("nan")
-    bytes_per_launch = step_bytes / mv_launches if mv_launches else 0.0
-    achieved = step_bytes / (mv_ms * 1e-3) / 1e9 if mv_launches else 0.0
+    sec_fb = timed(lambda: step(True), args.steps)
+    if graph_form is not None:
+        converged = graph_form.converged()      # the backward runs' stats
+    sec_f = None
+    if not args.profile:
+        sec_f = timed(lambda: step(False), args.steps)
+        if graph_form is not None:
+            converged = converged and graph_form.converged()
+    print(f"bench: fwd+bwd {sec_fb * 1e3:.3f} ms/step, fwd "
+          f"{'-' if sec_f is None else round(sec_f * 1e3, 3)} ms/step", file=sys.stderr,
+          flush=True)
 
+    plain = None
+    if form in ("graph", "autograd", "lowrank") and not (args.no_plain or args.profile):
+        full = {k: v for k, v in spec.items() if k != "lowrank"}
+        bw = form != "lowrank"
+        sec_plain = timed(lambda: single_step(inputs, full, bw), args.steps)
+        plain = pixels / sec_plain / 1e6
+        print(f"bench: plain single-image path {sec_plain * 1e3:.3f} ms/step",
+              file=sys.stderr, flush=True)
+
+    # kernel durations: the same launches, each bracketed by events (the
+    # graph form runs its plan eagerly: the graph's launch sequence)
+    if graph_form is not None:
+        sec_inst, kt = kernel_times(lambda: graph_form.eager(True), args.steps)
+    else:
+        sec_inst, kt = kernel_times(lambda: step(True), args.steps)
+    mv_ms, mv_launches = kt["pcg_matvec"]
+    it_ms = kt["pcg_matvec"][0] + kt["pcg_update"][0] + kt["pcg_reduce"][0]
+
+    # algorithmic bytes of one step's PCG iterations (forward and backward),
+    # each channel counted for its own iterations
+    V = [v for v, _, _ in keep]
+    rounds = spec["robust"][1] if spec.get("robust") else 1
+    fwd_it = [rounds * read_stats(st)["iters"][: (ranks[i] if ranks else None)]
+              for i, (_, st, _) in enumerate(keep)]
+    bwd_it = [[] if bst is None else read_stats(bst)["iters"] for _, _, bst in keep]
+    step_bytes = sum(pcg_bytes(v, f) + pcg_bytes(v, b) for v, f, b in zip(V, fwd_it, bwd_it))
+    achieved = step_bytes / (mv_ms * 1e-3) / 1e9 if mv_ms > 0 else 0.0
+    achieved_it = step_bytes / (it_ms * 1e-3) / 1e9 if it_ms > 0 else 0.0
+    avg_us = mv_ms / mv_launches * 1e3 if mv_launches else float("nan")
+    # per lane width (the PCG launches' groups): images, vertices, bytes
+    groups = {}
+    from paper_1511_03296_amd import _lib as L
+    for i, (v, f, b) in enumerate(zip(V, fwd_it, bwd_it)):
+        c = ranks[i] if ranks else problems[i].C
+        if c == 0:
+            continue
+        gK = groups.setdefault(str(int(L.lib.bs_lane_width(int(c)))),
+                               {"images": 0, "vertices": 0, "pcg_bytes_per_step": 0})
+        gK["images"] += 1
+        gK["vertices"] += int(v)
+        gK["pcg_bytes_per_step"] += pcg_bytes(v, f) + pcg_bytes(v, b)
+    fwd_max = [int(max(f)) if len(f) else 0 for f in fwd_it]
+    bwd_max = [int(max(b)) if len(b) else 0 for b in bwd_it]
     traffic = _measured_traffic(args.workload)
+    C = problems[0].C
+    engine = {"single": "single-image path", "robust": "single-image path",
+              "graph": "batch plan, forward+backward graph replay",
+              "autograd": "batched autograd function (batch plan per call, convergence polls)",
+              "lowrank": "batched low-rank reduction"}[form]
 
     line = {
         "metric": METRIC,
@@ -406,31 +589,44 @@ def main() -> int:
                          "sigma_l = sigma_uv": "sigma_xy / 2"},
                    "lambda": problems[0].lam, "vertices": V[0] if len(V) == 1 else sum(V),
                    "fwd_pcg": list(spec["fwd"]), "bwd_pcg": list(spec["bwd"]),
-                   "fwd_iters": fwd_iters[0] if len(V) == 1 else _spread(fwd_iters),
-                   "bwd_iters": bwd_iters[0] if len(V) == 1 else _spread(bwd_iters),
+                   "fwd_iters": fwd_max[0] if len(V) == 1 else _spread(fwd_max),
+                   "bwd_iters": bwd_max[0] if len(V) == 1 else _spread(bwd_max),
                    **({"robust": {"sigma_gm": spec["robust"][0], "irls_rounds": rounds,
                                   "pass": "forward only"}} if spec.get("robust") else {}),
-                   **({"lowrank": {"eps": spec["lowrank"], "ranks": _histogram(RANKS),
+                   **({"lowrank": {"eps": spec["lowrank"], "ranks": _histogram(ranks),
                                    "pass": "forward only"}}
                       if spec.get("lowrank") is not None else {}),
+                   **({"graph": {"iteration_caps": list(caps),
+                                 "all_channels_stopped_on_tolerance": converged}}
+                      if caps else {}),
                    **({"tiles_per_block": {str(K): v["tiles"] for K, v in tuned.items()}}
                       if tuned else {}),
                    "parallelism": "single-gpu",
-                   "engine": f"batch, {streams} streams" if streams else "single-image"},
-        "fwd_mpix_s": round(pixels / sec_f / 1e6, 3),
+                   "engine": engine},
+        "fwd_mpix_s": None if sec_f is None else round(pixels / sec_f / 1e6, 3),
         "plain_mpix_s": None if plain is None else round(plain, 3),
         "vs_plain": None if plain is None else round(pixels / sec_fb / 1e6 / plain, 3),
+        "host_ms_per_step": round(host_ms, 3),
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic, "kernel": "pcg_matvec",
-                     "bytes_per_launch": int(bytes_per_launch), "avg_us": round(avg_us, 3),
-                     "launches_per_step": mv_launches},
+                     "bytes_per_launch": int(step_bytes / mv_launches) if mv_launches else 0,
+                     "avg_us": round(avg_us, 3), "launches_per_step": mv_launches,
+                     "bytes_rule": "48 + 24 x (channels still iterating) per vertex and "
+                                   "PCG iteration",
+                     "lane_width_groups": groups,
+                     "pcg_iteration": {"kernels": "pcg_matvec + pcg_update + pcg_reduce",
+                                       "ms_per_step": round(it_ms, 4),
+                                       "achieved": round(achieved_it, 1),
+                                       "frac": round(achieved_it / HBM_PEAK_GBS, 4)}},
         "kernel_ms_per_step": {k: round(v[0], 4) for k, v in kt.items()},
+        "kernel_launches_per_step": {k: v[1] for k, v in kt.items()},
         "instrumented_ms_per_step": round(sec_inst * 1e3, 4),
     }
-    if not args.no_cpu_baseline:
-        print("bench: cpu baseline (oracle)", file=sys.stderr, flush=True)
-        line["cpu_baseline"] = cpu_baseline(problems, spec, args.cpu_seconds)
+    if not (args.no_cpu_baseline or args.profile):
+        cores = args.cpu_cores or min(16, os.cpu_count() or 1)
+        print(f"bench: cpu baseline (oracle, {cores} processes)", file=sys.stderr, flush=True)
+        line["cpu_baseline"] = cpu_baseline(problems, spec, args.cpu_seconds, cores)
     print(json.dumps(line), flush=True)
     return 0
 

@@ -1,12 +1,14 @@
 """Autotuner of the batched PCG's block shape.
 
-The batched PCG launches one block per `tiles` tiles of vertices of an image
-(per lane width K: K consecutive channels of a vertex per lane).  Fewer tiles
-per block gives more, shorter blocks; more gives fewer, longer-running ones
-that amortise each block's prologue.  The best value depends on the batch's
-sizes and channel counts, so it is measured on the caller's own batch: a
-coordinate search over the lane widths present, timing one pass of the batch
-for each candidate with the other widths at their current choice.
+A batch plan sizes each lane width's PCG launch (K consecutive channels of a
+vertex per lane) at one block per `tiles` tiles of its images' estimated
+vertices; the launch's blocks are then shared among the images on the
+device, in proportion to their true work.  Fewer tiles per block gives more,
+shorter blocks; more gives fewer, longer-running ones that amortise each
+block's prologue.  The best value depends on the batch's sizes and channel
+counts, so it is measured on the caller's own batch: a coordinate search over
+the lane widths present, timing one pass of the batch for each candidate with
+the other widths at their current choice.
 """
 from __future__ import annotations
 
@@ -61,6 +63,24 @@ def tune_batch(step, channels, candidates=CANDIDATES, repeats: int = 2) -> dict:
         for t in candidates:
             set_tiles(K, t)
             step()   # warm-up with this shape
+            times[t] = _time(step, repeats)
+        pick = min(times, key=times.get)
+        set_tiles(K, pick)
+        out[K] = {"tiles": pick, "seconds": {t: round(v, 5) for t, v in times.items()}}
+    return out
+
+
+def tune_plan(trial, channels, candidates=CANDIDATES, repeats: int = 2) -> dict:
+    """As tune_batch, for batch plans, which read the tiles per block when
+    they are made: `trial()` makes the plan anew and returns a function that
+    runs one pass of it."""
+    out = {}
+    for K in lane_widths(channels):
+        times = {}
+        for t in candidates:
+            set_tiles(K, t)
+            step = trial()
+            step()
             times[t] = _time(step, repeats)
         pick = min(times, key=times.get)
         set_tiles(K, pick)

@@ -1,4 +1,4 @@
-"""Host logic of bench.py: algorithmic bytes of the matvec forms, and the
+"""Host logic of bench.py: algorithmic bytes of the PCG iterations, and the
 rule that a committed HBM-traffic figure is reported only while the machine
 code of every kernel it was measured on is unchanged.  No GPU."""
 import json
@@ -6,12 +6,13 @@ import json
 import bench
 
 
-def test_matvec_bytes_counts_each_form():
-    # every 4th iteration is the exact form (52 + 24C), the others the
-    # recurrence (48 + 28C)
-    for C in (1, 2, 21):
-        assert bench.matvec_bytes(C, 4) == (52 + 24 * C) + 3 * (48 + 28 * C)
-        assert bench.matvec_bytes(C, 3) == 3 * (48 + 28 * C)
+def test_pcg_bytes_counts_active_channels():
+    # 48 bytes per vertex and iteration while any channel iterates, plus 24
+    # per channel for its own iterations
+    assert bench.pcg_bytes(10, [5]) == 10 * (48 * 5 + 24 * 5)
+    assert bench.pcg_bytes(10, [5, 3, 0]) == 10 * (48 * 5 + 24 * 8)
+    assert bench.pcg_bytes(7, []) == 0
+    assert bench.pcg_bytes(3, [4] * 21) == 3 * 4 * (48 + 24 * 21)
 
 
 def test_traffic_needs_the_measured_machine_code(tmp_path, monkeypatch):
