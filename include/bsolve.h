@@ -464,6 +464,13 @@ bs_status bs_batch_set_tiles_per_block(int32_t K, int32_t tiles);
 int32_t bs_batch_tiles_per_block(int32_t K);
 /* The lane width of C channels (host, pure; 0 outside 1..64). */
 int32_t bs_lane_width(int32_t C);
+/* Sets the lane width of C channels (1..4; 0 restores the default rule:
+ * C for C <= 2, 4 when 4 divides C, 3 when 3 does, else 4).  The channel
+ * stride becomes C rounded up to a multiple of it.  Process-wide; read when a
+ * workspace is laid out (workspace queries, solves, batch plans), so a
+ * workspace sized before a change may be too small after it (BS_EWORKSPACE).
+ * For the autotuner.  BS_EINVAL out of range. */
+bs_status bs_set_lane_width(int32_t C, int32_t K);
 
 /* Scratch bytes of bs_batch_forward_lowrank: every image's solve workspace
  * and reduced system, plus the batched PCG's tables (0 for an invalid

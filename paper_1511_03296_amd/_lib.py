@@ -132,6 +132,7 @@ _SIGS = {
     "bs_batch_set_tiles_per_block": (_i32, [_i32, _i32]),
     "bs_batch_tiles_per_block": (_i32, [_i32]),
     "bs_lane_width": (_i32, [_i32]),
+    "bs_set_lane_width": (_i32, [_i32, _i32]),
     "bs_batch_forward_lowrank": (_i32, [ct.POINTER(BatchItem), _i32, ct.POINTER(SolveParams),
                                         ct.POINTER(BistochParams), ct.POINTER(Grid), _i32,
                                         ct.c_double, ct.POINTER(_i32), _vp, _sz, _vp]),

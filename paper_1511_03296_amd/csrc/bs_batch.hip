@@ -311,6 +311,17 @@ struct PlanImpl {
     const SchedDesc* descs = nullptr;
     int ndesc = 0;
     std::vector<Group> groups;
+    // the lane-width groups' PCGs run concurrently: group g > 0 on library
+    // stream g, forked from and joined back into the run's stream by events
+    hipEvent_t fork = nullptr;
+    std::vector<hipEvent_t> join;
+    std::vector<hipStream_t> gstream;
+
+    ~PlanImpl() {
+        if (fork) (void)hipEventDestroy(fork);
+        for (hipEvent_t e : join)
+            if (e) (void)hipEventDestroy(e);
+    }
 };
 
 namespace {
@@ -794,12 +805,37 @@ bs_status run_setup(const PlanImpl& P, int dir, hipStream_t s) {
     return BS_OK;
 }
 
+// The PCG of every lane-width group.  The groups are independent: the
+// smaller groups' launches (latency-bound for one- and two-channel images)
+// run on their own streams beside the largest group's.  With convergence
+// polls or kernel timing they run one after another on `s` (a poll
+// synchronises its stream; a timed launch should have the device to itself).
 bs_status run_pcg_groups(const PlanImpl& P, int dir, hipStream_t s) {
-    for (const Group& gr : P.groups) {
-        const bs_status st = run_pcg(gr.K, gr.himg[dir].data(), (int)gr.members.size(), gr.dimg[dir],
-                                     gr.blk2img, gr.G, gr.max_cp, P.prm[dir], gr.act, s);
-        if (st != BS_OK) return st;
+    const int ng = (int)P.groups.size();
+    const bool concurrent = ng > 1 && P.prm[dir].check_every == 0 && !timing_enabled() &&
+                            (int)P.gstream.size() >= ng && P.fork;
+    auto group = [&](int g, hipStream_t st) {
+        const Group& gr = P.groups[g];
+        return run_pcg(gr.K, gr.himg[dir].data(), (int)gr.members.size(), gr.dimg[dir],
+                       gr.blk2img, gr.G, gr.max_cp, P.prm[dir], gr.act, st);
+    };
+    if (!concurrent) {
+        for (int g = 0; g < ng; ++g) {
+            const bs_status st = group(g, s);
+            if (st != BS_OK) return st;
+        }
+        return BS_OK;
     }
+    BS_TRY_HIP(hipEventRecord(P.fork, s));
+    for (int g = 1; g < ng; ++g) {
+        BS_TRY_HIP(hipStreamWaitEvent(P.gstream[g], P.fork, 0));
+        const bs_status st = group(g, P.gstream[g]);
+        if (st != BS_OK) return st;
+        BS_TRY_HIP(hipEventRecord(P.join[g], P.gstream[g]));
+    }
+    bs_status st = group(0, s);
+    if (st != BS_OK) return st;
+    for (int g = 1; g < ng; ++g) BS_TRY_HIP(hipStreamWaitEvent(s, P.join[g], 0));
     return BS_OK;
 }
 
@@ -862,6 +898,17 @@ bs_status make_plan(const bs_batch_item* items, int n, const bs_solve_params* fw
     BS_TRY_HIP(hipMemcpyAsync((char*)ws + P.img_bytes, b.host.data(), b.host.size(),
                               hipMemcpyHostToDevice, stream));
     BS_TRY_HIP(hipStreamSynchronize(stream));
+    const int ng = (int)P.groups.size();
+    if (ng > 1) {
+        BS_TRY_HIP(hipEventCreateWithFlags(&P.fork, hipEventDisableTiming));
+        P.join.assign(ng, nullptr);
+        P.gstream.assign(ng, nullptr);
+        for (int g = 1; g < ng; ++g) {
+            BS_TRY_HIP(hipEventCreateWithFlags(&P.join[g], hipEventDisableTiming));
+            st = library_stream(g, &P.gstream[g]);
+            if (st != BS_OK) return st;
+        }
+    }
     P.magic = kPlanMagic;
     return BS_OK;
 }

@@ -45,6 +45,18 @@ bs_status side_stream(hipStream_t s, hipStream_t* out) {
     return BS_OK;
 }
 
+bs_status library_stream(int index, hipStream_t* out) {
+    hipStream_t any;
+    const bs_status st = side_stream(nullptr, &any);   // creates the device's streams once
+    if (st != BS_OK) return st;
+    int dev = 0;
+    BS_TRY_HIP(hipGetDevice(&dev));
+    SideStreams& ss = sides();
+    std::lock_guard<std::mutex> lock(ss.mu);
+    *out = ss.per_device[dev][index % kSideStreams];
+    return BS_OK;
+}
+
 }  // namespace bs
 
 using namespace bs;

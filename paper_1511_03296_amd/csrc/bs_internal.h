@@ -194,6 +194,8 @@ bs_status build_pyramid(const GridImpl& g, hipStream_t s);
 // A library-owned stream of the current device paired with `s` (default
 // priority, created once), for work that may overlap work on `s`.
 bs_status side_stream(hipStream_t s, hipStream_t* out);
+// Library-owned stream `index` (of 8) of the current device.
+bs_status library_stream(int index, hipStream_t* out);
 
 // Lays out (or sizes, with base == nullptr) a grid for an H x W image.
 // Returns the bytes used; fills `g` when base != nullptr.

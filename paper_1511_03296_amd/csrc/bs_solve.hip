@@ -33,6 +33,7 @@
 // state, partials and stopping rule.
 #include "bs_setup_ops.h"
 #include "bs_solve_impl.h"
+#include <atomic>
 #include <type_traits>
 
 namespace bs {
@@ -1129,6 +1130,12 @@ bs_status solve_setup(const GridImpl& g, const SolveWs& w, const float* conf, co
 
 bool pcg_partials_fit(int Cp, int nb) { return PartialSums::fits(3 * Cp, nb); }
 
+static std::atomic<int> g_lane_override[BS_MAX_CHANNELS + 1];
+
+int lane_width_override(int C) {
+    return (C < 1 || C > BS_MAX_CHANNELS) ? 0 : g_lane_override[C].load(std::memory_order_relaxed);
+}
+
 PcgImage make_image(const GridImpl& g, const SolveWs& w, float lam, float* yw,
                     bs_chan_stats* stats) {
     PcgImage I;
@@ -1288,6 +1295,13 @@ extern "C" bs_status bs_solve_ws_view(const bs_grid* grid, int32_t C, void* ws, 
     if (sc) *sc = w.sc;
     if (diag) *diag = w.diag;
     if (minv) *minv = w.minv;
+    return BS_OK;
+}
+
+extern "C" bs_status bs_set_lane_width(int32_t C, int32_t K) {
+    if (C < 1 || C > BS_MAX_CHANNELS) return fail(BS_EINVAL, "channel count must be in 1..64");
+    if (K < 0 || K > 4) return fail(BS_EINVAL, "lane width must be in 0..4");
+    g_lane_override[C].store(K, std::memory_order_relaxed);
     return BS_OK;
 }
 

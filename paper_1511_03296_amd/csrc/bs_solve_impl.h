@@ -25,12 +25,19 @@ static_assert(sizeof(ChanRec) == 128, "one record per cache line");
 // Channels per lane of the vertex kernels (1, 2, 3 or 4: one float, float2,
 // 3-float or float4 access) and the channel stride of the bilateral-space
 // vectors, C rounded up to a multiple of the lane width (C = 21 = 7 x 3
-// needs no padding).
-inline int lane_width(int C) {
+// needs no padding).  The default rule takes the widest access that needs
+// little padding; bs_set_lane_width replaces it for a channel count (read
+// when a workspace is laid out).
+inline int default_lane_width(int C) {
     if (C <= 2) return C;
     if (C % 4 == 0) return 4;
     if (C % 3 == 0) return 3;
     return 4;
+}
+int lane_width_override(int C);   // 0: none
+inline int lane_width(int C) {
+    const int k = lane_width_override(C);
+    return k > 0 ? k : default_lane_width(C);
 }
 inline int padded_channels(int C) {
     const int K = lane_width(C);
