@@ -351,6 +351,12 @@ bs_status validate_items(const bs_batch_item* items, int n, bool backward) {
         if (it.C < 1 || it.C > BS_MAX_CHANNELS) return fail(BS_EINVAL, tag + "bad channel count");
         const size_t need = bs_grid_workspace_bytes(it.H, it.W, &it.sigma);
         if (need == 0) return fail(BS_EINVAL, tag + bs_last_error());
+        {
+            GridImpl g;
+            layout_grid(g, it.H, it.W, it.sigma, nullptr);
+            if (!solve_fits(g.vcap, it.C))
+                return fail(BS_EUNSUPPORTED, tag + "grid too large for 32-bit vector offsets");
+        }
         if (it.grid_ws && it.grid_ws_bytes < need)
             return fail(BS_EWORKSPACE, tag + "grid workspace needs " + std::to_string(need));
         if (((uintptr_t)it.grid_ws & 255) != 0)

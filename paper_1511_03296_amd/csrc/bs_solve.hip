@@ -131,6 +131,34 @@ __device__ inline void stv(gp<float> p, const Vec<K>& a) {
     }
 }
 
+// Element e of a vector as a 32-bit byte offset from its base: the base is
+// uniform over the block, so the loads and stores take the offset as their
+// only address register (no 64-bit address arithmetic per gather).  The
+// host keeps every [Vcap][Cp] vector below 2^30 elements.
+template <class T>
+__device__ inline gp<T> elem(gp<T> base, uint32_t e) {
+    using C = std::conditional_t<std::is_const_v<T>, const char, char>;
+    return reinterpret_cast<gp<T>>(reinterpret_cast<gp<C>>(base) + (e * (uint32_t)sizeof(T)));
+}
+
+template <int K>
+__device__ inline Vec<K> ldv(gp<const float> base, uint32_t e) {
+    return ldv<K>(elem(base, e));
+}
+template <int K>
+__device__ inline Vec<K> ldv(gp<float> base, uint32_t e) {
+    return ldv<K>(elem((gp<const float>)base, e));
+}
+template <int K>
+__device__ inline void stv(gp<float> base, uint32_t e, const Vec<K>& a) {
+    stv<K>(elem(base, e), a);
+}
+
+// Element offset of lane g's K channels of vertex v (stride Cp).
+__device__ inline uint32_t lane_elem(int v, int Cp, int g, int K) {
+    return (uint32_t)v * (uint32_t)Cp + (uint32_t)(g * K);
+}
+
 // Lane geometry of one image: lane t owns channels [g K, g K + K) of the
 // tile's vertex vl.
 struct Lanes {
@@ -577,8 +605,8 @@ __global__ void __launch_bounds__(kRedBlock) pcg_start(PcgArgs a) {
     for (int64_t tile = tl.first; tile < tl.end; tile += tl.step) {
         const int v = (int)(tile * ln.vpb) + ln.vl;
         if (!ln.ok || v >= V) continue;
-        const int64_t e = (int64_t)v * Cp + ln.g * K;
-        const Vec<K> yv = ldv<K>(I.y + e);
+        const uint32_t e = lane_elem(v, Cp, ln.g, K);
+        const Vec<K> yv = ldv<K>(I.y, e);
         float ns[K];
 #pragma unroll
         for (int k = 0; k < K; ++k) ns[k] = 0.0f;
@@ -588,15 +616,15 @@ __global__ void __launch_bounds__(kRedBlock) pcg_start(PcgArgs a) {
         for (int j = 0; j < 10; ++j) {
             const int u = nbv[j];
             if (u >= 0) {
-                const float nu = I.nfm[u].x;
-                const Vec<K> yu = ldv<K>(I.y + (int64_t)u * Cp + ln.g * K);
+                const float nu = elem(I.nfm, (uint32_t)u)->x;
+                const Vec<K> yu = ldv<K>(I.y, lane_elem(u, Cp, ln.g, K));
 #pragma unroll
                 for (int k = 0; k < K; ++k) ns[k] += nu * (yv.v[k] - yu.v[k]);
             }
         }
-        const float2 nmv = I.nfm[v];
+        const float2 nmv = *elem(I.nfm, (uint32_t)v);
         const float scv = I.sc[v];
-        const Vec<K> bv = ldv<K>(I.b + e);
+        const Vec<K> bv = ldv<K>(I.b, e);
         Vec<K> rv;
 #pragma unroll
         for (int k = 0; k < K; ++k) {
@@ -606,8 +634,8 @@ __global__ void __launch_bounds__(kRedBlock) pcg_start(PcgArgs a) {
             acc[1][k] += (double)bv.v[k] * (double)bv.v[k];
             acc[2][k] += (double)rv.v[k] * (double)(nmv.y * rv.v[k]);
         }
-        stv<K>(I.r + e, rv);
-        if constexpr (uses_recurrence<K>()) stv<K>(I.w + e, scaled_residual<K>(rv, nmv));
+        stv<K>(I.r, e, rv);
+        if constexpr (uses_recurrence<K>()) stv<K>(I.w, e, scaled_residual<K>(rv, nmv));
     }
     lane_partials<3, K>(acc, ln, Cp, nb, partial_slot(jb, nb), I.part0);
 }
@@ -641,23 +669,23 @@ __device__ inline void load_ops(MatOps<K, EXACT>& o, int v, const int (&nb)[10],
         o.nb[j] = nb[j];
         const int u = nb[j];
         if (u >= 0) {
-            const int64_t eu = (int64_t)u * Cp + ln.g * K;
+            const uint32_t eu = lane_elem(u, Cp, ln.g, K);
             if constexpr (EXACT) {
-                o.g[j] = ldv<K>(I.r + eu);
-                o.d[j] = ldv<K>(din + eu);
-                o.nm[j] = I.nfm[u];
+                o.g[j] = ldv<K>(I.r, eu);
+                o.d[j] = ldv<K>(din, eu);
+                o.nm[j] = *elem(I.nfm, (uint32_t)u);
             } else {
-                o.g[j] = ldv<K>(I.w + eu);
+                o.g[j] = ldv<K>(I.w, eu);
             }
         }
     }
-    const int64_t e = (int64_t)v * Cp + ln.g * K;
-    o.rv = ldv<K>(I.r + e);
-    o.dv = ldv<K>(din + e);
-    o.yv = ldv<K>(I.y + e);
-    o.nmv = I.nfm[v];
+    const uint32_t e = lane_elem(v, Cp, ln.g, K);
+    o.rv = ldv<K>(I.r, e);
+    o.dv = ldv<K>(din, e);
+    o.yv = ldv<K>(I.y, e);
+    o.nmv = *elem(I.nfm, (uint32_t)v);
     if constexpr (EXACT) o.scv = I.sc[v];
-    else o.qv = ldv<K>(I.q + e);
+    else o.qv = ldv<K>(I.q, e);
 }
 
 // load_ops from the packed words of load_nbr_words.
@@ -681,14 +709,14 @@ __device__ inline void load_ops_late(MatOps<K, EXACT>& o, int v, const int (&raw
         const uint32_t wd = (uint32_t)raw[j >> 1];
         const int u = unpack_offset(v, (j & 1) ? wd >> 16 : wd & 0xffffu);
         o.nb[j] = u;
-        if (u >= 0) o.g[j] = ldv<K>(I.w + (int64_t)u * Cp + ln.g * K);
+        if (u >= 0) o.g[j] = ldv<K>(I.w, lane_elem(u, Cp, ln.g, K));
     }
-    const int64_t e = (int64_t)v * Cp + ln.g * K;
-    o.rv = ldv<K>(I.r + e);
-    o.dv = ldv<K>(din + e);
-    o.yv = ldv<K>(I.y + e);
-    o.nmv = I.nfm[v];
-    o.qv = ldv<K>(I.q + e);
+    const uint32_t e = lane_elem(v, Cp, ln.g, K);
+    o.rv = ldv<K>(I.r, e);
+    o.dv = ldv<K>(din, e);
+    o.yv = ldv<K>(I.y, e);
+    o.nmv = *elem(I.nfm, (uint32_t)v);
+    o.qv = ldv<K>(I.q, e);
     }
 }
 
@@ -844,10 +872,10 @@ __global__ void __launch_bounds__(kRedBlock) pcg_matvec(PcgArgs a, int src) {
 #pragma unroll
             for (int k = 0; k < K; ++k)
                 yv.v[k] = pnd[k] ? fmaf(alpha[k], o.dv.v[k], o.yv.v[k]) : o.yv.v[k];
-            const int64_t e = (int64_t)o.v * Cp + ln.g * K;
-            stv<K>(I.y + e, yv);
-            stv<K>(dout + e, dv);
-            stv<K>(I.q + e, qv);
+            const uint32_t e = lane_elem(o.v, Cp, ln.g, K);
+            stv<K>(I.y, e, yv);
+            stv<K>(dout, e, dv);
+            stv<K>(I.q, e, qv);
 #pragma unroll
             for (int k = 0; k < K; ++k)
                 if (act[k]) acc[0][k] += (double)dv.v[k] * (double)qv.v[k];
@@ -891,10 +919,10 @@ __global__ void __launch_bounds__(kRedBlock) pcg_update(PcgArgs a, int want_w) {
     Vec<K> rv, qv;
     float2 nmv = make_float2(0.0f, 0.0f);
     if (have) {
-        const int64_t e = (int64_t)v * Cp + ln.g * K;
-        rv = ldv<K>(I.r + e);
-        qv = ldv<K>(I.q + e);
-        nmv = I.nfm[v];
+        const uint32_t e = lane_elem(v, Cp, ln.g, K);
+        rv = ldv<K>(I.r, e);
+        qv = ldv<K>(I.q, e);
+        nmv = *elem(I.nfm, (uint32_t)v);
     }
     ps.sum(I.part1, fin);
     if (t == 0) n_active = 0;
@@ -938,10 +966,10 @@ __global__ void __launch_bounds__(kRedBlock) pcg_update(PcgArgs a, int want_w) {
         Vec<K> rn, qn;
         float2 nmn = make_float2(0.0f, 0.0f);
         if (hn) {
-            const int64_t e = (int64_t)vn * Cp + ln.g * K;
-            rn = ldv<K>(I.r + e);
-            qn = ldv<K>(I.q + e);
-            nmn = I.nfm[vn];
+            const uint32_t e = lane_elem(vn, Cp, ln.g, K);
+            rn = ldv<K>(I.r, e);
+            qn = ldv<K>(I.q, e);
+            nmn = *elem(I.nfm, (uint32_t)vn);
         }
         if (any && have) {
             Vec<K> r1;
@@ -955,10 +983,10 @@ __global__ void __launch_bounds__(kRedBlock) pcg_update(PcgArgs a, int want_w) {
                     r1.v[k] = rv.v[k];
                 }
             }
-            const int64_t e = (int64_t)v * Cp + ln.g * K;
-            stv<K>(I.r + e, r1);
+            const uint32_t e = lane_elem(v, Cp, ln.g, K);
+            stv<K>(I.r, e, r1);
             if constexpr (uses_recurrence<K>()) {
-                if (want_w) stv<K>(I.w + e, scaled_residual<K>(r1, nmv));
+                if (want_w) stv<K>(I.w, e, scaled_residual<K>(r1, nmv));
             }
         }
         v = vn;
@@ -1009,13 +1037,13 @@ __global__ void __launch_bounds__(kRedBlock) pcg_flush(PcgArgs a, int src) {
     for (int64_t tile = tl.first; tile < tl.end; tile += tl.step) {
         const int v = (int)(tile * ln.vpb) + ln.vl;
         if (v >= V) continue;
-        const int64_t e = (int64_t)v * Cp + ln.g * K;
-        const Vec<K> dv = ldv<K>(d + e);
-        Vec<K> yv = ldv<K>(I.y + e);
+        const uint32_t e = lane_elem(v, Cp, ln.g, K);
+        const Vec<K> dv = ldv<K>(d, e);
+        Vec<K> yv = ldv<K>(I.y, e);
 #pragma unroll
         for (int k = 0; k < K; ++k)
             if (alpha[k] != 0.0f) yv.v[k] = fmaf(alpha[k], dv.v[k], yv.v[k]);
-        stv<K>(I.y + e, yv);
+        stv<K>(I.y, e, yv);
     }
 }
 
@@ -1065,6 +1093,8 @@ bs_status validate_solve(const bs_grid* grid, int C, const bs_solve_params* p) {
     if (!grid || impl(grid)->magic != kGridMagic) return fail(BS_EINVAL, "grid was not built");
     if (!impl(grid)->bistochastized) return fail(BS_EINVAL, "grid was not bistochastized");
     if (C < 1 || C > BS_MAX_CHANNELS) return fail(BS_EINVAL, "channel count must be in 1..64");
+    if (!solve_fits(impl(grid)->vcap, C))
+        return fail(BS_EUNSUPPORTED, "grid too large for 32-bit vector offsets at this channel count");
     if (!p) return fail(BS_EINVAL, "solve params is NULL");
     if (!(p->lambda >= 0.0f) || !std::isfinite(p->lambda))
         return fail(BS_EINVAL, "lambda must be finite and >= 0");

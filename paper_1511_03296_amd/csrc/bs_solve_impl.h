@@ -44,6 +44,13 @@ inline int padded_channels(int C) {
     return (C + K - 1) / K * K;
 }
 
+// The PCG kernels address a vector element by a 32-bit byte offset from the
+// vector's base: every [Vcap][Cp] float vector, and the packed neighbour
+// table [5][Vcap], must stay below 2^30 elements (4 GiB).
+inline bool solve_fits(int64_t vcap, int C) {
+    return vcap * padded_channels(C) < ((int64_t)1 << 30) && 5 * vcap < ((int64_t)1 << 30);
+}
+
 // One image of a PCG launch.  In a launch over several images, blocks
 // [block0, block0 + nb) work on this image; block0 and nb are multiples of 8,
 // so the image's local block j runs on die j % 8.  Vectors are [V][Cp].

@@ -5,6 +5,9 @@ batch engine on 4 streams, forward and backward with the bench's tolerances
 and upstream gradients.  Every image's channels must stop on the tolerance;
 images the oracle can solve in seconds (the smallest of each channel count,
 or the first) are compared with it, forward and backward."""
+import json
+import os
+
 import numpy as np
 import pytest
 import torch
@@ -17,6 +20,7 @@ from tests.gpu_helpers import check_grad_c, rel_l2, say
 pytestmark = [pytest.mark.gpu, pytest.mark.slow]
 
 TOL = 1e-4
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
 
 
 def test_mixed64_batch_in_bench_configuration():
@@ -56,6 +60,25 @@ def test_mixed64_batch_in_bench_configuration():
         # confidences U[0, 1]: dL/dc through c o dL/dc (check_grad_c)
         plain, weighted = check_grad_c(gcs[i].cpu().numpy(), og.grad_c, p.conf, TOL)
         say(f"    dL/dc rel-L2 {plain:.2e}, c o dL/dc {weighted:.2e}")
+    # the largest image, the widest (next to the packed table's 16-bit bound)
+    # and the widest 21-channel image against the oracle's stored samples
+    # (tests/golden/make_golden.py, the same solves in float64)
+    for i in (4, 7, 10):
+        with open(os.path.join(GOLDEN, f"mixed64_image{i}.json")) as f:
+            gold = json.load(f)
+        p = probs[i]
+        assert (gold["W"], gold["H"], gold["C"]) == (p.W, p.H, p.C)
+        ch, px = np.array(gold["channels"]), np.array(gold["pixels"])
+        x = xs[i].cpu().numpy().reshape(p.C, -1)[ch, px]
+        gt = gts[i].cpu().numpy().reshape(p.C, -1)[ch, px]
+        pc = np.array(gold["grad_c_pixels"])
+        gc = gcs[i].cpu().numpy().reshape(-1)[pc]
+        ex, et = rel_l2(x, gold["x"]), rel_l2(gt, gold["grad_t"])
+        ec = rel_l2(np.array(gold["conf_at_grad_c_pixels"]) * gc,
+                    np.array(gold["conf_at_grad_c_pixels"]) * np.array(gold["grad_c"]))
+        say(f"  golden image {i} ({p.W}x{p.H} C={p.C}): x {ex:.2e}, dL/dt {et:.2e}, "
+            f"c o dL/dc {ec:.2e} on 1024 samples")
+        assert ex <= TOL and et <= TOL and ec <= TOL, (i, ex, et, ec)
 
 
 def test_seg16_batch_in_bench_configuration():

@@ -248,6 +248,31 @@ def test_full_size_stereo_backward():
     check_grad_c(gc.cpu().numpy(), og.grad_c, p.conf)
 
 
+@pytest.mark.parametrize("h,w", [(240, 320), (480, 640)])
+def test_depth_backward_crop(h, w):
+    """The depth workload's backward pass as bench.py runs it: a centre crop
+    (on the 16-pixel sample grid, so 1 pixel in 256 keeps confidence 1 and
+    the rest 0), forward and adjoint PCG to 1e-5, and the confidence-weighted
+    upstream gradient, for which the singular adjoint system is consistent:
+    x, dL/dt and dL/dc against the oracle's same-algorithm solves."""
+    full = WL.depth_superres()
+    y0 = (full.H - h) // 2 // 16 * 16
+    x0 = (full.W - w) // 2 // 16 * 16
+    p = WL.crop(full, y0, x0, h, w)
+    say(f"depth backward crop {w}x{h} at ({x0}, {y0})")
+    G, ws, y, x, st, sol, prm = _solve_both(p)
+    gx = WL.random_grad(0, 1, h, w) * p.conf[None]
+    gt, gc, _, bst = G.backward(to_dev(p.target), to_dev(p.conf), y, to_dev(gx), prm.lam,
+                                max_iters=prm.max_iters, rel_tol=prm.rel_tol, ws=ws)
+    torch.cuda.synchronize()
+    from paper_1511_03296_amd import read_stats
+    assert read_stats(st)[0]["reason"] == 1 and read_stats(bst)[0]["reason"] == 1
+    og = O.solve_backward(sol, p.target, p.conf, gx, prm)
+    assert rel_l2(x.cpu().numpy(), sol.x) <= TOL_X
+    assert rel_l2(gt.cpu().numpy(), og.grad_t) <= TOL_X
+    check_grad_c(gc.cpu().numpy(), og.grad_c, p.conf)
+
+
 def test_full_size_depth_2048x1536():
     """Depth super-resolution workload at full size (V ~ 1.6M): grid and
     bistochastization bit-exact / 1e-12 against the oracle; the solution at
