@@ -168,6 +168,7 @@ def single_step(inputs, spec, backward=True, keep=None):
     (fi, ft), (bi, bt) = spec["fwd"], spec["bwd"]
     fce = 0 if ft == 0.0 else 8
     bce = 0 if bt == 0.0 else 8
+    pre = spec.get("precond", "jacobi")
     for d in inputs:
         p = d["p"]
         G = BilateralGrid(d["ref"], p.sigma_xy, p.sigma_l, p.sigma_uv)
@@ -179,12 +180,13 @@ def single_step(inputs, spec, backward=True, keep=None):
                 keep.append((G.vertex_count(), st, None))
             continue
         ws = G.solve_workspace(p.C)
-        y, st = G.solve(d["t"], d["c"], p.lam, max_iters=fi, rel_tol=ft, check_every=fce, ws=ws)
+        y, st = G.solve(d["t"], d["c"], p.lam, max_iters=fi, rel_tol=ft, check_every=fce, ws=ws,
+                        precond=pre)
         G.slice(y, p.C)
         bst = None
         if backward and bi > 0:
             _, _, _, bst = G.backward(d["t"], d["c"], y, d["gx"], p.lam, max_iters=bi, rel_tol=bt,
-                                      check_every=bce, ws=ws)
+                                      check_every=bce, ws=ws, precond=pre)
         if keep is not None:
             keep.append((G.vertex_count(), st, bst))
 
@@ -428,6 +430,9 @@ def main() -> int:
                          "them on the batch first")
     ap.add_argument("--no-plain", action="store_true",
                     help="batched forms: skip the single-image comparison (counter runs)")
+    ap.add_argument("--precond", default="jacobi", choices=["jacobi", "hier"],
+                    help="PCG preconditioner; the hierarchical one runs image after image "
+                         "through the single-image path")
     ap.add_argument("--profile", action="store_true",
                     help="the launches of forward+backward steps only, for a profiler's "
                          "kernel trace: no autotuning, single-image comparison, "
@@ -448,7 +453,15 @@ def main() -> int:
         return 1
     from paper_1511_03296_amd import read_stats
     dev = torch.device("cuda:0")
-    spec = WORKLOADS[args.workload]
+    spec = dict(WORKLOADS[args.workload])
+    if args.precond != "jacobi":
+        if spec["form"] in ("lowrank", "robust"):
+            print("the low-rank and robust workloads use the Jacobi preconditioner",
+                  file=sys.stderr)
+            return 2
+        spec["precond"] = args.precond
+        if spec["form"] in ("graph", "autograd"):
+            spec["form"] = "single"
     form = spec["form"]
     problems = make_problems(args.workload)
     inputs = gpu_inputs(problems, spec, dev)
@@ -601,6 +614,7 @@ def main() -> int:
                       if caps else {}),
                    **({"tiles_per_block": {str(K): v["tiles"] for K, v in tuned.items()}}
                       if tuned else {}),
+                   "precond": args.precond,
                    "parallelism": "single-gpu",
                    "engine": engine},
         "fwd_mpix_s": None if sec_f is None else round(pixels / sec_f / 1e6, 3),

@@ -89,8 +89,16 @@ typedef struct bs_bistoch_params {
 } bs_bistoch_params;
 
 enum { BS_INIT_FLAT = 0, BS_INIT_HIER = 1 };
+enum { BS_PRECOND_JACOBI = 0, BS_PRECOND_HIER = 1 };
 
 /* The solve (Eq. quad_min, supplement Algorithm 2, Section 4).
+ * Preconditioner (Section 4, Eq. hier_precond): the Jacobi inverse
+ * 1 / diag(A), or the hierarchical M_hier^-1 r = P^T(s o P(r)) with level
+ * scales s_k = pre_alpha^-(pre_beta + k) P(1)_k / P(diag A)_k for k >= 1 and
+ * 1 / diag(A) at k = 0 (a coefficient with P(diag A) = 0 is 0).  With the
+ * hierarchical preconditioner every PCG iteration applies A directly and runs
+ * the preconditioner's pyramid passes (about 2 K launches per iteration);
+ * single-image solves only (batch plans return BS_EUNSUPPORTED).
  * One PCG per channel with its own scalars.  A channel stops when its
  * recursive ||r|| / ||b|| <= rel_tol (rel_tol = 0: never), after max_iters
  * iterations, when r^T s = 0, or when d^T A d <= 0.  `check_every` works as
@@ -104,6 +112,9 @@ typedef struct bs_solve_params {
     double rel_tol;        /* relative residual target, 0 = fixed iterations    */
     float init_alpha;      /* hierarchical init level weighting, default 4      */
     float init_beta;       /* default 0                                         */
+    int32_t precond;       /* BS_PRECOND_JACOBI (default) or BS_PRECOND_HIER     */
+    float pre_alpha;       /* hierarchical preconditioner level weighting,     */
+    float pre_beta;        /* default 2 and 5                                   */
 } bs_solve_params;
 
 /* Per-channel outcome, written to device memory by a solve. */

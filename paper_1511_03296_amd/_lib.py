@@ -18,6 +18,7 @@ BS_MAX_CHANNELS = 64
 BS_MAX_LEVELS = 24
 BS_GRID_BYTES = 4096
 BS_INIT_FLAT, BS_INIT_HIER = 0, 1
+BS_PRECOND_JACOBI, BS_PRECOND_HIER = 0, 1
 BS_NOALLOC_SCRATCH_BYTES = 64 << 20
 
 # Slots of the device counter array.
@@ -37,7 +38,8 @@ class BistochParams(ct.Structure):
 class SolveParams(ct.Structure):
     _fields_ = [("lambda_", ct.c_float), ("init", ct.c_int32), ("max_iters", ct.c_int32),
                 ("check_every", ct.c_int32), ("rel_tol", ct.c_double),
-                ("init_alpha", ct.c_float), ("init_beta", ct.c_float)]
+                ("init_alpha", ct.c_float), ("init_beta", ct.c_float),
+                ("precond", ct.c_int32), ("pre_alpha", ct.c_float), ("pre_beta", ct.c_float)]
 
 
 class ChanStats(ct.Structure):

@@ -339,6 +339,8 @@ bs_status check_params(const bs_solve_params* p) {
         return fail(BS_EINVAL, "init_alpha must be positive");
     if (p->init == BS_INIT_HIER && !std::isfinite(p->init_beta))
         return fail(BS_EINVAL, "init_beta must be finite");
+    if (p->precond != BS_PRECOND_JACOBI)
+        return fail(BS_EUNSUPPORTED, "batches use the Jacobi preconditioner");
     return BS_OK;
 }
 

@@ -303,6 +303,8 @@ extern "C" bs_status bs_solve_lowrank(const bs_grid* grid, const float* target, 
                                       int32_t* rank, void* stream) {
     bs_status st = validate_solve(grid, C, params);
     if (st != BS_OK) return st;
+    if (params->precond != BS_PRECOND_JACOBI)
+        return fail(BS_EUNSUPPORTED, "the low-rank solve uses the Jacobi preconditioner");
     if (!(eps >= 0.0 && eps < 1.0)) return fail(BS_EINVAL, "eps must be in [0, 1)");
     if (!target || !conf || !y || !ws || !rank) return fail(BS_EINVAL, "NULL pointer argument");
     if (((uintptr_t)target & 3) || ((uintptr_t)conf & 3) || ((uintptr_t)y & 3) ||

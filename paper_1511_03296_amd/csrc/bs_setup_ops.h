@@ -377,6 +377,180 @@ struct HierFinal {
 };
 
 // ---------------------------------------------------------------------------
+// Hierarchical preconditioner (Section 4, Eq. hier_precond):
+//     M_hier^-1 r = P^T(s o P(r)),   s_k = w_k P(1)_k / P(diag A)_k,
+// w_0 = 1 (at level 0, s_0 = 1 / diag(A): the Jacobi inverse), w_k =
+// alpha^-(beta + k) above; a coefficient with P(diag A)_k = 0 is 0.  Level
+// k >= 1 uses the pyramid buffer up_k [cap_k][Cp + 1]: channel Cp holds s_k
+// (set once per solve), channels 0..Cp-1 hold P_k(r) and then the collapse.
+// ---------------------------------------------------------------------------
+
+// Set-up: P_k(diag A) into channel Cp of up_k (level 1 sums diag(A) over its
+// children, level k >= 2 the channel Cp of level k-1).
+struct PrecLift {
+    static constexpr int kThreads = kBlock;
+    struct Args {
+        const int32_t* cptr;
+        const int32_t* clist;
+        const float* diag;
+        const float* prev;
+        float* up;
+        const int32_t* counts;
+        int Cp, level;
+    };
+    __device__ static void run(const Args& a, int jb, int nb, int) {
+        if (a.counts[CNT_K] < a.level) return;
+        const int Vk = a.counts[CNT_LEVEL0 + a.level];
+        const int C1 = a.Cp + 1;
+        const XcdTiles tl((Vk + kBlock - 1) / kBlock, jb, nb);
+        for (int64_t tile = tl.first; tile < tl.end; tile += tl.step) {
+            const int u = (int)(tile * kBlock) + threadIdx.x;
+            if (u >= Vk) continue;
+            double s = 0.0;
+            for (int j = a.cptr[u]; j < a.cptr[u + 1]; ++j) {
+                const int c = a.clist[j];
+                s += a.prev ? (double)a.prev[(int64_t)c * C1 + a.Cp] : (double)a.diag[c];
+            }
+            a.up[(int64_t)u * C1 + a.Cp] = (float)s;
+        }
+    }
+};
+
+// Set-up: s_k = w_k P(1)_k / P(diag A)_k in place of P(diag A)_k (after every
+// level is lifted).
+struct PrecScale {
+    static constexpr int kThreads = kBlock;
+    struct Args {
+        float* up;
+        const int32_t* ones;
+        const int32_t* counts;
+        float wk;
+        int Cp, level;
+    };
+    __device__ static void run(const Args& a, int jb, int nb, int) {
+        if (a.counts[CNT_K] < a.level) return;
+        const int Vk = a.counts[CNT_LEVEL0 + a.level];
+        const int C1 = a.Cp + 1;
+        const XcdTiles tl((Vk + kBlock - 1) / kBlock, jb, nb);
+        for (int64_t tile = tl.first; tile < tl.end; tile += tl.step) {
+            const int u = (int)(tile * kBlock) + threadIdx.x;
+            if (u >= Vk) continue;
+            const float pd = a.up[(int64_t)u * C1 + a.Cp];
+            a.up[(int64_t)u * C1 + a.Cp] =
+                pd > 0.0f ? (float)((double)a.wk * (double)a.ones[u] / (double)pd) : 0.0f;
+        }
+    }
+};
+
+// Per application: channels 0..Cp-1 of up_k = child sums of r (level 1,
+// stride Cp) or of level k-1's channels (stride Cp + 1).
+struct PrecUp {
+    static constexpr int kThreads = kBlock;
+    struct Args {
+        const int32_t* cptr;
+        const int32_t* clist;
+        const float* r;
+        const float* prev;
+        float* up;
+        const int32_t* counts;
+        int Cp, level;
+    };
+    __device__ static void run(const Args& a, int jb, int nb, int) {
+        if (a.counts[CNT_K] < a.level) return;
+        const int Vk = a.counts[CNT_LEVEL0 + a.level];
+        const int Cp = a.Cp, C1 = Cp + 1;
+        const int64_t n = (int64_t)Vk * Cp;
+        const XcdTiles tl((n + kBlock - 1) / kBlock, jb, nb);
+        for (int64_t tile = tl.first; tile < tl.end; tile += tl.step) {
+            const int64_t e = tile * kBlock + threadIdx.x;
+            if (e >= n) continue;
+            const int u = (int)(e / Cp), ch = (int)(e - (int64_t)u * Cp);
+            double s = 0.0;
+            for (int j = a.cptr[u]; j < a.cptr[u + 1]; ++j) {
+                const int c = a.clist[j];
+                s += a.prev ? (double)a.prev[(int64_t)c * C1 + ch] : (double)a.r[(int64_t)c * Cp + ch];
+            }
+            a.up[(int64_t)u * C1 + ch] = (float)s;
+        }
+    }
+};
+
+// Per application, top-down: up_k = s_k o up_k + up_{k+1}[parent] (channels
+// 0..Cp-1; the top level has no parent term).
+struct PrecDown {
+    static constexpr int kThreads = kBlock;
+    struct Args {
+        float* up;
+        const float* up_parent;
+        const int32_t* parent;
+        const int32_t* counts;
+        int Cp, level;
+    };
+    __device__ static void run(const Args& a, int jb, int nb, int) {
+        const int K = a.counts[CNT_K];
+        if (K < a.level) return;
+        const int Vk = a.counts[CNT_LEVEL0 + a.level];
+        const int Cp = a.Cp, C1 = Cp + 1;
+        const int64_t n = (int64_t)Vk * Cp;
+        const XcdTiles tl((n + kBlock - 1) / kBlock, jb, nb);
+        for (int64_t tile = tl.first; tile < tl.end; tile += tl.step) {
+            const int64_t e = tile * kBlock + threadIdx.x;
+            if (e >= n) continue;
+            const int u = (int)(e / Cp), ch = (int)(e - (int64_t)u * Cp);
+            float v = a.up[(int64_t)u * C1 + Cp] * a.up[(int64_t)u * C1 + ch];
+            if (a.level < K) v += a.up_parent[(int64_t)a.parent[u] * C1 + ch];
+            a.up[(int64_t)u * C1 + ch] = v;
+        }
+    }
+};
+
+// The small top levels k0 .. levels-1 of one application in one block: the
+// lift bottom-up, then the collapse top-down (PrecUp and PrecDown).
+struct PrecSmall {
+    static constexpr int kThreads = 1024;
+    struct Args {
+        PyrLevels lv;        // cptr, clist, parent and up of every level (wk, ones unused)
+        const float* r;
+        const int32_t* counts;
+        int Cp;
+    };
+    __device__ static void run(const Args& A, int, int, int) {
+        const PyrLevels& a = A.lv;
+        const int K = A.counts[CNT_K];
+        const int Cp = A.Cp, C1 = Cp + 1;
+        for (int k = a.k0; k < a.levels && k <= K; ++k) {
+            const int Vk = A.counts[CNT_LEVEL0 + k];
+            const float* prev = k >= 2 ? a.up[k - 1] : nullptr;
+            const int64_t n = (int64_t)Vk * Cp;
+            for (int64_t e = threadIdx.x; e < n; e += kThreads) {
+                const int u = (int)(e / Cp), ch = (int)(e - (int64_t)u * Cp);
+                double s = 0.0;
+                for (int j = a.cptr[k][u]; j < a.cptr[k][u + 1]; ++j) {
+                    const int c = a.clist[k][j];
+                    s += prev ? (double)prev[(int64_t)c * C1 + ch] : (double)A.r[(int64_t)c * Cp + ch];
+                }
+                a.up[k][(int64_t)u * C1 + ch] = (float)s;
+            }
+            __syncthreads();
+        }
+        for (int k = a.levels - 1; k >= a.k0; --k) {
+            if (K < k) continue;
+            const int Vk = A.counts[CNT_LEVEL0 + k];
+            float* up = a.up[k];
+            const float* upp = (k < K) ? a.up[k + 1] : nullptr;
+            const int64_t n = (int64_t)Vk * Cp;
+            for (int64_t e = threadIdx.x; e < n; e += kThreads) {
+                const int u = (int)(e / Cp), ch = (int)(e - (int64_t)u * Cp);
+                float v = up[(int64_t)u * C1 + Cp] * up[(int64_t)u * C1 + ch];
+                if (upp) v += upp[(int64_t)a.parent[k][u] * C1 + ch];
+                up[(int64_t)u * C1 + ch] = v;
+            }
+            __syncthreads();
+        }
+    }
+};
+
+// ---------------------------------------------------------------------------
 // Output.
 // ---------------------------------------------------------------------------
 

@@ -505,6 +505,7 @@ struct ImgView {
     int64_t vcap;
     float lam;
     int C, Cp, nb;
+    int zmode;
 };
 
 __device__ inline ImgView view_of(const PcgImage& s) {
@@ -536,6 +537,7 @@ __device__ inline ImgView view_of(const PcgImage& s) {
     I.C = s.C;
     I.Cp = s.Cp;
     I.nb = s.nb;
+    I.zmode = s.zmode;
     return I;
 }
 
@@ -671,7 +673,7 @@ __device__ inline void load_ops(MatOps<K, EXACT>& o, int v, const int (&nb)[10],
         if (u >= 0) {
             const uint32_t eu = lane_elem(u, Cp, ln.g, K);
             if constexpr (EXACT) {
-                o.g[j] = ldv<K>(I.r, eu);
+                o.g[j] = ldv<K>(I.zmode ? I.w : I.r, eu);
                 o.d[j] = ldv<K>(din, eu);
                 o.nm[j] = *elem(I.nfm, (uint32_t)u);
             } else {
@@ -680,7 +682,8 @@ __device__ inline void load_ops(MatOps<K, EXACT>& o, int v, const int (&nb)[10],
         }
     }
     const uint32_t e = lane_elem(v, Cp, ln.g, K);
-    o.rv = ldv<K>(I.r, e);
+    if constexpr (EXACT) o.rv = ldv<K>(I.zmode ? I.w : I.r, e);
+    else o.rv = ldv<K>(I.r, e);
     o.dv = ldv<K>(din, e);
     o.yv = ldv<K>(I.y, e);
     o.nmv = *elem(I.nfm, (uint32_t)v);
@@ -834,9 +837,11 @@ __global__ void __launch_bounds__(kRedBlock) pcg_matvec(PcgArgs a, int src) {
         if (any && have) {
             float zv[K], ns[K];
             Vec<K> dv, qv;
+            // z = M^-1 r: the Jacobi inverse times r, or as stored (zmode)
+            const bool zm = EXACT && I.zmode;
 #pragma unroll
             for (int k = 0; k < K; ++k) {
-                zv[k] = o.nmv.y * o.rv.v[k];
+                zv[k] = zm ? o.rv.v[k] : o.nmv.y * o.rv.v[k];
                 dv.v[k] = pcg_dir(zv[k], o.dv.v[k], beta[k], first[k]);
                 ns[k] = 0.0f;
             }
@@ -847,8 +852,9 @@ __global__ void __launch_bounds__(kRedBlock) pcg_matvec(PcgArgs a, int src) {
 #pragma unroll
                         for (int k = 0; k < K; ++k)
                             ns[k] += o.nm[j].x *
-                                     (dv.v[k] - pcg_dir(o.nm[j].y * o.g[j].v[k], o.d[j].v[k],
-                                                        beta[k], first[k]));
+                                     (dv.v[k] - pcg_dir(zm ? o.g[j].v[k]
+                                                           : o.nm[j].y * o.g[j].v[k],
+                                                        o.d[j].v[k], beta[k], first[k]));
                     }
                 }
 #pragma unroll
@@ -998,6 +1004,44 @@ __global__ void __launch_bounds__(kRedBlock) pcg_update(PcgArgs a, int want_w) {
     lane_partials<3, K>(acc, ln, Cp, nb, partial_slot(jb, nb), I.part0);
 }
 
+// Level 0 of the hierarchical preconditioner's collapse (one image):
+// z = M^-1_jacobi r + up1[parent0] (the coarser levels' share), stored in w,
+// and the partials of r^T z into the third slot-0 partial (the residual
+// update or pcg_start wrote the first two).
+template <int K>
+__global__ void __launch_bounds__(kRedBlock) pcg_prec_final(PcgArgs a, const float* up1,
+                                                             const int32_t* parent0) {
+    const ImgView I = view_of(a.one);
+    const int jb = (int)blockIdx.x;
+    const int V = I.counts[CNT_V];
+    const int Ktop = I.counts[CNT_K];
+    const int Cp = I.Cp, nb = I.nb, C1 = Cp + 1;
+    const Lanes ln(Cp, K);
+    double acc[1][K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) acc[0][k] = 0.0;
+    const XcdTiles tl((V + ln.vpb - 1) / ln.vpb, jb, nb);
+    for (int64_t tile = tl.first; tile < tl.end; tile += tl.step) {
+        const int v = (int)(tile * ln.vpb) + ln.vl;
+        if (!ln.ok || v >= V) continue;
+        const uint32_t e = lane_elem(v, Cp, ln.g, K);
+        const Vec<K> rv = ldv<K>(I.r, e);
+        const float mi = elem(I.nfm, (uint32_t)v)->y;
+        Vec<K> zv;
+#pragma unroll
+        for (int k = 0; k < K; ++k) zv.v[k] = mi * rv.v[k];
+        if (Ktop >= 1) {
+            const int64_t pu = (int64_t)parent0[v] * C1 + ln.g * K;
+#pragma unroll
+            for (int k = 0; k < K; ++k) zv.v[k] += up1[pu + k];
+        }
+        stv<K>(I.w, e, zv);
+#pragma unroll
+        for (int k = 0; k < K; ++k) acc[0][k] += (double)rv.v[k] * (double)zv.v[k];
+    }
+    lane_partials<1, K>(acc, ln, Cp, nb, partial_slot(jb, nb), I.part0 + (int64_t)2 * Cp * nb);
+}
+
 // After the last enqueued iteration: applies the step y += alpha d that the
 // last update left pending (d = d[src]) for the channels it left active.  An
 // image whose active count is 0 has none pending: its channels stopped in an
@@ -1105,6 +1149,11 @@ bs_status validate_solve(const bs_grid* grid, int C, const bs_solve_params* p) {
         return fail(BS_EINVAL, "init_alpha must be positive");
     if (p->init == BS_INIT_HIER && !std::isfinite(p->init_beta))
         return fail(BS_EINVAL, "init_beta must be finite");
+    if (p->precond != BS_PRECOND_JACOBI && p->precond != BS_PRECOND_HIER)
+        return fail(BS_EINVAL, "unknown preconditioner");
+    if (p->precond == BS_PRECOND_HIER &&
+        !(p->pre_alpha > 0.0f && std::isfinite(p->pre_alpha) && std::isfinite(p->pre_beta)))
+        return fail(BS_EINVAL, "pre_alpha must be positive and pre_beta finite");
     return BS_OK;
 }
 
@@ -1203,19 +1252,106 @@ PcgImage make_image(const GridImpl& g, const SolveWs& w, float lam, float* yw,
 }
 
 
+bs_status prec_setup(const GridImpl& g, const SolveWs& w, float alpha, float beta,
+                     HierPrecPlan& hp, hipStream_t s) {
+    const int Cp = w.Cp;
+    hp.levels = g.levels;
+    hp.Cp = Cp;
+    hp.counts = g.counts;
+    hp.r = w.r;
+    hp.up1 = g.levels > 1 ? w.up[1] : nullptr;
+    hp.parent0 = g.levels > 1 ? g.lv[1].item_parent : nullptr;
+    // levels whose application fits one block run in one launch
+    int k0 = 1;
+    while (k0 < g.levels && g.lv[k0].cap * (Cp + 1) > kSmallPyrElems) ++k0;
+    hp.k0 = k0;
+    for (int k = 1; k < g.levels; ++k) {
+        HierPrecPlan::Level& L = hp.lv[k];
+        L.cptr = g.lv[k].ptr;
+        L.clist = g.lv[k].list;
+        L.prev = k >= 2 ? w.up[k - 1] : nullptr;
+        L.up = w.up[k];
+        L.up_parent = (k + 1 < g.levels) ? w.up[k + 1] : nullptr;
+        L.parent = (k + 1 < g.levels) ? g.lv[k + 1].item_parent : nullptr;
+        L.blocks = grid_blocks(ceil_div(g.lv[k].cap * Cp, kBlock));
+    }
+    // P(diag A) bottom-up, then the scales
+    for (int k = 1; k < g.levels; ++k) {
+        const int bk = grid_blocks(ceil_div(g.lv[k].cap, kBlock));
+        BS_LAUNCH(s, K_INIT, "prec_lift", one_launch<PrecLift>, dim3(bk), dim3(kBlock), 0, s,
+                  (PrecLift::Args{g.lv[k].ptr, g.lv[k].list, w.diag,
+                                  k >= 2 ? w.up[k - 1] : nullptr, w.up[k], g.counts, Cp, k}),
+                  0);
+    }
+    for (int k = 1; k < g.levels; ++k) {
+        const int bk = grid_blocks(ceil_div(g.lv[k].cap, kBlock));
+        const float wk = (float)std::pow((double)alpha, -((double)beta + k));
+        BS_LAUNCH(s, K_INIT, "prec_scale", one_launch<PrecScale>, dim3(bk), dim3(kBlock), 0, s,
+                  (PrecScale::Args{w.up[k], g.lv[k].ones, g.counts, wk, Cp, k}), 0);
+    }
+    return BS_OK;
+}
+
+// One application z = M_hier^-1 r into w, with the r^T z partials.
+template <int K>
+static bs_status prec_apply(const PcgArgs& a, const HierPrecPlan& hp, int G, hipStream_t s) {
+    for (int k = 1; k < hp.k0; ++k) {
+        const HierPrecPlan::Level& L = hp.lv[k];
+        BS_LAUNCH(s, K_PCG_UPDATE, "prec_up", one_launch<PrecUp>, dim3(L.blocks), dim3(kBlock), 0,
+                  s, (PrecUp::Args{L.cptr, L.clist, hp.r, L.prev, L.up, hp.counts, hp.Cp, k}), 0);
+    }
+    if (hp.k0 < hp.levels) {
+        PrecSmall::Args A;
+        std::memset(&A, 0, sizeof(A));
+        A.lv.k0 = hp.k0;
+        A.lv.levels = hp.levels;
+        for (int k = 1; k < hp.levels; ++k) {
+            A.lv.cptr[k] = hp.lv[k].cptr;
+            A.lv.clist[k] = hp.lv[k].clist;
+            A.lv.parent[k] = hp.lv[k].parent;
+            A.lv.up[k] = hp.lv[k].up;
+        }
+        A.r = hp.r;
+        A.counts = hp.counts;
+        A.Cp = hp.Cp;
+        BS_LAUNCH(s, K_PCG_UPDATE, "prec_small", one_launch<PrecSmall>, dim3(1), dim3(1024), 0, s,
+                  A, 0);
+    }
+    for (int k = hp.k0 - 1; k >= 1; --k) {
+        const HierPrecPlan::Level& L = hp.lv[k];
+        BS_LAUNCH(s, K_PCG_UPDATE, "prec_down", one_launch<PrecDown>, dim3(L.blocks), dim3(kBlock),
+                  0, s, (PrecDown::Args{L.up, L.up_parent, L.parent, hp.counts, hp.Cp, k}), 0);
+    }
+    BS_LAUNCH(s, K_PCG_UPDATE, "pcg_prec_final", pcg_prec_final<K>, dim3(G), dim3(kRedBlock), 0, s,
+              a, hp.up1, hp.parent0);
+    return BS_OK;
+}
+
 template <int K, bool MULTI, bool PACKED>
 static bs_status run_pcg_k(const PcgArgs& a, int n, int G, int max_cp, bool sep,
-                           const bs_solve_params& p, const int32_t* act, hipStream_t s) {
+                           const bs_solve_params& p, const int32_t* act, hipStream_t s,
+                           const HierPrecPlan* hp) {
     const dim3 grid(G), block(kRedBlock);
+    if constexpr (MULTI) {
+        if (hp) return fail(BS_EUNSUPPORTED, "hierarchical preconditioner on an image table");
+    }
     BS_LAUNCH(s, K_INIT, "pcg_prologue", pcg_prologue<MULTI>, grid, block, 0, s, a);
     BS_LAUNCH(s, K_PCG_START, "pcg_start", (pcg_start<K, MULTI, PACKED>), grid, block, 0, s, a);
+    if constexpr (!MULTI) {
+        if (hp) {
+            const bs_status st = prec_apply<K>(a, *hp, G, s);
+            if (st != BS_OK) return st;
+        }
+    }
     if (sep)
         BS_LAUNCH(s, K_PCG_REDUCE, "pcg_reduce", pcg_reduce<MULTI>, dim3(3 * max_cp, n), block, 0,
                   s, a, 0, 3);
     std::vector<int32_t> poll(n);
     int src = 0;   // the buffer holding d
     for (int it = 0; it < p.max_iters; ++it) {
-        if (exact_iteration<K>(it)) {
+        // with the hierarchical preconditioner every matvec is the exact form
+        // (the recurrence needs diag(A) z = r)
+        if (hp || exact_iteration<K>(it)) {
             BS_LAUNCH(s, K_PCG_MATVEC, "pcg_matvec", (pcg_matvec<K, MULTI, true, PACKED>), grid, block, 0,
                       s, a, src);
             src ^= 1;
@@ -1226,9 +1362,15 @@ static bs_status run_pcg_k(const PcgArgs& a, int n, int G, int max_cp, bool sep,
         if (sep)
             BS_LAUNCH(s, K_PCG_REDUCE, "pcg_reduce", pcg_reduce<MULTI>, dim3(max_cp, n), block, 0,
                       s, a, 1, 1);
-        const int want_w = exact_iteration<K>(it + 1) ? 0 : 1;
+        const int want_w = (hp || exact_iteration<K>(it + 1)) ? 0 : 1;
         BS_LAUNCH(s, K_PCG_UPDATE, "pcg_update", (pcg_update<K, MULTI>), grid, block, 0, s, a,
                   want_w);
+        if constexpr (!MULTI) {
+            if (hp) {
+                const bs_status st = prec_apply<K>(a, *hp, G, s);
+                if (st != BS_OK) return st;
+            }
+        }
         if (sep)
             BS_LAUNCH(s, K_PCG_REDUCE, "pcg_reduce", pcg_reduce<MULTI>, dim3(3 * max_cp, n), block,
                       0, s, a, 0, 3);
@@ -1248,7 +1390,7 @@ static bs_status run_pcg_k(const PcgArgs& a, int n, int G, int max_cp, bool sep,
 
 bs_status run_pcg(int K, const PcgImage* imgs, int n, const PcgImage* dev_imgs,
                   const int32_t* blk2img, int G, int max_cp, const bs_solve_params& p,
-                  const int32_t* act, hipStream_t s) {
+                  const int32_t* act, hipStream_t s, const HierPrecPlan* hp) {
     PcgArgs a;
     std::memset(&a, 0, sizeof(a));
     a.one = imgs[0];
@@ -1267,10 +1409,10 @@ bs_status run_pcg(int K, const PcgImage* imgs, int n, const PcgImage* dev_imgs,
     auto go = [&](auto k) -> bs_status {
         constexpr int Kc = decltype(k)::value;
         switch (mode) {
-            case 0: return run_pcg_k<Kc, false, false>(a, n, G, max_cp, sep, p, act, s);
-            case 1: return run_pcg_k<Kc, true, false>(a, n, G, max_cp, sep, p, act, s);
-            case 2: return run_pcg_k<Kc, false, true>(a, n, G, max_cp, sep, p, act, s);
-            default: return run_pcg_k<Kc, true, true>(a, n, G, max_cp, sep, p, act, s);
+            case 0: return run_pcg_k<Kc, false, false>(a, n, G, max_cp, sep, p, act, s, hp);
+            case 1: return run_pcg_k<Kc, true, false>(a, n, G, max_cp, sep, p, act, s, hp);
+            case 2: return run_pcg_k<Kc, false, true>(a, n, G, max_cp, sep, p, act, s, hp);
+            default: return run_pcg_k<Kc, true, true>(a, n, G, max_cp, sep, p, act, s, hp);
         }
     };
     switch (K) {
@@ -1359,8 +1501,15 @@ extern "C" bs_status bs_solve(const bs_grid* grid, const float* target, const fl
     float* yw = (w.Cp == C && ((uintptr_t)y & 15) == 0) ? y : w.yi;
     st = solve_setup(g, w, conf, target, true, p, yw, s);
     if (st != BS_OK) return st;
-    const PcgImage I = make_image(g, w, p.lambda, yw, stats);
-    st = run_pcg(w.K, &I, 1, nullptr, nullptr, w.nb, w.Cp, p, w.act, s);
+    PcgImage I = make_image(g, w, p.lambda, yw, stats);
+    HierPrecPlan hp;
+    if (p.precond == BS_PRECOND_HIER) {
+        st = prec_setup(g, w, p.pre_alpha, p.pre_beta, hp, s);
+        if (st != BS_OK) return st;
+        I.zmode = 1;
+    }
+    st = run_pcg(w.K, &I, 1, nullptr, nullptr, w.nb, w.Cp, p, w.act, s,
+                 p.precond == BS_PRECOND_HIER ? &hp : nullptr);
     if (st != BS_OK) return st;
     if (yw != y) return copy_unpadded(g, yw, C, w.Cp, y, s);
     return BS_OK;
@@ -1405,8 +1554,15 @@ extern "C" bs_status bs_solve_backward(const bs_grid* grid, const float* target,
     float* gb = (g_out && w.Cp == C && ((uintptr_t)g_out & 15) == 0) ? g_out : w.yi;
     st = solve_setup(g, w, conf, grad_x, false, p, gb, s);
     if (st != BS_OK) return st;
-    const PcgImage I = make_image(g, w, p.lambda, gb, stats);
-    st = run_pcg(w.K, &I, 1, nullptr, nullptr, w.nb, w.Cp, p, w.act, s);
+    PcgImage I = make_image(g, w, p.lambda, gb, stats);
+    HierPrecPlan hp;
+    if (p.precond == BS_PRECOND_HIER) {
+        st = prec_setup(g, w, p.pre_alpha, p.pre_beta, hp, s);
+        if (st != BS_OK) return st;
+        I.zmode = 1;
+    }
+    st = run_pcg(w.K, &I, 1, nullptr, nullptr, w.nb, w.Cp, p, w.act, s,
+                 p.precond == BS_PRECOND_HIER ? &hp : nullptr);
     if (st != BS_OK) return st;
     st = grad_scatter_launch(g, gb, w.Cp, y_hat, target, conf, C, grad_t, grad_c, s);
     if (st != BS_OK) return st;

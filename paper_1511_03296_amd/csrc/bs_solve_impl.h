@@ -75,6 +75,8 @@ struct PcgImage {
     int64_t vcap;
     float lam;
     int32_t C, Cp, nb, block0;
+    int32_t zmode;           // 1: the preconditioned residual z is stored in w (hierarchical
+                             // preconditioner) and the matvec reads it; 0: z = M^-1 r, Jacobi
 };
 
 // Kernel argument of the PCG kernels: one image by value, or a table of
@@ -140,6 +142,33 @@ bool pcg_partials_fit(int Cp, int nb);
 PcgImage make_image(const GridImpl& g, const SolveWs& w, float lam, float* yw,
                     bs_chan_stats* stats);
 
+// Launches of the hierarchical preconditioner z = M_hier^-1 r of one image
+// (set up by prec_setup, applied after every residual update).
+struct HierPrecPlan {
+    int levels = 0, k0 = 1;              // levels k0.. run in one block
+    struct Level {
+        const int32_t* cptr;
+        const int32_t* clist;
+        const float* prev;               // level k-1's buffer (k >= 2)
+        float* up;
+        const float* up_parent;          // level k+1's buffer
+        const int32_t* parent;           // level k vertex -> level k+1 vertex
+        int blocks;
+    };
+    Level lv[BS_MAX_LEVELS];
+    const float* up1 = nullptr;          // level 1's collapse, read by the final kernel
+    const int32_t* parent0 = nullptr;    // level-0 vertex -> level-1 vertex
+    const int32_t* counts = nullptr;
+    const float* r = nullptr;
+    int Cp = 0;
+};
+
+// Lifts diag(A) and sets the level scales s_k of M_hier^-1 (alpha, beta:
+// the preconditioner's level weighting) into the pyramid buffers of w, and
+// fills `hp` with the launches of one application.
+bs_status prec_setup(const GridImpl& g, const SolveWs& w, float alpha, float beta,
+                     HierPrecPlan& hp, hipStream_t s);
+
 // PCG over n images sharing lane width K.  `dev_imgs` / `blk2img` are device
 // copies of `imgs` and of the block-to-image map (-1: an idle block); with
 // dev_imgs NULL the one image is passed by value, with block0 = 0, and runs
@@ -149,7 +178,7 @@ PcgImage make_image(const GridImpl& g, const SolveWs& w, float lam, float* yw,
 // iterations.
 bs_status run_pcg(int K, const PcgImage* imgs, int n, const PcgImage* dev_imgs,
                   const int32_t* blk2img, int G, int max_cp, const bs_solve_params& p,
-                  const int32_t* act, hipStream_t s);
+                  const int32_t* act, hipStream_t s, const HierPrecPlan* hp = nullptr);
 
 // y[v][c] = yw[v][c] for c < C (yw has stride Cp).
 bs_status copy_unpadded(const GridImpl& g, const float* yw, int C, int Cp, float* y,

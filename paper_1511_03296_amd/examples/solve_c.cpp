@@ -81,7 +81,8 @@ int main(int argc, char** argv) {
     float* y = (float*)device(P * C * sizeof(float));
     float* x = (float*)device(P * C * sizeof(float));
     bs_chan_stats* stats = (bs_chan_stats*)device(C * sizeof(bs_chan_stats));
-    const bs_solve_params sp = {lambda, BS_INIT_HIER, max_iters, 8, rel_tol, 4.0f, 0.0f};
+    const bs_solve_params sp = {lambda,  BS_INIT_HIER, max_iters, 8, rel_tol, 4.0f, 0.0f,
+                                BS_PRECOND_JACOBI, 2.0f, 5.0f};
     check(bs_solve(&grid, target, conf, C, &sp, y, ws, ws_bytes, stats, nullptr), "bs_solve");
     check(bs_slice(&grid, y, C, x, nullptr), "bs_slice");
     check_hip(hipDeviceSynchronize(), "hipDeviceSynchronize");

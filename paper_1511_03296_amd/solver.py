@@ -48,14 +48,21 @@ class SolveOptions:
     init_alpha: float = 4.0
     init_beta: float = 0.0
     check_every: int = 8
+    precond: str = "jacobi"
+    pre_alpha: float = 2.0
+    pre_beta: float = 5.0
 
     def struct(self) -> L.SolveParams:
         if self.init not in ("hier", "flat"):
             raise ValueError("init must be 'hier' or 'flat'")
+        if self.precond not in ("jacobi", "hier"):
+            raise ValueError("precond must be 'jacobi' or 'hier'")
         return L.SolveParams(float(self.lam),
                              L.BS_INIT_HIER if self.init == "hier" else L.BS_INIT_FLAT,
                              int(self.max_iters), int(self.check_every), float(self.rel_tol),
-                             float(self.init_alpha), float(self.init_beta))
+                             float(self.init_alpha), float(self.init_beta),
+                             L.BS_PRECOND_HIER if self.precond == "hier" else L.BS_PRECOND_JACOBI,
+                             float(self.pre_alpha), float(self.pre_beta))
 
 
 class BilateralGrid:
@@ -132,12 +139,14 @@ class BilateralGrid:
     def solve(self, target: torch.Tensor, conf: torch.Tensor, lam: float, max_iters: int = 25,
               rel_tol: float = 0.0, init: str = "hier", init_alpha: float = 4.0,
               init_beta: float = 0.0, check_every: int = 8, ws: torch.Tensor | None = None,
-              y: torch.Tensor | None = None, stats: torch.Tensor | None = None):
+              y: torch.Tensor | None = None, stats: torch.Tensor | None = None,
+              precond: str = "jacobi", pre_alpha: float = 2.0, pre_beta: float = 5.0):
         """Bilateral-space solution y [Vcap][C] and per-channel stats (device bytes)."""
         C = int(target.shape[0])
         target = _dev_f32(target, "target", (C, self.H, self.W))
         conf = _dev_f32(conf, "confidence", (self.H, self.W))
-        opts = SolveOptions(lam, max_iters, rel_tol, init, init_alpha, init_beta, check_every)
+        opts = SolveOptions(lam, max_iters, rel_tol, init, init_alpha, init_beta, check_every,
+                            precond, pre_alpha, pre_beta)
         if ws is None:
             ws = self.solve_workspace(C)
         if y is None:
@@ -214,13 +223,15 @@ class BilateralGrid:
                  grad_x: torch.Tensor, lam: float, max_iters: int = 25, rel_tol: float = 0.0,
                  init: str = "hier", init_alpha: float = 4.0, init_beta: float = 0.0,
                  check_every: int = 8, ws: torch.Tensor | None = None,
-                 stats: torch.Tensor | None = None, want_g: bool = False):
+                 stats: torch.Tensor | None = None, want_g: bool = False,
+                 precond: str = "jacobi", pre_alpha: float = 2.0, pre_beta: float = 5.0):
         """(dL/dt, dL/dc, dL/db or None) from dL/dx (Section 3)."""
         C = int(target.shape[0])
         target = _dev_f32(target, "target", (C, self.H, self.W))
         conf = _dev_f32(conf, "confidence", (self.H, self.W))
         grad_x = _dev_f32(grad_x, "grad_x", (C, self.H, self.W))
-        opts = SolveOptions(lam, max_iters, rel_tol, init, init_alpha, init_beta, check_every)
+        opts = SolveOptions(lam, max_iters, rel_tol, init, init_alpha, init_beta, check_every,
+                            precond, pre_alpha, pre_beta)
         if ws is None:
             ws = self.solve_workspace(C)
         gt = torch.empty((C, self.H, self.W), dtype=torch.float32, device=self.device)

@@ -42,7 +42,7 @@ def test_struct_sizes_match_header_layout():
     from paper_1511_03296_amd import _lib as L
     assert ct.sizeof(L.Grid) == L.BS_GRID_BYTES
     assert ct.sizeof(L.ChanStats) == 24
-    assert ct.sizeof(L.SolveParams) == 32
+    assert ct.sizeof(L.SolveParams) == 48
     assert ct.sizeof(L.BistochParams) == 16
 
 
