@@ -70,6 +70,13 @@ WORKLOADS = {
     # give the "vs plain" ratio
     "segprob16x512x512": dict(gen="segmentation_probs", images=16, form="lowrank",
                               fwd=(20000, 1e-6), bwd=(0, 0.0), lowrank=0.01),
+    # the domain transform on the stereo shape: the robust solver's initial
+    # confidence from the input disparity (sigma_xy = sigma_rgb = 32,
+    # sigma_dt = 2, 80 columns zeroed) and the post-process of a disparity
+    # map (sigma'_xy = sigma'_rgb = 4), three iterations each
+    "dt_stereo1024x768": dict(gen="stereo_refine", images=1, form="dt", fwd=(0, 0.0),
+                              bwd=(0, 0.0), dt=dict(conf=(32.0, 32.0, 2.0, 80),
+                                                    post=(4.0, 4.0), iters=3)),
 }
 
 # Iteration caps of the graph form: the calibration run's largest count times
@@ -189,6 +196,38 @@ def single_step(inputs, spec, backward=True, keep=None):
                                       check_every=bce, ws=ws, precond=pre)
         if keep is not None:
             keep.append((G.vertex_count(), st, bst))
+
+
+class DtStep:
+    """One step of the domain-transform workload: the initial confidence of
+    the input disparity, then the post-process of the disparity map, with
+    the workspace and outputs allocated once."""
+
+    def __init__(self, inputs, spec):
+        import torch
+        from paper_1511_03296_amd import _lib as L
+        d = inputs[0]
+        self.ref, self.t = d["ref"], d["t"]
+        H, W = d["p"].H, d["p"].W
+        self.ws = torch.empty(L.lib.bs_dt_workspace_bytes(H, W), dtype=torch.uint8,
+                              device=self.t.device)
+        self.out = torch.empty_like(self.t)
+        self.dt = spec["dt"]
+
+    def __call__(self, backward=True):
+        from paper_1511_03296_amd import domain_transform, dt_confidence
+        ss, sr, sdt, zc = self.dt["conf"]
+        dt_confidence(self.ref, self.t[0], ss, sr, sdt, zc, self.dt["iters"], ws=self.ws)
+        domain_transform(self.ref, self.t, *self.dt["post"], self.dt["iters"], out=self.out,
+                         ws=self.ws)
+
+
+def dt_bytes(P: int, C: int) -> int:
+    """Algorithmic bytes of one pass kernel (dt_rows or dt_cols) over C planes
+    of P pixels: every sample read and written once (float32) and its domain
+    distance word read once, 8 C + 4 bytes per pixel; both directions of the
+    pass are one kernel."""
+    return int(P) * (8 * int(C) + 4)
 
 
 def lowrank_step(inputs, spec, backward=False, keep=None, ranks=None):
@@ -323,7 +362,7 @@ def timed(step, steps):
 
 KERNELS = ["level_count", "level_scan", "level_write", "neighbour_table", "bist_step",
            "bist_other", "splat", "init", "pcg_start", "pcg_matvec", "pcg_update", "pcg_reduce",
-           "slice", "grad_scatter"]
+           "slice", "grad_scatter", "dt_rows", "dt_cols", "dt_other"]
 
 
 def kernel_times(step, steps):
@@ -353,6 +392,12 @@ def _oracle_sample(args):
     from oracle import bilateral as O
     import workloads as WL
     p, spec = args
+    if spec.get("dt"):
+        from oracle import domain_transform as DT
+        ss, sr, sdt, zc = spec["dt"]["conf"]
+        DT.dt_confidence(p.ref, p.target[0], ss, sr, sdt, zc, spec["dt"]["iters"])
+        DT.domain_transform(p.ref, p.target, *spec["dt"]["post"], spec["dt"]["iters"])
+        return p.pixels
     (fi, ft), (bi, bt) = spec["fwd"], spec["bwd"]
     prm = O.Params(p.sigma_xy, p.sigma_l, p.sigma_uv, p.lam, max_iters=fi, rel_tol=ft)
     if spec.get("robust"):
@@ -385,11 +430,12 @@ def cpu_baseline(problems, spec, seconds, cores):
     import workloads as WL
     crops = []
     for p in problems:
-        if p.pixels > 200_000 or spec["fwd"][1] > 0:
+        if not spec.get("dt") and (p.pixels > 200_000 or spec["fwd"][1] > 0):
             h, w = (min(p.H, 256), min(p.W, 256)) if p.C < 8 else (min(p.H, 96), min(p.W, 96))
             p = WL.crop(p, (p.H - h) // 2, (p.W - w) // 2, h, w)
         crops.append(p)
-    what = {"robust": "robust forward", "lowrank": "low-rank forward"}
+    what = {"robust": "robust forward", "lowrank": "low-rank forward",
+            "dt": "domain-transform (confidence + post-process)"}
     kind = next((v for k, v in what.items() if spec.get(k) is not None), "forward+backward")
     ctx = mp.get_context("fork")
     done_px, n = 0, 0
@@ -408,10 +454,58 @@ def cpu_baseline(problems, spec, seconds, cores):
     shape = f"{crops[0].W}x{crops[0].H}" if len(crops) == 1 else "crops"
     return {"value": round(done_px / el / 1e6, 4), "unit": "Mpix/s", "cores": cores,
             "kind": "oracle",
-            "sample": f"{n} {kind} passes of centre crops (at most 256x256, 96x96 for "
-                      f"21 channels; {shape}) cycling through the workload's images, "
-                      f"{cores} worker processes of one thread each, {el:.1f} s, "
-                      f"NumPy float64"}
+            "sample": (f"{n} {kind} passes of the full {shape} image" if spec.get("dt") else
+                       f"{n} {kind} passes of centre crops (at most 256x256, 96x96 for "
+                       f"21 channels; {shape}) cycling through the workload's images")
+                      + f", {cores} worker processes of one thread each, {el:.1f} s, "
+                        f"NumPy float64"}
+
+
+def dt_line(args, problems, inputs, spec) -> dict:
+    """The JSON line of the domain-transform workload: Mpix/s of steps, and
+    the roofline of the slower pass kernel."""
+    import torch
+    step = DtStep(inputs, spec)
+    for _ in range(max(1, args.warmup)):
+        step()
+    torch.cuda.synchronize()
+    print("bench: warm-up done", file=sys.stderr, flush=True)
+    sec = timed(step, args.steps)
+    sec_inst, kt = kernel_times(step, args.steps)
+    p = problems[0]
+    it = spec["dt"]["iters"]
+    # per step each pass kernel runs `iters` times on the confidence's two
+    # signals and `iters` times on the C planes of the post-process
+    bytes_step = it * (dt_bytes(p.pixels, 2) + dt_bytes(p.pixels, p.C))
+    name = max(("dt_rows", "dt_cols"), key=lambda k: kt[k][0])
+    ms, launches = kt[name]
+    achieved = bytes_step / (ms * 1e-3) / 1e9 if ms > 0 else 0.0
+    return {
+        "metric": METRIC,
+        "value": round(p.pixels / sec / 1e6, 3),
+        "unit": "Mpix/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(sec * 1e3, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": args.workload, "images": 1, "pixels": p.pixels,
+                   "channels": p.C, "confidence": dict(zip(
+                       ("sigma_xy", "sigma_rgb", "sigma_dt", "zero_cols"), spec["dt"]["conf"])),
+                   "post_process": dict(zip(("sigma_xy", "sigma_rgb"), spec["dt"]["post"])),
+                   "iterations": it, "parallelism": "single-gpu",
+                   "engine": "domain transform (confidence + post-process)"},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": _measured_traffic(args.workload), "kernel": name,
+                     "bytes_per_launch": int(bytes_step / launches) if launches else 0,
+                     "avg_us": round(ms / launches * 1e3, 3) if launches else None,
+                     "launches_per_step": launches,
+                     "bytes_rule": "8 x channels + 4 per pixel and pass (samples read and "
+                                   "written once, the domain distance word read once)"},
+        "kernel_ms_per_step": {k: round(kt[k][0], 4) for k in ("dt_rows", "dt_cols", "dt_other")},
+        "kernel_launches_per_step": {k: kt[k][1] for k in ("dt_rows", "dt_cols", "dt_other")},
+        "instrumented_ms_per_step": round(sec_inst * 1e3, 4),
+    }
 
 
 # ---------------------------------------------------------------------------
@@ -455,8 +549,9 @@ def main() -> int:
     dev = torch.device("cuda:0")
     spec = dict(WORKLOADS[args.workload])
     if args.precond != "jacobi":
-        if spec["form"] in ("lowrank", "robust"):
-            print("the low-rank and robust workloads use the Jacobi preconditioner",
+        if spec["form"] in ("lowrank", "robust", "dt"):
+            print("the low-rank, robust and domain-transform workloads use no other "
+                  "preconditioner",
                   file=sys.stderr)
             return 2
         spec["precond"] = args.precond
@@ -475,6 +570,15 @@ def main() -> int:
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+
+    if form == "dt":
+        line = dt_line(args, problems, inputs, spec)
+        if not (args.no_cpu_baseline or args.profile):
+            cores = args.cpu_cores or min(16, os.cpu_count() or 1)
+            print(f"bench: cpu baseline (oracle, {cores} processes)", file=sys.stderr, flush=True)
+            line["cpu_baseline"] = cpu_baseline(problems, spec, args.cpu_seconds, cores)
+        print(json.dumps(line), flush=True)
+        return 0
 
     keep, ranks = [], []
     tuned, caps, converged, graph_form = None, None, None, None

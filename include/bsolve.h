@@ -11,8 +11,9 @@
  * supplement Section 2), slice y back to pixels (Eq. solution), and
  * back-propagate onto the target and confidence (Section 3).  On top of the
  * solve: batches of images of uneven size and channel count, the robust
- * solver (supplement Algorithm RBS) and the low-rank reduction of many
- * right-hand sides (supplement Section Multiple Output Channels).
+ * solver (supplement Algorithm RBS), the low-rank reduction of many
+ * right-hand sides (supplement Section Multiple Output Channels) and the
+ * domain-transform post-process of the output (Section 4).
  *
  * Conventions shared by every entry point:
  *  - Pointers named as device pointers must point to device memory of the
@@ -353,6 +354,62 @@ bs_status bs_lowrank_factor(const double* gram, int32_t C, double eps, float* M,
                             int32_t* rank);
 
 /* ---------------------------------------------------------------------- */
+/* Domain transform: the post-process of the solver's output (Section 4,   */
+/* post-processing) and the robust solver's initial confidence (supplement */
+/* Section Robustness, the equations for V and c_init).                    */
+/* ---------------------------------------------------------------------- */
+
+/* The recursive filter of Gastal and Oliveira's domain transform, guided by
+ * the reference image.  Neighbouring pixels lie d = 1 + (sigma_s / sigma_r)
+ * sum_c |I_c(p) - I_c(q)| apart, I the reference's 8-bit R, G, B codes
+ * (clamp(floor(255 v + 1/2), 0, 255), as the grid quantises them).  Each of
+ * `iters` iterations filters every row, then every column: the recursion
+ * J[x] = (1 - a^d) I[x] + a^d J[x-1] forwards along the line, then backwards
+ * on its output, a = exp(-sqrt(2) / sigma_i), sigma_i = sigma_s sqrt(3)
+ * 2^(iters - i) / sqrt(4^iters - 1) for iteration i = 1..iters (the
+ * iterations' variances add up to sigma_s^2).  The first pixel of a line in
+ * each direction passes unchanged.  The paper does not state the iteration
+ * count; 3 is the filter's usual one. */
+typedef struct bs_dt_params {
+    float sigma_s;         /* spatial bandwidth sigma'_xy in pixels, > 0        */
+    float sigma_r;         /* range bandwidth sigma'_rgb in 8-bit codes, > 0    */
+    int32_t iters;         /* 1..16                                             */
+} bs_dt_params;
+
+/* Bytes of device workspace of bs_domain_transform and bs_dt_confidence for
+ * an H x W image: the domain distances (uint32 [H][W]), the two signals of
+ * the variance (float32 [2][H][W]) and 256 float64 partial sums.  Host, pure; 0 for
+ * invalid sides (below 1, above 65535, or above 2^30 pixels). */
+size_t bs_dt_workspace_bytes(int32_t H, int32_t W);
+
+/* Filters x (device float32 [C][H][W], 1 <= C <= BS_MAX_CHANNELS) into out
+ * (device float32 [C][H][W]; out == x filters in place, any other overlap is
+ * BS_EINVAL), guided by ref (device float32 [3][H][W] in [0, 1], as for
+ * bs_build_grid).  ws: device workspace of bs_dt_workspace_bytes(H, W) bytes,
+ * 256-byte aligned.  Errors: BS_EINVAL for a NULL or misaligned pointer,
+ * sides below 1, C out of range, sigma_s or sigma_r not positive and finite,
+ * iters outside 1..16; BS_EUNSUPPORTED for sides above 65535 or more than
+ * 2^30 pixels; BS_EWORKSPACE for a short workspace.  Enqueues 1 + 2 iters
+ * launches on `stream` and never synchronises it (graph-capturable). */
+bs_status bs_domain_transform(const float* ref, int32_t H, int32_t W, const float* x, int32_t C,
+                              const bs_dt_params* params, float* out, void* ws, size_t ws_bytes,
+                              void* stream);
+
+/* The initial confidence of the robust solver from the edge-aware variance
+ * of a depth or disparity map z (device float32 [H][W]):
+ *     V = DT(z^2) - DT(z)^2,   conf = exp(-max(V, 0) / (2 sigma_dt^2)),
+ * DT the filter of bs_domain_transform with `params`, and conf = 0 in the
+ * leftmost zero_cols columns (the paper zeroes 80 columns of its stereo
+ * pairs, whose left side has no match in the other view).  V is evaluated on
+ * z minus its mean (float64), which leaves it unchanged and keeps float32
+ * rounding relative to the spread of z.  conf: device float32 [H][W] output.
+ * Errors as bs_domain_transform, plus BS_EINVAL for sigma_dt not positive and
+ * finite or zero_cols < 0.  Enqueues on `stream` without synchronising. */
+bs_status bs_dt_confidence(const float* ref, int32_t H, int32_t W, const float* z,
+                           const bs_dt_params* params, float sigma_dt, int32_t zero_cols,
+                           float* conf, void* ws, size_t ws_bytes, void* stream);
+
+/* ---------------------------------------------------------------------- */
 /* Batches: many images of uneven size and channel count (Section 3's      */
 /* forward and backward over a batch, e.g. a segmentation minibatch).      */
 /* ---------------------------------------------------------------------- */
@@ -539,7 +596,8 @@ bs_status bs_solve_ws_view(const bs_grid* grid, int32_t C, void* ws, size_t ws_b
  * returns the summed elapsed milliseconds and launch count of one kernel:
  * "level_count", "level_scan", "level_write", "neighbour_table", "bist_step",
  * "bist_other", "splat", "init", "pcg_start", "pcg_matvec", "pcg_update",
- * "pcg_reduce", "slice" or "grad_scatter".  bs_timing_reset clears the sums.
+ * "pcg_reduce", "slice", "grad_scatter", "dt_rows", "dt_cols" or "dt_other"
+ * (the domain transform's other kernels).  bs_timing_reset clears the sums.
  * Every call enqueues its launches on one stream, one after another, so each
  * timed launch has the device to itself. */
 bs_status bs_timing_enable(int32_t on);

@@ -42,6 +42,10 @@ class SolveParams(ct.Structure):
                 ("precond", ct.c_int32), ("pre_alpha", ct.c_float), ("pre_beta", ct.c_float)]
 
 
+class DtParams(ct.Structure):
+    _fields_ = [("sigma_s", ct.c_float), ("sigma_r", ct.c_float), ("iters", ct.c_int32)]
+
+
 class ChanStats(ct.Structure):
     _fields_ = [("iters", ct.c_int32), ("reason", ct.c_int32), ("rel_residual", ct.c_double),
                 ("bnorm", ct.c_double)]
@@ -138,6 +142,11 @@ _SIGS = {
     "bs_batch_forward_lowrank": (_i32, [ct.POINTER(BatchItem), _i32, ct.POINTER(SolveParams),
                                         ct.POINTER(BistochParams), ct.POINTER(Grid), _i32,
                                         ct.c_double, ct.POINTER(_i32), _vp, _sz, _vp]),
+    "bs_dt_workspace_bytes": (_sz, [_i32, _i32]),
+    "bs_domain_transform": (_i32, [_vp, _i32, _i32, _vp, _i32, ct.POINTER(DtParams), _vp, _vp,
+                                   _sz, _vp]),
+    "bs_dt_confidence": (_i32, [_vp, _i32, _i32, _vp, ct.POINTER(DtParams), ct.c_float, _i32,
+                                _vp, _vp, _sz, _vp]),
     "bs_timing_enable": (_i32, [_i32]),
     "bs_timing_reset": (_i32, []),
     "bs_timing_read": (_i32, [ct.c_char_p, ct.POINTER(ct.c_double), ct.POINTER(ct.c_int64)]),

@@ -41,7 +41,7 @@ bs_status check_hip(hipError_t e, const char* what);
 enum KernelId : int {
     K_LEVEL_COUNT, K_LEVEL_SCAN, K_LEVEL_WRITE, K_NEIGHBOURS, K_BIST_STEP, K_BIST_OTHER,
     K_SPLAT, K_INIT, K_PCG_START, K_PCG_MATVEC, K_PCG_UPDATE, K_PCG_REDUCE, K_SLICE,
-    K_GRAD_SCATTER,
+    K_GRAD_SCATTER, K_DT_ROWS, K_DT_COLS, K_DT_OTHER,
     K_COUNT
 };
 void timing_begin(hipStream_t s, int id);

@@ -15,7 +15,7 @@ namespace bs {
 static const char* const kKernelNames[K_COUNT] = {
     "level_count", "level_scan", "level_write", "neighbour_table", "bist_step", "bist_other",
     "splat", "init", "pcg_start", "pcg_matvec", "pcg_update", "pcg_reduce", "slice",
-    "grad_scatter"};
+    "grad_scatter", "dt_rows", "dt_cols", "dt_other"};
 
 namespace {
 struct Pending {

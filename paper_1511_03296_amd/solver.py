@@ -9,7 +9,9 @@ step of the solver runs in the HIP library behind the C ABI (``_lib``):
     gt, gc, g = grid.backward(target, conf, y, grad_x, lam=128.0)  # Section 3 adjoint
 
 ``bilateral_solve`` wraps these in a ``torch.autograd.Function`` that is
-differentiable in the target and the confidence.
+differentiable in the target and the confidence.  ``domain_transform``
+post-processes an output; ``dt_confidence`` gives the robust solver an initial
+confidence from the edge-aware variance of its input.
 """
 from __future__ import annotations
 
@@ -269,6 +271,56 @@ class BilateralGrid:
 def read_stats(stats: torch.Tensor) -> np.ndarray:
     """Per-channel solve stats (iters, reason, rel_residual, bnorm) as a NumPy record array."""
     return np.frombuffer(stats.cpu().numpy().tobytes(), dtype=_STATS_DTYPE)
+
+
+def _dt_workspace(H: int, W: int, device, ws: torch.Tensor | None) -> torch.Tensor:
+    nbytes = L.lib.bs_dt_workspace_bytes(H, W)
+    if nbytes == 0:
+        raise ValueError(f"unsupported image size {H}x{W}")
+    if ws is None or ws.numel() < nbytes:
+        ws = torch.empty(nbytes, dtype=torch.uint8, device=device)
+    return ws
+
+
+def domain_transform(ref: torch.Tensor, x: torch.Tensor, sigma_s: float, sigma_r: float,
+                     iters: int = 3, out: torch.Tensor | None = None,
+                     ws: torch.Tensor | None = None) -> torch.Tensor:
+    """The recursive-filter domain transform of x [C][H][W] guided by the
+    reference [3][H][W] (the post-process of the solver's output, Section 4);
+    out=x filters in place."""
+    H, W = int(ref.shape[1]), int(ref.shape[2])
+    ref = _dev_f32(ref, "reference", (3, H, W))
+    C = int(x.shape[0])
+    x = _dev_f32(x, "x", (C, H, W))
+    if out is None:
+        out = torch.empty_like(x)
+    elif not out.is_contiguous() or tuple(out.shape) != (C, H, W) or out.dtype != torch.float32:
+        raise ValueError("out must be a contiguous float32 tensor shaped like x")
+    ws = _dt_workspace(H, W, x.device, ws)
+    p = L.DtParams(float(sigma_s), float(sigma_r), int(iters))
+    L.check(L.lib.bs_domain_transform(ref.data_ptr(), H, W, x.data_ptr(), C, ct.byref(p),
+                                      out.data_ptr(), ws.data_ptr(), ws.numel(), _stream()),
+            "bs_domain_transform")
+    return out
+
+
+def dt_confidence(ref: torch.Tensor, z: torch.Tensor, sigma_s: float, sigma_r: float,
+                  sigma_dt: float, zero_cols: int = 0, iters: int = 3,
+                  ws: torch.Tensor | None = None) -> torch.Tensor:
+    """The robust solver's initial confidence exp(-V / (2 sigma_dt^2)) from the
+    edge-aware variance V = DT(z^2) - DT(z)^2 of z [H][W] (supplement Section
+    Robustness), 0 in the leftmost zero_cols columns."""
+    H, W = int(ref.shape[1]), int(ref.shape[2])
+    ref = _dev_f32(ref, "reference", (3, H, W))
+    z = _dev_f32(z, "z", (H, W))
+    conf = torch.empty((H, W), dtype=torch.float32, device=z.device)
+    ws = _dt_workspace(H, W, z.device, ws)
+    p = L.DtParams(float(sigma_s), float(sigma_r), int(iters))
+    L.check(L.lib.bs_dt_confidence(ref.data_ptr(), H, W, z.data_ptr(), ct.byref(p),
+                                   float(sigma_dt), int(zero_cols), conf.data_ptr(),
+                                   ws.data_ptr(), ws.numel(), _stream()),
+            "bs_dt_confidence")
+    return conf
 
 
 class _BilateralSolveFn(torch.autograd.Function):

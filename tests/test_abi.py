@@ -118,7 +118,8 @@ def test_ctypes_mirrors_match_the_c_layout(tmp_path):
     from paper_1511_03296_amd import _lib as L
     mirrors = {"bs_grid_params": L.GridParams, "bs_bistoch_params": L.BistochParams,
                "bs_solve_params": L.SolveParams, "bs_chan_stats": L.ChanStats,
-               "bs_grid": L.Grid, "bs_grid_view": L.GridView, "bs_batch_item": L.BatchItem}
+               "bs_grid": L.Grid, "bs_grid_view": L.GridView, "bs_batch_item": L.BatchItem,
+               "bs_dt_params": L.DtParams}
     c_name = {"lambda_": "lambda"}
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "bsolve.h"',
              'int main(void) {']
@@ -156,3 +157,36 @@ def test_image_size_limits():
     assert L.lib.bs_grid_workspace_bytes(65536, 1, q) == 0
     assert L.lib.bs_grid_workspace_bytes(32768, 32768, q) > 0      # exactly 2^30 pixels
     assert L.lib.bs_grid_workspace_bytes(32768, 32769, q) == 0
+
+
+def test_domain_transform_arguments_are_rejected_before_launch():
+    from paper_1511_03296_amd import _lib as L
+    assert ct.sizeof(L.DtParams) == 12
+    n = L.lib.bs_dt_workspace_bytes(48, 64)
+    assert n >= 48 * 64 * 12 and n % 256 == 0
+    assert L.lib.bs_dt_workspace_bytes(0, 64) == 0
+    assert L.lib.bs_dt_workspace_bytes(70000, 4) == 0
+    good = L.DtParams(8.0, 16.0, 3)
+    dev, ws = ct.c_void_p(256), ct.c_void_p(1 << 20)
+
+    def dt(ref=dev, H=48, W=64, x=dev, C=1, p=good, out=dev, w=ws, nb=n):
+        return L.lib.bs_domain_transform(ref, H, W, x, C, ct.byref(p) if p else None, out, w,
+                                         nb, None)
+    assert dt(ref=None) == L.BS_EINVAL
+    assert dt(p=None) == L.BS_EINVAL
+    assert dt(p=L.DtParams(0.0, 16.0, 3)) == L.BS_EINVAL
+    assert dt(p=L.DtParams(8.0, float("inf"), 3)) == L.BS_EINVAL
+    assert dt(p=L.DtParams(8.0, 16.0, 0)) == L.BS_EINVAL
+    assert dt(p=L.DtParams(8.0, 16.0, 17)) == L.BS_EINVAL
+    assert dt(C=0) == L.BS_EINVAL and dt(C=65) == L.BS_EINVAL
+    assert dt(x=ct.c_void_p(258)) == L.BS_EINVAL
+    # partly overlapping input and output (x and out equal is allowed)
+    assert dt(x=ct.c_void_p(256), out=ct.c_void_p(512)) == L.BS_EINVAL
+    assert b"overlap" in L.lib.bs_last_error()
+    assert dt(H=70000) == L.BS_EUNSUPPORTED
+    assert dt(w=ct.c_void_p((1 << 20) + 4)) == L.BS_EINVAL
+    assert dt(nb=n - 1) == L.BS_EWORKSPACE
+    st = L.lib.bs_dt_confidence(dev, 48, 64, dev, ct.byref(good), 0.0, 0, dev, ws, n, None)
+    assert st == L.BS_EINVAL and b"sigma_dt" in L.lib.bs_last_error()
+    st = L.lib.bs_dt_confidence(dev, 48, 64, dev, ct.byref(good), 2.0, -1, dev, ws, n, None)
+    assert st == L.BS_EINVAL

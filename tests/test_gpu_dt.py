@@ -1,0 +1,129 @@
+"""The domain transform on the GPU against the FP64 oracle
+(oracle/domain_transform.py): the post-process of the solver's output
+(Section 4) and the robust solver's initial confidence (supplement Section
+Robustness), through the C ABI.
+
+Tolerances, from the arithmetic: every recursion step is a convex combination
+(weights in [0, 1] summing to 1) evaluated in float32, so a pass adds a few
+ulp of the signal's magnitude and the 6 passes of 3 iterations stay within
+1e-5 of max|x| (relative L2 1e-5).  The confidence takes V = DT(z^2) - DT(z)^2
+about the mean of z: its float32 error is a few tens of ulp of max (z - mean)^2,
+so |dc| <= 1e-5 max (z - mean)^2 / (2 sigma_dt^2) (plus 1e-6 for exp)."""
+import numpy as np
+import pytest
+import torch
+
+import workloads as WL
+from oracle import domain_transform as DT
+from tests.gpu_helpers import rel_l2, say, to_dev
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-5
+
+
+def _check(got, want, what):
+    got = np.asarray(got, np.float64)
+    scale = max(float(np.max(np.abs(want))), 1e-30)
+    err = float(np.max(np.abs(got - want))) / scale
+    rel = rel_l2(got, want)
+    say(f"    {what}: max |err| / max |x| {err:.2e}, rel-L2 {rel:.2e}")
+    assert err <= TOL and rel <= TOL, (what, err, rel)
+
+
+def _run(ref, x, ss, sr, iters=3, inplace=False):
+    from paper_1511_03296_amd import domain_transform
+    xd = to_dev(x)
+    out = domain_transform(to_dev(ref), xd, ss, sr, iters, out=xd if inplace else None)
+    torch.cuda.synchronize()
+    return out.cpu().numpy()
+
+
+@pytest.mark.parametrize("H,W,C,ss,sr", [
+    (1, 1, 1, 4.0, 4.0),
+    (1, 513, 2, 16.0, 8.0),        # one row, a ragged second chunk
+    (700, 1, 1, 8.0, 16.0),        # one column, ragged row segments
+    (17, 1100, 3, 16.0, 16.0),     # three row chunks, 17 rows in 16 segments
+    (95, 161, 21, 4.0, 8.0),       # 21 channels, ragged column strips
+    (200, 300, 1, 64.0, 4.0),      # wide support, strong edges
+])
+def test_domain_transform_against_oracle(H, W, C, ss, sr):
+    say(f"domain transform {H}x{W} C={C} sigma_s={ss} sigma_r={sr}")
+    rng = np.random.default_rng(H * 1000 + W)
+    ref, _ = WL.voronoi_reference(rng, H, W, max(1, H * W // 400))
+    x = rng.normal(0.0, 1.0, (C, H, W)).astype(np.float32) + 3.0
+    want = DT.domain_transform(ref, x, ss, sr)
+    _check(_run(ref, x, ss, sr), want, "out of place")
+    got_in = _run(ref, x, ss, sr, inplace=True)
+    assert np.array_equal(got_in, _run(ref, x, ss, sr))
+
+
+def test_iteration_counts_and_flat_guide():
+    """N = 1 and N = 5, and a flat guide (every edge at distance 1)."""
+    rng = np.random.default_rng(5)
+    H, W = 40, 600
+    ref, _ = WL.voronoi_reference(rng, H, W, 30)
+    x = rng.normal(size=(2, H, W)).astype(np.float32)
+    for n in (1, 5):
+        say(f"domain transform, {n} iterations")
+        _check(_run(ref, x, 12.0, 10.0, n), DT.domain_transform(ref, x, 12.0, 10.0, n),
+               f"N={n}")
+    flat = np.full((3, H, W), 0.25, np.float32)
+    say("domain transform, flat guide")
+    _check(_run(flat, x, 30.0, 1.0), DT.domain_transform(flat, x, 30.0, 1.0), "flat guide")
+
+
+def test_longest_sides():
+    """A 65535-wide row (128 chunks) and a 65535-high column (segments of
+    4096 rows)."""
+    rng = np.random.default_rng(6)
+    for H, W in ((1, 65535), (65535, 1)):
+        say(f"domain transform {H}x{W}")
+        ref = rng.uniform(0, 1, (3, H, W)).astype(np.float32)
+        x = rng.normal(size=(1, H, W)).astype(np.float32)
+        _check(_run(ref, x, 32.0, 64.0), DT.domain_transform(ref, x, 32.0, 64.0), f"{H}x{W}")
+
+
+def test_full_size_post_process_and_confidence():
+    """The stereo workload (1024x768) with the paper's RBS post-process
+    bandwidths (sigma'_xy = sigma'_rgb = 4) and its confidence parameters
+    (sigma_xy = sigma_rgb = 32, sigma_dt = 2, 80 columns zeroed); the
+    segmentation shape (512x512, 21 channels) with the colorization
+    bandwidths (4, 8)."""
+    from paper_1511_03296_amd import dt_confidence
+    p = WL.stereo_refine(seed=0)
+    say("full size: stereo 1024x768 post-process")
+    _check(_run(p.ref, p.target, 4.0, 4.0), DT.domain_transform(p.ref, p.target, 4.0, 4.0),
+           "stereo post-process")
+    say("full size: stereo 1024x768 confidence")
+    z = p.target[0]
+    c = dt_confidence(to_dev(p.ref), to_dev(z), 32.0, 32.0, 2.0, zero_cols=80)
+    torch.cuda.synchronize()
+    c = c.cpu().numpy().astype(np.float64)
+    want = DT.dt_confidence(p.ref, z, 32.0, 32.0, 2.0, zero_cols=80)
+    zz = z.astype(np.float64)
+    bound = 1e-5 * float(np.max((zz - zz.mean()) ** 2)) / 8.0 + 1e-6
+    err = float(np.max(np.abs(c - want)))
+    say(f"    confidence: max |err| {err:.2e} (bound {bound:.2e}), "
+        f"mean c {want.mean():.3f}")
+    assert err <= bound
+    assert np.all(c[:, :80] == 0.0)
+    s = WL.segmentation(seed=1)
+    say("full size: segmentation 512x512x21 post-process")
+    _check(_run(s.ref, s.target, 4.0, 8.0), DT.domain_transform(s.ref, s.target, 4.0, 8.0),
+           "segmentation post-process")
+
+
+def test_confidence_small_images():
+    from paper_1511_03296_amd import dt_confidence
+    rng = np.random.default_rng(7)
+    for H, W, zc in ((1, 1, 0), (30, 50, 3), (64, 130, 200)):
+        say(f"confidence {H}x{W} zero_cols={zc}")
+        ref, _ = WL.voronoi_reference(rng, H, W, 5)
+        z = rng.uniform(0.0, 256.0, (H, W)).astype(np.float32)
+        c = dt_confidence(to_dev(ref), to_dev(z), 8.0, 16.0, 2.0, zero_cols=zc)
+        torch.cuda.synchronize()
+        want = DT.dt_confidence(ref, z, 8.0, 16.0, 2.0, zero_cols=zc)
+        zz = z.astype(np.float64)
+        bound = 1e-5 * float(np.max((zz - zz.mean()) ** 2)) / 8.0 + 1e-6
+        assert float(np.max(np.abs(c.cpu().numpy() - want))) <= bound
