@@ -14,10 +14,16 @@
 // iteration is two kernels, each with one grid-wide reduction:
 //   pcg_matvec:  z = M^-1 r,  d = z + beta d,  q = A d,  d^T q;
 //   pcg_update:  y += alpha d,  r -= alpha q,  r^T r,  r^T M^-1 r.
-// The new d is not stored before the reduction that yields beta, so the
-// matvec either recomputes the neighbours' new d from their gathered r and
-// old d (two gathered vectors), or, on 3 of every 4 iterations, takes
-// q = A z + beta q by linearity and gathers w = n o M^-1 r alone.
+// With the Jacobi preconditioner the residual is stored scaled, as
+// w = n o M^-1 r (s = n M^-1 per vertex): the neighbours' share of A z is
+// n o z = w, so the matvec gathers the stored residual itself, and
+// z = w / n, r = w / s are recovered per vertex (r = 0 on a row with
+// diag(A) = 0, where s = 0).  The new d is not stored before the reduction
+// that yields beta, so the matvec either recomputes the neighbours' new d
+// from their gathered w, old d and n (two gathered vectors), or, on 3 of
+// every 4 iterations, takes q = A z + beta q by linearity and gathers w
+// alone.  (With the hierarchical preconditioner r is stored as it is, and z
+// beside it in w.)
 // A z is evaluated in Laplacian form,
 //   (A z)_v = (S c)_v z_v + lam n_v sum_u n_u (z_v - z_u),
 // which equals diag(A) z - lam n o N(n o z) with diag(A) = lam n o N n + S c,
@@ -580,17 +586,32 @@ __global__ void __launch_bounds__(kRedBlock) pcg_prologue(PcgArgs a) {
     if (jb == 0 && t == 0) *I.active = 1;
 }
 
-// w = n o M^-1 r, the neighbours' share of the recurrence matvec.
+// w = s o r, s = n M^-1 (rounded to float32 once, as the update's s), the
+// stored form of the Jacobi iteration's residual.
 template <int K>
 __device__ inline Vec<K> scaled_residual(const Vec<K>& r, float2 nm) {
     Vec<K> w;
+    const float sv = nm.x * nm.y;
 #pragma unroll
-    for (int k = 0; k < K; ++k) w.v[k] = nm.x * (nm.y * r.v[k]);
+    for (int k = 0; k < K; ++k) w.v[k] = sv * r.v[k];
     return w;
 }
 
-// r = b - A y0 (and w for the recurrence matvec); partials r^T r, b^T b,
-// r^T M^-1 r.
+// Per-vertex factors that recover z = w / n and r = w / s (s = n M^-1) from
+// the stored residual w; r is 0 on a row with diag(A) = 0 (M^-1 = 0).  n > 0
+// on every vertex (bistochastization scales are positive).
+struct ResScale {
+    float inv_n, inv_s;
+};
+__device__ inline ResScale res_scale(float2 nm) {
+    ResScale o;
+    o.inv_n = __builtin_amdgcn_rcpf(nm.x);
+    o.inv_s = nm.y > 0.0f ? __builtin_amdgcn_rcpf(nm.x * nm.y) : 0.0f;
+    return o;
+}
+
+// r = b - A y0, stored as w = n o M^-1 r (as r with the hierarchical
+// preconditioner); partials r^T r, b^T b, r^T M^-1 r.
 template <int K, bool MULTI, bool PACKED>
 __global__ void __launch_bounds__(kRedBlock) pcg_start(PcgArgs a) {
     int jb;
@@ -636,8 +657,8 @@ __global__ void __launch_bounds__(kRedBlock) pcg_start(PcgArgs a) {
             acc[1][k] += (double)bv.v[k] * (double)bv.v[k];
             acc[2][k] += (double)rv.v[k] * (double)(nmv.y * rv.v[k]);
         }
-        stv<K>(I.r, e, rv);
-        if constexpr (uses_recurrence<K>()) stv<K>(I.w, e, scaled_residual<K>(rv, nmv));
+        if (I.zmode) stv<K>(I.r, e, rv);
+        else stv<K>(I.w, e, scaled_residual<K>(rv, nmv));
     }
     lane_partials<3, K>(acc, ln, Cp, nb, partial_slot(jb, nb), I.part0);
 }
@@ -645,12 +666,14 @@ __global__ void __launch_bounds__(kRedBlock) pcg_start(PcgArgs a) {
 // Operands of one lane of pcg_matvec.  Loading them does not depend on the
 // iteration's scalars, so the first tile's loads are issued before the
 // prologue and overlap its reduction.  The exact form gathers the
-// neighbours' r, old d and {n, M^-1}; the recurrence form their w alone.
+// neighbours' w, old d and {n, M^-1}; the recurrence form their w alone.
+// rv is the vertex's own stored residual w (z with the hierarchical
+// preconditioner).
 template <int K, bool EXACT>
 struct MatOps {
     int v;
     int nb[10];
-    Vec<K> g[10];                  // r (EXACT) or w of the neighbours
+    Vec<K> g[10];                  // w (z with the hierarchical preconditioner)
     Vec<K> d[EXACT ? 10 : 1];
     float2 nm[EXACT ? 10 : 1];
     Vec<K> rv, dv, qv, yv;
@@ -672,18 +695,15 @@ __device__ inline void load_ops(MatOps<K, EXACT>& o, int v, const int (&nb)[10],
         const int u = nb[j];
         if (u >= 0) {
             const uint32_t eu = lane_elem(u, Cp, ln.g, K);
+            o.g[j] = ldv<K>(I.w, eu);
             if constexpr (EXACT) {
-                o.g[j] = ldv<K>(I.zmode ? I.w : I.r, eu);
                 o.d[j] = ldv<K>(din, eu);
                 o.nm[j] = *elem(I.nfm, (uint32_t)u);
-            } else {
-                o.g[j] = ldv<K>(I.w, eu);
             }
         }
     }
     const uint32_t e = lane_elem(v, Cp, ln.g, K);
-    if constexpr (EXACT) o.rv = ldv<K>(I.zmode ? I.w : I.r, e);
-    else o.rv = ldv<K>(I.r, e);
+    o.rv = ldv<K>(I.w, e);
     o.dv = ldv<K>(din, e);
     o.yv = ldv<K>(I.y, e);
     o.nmv = *elem(I.nfm, (uint32_t)v);
@@ -715,7 +735,7 @@ __device__ inline void load_ops_late(MatOps<K, EXACT>& o, int v, const int (&raw
         if (u >= 0) o.g[j] = ldv<K>(I.w, lane_elem(u, Cp, ln.g, K));
     }
     const uint32_t e = lane_elem(v, Cp, ln.g, K);
-    o.rv = ldv<K>(I.r, e);
+    o.rv = ldv<K>(I.w, e);
     o.dv = ldv<K>(din, e);
     o.yv = ldv<K>(I.y, e);
     o.nmv = *elem(I.nfm, (uint32_t)v);
@@ -731,15 +751,15 @@ __device__ inline float pcg_dir(float z, float d_old, float beta, bool first) {
 // Prologue: finish the previous step (stopping rule, beta) from the slot-0
 // partials.  Then y += alpha d_old, the previous iteration's step (deferred
 // from the update to here, where d_old is read anyway; pcg_flush applies
-// the last one), and, with z = M^-1 r, d = z + beta d and partials of d^T q,
-// where q = A d is either
+// the last one), and, with z = M^-1 r = w / n, d = z + beta d and partials
+// of d^T q, where q = A d is either
 //   EXACT false:  A z + beta q, its recurrence.  diag(A) z = r, so
-//                   (A z)_v = r_v - lam n_v sum_u w_u,  w = n o M^-1 r,
-//                 and only w is gathered from the neighbours (it is written
-//                 by the previous update); d and q are updated in place
-//                 (d[src]).  A row with diag(A) = 0 is zero: (A z)_v = 0.
+//                   (A z)_v = r_v - lam n_v sum_u w_u,  r_v = w_v / s_v,
+//                 and only the stored residual w is gathered from the
+//                 neighbours; d and q are updated in place (d[src]).  A row
+//                 with diag(A) = 0 is zero: (A z)_v = 0.
 //   EXACT true:   A d itself, in Laplacian form, with the neighbours' new d
-//                 recomputed from their gathered r and old d (read from
+//                 recomputed from their gathered w, n and old d (read from
 //                 d[src], written to d[src ^ 1]).  It resets the rounding
 //                 that the recurrence accumulates.
 // On a channel's first iteration d = z and q = A z.
@@ -837,11 +857,12 @@ __global__ void __launch_bounds__(kRedBlock) pcg_matvec(PcgArgs a, int src) {
         if (any && have) {
             float zv[K], ns[K];
             Vec<K> dv, qv;
-            // z = M^-1 r: the Jacobi inverse times r, or as stored (zmode)
+            // z = M^-1 r: the stored residual over n, or as stored (zmode)
             const bool zm = EXACT && I.zmode;
+            const ResScale rs = res_scale(o.nmv);
 #pragma unroll
             for (int k = 0; k < K; ++k) {
-                zv[k] = zm ? o.rv.v[k] : o.nmv.y * o.rv.v[k];
+                zv[k] = zm ? o.rv.v[k] : o.rv.v[k] * rs.inv_n;
                 dv.v[k] = pcg_dir(zv[k], o.dv.v[k], beta[k], first[k]);
                 ns[k] = 0.0f;
             }
@@ -849,12 +870,12 @@ __global__ void __launch_bounds__(kRedBlock) pcg_matvec(PcgArgs a, int src) {
 #pragma unroll
                 for (int j = 0; j < 10; ++j) {
                     if (o.nb[j] >= 0) {
+                        const float inu = zm ? 1.0f : __builtin_amdgcn_rcpf(o.nm[j].x);
 #pragma unroll
                         for (int k = 0; k < K; ++k)
                             ns[k] += o.nm[j].x *
-                                     (dv.v[k] - pcg_dir(zm ? o.g[j].v[k]
-                                                           : o.nm[j].y * o.g[j].v[k],
-                                                        o.d[j].v[k], beta[k], first[k]));
+                                     (dv.v[k] - pcg_dir(o.g[j].v[k] * inu, o.d[j].v[k], beta[k],
+                                                        first[k]));
                     }
                 }
 #pragma unroll
@@ -867,10 +888,9 @@ __global__ void __launch_bounds__(kRedBlock) pcg_matvec(PcgArgs a, int src) {
                         for (int k = 0; k < K; ++k) ns[k] += o.g[j].v[k];
                     }
                 }
-                const bool row = o.nmv.y > 0.0f;
 #pragma unroll
                 for (int k = 0; k < K; ++k) {
-                    const float az = (row ? o.rv.v[k] : 0.0f) - lam * o.nmv.x * ns[k];
+                    const float az = o.rv.v[k] * rs.inv_s - lam * o.nmv.x * ns[k];
                     qv.v[k] = first[k] ? az : fmaf(beta[k], o.qv.v[k], az);
                 }
             }
@@ -896,12 +916,13 @@ __global__ void __launch_bounds__(kRedBlock) pcg_matvec(PcgArgs a, int src) {
 }
 
 // Prologue: alpha = r^T M^-1 r / d^T q from the slot-1 partials (a channel
-// with d^T q <= 0 stops).  Then r -= alpha q and partials of r^T r and
-// r^T M^-1 r; with want_w, also w = n o M^-1 r for a following recurrence
-// matvec.  The step y += alpha d is left to the next matvec (or pcg_flush).
-// Stopped channels keep their values.
+// with d^T q <= 0 stops).  Then r -= alpha q, on the stored residual
+// w = s o r as w -= (alpha s) q, and partials of r^T r and r^T M^-1 r from
+// r = w / s and z = w / n (with the hierarchical preconditioner r itself is
+// stored and updated).  The step y += alpha d is left to the next matvec (or
+// pcg_flush).  Stopped channels keep their values.
 template <int K, bool MULTI>
-__global__ void __launch_bounds__(kRedBlock) pcg_update(PcgArgs a, int want_w) {
+__global__ void __launch_bounds__(kRedBlock) pcg_update(PcgArgs a) {
     __shared__ ChanState S[BS_MAX_CHANNELS];
     __shared__ double fin[BS_MAX_CHANNELS];
     __shared__ int n_active;
@@ -919,6 +940,8 @@ __global__ void __launch_bounds__(kRedBlock) pcg_update(PcgArgs a, int want_w) {
     PartialSums ps;
     ps.load(I.part1, Cp, nb, I.sums1);
     ChanState st0 = load_state(I.cs1 + (int64_t)jb * Cp + min(t, Cp - 1));
+    // the stored residual: w = s o r (Jacobi), or r itself (zmode)
+    gp<float> res = I.zmode ? I.r : I.w;
     // first tile's operands in flight during the reduction
     int v = (int)(tl.first * ln.vpb) + ln.vl;
     bool have = ln.ok && tl.first < tl.end && v < V;
@@ -926,7 +949,7 @@ __global__ void __launch_bounds__(kRedBlock) pcg_update(PcgArgs a, int want_w) {
     float2 nmv = make_float2(0.0f, 0.0f);
     if (have) {
         const uint32_t e = lane_elem(v, Cp, ln.g, K);
-        rv = ldv<K>(I.r, e);
+        rv = ldv<K>(res, e);
         qv = ldv<K>(I.q, e);
         nmv = *elem(I.nfm, (uint32_t)v);
     }
@@ -973,27 +996,41 @@ __global__ void __launch_bounds__(kRedBlock) pcg_update(PcgArgs a, int want_w) {
         float2 nmn = make_float2(0.0f, 0.0f);
         if (hn) {
             const uint32_t e = lane_elem(vn, Cp, ln.g, K);
-            rn = ldv<K>(I.r, e);
+            rn = ldv<K>(res, e);
             qn = ldv<K>(I.q, e);
             nmn = *elem(I.nfm, (uint32_t)vn);
         }
         if (any && have) {
-            Vec<K> r1;
+            Vec<K> w1;
+            if (I.zmode) {
 #pragma unroll
-            for (int k = 0; k < K; ++k) {
-                if (act[k]) {
-                    r1.v[k] = fmaf(-alpha[k], qv.v[k], rv.v[k]);
-                    acc[0][k] += (double)r1.v[k] * (double)r1.v[k];
-                    acc[2][k] += (double)r1.v[k] * (double)(nmv.y * r1.v[k]);
-                } else {
-                    r1.v[k] = rv.v[k];
+                for (int k = 0; k < K; ++k) {
+                    if (act[k]) {
+                        w1.v[k] = fmaf(-alpha[k], qv.v[k], rv.v[k]);
+                        acc[0][k] += (double)w1.v[k] * (double)w1.v[k];
+                    } else {
+                        w1.v[k] = rv.v[k];
+                    }
+                }
+            } else {
+                const ResScale rs = res_scale(nmv);
+                const double sv = (double)(nmv.x * nmv.y);
+#pragma unroll
+                for (int k = 0; k < K; ++k) {
+                    if (act[k]) {
+                        // w - alpha s q rounded once, as r - alpha q would be:
+                        // the implied r = w / s keeps one rounding per step
+                        w1.v[k] = (float)fma(-(double)alpha[k] * sv, (double)qv.v[k],
+                                             (double)rv.v[k]);
+                        const float r1 = w1.v[k] * rs.inv_s;
+                        acc[0][k] += (double)r1 * (double)r1;
+                        acc[2][k] += (double)r1 * (double)(w1.v[k] * rs.inv_n);
+                    } else {
+                        w1.v[k] = rv.v[k];
+                    }
                 }
             }
-            const uint32_t e = lane_elem(v, Cp, ln.g, K);
-            stv<K>(I.r, e, r1);
-            if constexpr (uses_recurrence<K>()) {
-                if (want_w) stv<K>(I.w, e, scaled_residual<K>(r1, nmv));
-            }
+            stv<K>(res, lane_elem(v, Cp, ln.g, K), w1);
         }
         v = vn;
         have = hn;
@@ -1362,9 +1399,7 @@ static bs_status run_pcg_k(const PcgArgs& a, int n, int G, int max_cp, bool sep,
         if (sep)
             BS_LAUNCH(s, K_PCG_REDUCE, "pcg_reduce", pcg_reduce<MULTI>, dim3(max_cp, n), block, 0,
                       s, a, 1, 1);
-        const int want_w = (hp || exact_iteration<K>(it + 1)) ? 0 : 1;
-        BS_LAUNCH(s, K_PCG_UPDATE, "pcg_update", (pcg_update<K, MULTI>), grid, block, 0, s, a,
-                  want_w);
+        BS_LAUNCH(s, K_PCG_UPDATE, "pcg_update", (pcg_update<K, MULTI>), grid, block, 0, s, a);
         if constexpr (!MULTI) {
             if (hp) {
                 const bs_status st = prec_apply<K>(a, *hp, G, s);

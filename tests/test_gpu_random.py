@@ -30,7 +30,11 @@ def test_random_case(seed):
     x = G.slice(y, p.C)
     torch.cuda.synchronize()
     got = grid_arrays(G)
-    sol = O.solve(p.ref, p.target, p.conf, params(p, rel_tol=1e-12, max_iters=20000))
+    # the oracle under the same stopping rule (R10): on case 28 (3366 vertices
+    # in components without confidence) even its float64 iterate at 1e-6 lies
+    # 1.1e-4 from the converged minimiser, so a 1e-12 reference would measure
+    # the stopping rule rather than the GPU
+    sol = O.solve(p.ref, p.target, p.conf, params(p, rel_tol=1e-6, max_iters=20000))
     assert got["V"] == sol.grid.V and np.array_equal(got["key"], sol.grid.keys)
     assert np.array_equal(got["idx"], sol.grid.idx) and np.array_equal(got["nbr"], sol.grid.nbr)
     if got["nb_packed"]:
