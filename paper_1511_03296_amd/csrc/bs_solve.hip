@@ -672,7 +672,7 @@ __global__ void __launch_bounds__(kRedBlock) pcg_start(PcgArgs a) {
 template <int K, bool EXACT>
 struct MatOps {
     int v;
-    int nb[10];
+    uint32_t have;                 // bit j: neighbour j exists
     Vec<K> g[10];                  // w (z with the hierarchical preconditioner)
     Vec<K> d[EXACT ? 10 : 1];
     float2 nm[EXACT ? 10 : 1];
@@ -686,14 +686,15 @@ template <int K, bool EXACT>
 __device__ inline void load_ops(MatOps<K, EXACT>& o, int v, const int (&nb)[10], const Lanes& ln,
                                 const ImgView& I, gp<const float> din) {
     o.v = v;
+    o.have = 0;
     const int Cp = I.Cp;
     // Missing neighbours (about half of the slots) load nothing: the lanes
     // are masked off, which halves the bytes the texture path delivers.
 #pragma unroll
     for (int j = 0; j < 10; ++j) {
-        o.nb[j] = nb[j];
         const int u = nb[j];
         if (u >= 0) {
+            o.have |= 1u << j;
             const uint32_t eu = lane_elem(u, Cp, ln.g, K);
             o.g[j] = ldv<K>(I.w, eu);
             if constexpr (EXACT) {
@@ -726,13 +727,16 @@ __device__ inline void load_ops_late(MatOps<K, EXACT>& o, int v, const int (&raw
         return;
     } else {
     o.v = v;
+    o.have = 0;
     const int Cp = I.Cp;
 #pragma unroll
     for (int j = 0; j < 10; ++j) {
         const uint32_t wd = (uint32_t)raw[j >> 1];
         const int u = unpack_offset(v, (j & 1) ? wd >> 16 : wd & 0xffffu);
-        o.nb[j] = u;
-        if (u >= 0) o.g[j] = ldv<K>(I.w, lane_elem(u, Cp, ln.g, K));
+        if (u >= 0) {
+            o.have |= 1u << j;
+            o.g[j] = ldv<K>(I.w, lane_elem(u, Cp, ln.g, K));
+        }
     }
     const uint32_t e = lane_elem(v, Cp, ln.g, K);
     o.rv = ldv<K>(I.w, e);
@@ -763,8 +767,9 @@ __device__ inline float pcg_dir(float z, float d_old, float beta, bool first) {
 //                 d[src], written to d[src ^ 1]).  It resets the rounding
 //                 that the recurrence accumulates.
 // On a channel's first iteration d = z and q = A z.
-template <int K, bool MULTI, bool EXACT, bool PACKED>
+template <int K, bool MULTI, bool EXACT, bool PACKED, bool ZMODE = false>
 __global__ void __launch_bounds__(kRedBlock) pcg_matvec(PcgArgs a, int src) {
+    static_assert(!ZMODE || (EXACT && !MULTI), "z is stored for single-image exact matvecs");
     __shared__ ChanState S[BS_MAX_CHANNELS];
     __shared__ double fin[3 * BS_MAX_CHANNELS];
     __shared__ float pend[BS_MAX_CHANNELS];
@@ -857,8 +862,8 @@ __global__ void __launch_bounds__(kRedBlock) pcg_matvec(PcgArgs a, int src) {
         if (any && have) {
             float zv[K], ns[K];
             Vec<K> dv, qv;
-            // z = M^-1 r: the stored residual over n, or as stored (zmode)
-            const bool zm = EXACT && I.zmode;
+            // z = M^-1 r: the stored residual over n, or as stored (ZMODE)
+            constexpr bool zm = ZMODE;
             const ResScale rs = res_scale(o.nmv);
 #pragma unroll
             for (int k = 0; k < K; ++k) {
@@ -869,7 +874,7 @@ __global__ void __launch_bounds__(kRedBlock) pcg_matvec(PcgArgs a, int src) {
             if constexpr (EXACT) {
 #pragma unroll
                 for (int j = 0; j < 10; ++j) {
-                    if (o.nb[j] >= 0) {
+                    if (o.have & (1u << j)) {
                         const float inu = zm ? 1.0f : __builtin_amdgcn_rcpf(o.nm[j].x);
 #pragma unroll
                         for (int k = 0; k < K; ++k)
@@ -883,7 +888,7 @@ __global__ void __launch_bounds__(kRedBlock) pcg_matvec(PcgArgs a, int src) {
             } else {
 #pragma unroll
                 for (int j = 0; j < 10; ++j) {
-                    if (o.nb[j] >= 0) {
+                    if (o.have & (1u << j)) {
 #pragma unroll
                         for (int k = 0; k < K; ++k) ns[k] += o.g[j].v[k];
                     }
@@ -921,7 +926,7 @@ __global__ void __launch_bounds__(kRedBlock) pcg_matvec(PcgArgs a, int src) {
 // r = w / s and z = w / n (with the hierarchical preconditioner r itself is
 // stored and updated).  The step y += alpha d is left to the next matvec (or
 // pcg_flush).  Stopped channels keep their values.
-template <int K, bool MULTI>
+template <int K, bool MULTI, bool ZMODE = false>
 __global__ void __launch_bounds__(kRedBlock) pcg_update(PcgArgs a) {
     __shared__ ChanState S[BS_MAX_CHANNELS];
     __shared__ double fin[BS_MAX_CHANNELS];
@@ -940,8 +945,8 @@ __global__ void __launch_bounds__(kRedBlock) pcg_update(PcgArgs a) {
     PartialSums ps;
     ps.load(I.part1, Cp, nb, I.sums1);
     ChanState st0 = load_state(I.cs1 + (int64_t)jb * Cp + min(t, Cp - 1));
-    // the stored residual: w = s o r (Jacobi), or r itself (zmode)
-    gp<float> res = I.zmode ? I.r : I.w;
+    // the stored residual: w = s o r (Jacobi), or r itself (ZMODE)
+    gp<float> res = ZMODE ? I.r : I.w;
     // first tile's operands in flight during the reduction
     int v = (int)(tl.first * ln.vpb) + ln.vl;
     bool have = ln.ok && tl.first < tl.end && v < V;
@@ -1002,7 +1007,7 @@ __global__ void __launch_bounds__(kRedBlock) pcg_update(PcgArgs a) {
         }
         if (any && have) {
             Vec<K> w1;
-            if (I.zmode) {
+            if constexpr (ZMODE) {
 #pragma unroll
                 for (int k = 0; k < K; ++k) {
                     if (act[k]) {
@@ -1388,7 +1393,15 @@ static bs_status run_pcg_k(const PcgArgs& a, int n, int G, int max_cp, bool sep,
     for (int it = 0; it < p.max_iters; ++it) {
         // with the hierarchical preconditioner every matvec is the exact form
         // (the recurrence needs diag(A) z = r)
-        if (hp || exact_iteration<K>(it)) {
+        if constexpr (!MULTI) {
+            if (hp) {
+                BS_LAUNCH(s, K_PCG_MATVEC, "pcg_matvec", (pcg_matvec<K, false, true, PACKED, true>),
+                          grid, block, 0, s, a, src);
+                src ^= 1;
+            }
+        }
+        if (hp) {
+        } else if (exact_iteration<K>(it)) {
             BS_LAUNCH(s, K_PCG_MATVEC, "pcg_matvec", (pcg_matvec<K, MULTI, true, PACKED>), grid, block, 0,
                       s, a, src);
             src ^= 1;
@@ -1399,7 +1412,13 @@ static bs_status run_pcg_k(const PcgArgs& a, int n, int G, int max_cp, bool sep,
         if (sep)
             BS_LAUNCH(s, K_PCG_REDUCE, "pcg_reduce", pcg_reduce<MULTI>, dim3(max_cp, n), block, 0,
                       s, a, 1, 1);
-        BS_LAUNCH(s, K_PCG_UPDATE, "pcg_update", (pcg_update<K, MULTI>), grid, block, 0, s, a);
+        if constexpr (!MULTI) {
+            if (hp)
+                BS_LAUNCH(s, K_PCG_UPDATE, "pcg_update", (pcg_update<K, false, true>), grid, block, 0,
+                          s, a);
+        }
+        if (!hp)
+            BS_LAUNCH(s, K_PCG_UPDATE, "pcg_update", (pcg_update<K, MULTI>), grid, block, 0, s, a);
         if constexpr (!MULTI) {
             if (hp) {
                 const bs_status st = prec_apply<K>(a, *hp, G, s);
