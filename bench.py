@@ -366,8 +366,8 @@ KERNELS = ["level_count", "level_scan", "level_write", "neighbour_table", "bist_
 
 
 def kernel_times(step, steps):
-    """Per-kernel summed launch durations and launch counts per step (HIP
-    events recorded on the launch stream around every launch)."""
+    """Per-kernel summed launch durations and launch counts per step (the
+    start and end events every launch carries, on its own stream)."""
     from paper_1511_03296_amd import _lib as L
     import ctypes as ct
     L.check(L.lib.bs_timing_reset(), "timing_reset")
@@ -644,8 +644,8 @@ def main() -> int:
         print(f"bench: plain single-image path {sec_plain * 1e3:.3f} ms/step",
               file=sys.stderr, flush=True)
 
-    # kernel durations: the same launches, each bracketed by events (the
-    # graph form runs its plan eagerly: the graph's launch sequence)
+    # kernel durations: the same launches, each with its start and end events
+    # (the graph form runs its plan eagerly: the graph's launch sequence)
     if graph_form is not None:
         sec_inst, kt = kernel_times(lambda: graph_form.eager(True), args.steps)
     else:

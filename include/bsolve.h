@@ -591,8 +591,9 @@ bs_status bs_solve_ws_view(const bs_grid* grid, int32_t C, void* ws, size_t ws_b
                            const float** minv);
 
 /* Kernel timing for benchmarks.  While enabled, every kernel launch of the
- * library is bracketed by two hipEvents recorded on its stream (not
- * graph-capturable).  bs_timing_read waits for the recorded events and
+ * library carries two hipEvents of its own, taken at the kernel's start and
+ * end (hipExtLaunchKernelGGL; not graph-capturable).  bs_timing_read waits for
+ * the events and
  * returns the summed elapsed milliseconds and launch count of one kernel:
  * "level_count", "level_scan", "level_write", "neighbour_table", "bist_step",
  * "bist_other", "splat", "init", "pcg_start", "pcg_matvec", "pcg_update",

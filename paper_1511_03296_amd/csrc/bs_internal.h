@@ -3,6 +3,7 @@
 // device-side reduction helpers shared by the kernels.
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -44,18 +45,25 @@ enum KernelId : int {
     K_GRAD_SCATTER, K_DT_ROWS, K_DT_COLS, K_DT_OTHER,
     K_COUNT
 };
-void timing_begin(hipStream_t s, int id);
 bool timing_enabled();
-void timing_end(hipStream_t s, int id);
+// The start and stop events of one timed launch of kernel `id` (both null
+// while timing is disabled).  The launch takes them itself
+// (hipExtLaunchKernelGGL), so they bracket the kernel's execution alone,
+// without the cost of separate event records on the stream.
+void timing_pair(int id, hipEvent_t* start, hipEvent_t* stop);
 
-// Enqueues `launch` on `stream`, bracketed by timing events when enabled, and
-// checks it.
-#define BS_LAUNCH(stream, id, name, ...)                    \
-    do {                                                    \
-        ::bs::timing_begin(stream, id);                     \
-        hipLaunchKernelGGL(__VA_ARGS__);                    \
-        ::bs::timing_end(stream, id);                       \
-        BS_CHECK_LAUNCH(name);                              \
+// Enqueues `kernel` on `lstream` (the launch's stream, the same as `stream`),
+// timed when timing is enabled, and checks it.
+#define BS_LAUNCH(stream, id, name, kernel, grid, block, shmem, lstream, ...)                \
+    do {                                                                                    \
+        hipEvent_t e0_ = nullptr, e1_ = nullptr;                                            \
+        ::bs::timing_pair(id, &e0_, &e1_);                                                  \
+        if (e0_)                                                                            \
+            hipExtLaunchKernelGGL(kernel, grid, block, shmem, lstream, e0_, e1_, 0,         \
+                                  __VA_ARGS__);                                             \
+        else                                                                                \
+            hipLaunchKernelGGL(kernel, grid, block, shmem, lstream, __VA_ARGS__);           \
+        BS_CHECK_LAUNCH(name);                                                              \
     } while (0)
 
 // ---------------------------------------------------------------------------

@@ -1,9 +1,8 @@
 // Optional kernel timing for benchmarks: when enabled, every launch of the
-// library's kernels is bracketed by a pair of hipEvents recorded on the launch
-// stream, and bs_timing_read sums the elapsed times per kernel.  Disabled by
-// default; when disabled the hooks cost one relaxed atomic load.  The event
-// that opens a launch is kept per host thread, so the batch engine's worker
-// threads may time their streams concurrently.
+// library's kernels carries a start and a stop hipEvent of its own
+// (hipExtLaunchKernelGGL records them at the kernel's start and end), and
+// bs_timing_read sums the elapsed times per kernel.  Disabled by default; when
+// disabled the hook costs one relaxed atomic load.
 #include "bs_internal.h"
 
 #include <atomic>
@@ -57,28 +56,24 @@ bs_status drain(Timing& t) {
     t.pending.clear();
     return BS_OK;
 }
-thread_local hipEvent_t t_open[K_COUNT] = {};
 }  // namespace
 
 bool timing_enabled() { return T().on.load(std::memory_order_relaxed); }
 
-void timing_begin(hipStream_t s, int id) {
+void timing_pair(int id, hipEvent_t* start, hipEvent_t* stop) {
+    *start = *stop = nullptr;
     Timing& t = T();
     if (!t.on.load(std::memory_order_relaxed)) return;
     std::lock_guard<std::mutex> g(t.mu);
-    hipEvent_t e = take_event(t);
-    if (e && hipEventRecord(e, s) == hipSuccess) t_open[id] = e;
-}
-
-void timing_end(hipStream_t s, int id) {
-    Timing& t = T();
-    if (!t.on.load(std::memory_order_relaxed)) return;
-    std::lock_guard<std::mutex> g(t.mu);
-    hipEvent_t start = t_open[id];
-    t_open[id] = nullptr;
-    if (!start) return;
-    hipEvent_t e = take_event(t);
-    if (e && hipEventRecord(e, s) == hipSuccess) t.pending.push_back({id, start, e});
+    hipEvent_t a = take_event(t), b = take_event(t);
+    if (!a || !b) {
+        if (a) t.pool.push_back(a);
+        if (b) t.pool.push_back(b);
+        return;
+    }
+    t.pending.push_back({id, a, b});
+    *start = a;
+    *stop = b;
 }
 
 }  // namespace bs
