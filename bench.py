@@ -592,8 +592,9 @@ def main() -> int:
             def trial():
                 graph_form.build()
                 return lambda: graph_form.eager(True)
-            tuned = autotune.tune_plan(trial, [p.C for p in problems])
-            print(f"bench: autotuned tiles per block {tuned}", file=sys.stderr, flush=True)
+            tuned = autotune.tune_plan(trial, [p.C for p in problems], lanes=True)
+            print(f"bench: autotuned lane widths and tiles per block {tuned}", file=sys.stderr,
+                  flush=True)
         graph_form.build()
         graph_form.capture()
         for _ in range(max(1, args.warmup)):
@@ -716,7 +717,10 @@ def main() -> int:
                    **({"graph": {"iteration_caps": list(caps),
                                  "all_channels_stopped_on_tolerance": converged}}
                       if caps else {}),
-                   **({"tiles_per_block": {str(K): v["tiles"] for K, v in tuned.items()}}
+                   **({"lane_widths": {str(C): v["lane"]
+                                       for C, v in tuned.get("lanes", {}).items()},
+                       "tiles_per_block": {str(K): v["tiles"] for K, v in tuned.items()
+                                           if K != "lanes"}}
                       if tuned else {}),
                    "precond": args.precond,
                    "parallelism": "single-gpu",

@@ -190,3 +190,11 @@ def test_domain_transform_arguments_are_rejected_before_launch():
     assert st == L.BS_EINVAL and b"sigma_dt" in L.lib.bs_last_error()
     st = L.lib.bs_dt_confidence(dev, 48, 64, dev, ct.byref(good), 2.0, -1, dev, ws, n, None)
     assert st == L.BS_EINVAL
+
+
+def test_autotuner_default_lane_rule_matches_the_library():
+    from paper_1511_03296_amd import _lib as L, autotune
+    for C in range(1, 65):
+        assert L.lib.bs_set_lane_width(C, 0) == L.BS_OK
+        assert autotune.lane_candidates_default(C) == L.lib.bs_lane_width(C), C
+        assert autotune.lane_candidates_default(C) in autotune.lane_candidates(C)

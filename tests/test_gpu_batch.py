@@ -197,3 +197,45 @@ def test_autotuned_tiles_keep_the_results():
         assert all(autotune.current()[K] == v["tiles"] for K, v in tuned.items())
     finally:
         autotune.reset()
+
+
+def test_autotuned_lane_widths_keep_the_results():
+    """Every lane width the autotuner tries lays the channels out anew (with or
+    without padding): a batch plan made after tuning gives the default
+    layout's results to the solver's tolerance, and the choice is one of the
+    candidates."""
+    from paper_1511_03296_amd import BatchPlan, SolveOptions, autotune
+    batch = [WL.segmentation(seed=s, H=96, W=128, regions=20, C=C, rel_tol=1e-6)
+             for s, C in enumerate((21, 2, 1))]
+    say("autotune lanes: 3 images, C = 21, 2, 1")
+    opts = SolveOptions(128.0, 400, 1e-6, check_every=0)
+
+    def make():
+        return BatchPlan([to_dev(p.ref) for p in batch], [to_dev(p.target) for p in batch],
+                         [to_dev(p.conf) for p in batch],
+                         [(p.sigma_xy, p.sigma_l, p.sigma_uv) for p in batch], opts)
+
+    try:
+        autotune.reset()
+        base = make()
+        base.forward()
+        torch.cuda.synchronize()
+        ref = [x.clone() for x in base.xs]
+        base.close()
+
+        def trial():
+            plan = make()
+            return plan.forward
+        tuned = autotune.tune_plan(trial, [p.C for p in batch], candidates=(8, 16), repeats=1,
+                                   lanes=True)
+        assert set(tuned["lanes"]) == {21, 2}
+        for C, v in tuned["lanes"].items():
+            assert v["lane"] in autotune.lane_candidates(C)
+        plan = make()
+        plan.forward()
+        torch.cuda.synchronize()
+        for a, b in zip(ref, plan.xs):
+            assert rel_l2(b.cpu().numpy(), a.cpu().numpy()) <= 1e-4
+        plan.close()
+    finally:
+        autotune.reset()
