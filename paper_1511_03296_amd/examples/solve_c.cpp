@@ -1,13 +1,15 @@
 // The C ABI used directly from a host program, without the Python binding:
-// build the grid, bistochastize, solve and slice one image (the calls of
-// include/bsolve.h), with device memory from the HIP runtime.
+// build the grid, bistochastize, solve and slice one image, then smooth the
+// output with the domain transform (the calls of include/bsolve.h), with
+// device memory from the HIP runtime.
 //
 //   solve_c H W C sigma_xy sigma_l sigma_uv lambda max_iters rel_tol in.bin out.bin
 //
 // in.bin holds float32 reference [3][H][W], target [C][H][W] and confidence
-// [H][W]; out.bin receives x [C][H][W] as float32 followed by the iteration
-// count of every channel (int32 [C]).  Exits 1 with the library's error text
-// on any failure.
+// [H][W]; out.bin receives x [C][H][W] as float32, the iteration count of
+// every channel (int32 [C]) and the post-processed output [C][H][W] (domain
+// transform with sigma'_xy = 4, sigma'_rgb = 8, 3 iterations).  Exits 1 with
+// the library's error text on any failure.
 #include <hip/hip_runtime.h>
 
 #include <cstdio>
@@ -85,11 +87,22 @@ int main(int argc, char** argv) {
                                 BS_PRECOND_JACOBI, 2.0f, 5.0f};
     check(bs_solve(&grid, target, conf, C, &sp, y, ws, ws_bytes, stats, nullptr), "bs_solve");
     check(bs_slice(&grid, y, C, x, nullptr), "bs_slice");
+
+    // domain-transform post-process (Section 4)
+    const size_t dws_bytes = bs_dt_workspace_bytes(H, W);
+    if (dws_bytes == 0) check(BS_EINVAL, "bs_dt_workspace_bytes");
+    void* dws = device(dws_bytes);
+    float* xd = (float*)device(P * C * sizeof(float));
+    const bs_dt_params dp = {4.0f, 8.0f, 3};
+    check(bs_domain_transform(ref, H, W, x, C, &dp, xd, dws, dws_bytes, nullptr),
+          "bs_domain_transform");
     check_hip(hipDeviceSynchronize(), "hipDeviceSynchronize");
 
-    std::vector<float> xo(P * C);
+    std::vector<float> xo(P * C), xdo(P * C);
     std::vector<bs_chan_stats> so(C);
     check_hip(hipMemcpy(xo.data(), x, xo.size() * sizeof(float), hipMemcpyDeviceToHost), "copy");
+    check_hip(hipMemcpy(xdo.data(), xd, xdo.size() * sizeof(float), hipMemcpyDeviceToHost),
+              "copy");
     check_hip(hipMemcpy(so.data(), stats, so.size() * sizeof(bs_chan_stats),
                         hipMemcpyDeviceToHost), "copy");
     std::vector<int32_t> iters(C);
@@ -101,9 +114,10 @@ int main(int argc, char** argv) {
     }
     std::fwrite(xo.data(), sizeof(float), xo.size(), o);
     std::fwrite(iters.data(), sizeof(int32_t), iters.size(), o);
+    std::fwrite(xdo.data(), sizeof(float), xdo.size(), o);
     std::fclose(o);
     for (void* p : {(void*)ref, (void*)target, (void*)conf, gws, ws, (void*)y, (void*)x,
-                    (void*)stats})
+                    (void*)stats, dws, (void*)xd})
         check_hip(hipFree(p), "hipFree");
     return 0;
 }

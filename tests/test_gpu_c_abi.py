@@ -1,7 +1,8 @@
 """The C ABI used directly from a host program (paper_1511_03296_amd/
-examples/solve_c.cpp, built by build()): grid, bistochastization, solve and
-slice through include/bsolve.h alone.  Its output must match the FP64 oracle
-and, bit for bit, the Python binding, which makes the same calls."""
+examples/solve_c.cpp, built by build()): grid, bistochastization, solve,
+slice and the domain-transform post-process through include/bsolve.h alone.
+Its output must match the FP64 oracle and, bit for bit, the Python binding,
+which makes the same calls."""
 import os
 import subprocess
 
@@ -11,6 +12,7 @@ import torch
 
 import workloads as WL
 from oracle import bilateral as O
+from oracle import domain_transform as DT
 from tests.gpu_helpers import gpu_grid, params, rel_l2, say, to_dev
 
 pytestmark = pytest.mark.gpu
@@ -37,7 +39,8 @@ def test_c_program_matches_oracle_and_binding(tmp_path):
     raw = np.fromfile(out, dtype=np.uint8)
     n = p.C * p.H * p.W
     x = raw[: 4 * n].view(np.float32).reshape(p.C, p.H, p.W)
-    iters = raw[4 * n:].view(np.int32)
+    iters = raw[4 * n: 4 * n + 4 * p.C].view(np.int32)
+    xd = raw[4 * n + 4 * p.C:].view(np.float32).reshape(p.C, p.H, p.W)
     sol = O.solve(p.ref, p.target, p.conf, prm)
     assert rel_l2(x, sol.x) <= 1e-4
     assert all(abs(int(i) - r.iters) <= 3 for i, r in zip(iters, sol.runs))
@@ -47,3 +50,11 @@ def test_c_program_matches_oracle_and_binding(tmp_path):
     xb = G.slice(y, p.C)
     torch.cuda.synchronize()
     assert np.array_equal(xb.cpu().numpy(), x)
+    # the post-process of the program's own x: the float64 filter, and the
+    # binding's call bit for bit
+    want = DT.domain_transform(p.ref, x, 4.0, 8.0, 3)
+    assert rel_l2(xd, want) <= 1e-5
+    from paper_1511_03296_amd import domain_transform
+    xdb = domain_transform(to_dev(p.ref), xb, 4.0, 8.0, 3)
+    torch.cuda.synchronize()
+    assert np.array_equal(xdb.cpu().numpy(), xd)

@@ -127,3 +127,52 @@ def test_confidence_small_images():
         zz = z.astype(np.float64)
         bound = 1e-5 * float(np.max((zz - zz.mean()) ** 2)) / 8.0 + 1e-6
         assert float(np.max(np.abs(c.cpu().numpy() - want))) <= bound
+
+
+def test_domain_transform_replays_from_a_graph():
+    """Both calls only enqueue kernels (no host synchronisation, no memset):
+    captured into one graph and replayed three times, with eager work and
+    synchronisations between the replays, they give the eager results bit for
+    bit, and inputs rewritten in place are picked up."""
+    from paper_1511_03296_amd import _lib as L, domain_transform, dt_confidence
+    p = WL.stereo_refine(seed=2, H=120, W=200, regions=30)
+    say("domain transform: graph capture and replay")
+    ref, t = to_dev(p.ref), to_dev(p.target)
+    z = t[0].clone()
+    ws = torch.empty(L.lib.bs_dt_workspace_bytes(p.H, p.W), dtype=torch.uint8, device="cuda")
+    out = torch.empty_like(t)
+    conf = torch.empty_like(z)
+
+    def run():
+        conf.copy_(dt_confidence(ref, z, 16.0, 32.0, 2.0, zero_cols=7, ws=ws))
+        domain_transform(ref, t, 4.0, 8.0, out=out, ws=ws)
+
+    run()
+    torch.cuda.synchronize()
+    want_out, want_conf = out.clone(), conf.clone()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        run()   # warm-up on the capture stream
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        run()
+    torch.cuda.synchronize()
+    for r in range(3):
+        out.fill_(float("nan"))
+        conf.fill_(float("nan"))
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(out, want_out) and torch.equal(conf, want_conf), r
+        domain_transform(ref, t, 8.0, 8.0)   # eager work between replays
+        torch.cuda.synchronize()
+    # a new disparity written in place: the replay filters it
+    t.mul_(0.5)
+    z.mul_(0.5)
+    g.replay()
+    torch.cuda.synchronize()
+    _check(out.cpu().numpy(), DT.domain_transform(p.ref, p.target * np.float32(0.5), 4.0, 8.0),
+           "replay after new input")
