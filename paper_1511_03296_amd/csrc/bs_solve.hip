@@ -317,6 +317,7 @@ __device__ inline ChanState load_state(const ChanState& r) {
     ChanState s;
     s.rho = r.rho;
     s.alpha = r.alpha;
+    s.alpha_prev = r.alpha_prev;
     s.beta = r.beta;
     s.bnorm = r.bnorm;
     s.res = r.res;
@@ -330,6 +331,7 @@ __device__ inline ChanState load_state(const ChanState& r) {
 __device__ inline void store_state(ChanState& d, const ChanState& s) {
     d.rho = s.rho;
     d.alpha = s.alpha;
+    d.alpha_prev = s.alpha_prev;
     d.beta = s.beta;
     d.bnorm = s.bnorm;
     d.res = s.res;
@@ -343,6 +345,7 @@ __device__ inline ChanState load_state(gp<const ChanRec> p) {
     ChanState s;
     s.rho = p->s.rho;
     s.alpha = p->s.alpha;
+    s.alpha_prev = p->s.alpha_prev;
     s.beta = p->s.beta;
     s.bnorm = p->s.bnorm;
     s.res = p->s.res;
@@ -356,6 +359,7 @@ __device__ inline ChanState load_state(gp<const ChanRec> p) {
 __device__ inline void store_state(gp<ChanRec> p, const ChanState& s) {
     p->s.rho = s.rho;
     p->s.alpha = s.alpha;
+    p->s.alpha_prev = s.alpha_prev;
     p->s.beta = s.beta;
     p->s.bnorm = s.bnorm;
     p->s.res = s.res;
@@ -367,7 +371,7 @@ __device__ inline void store_state(gp<ChanRec> p, const ChanState& s) {
 
 __device__ inline ChanState zero_state() {
     ChanState z;
-    z.rho = z.alpha = z.beta = z.bnorm = z.res = 0.0;
+    z.rho = z.alpha = z.beta = z.bnorm = z.res = z.alpha_prev = 0.0;
     z.active = z.iters = z.reason = z.phase = 0;
     return z;
 }
@@ -663,6 +667,15 @@ __global__ void __launch_bounds__(kRedBlock) pcg_start(PcgArgs a) {
     lane_partials<3, K>(acc, ln, Cp, nb, partial_slot(jb, nb), I.part0);
 }
 
+// Whether lanes of width K take the steps y += alpha d every other iteration
+// (lazy) or every iteration.  With one channel per lane y is 4 of some 60
+// bytes a vertex moves per iteration and the deferred step's registers cost
+// the exact form a wave per SIMD (depth: 66.0 against 65.0 Mpix/s every
+// iteration); with 2 and more channels it saves a y pass every other
+// iteration (seg16 45.6 -> 47.5, mixed64 150.3 -> 155.3 Mpix/s).
+template <int K>
+constexpr bool lazy_y() { return K >= 2; }
+
 // Operands of one lane of pcg_matvec.  Loading them does not depend on the
 // iteration's scalars, so the first tile's loads are issued before the
 // prologue and overlap its reduction.  The exact form gathers the
@@ -677,6 +690,8 @@ struct MatOps {
     Vec<K> d[EXACT ? 10 : 1];
     float2 nm[EXACT ? 10 : 1];
     Vec<K> rv, dv, qv, yv;
+    Vec<K> d2;                     // the other d buffer's old value (a deferred step's d)
+    bool with_y;                   // yv and d2 loaded
     float2 nmv;
     float scv;
 };
@@ -684,7 +699,8 @@ struct MatOps {
 // The gathers and per-vertex operands of vertex v (phase 2).
 template <int K, bool EXACT>
 __device__ inline void load_ops(MatOps<K, EXACT>& o, int v, const int (&nb)[10], const Lanes& ln,
-                                const ImgView& I, gp<const float> din) {
+                                const ImgView& I, gp<const float> din, gp<const float> dold,
+                                bool with_y) {
     o.v = v;
     o.have = 0;
     const int Cp = I.Cp;
@@ -706,7 +722,13 @@ __device__ inline void load_ops(MatOps<K, EXACT>& o, int v, const int (&nb)[10],
     const uint32_t e = lane_elem(v, Cp, ln.g, K);
     o.rv = ldv<K>(I.w, e);
     o.dv = ldv<K>(din, e);
-    o.yv = ldv<K>(I.y, e);
+    // (lane widths that take every step load y unconditionally: a branch
+    // here would make the compiler wait for the loads in flight)
+    o.with_y = lazy_y<K>() ? with_y : true;
+    if (o.with_y) {
+        o.yv = ldv<K>(I.y, e);
+        if constexpr (lazy_y<K>()) o.d2 = ldv<K>(dold, e);
+    }
     o.nmv = *elem(I.nfm, (uint32_t)v);
     if constexpr (EXACT) o.scv = I.sc[v];
     else o.qv = ldv<K>(I.q, e);
@@ -715,7 +737,8 @@ __device__ inline void load_ops(MatOps<K, EXACT>& o, int v, const int (&nb)[10],
 // load_ops from the packed words of load_nbr_words.
 template <int K, bool EXACT>
 __device__ inline void load_ops_late(MatOps<K, EXACT>& o, int v, const int (&raw)[10],
-                                     const Lanes& ln, const ImgView& I, gp<const float> din) {
+                                     const Lanes& ln, const ImgView& I, gp<const float> din,
+                                     gp<const float> dold, bool with_y) {
     if constexpr (EXACT) {
         int nb[10];
 #pragma unroll
@@ -723,7 +746,7 @@ __device__ inline void load_ops_late(MatOps<K, EXACT>& o, int v, const int (&raw
             const uint32_t wd = (uint32_t)raw[j >> 1];
             nb[j] = unpack_offset(v, (j & 1) ? wd >> 16 : wd & 0xffffu);
         }
-        load_ops<K, true>(o, v, nb, ln, I, din);
+        load_ops<K, true>(o, v, nb, ln, I, din, dold, with_y);
         return;
     } else {
     o.v = v;
@@ -741,7 +764,11 @@ __device__ inline void load_ops_late(MatOps<K, EXACT>& o, int v, const int (&raw
     const uint32_t e = lane_elem(v, Cp, ln.g, K);
     o.rv = ldv<K>(I.w, e);
     o.dv = ldv<K>(din, e);
-    o.yv = ldv<K>(I.y, e);
+    o.with_y = lazy_y<K>() ? with_y : true;
+    if (o.with_y) {
+        o.yv = ldv<K>(I.y, e);
+        if constexpr (lazy_y<K>()) o.d2 = ldv<K>(dold, e);
+    }
     o.nmv = *elem(I.nfm, (uint32_t)v);
     o.qv = ldv<K>(I.q, e);
     }
@@ -753,35 +780,41 @@ __device__ inline float pcg_dir(float z, float d_old, float beta, bool first) {
 }
 
 // Prologue: finish the previous step (stopping rule, beta) from the slot-0
-// partials.  Then y += alpha d_old, the previous iteration's step (deferred
-// from the update to here, where d_old is read anyway; pcg_flush applies
-// the last one), and, with z = M^-1 r = w / n, d = z + beta d and partials
-// of d^T q, where q = A d is either
+// partials.  Then the pending steps y += alpha d: the previous update's step
+// on d_old (read here anyway) is taken on even iterations (`defer` 0) and on
+// odd ones deferred to the next matvec, which then also takes it on the
+// direction still in the other d buffer (read before d_new overwrites it), so
+// y is read and written every other iteration; a channel that stops takes
+// its steps at once, and pcg_flush takes the last ones.  With
+// z = M^-1 r = w / n, d = z + beta d and partials of d^T q, where q = A d is
+// either
 //   EXACT false:  A z + beta q, its recurrence.  diag(A) z = r, so
 //                   (A z)_v = r_v - lam n_v sum_u w_u,  r_v = w_v / s_v,
 //                 and only the stored residual w is gathered from the
-//                 neighbours; d and q are updated in place (d[src]).  A row
-//                 with diag(A) = 0 is zero: (A z)_v = 0.
+//                 neighbours.  A row with diag(A) = 0 is zero: (A z)_v = 0.
 //   EXACT true:   A d itself, in Laplacian form, with the neighbours' new d
-//                 recomputed from their gathered w, n and old d (read from
-//                 d[src], written to d[src ^ 1]).  It resets the rounding
-//                 that the recurrence accumulates.
+//                 recomputed from their gathered w, n and old d.  It resets
+//                 the rounding that the recurrence accumulates.
+// Both read d_old from d[src] and write d_new to d[src ^ 1] (the recurrence
+// form of lane widths without deferred steps updates d[src] in place).
 // On a channel's first iteration d = z and q = A z.
 template <int K, bool MULTI, bool EXACT, bool PACKED, bool ZMODE = false>
-__global__ void __launch_bounds__(kRedBlock) pcg_matvec(PcgArgs a, int src) {
+__global__ void __launch_bounds__(kRedBlock) pcg_matvec(PcgArgs a, int src, int defer) {
     static_assert(!ZMODE || (EXACT && !MULTI), "z is stored for single-image exact matvecs");
     __shared__ ChanState S[BS_MAX_CHANNELS];
     __shared__ double fin[3 * BS_MAX_CHANNELS];
-    __shared__ float pend[BS_MAX_CHANNELS];
+    __shared__ float pend[BS_MAX_CHANNELS], pend2[BS_MAX_CHANNELS];
     __shared__ int n_active, n_pend;
     int jb;
     if (idle_block<MULTI>(a)) return;
     const ImgView I = view_of(block_image<MULTI>(a, jb));
     if constexpr (MULTI) {
-        if (*I.active == 0) return;   // stopped image (its last step applied)
+        if (*I.active == 0) return;   // stopped image (its last steps applied)
     }
-    const int dst = EXACT ? (src ^ 1) : src;
+    // the new d goes to the other buffer, except in the recurrence form of
+    // lane widths that take every step at once, which updates d in place
     gp<const float> din = src ? I.d1 : I.d0;
+    const int dst = (EXACT || lazy_y<K>()) ? (src ^ 1) : src;
     gp<float> dout = dst ? I.d1 : I.d0;
     const int t = threadIdx.x;
     const int V = I.counts[CNT_V];
@@ -800,24 +833,40 @@ __global__ void __launch_bounds__(kRedBlock) pcg_matvec(PcgArgs a, int src) {
     int v = (int)(tl.first * ln.vpb) + ln.vl;
     bool have = ln.ok && tl.first < tl.end && v < V;
     constexpr bool kLate = late_decode<K, EXACT, PACKED, MULTI>();
+    // y and the other buffer's d are read on the iterations that take steps
+    // (the host passes defer = 0 to lane widths that take them every time)
+    const bool y_guess = defer == 0;
     if (have) {
         if constexpr (kLate) {
             load_nbr_words(nbn, v, I);
-            load_ops_late<K, EXACT>(o, v, nbn, ln, I, din);
+            load_ops_late<K, EXACT>(o, v, nbn, ln, I, din, dout, y_guess);
         } else {
             load_nbr<PACKED>(nbn, v, I);
-            load_ops<K, EXACT>(o, v, nbn, ln, I, din);
+            load_ops<K, EXACT>(o, v, nbn, ln, I, din, dout, y_guess);
         }
     }
     ps.sum(I.part0, fin);
     if (t == 0) n_active = n_pend = 0;
     __syncthreads();
     if (t < Cp) {
-        // a channel the update left active has its step alpha d_old pending
+        // a channel the update left active has its step alpha d_old pending;
+        // a step deferred by the previous matvec waits on the other buffer
         const bool p = st0.phase != 0 && st0.active;
-        pend[t] = p ? (float)st0.alpha : 0.0f;
-        if (p) atomicAdd(&n_pend, 1);
+        float cur = p ? (float)st0.alpha : 0.0f;
+        float prev = 0.0f;
         st0 = advance_state(st0, fin[t], fin[Cp + t], fin[2 * Cp + t], a.max_iters, a.tol);
+        if constexpr (lazy_y<K>()) {
+            prev = (float)st0.alpha_prev;
+            if (defer && st0.active) {
+                st0.alpha_prev = cur;   // taken by the next matvec
+                cur = 0.0f;
+            } else {
+                st0.alpha_prev = 0.0;
+            }
+            pend2[t] = prev;
+        }
+        pend[t] = cur;
+        if (cur != 0.0f || prev != 0.0f) atomicAdd(&n_pend, 1);
         store_state(S[t], st0);
         if (st0.active) atomicAdd(&n_active, 1);
         store_state(I.cs1 + (int64_t)jb * Cp + t, st0);
@@ -828,22 +877,25 @@ __global__ void __launch_bounds__(kRedBlock) pcg_matvec(PcgArgs a, int src) {
     // next update stores the true count).
     if (jb == 0 && t == 0) *I.active = n_active > 0 ? n_active : (n_pend > 0 ? -1 : 0);
     if (n_active == 0 && n_pend == 0) return;
-    float beta[K], alpha[K];
-    bool first[K], act[K], pnd[K];
-    bool any = false;
+    float beta[K], alpha[K], alpha2[K];
+    bool first[K], act[K];
+    bool any = false, lane_y = false;
 #pragma unroll
     for (int k = 0; k < K; ++k) {
         const int c = ln.ok ? ln.g * K + k : 0;
         const ChanState& s = S[c];
         act[k] = ln.ok && s.active;
-        alpha[k] = pend[c];
-        pnd[k] = ln.ok && alpha[k] != 0.0f;
+        alpha[k] = ln.ok ? pend[c] : 0.0f;
+        alpha2[k] = (lazy_y<K>() && ln.ok) ? pend2[c] : 0.0f;
+        lane_y = lane_y || alpha[k] != 0.0f || alpha2[k] != 0.0f;
         beta[k] = (float)s.beta;
         // stopped channels restart their (unused) recurrences, which keeps
         // them bounded while the other channels iterate
         first[k] = s.iters == 0 || !act[k];
-        any = any || act[k] || pnd[k];
+        any = any || act[k];
     }
+    any = any || lane_y;
+    const bool need_y = n_pend > 0;
     const float lam = I.lam;
     double acc[1][K];
 #pragma unroll
@@ -899,12 +951,25 @@ __global__ void __launch_bounds__(kRedBlock) pcg_matvec(PcgArgs a, int src) {
                     qv.v[k] = first[k] ? az : fmaf(beta[k], o.qv.v[k], az);
                 }
             }
-            Vec<K> yv;
-#pragma unroll
-            for (int k = 0; k < K; ++k)
-                yv.v[k] = pnd[k] ? fmaf(alpha[k], o.dv.v[k], o.yv.v[k]) : o.yv.v[k];
             const uint32_t e = lane_elem(o.v, Cp, ln.g, K);
-            stv<K>(I.y, e, yv);
+            if (!lazy_y<K>() || lane_y) {
+                if (!o.with_y) {   // a channel stops on an iteration that defers
+                    o.yv = ldv<K>(I.y, e);
+                    if constexpr (lazy_y<K>()) o.d2 = ldv<K>((gp<const float>)dout, e);
+                }
+                Vec<K> yv;
+                // (a buffer without a step may hold anything, even non-finite
+                // values: only the steps taken read it)
+#pragma unroll
+                for (int k = 0; k < K; ++k) {
+                    float yk = o.yv.v[k];
+                    if constexpr (lazy_y<K>())
+                        if (alpha2[k] != 0.0f) yk = fmaf(alpha2[k], o.d2.v[k], yk);
+                    if (alpha[k] != 0.0f) yk = fmaf(alpha[k], o.dv.v[k], yk);
+                    yv.v[k] = yk;
+                }
+                stv<K>(I.y, e, yv);
+            }
             stv<K>(dout, e, dv);
             stv<K>(I.q, e, qv);
 #pragma unroll
@@ -912,8 +977,8 @@ __global__ void __launch_bounds__(kRedBlock) pcg_matvec(PcgArgs a, int src) {
                 if (act[k]) acc[0][k] += (double)dv.v[k] * (double)qv.v[k];
         }
         if (hn) {
-            if constexpr (kLate) load_ops_late<K, EXACT>(o, vn, nbn, ln, I, din);
-            else load_ops<K, EXACT>(o, vn, nbn, ln, I, din);
+            if constexpr (kLate) load_ops_late<K, EXACT>(o, vn, nbn, ln, I, din, dout, need_y);
+            else load_ops<K, EXACT>(o, vn, nbn, ln, I, din, dout, need_y);
         }
         have = hn;
     }
@@ -930,7 +995,7 @@ template <int K, bool MULTI, bool ZMODE = false>
 __global__ void __launch_bounds__(kRedBlock) pcg_update(PcgArgs a) {
     __shared__ ChanState S[BS_MAX_CHANNELS];
     __shared__ double fin[BS_MAX_CHANNELS];
-    __shared__ int n_active;
+    __shared__ int n_active, n_defer;
     int jb;
     if (idle_block<MULTI>(a)) return;
     const ImgView I = view_of(block_image<MULTI>(a, jb));
@@ -959,7 +1024,7 @@ __global__ void __launch_bounds__(kRedBlock) pcg_update(PcgArgs a) {
         nmv = *elem(I.nfm, (uint32_t)v);
     }
     ps.sum(I.part1, fin);
-    if (t == 0) n_active = 0;
+    if (t == 0) n_active = n_defer = 0;
     __syncthreads();
     if (t < Cp) {
         if (st0.active) {
@@ -973,10 +1038,13 @@ __global__ void __launch_bounds__(kRedBlock) pcg_update(PcgArgs a) {
         }
         store_state(S[t], st0);
         if (st0.active) atomicAdd(&n_active, 1);
+        else if (st0.alpha_prev != 0.0) atomicAdd(&n_defer, 1);
         store_state(I.cs0 + (int64_t)jb * Cp + t, st0);
     }
     __syncthreads();
-    if (jb == 0 && t == 0) *I.active = n_active;
+    // a channel stopped here with a deferred step keeps the image running
+    // (-1) until the next matvec (or pcg_flush) takes the step
+    if (jb == 0 && t == 0) *I.active = n_active > 0 ? n_active : (n_defer > 0 ? -1 : 0);
     if (n_active == 0) return;
     float alpha[K];
     bool act[K];
@@ -1085,12 +1153,13 @@ __global__ void __launch_bounds__(kRedBlock) pcg_prec_final(PcgArgs a, const flo
 }
 
 // After the last enqueued iteration: applies the step y += alpha d that the
-// last update left pending (d = d[src]) for the channels it left active.  An
-// image whose active count is 0 has none pending: its channels stopped in an
-// update (no step) or in a matvec, which applied the step.
+// last update left pending (d = d[src]) for the channels it left active, and
+// a step the last matvec deferred (on the other buffer).  An image whose
+// active count is 0 has none pending: its channels stopped in an update with
+// no deferred step, or in a matvec, which applied their steps.
 template <int K, bool MULTI>
 __global__ void __launch_bounds__(kRedBlock) pcg_flush(PcgArgs a, int src) {
-    __shared__ float pend[BS_MAX_CHANNELS];
+    __shared__ float pend[BS_MAX_CHANNELS], pend2[BS_MAX_CHANNELS];
     __shared__ int n_pend;
     int jb;
     if (idle_block<MULTI>(a)) return;
@@ -1101,34 +1170,46 @@ __global__ void __launch_bounds__(kRedBlock) pcg_flush(PcgArgs a, int src) {
     const int Cp = I.Cp, nb = I.nb;
     const Lanes ln(Cp, K);
     gp<const float> d = src ? I.d1 : I.d0;
+    gp<const float> d_other = src ? I.d0 : I.d1;
     if (t == 0) n_pend = 0;
     __syncthreads();
     if (t < Cp) {
         const ChanState st = load_state(I.cs0 + (int64_t)jb * Cp + t);
         const bool p = st.phase != 0 && st.active;
         pend[t] = p ? (float)st.alpha : 0.0f;
-        if (p) atomicAdd(&n_pend, 1);
+        pend2[t] = (float)st.alpha_prev;
+        if (p || st.alpha_prev != 0.0) atomicAdd(&n_pend, 1);
     }
     __syncthreads();
     if (n_pend == 0 || !ln.ok) return;
-    float alpha[K];
-    bool any = false;
+    float alpha[K], alpha2[K];
+    bool any = false, any2 = false;
 #pragma unroll
     for (int k = 0; k < K; ++k) {
         alpha[k] = pend[ln.g * K + k];
+        alpha2[k] = pend2[ln.g * K + k];
         any = any || alpha[k] != 0.0f;
+        any2 = any2 || alpha2[k] != 0.0f;
     }
-    if (!any) return;
+    if (!any && !any2) return;
     const XcdTiles tl((V + ln.vpb - 1) / ln.vpb, jb, nb);
     for (int64_t tile = tl.first; tile < tl.end; tile += tl.step) {
         const int v = (int)(tile * ln.vpb) + ln.vl;
         if (v >= V) continue;
         const uint32_t e = lane_elem(v, Cp, ln.g, K);
-        const Vec<K> dv = ldv<K>(d, e);
         Vec<K> yv = ldv<K>(I.y, e);
+        if (any2) {   // the deferred step, on the older direction
+            const Vec<K> dv2 = ldv<K>(d_other, e);
 #pragma unroll
-        for (int k = 0; k < K; ++k)
-            if (alpha[k] != 0.0f) yv.v[k] = fmaf(alpha[k], dv.v[k], yv.v[k]);
+            for (int k = 0; k < K; ++k)
+                if (alpha2[k] != 0.0f) yv.v[k] = fmaf(alpha2[k], dv2.v[k], yv.v[k]);
+        }
+        if (any) {
+            const Vec<K> dv = ldv<K>(d, e);
+#pragma unroll
+            for (int k = 0; k < K; ++k)
+                if (alpha[k] != 0.0f) yv.v[k] = fmaf(alpha[k], dv.v[k], yv.v[k]);
+        }
         stv<K>(I.y, e, yv);
     }
 }
@@ -1393,22 +1474,24 @@ static bs_status run_pcg_k(const PcgArgs& a, int n, int G, int max_cp, bool sep,
     for (int it = 0; it < p.max_iters; ++it) {
         // with the hierarchical preconditioner every matvec is the exact form
         // (the recurrence needs diag(A) z = r)
+        // odd iterations defer their y step to the next matvec
+        const int defer = lazy_y<K>() ? (it & 1) : 0;
         if constexpr (!MULTI) {
-            if (hp) {
+            if (hp)
                 BS_LAUNCH(s, K_PCG_MATVEC, "pcg_matvec", (pcg_matvec<K, false, true, PACKED, true>),
-                          grid, block, 0, s, a, src);
-                src ^= 1;
-            }
+                          grid, block, 0, s, a, src, defer);
         }
         if (hp) {
         } else if (exact_iteration<K>(it)) {
             BS_LAUNCH(s, K_PCG_MATVEC, "pcg_matvec", (pcg_matvec<K, MULTI, true, PACKED>), grid, block, 0,
-                      s, a, src);
-            src ^= 1;
+                      s, a, src, defer);
         } else if constexpr (uses_recurrence<K>()) {
             BS_LAUNCH(s, K_PCG_MATVEC, "pcg_matvec", (pcg_matvec<K, MULTI, false, PACKED>), grid, block, 0,
-                      s, a, src);
+                      s, a, src, defer);
         }
+        // the matvec wrote the new d to the other buffer (in place: the
+        // recurrence form of lane widths without deferred steps)
+        if (lazy_y<K>() || hp || exact_iteration<K>(it)) src ^= 1;
         if (sep)
             BS_LAUNCH(s, K_PCG_REDUCE, "pcg_reduce", pcg_reduce<MULTI>, dim3(max_cp, n), block, 0,
                       s, a, 1, 1);

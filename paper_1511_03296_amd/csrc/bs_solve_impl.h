@@ -10,6 +10,7 @@ namespace bs {
 // PCG state of one channel.
 struct ChanState {
     double rho, alpha, beta, bnorm, res;
+    double alpha_prev;   // a deferred step alpha d on the direction in the other d buffer
     int32_t active, iters, reason, phase;   // phase 0: initial residual not yet reduced
 };
 
