@@ -14,6 +14,8 @@
 // iteration is two kernels, each with one grid-wide reduction:
 //   pcg_matvec:  z = M^-1 r,  d = z + beta d,  q = A d,  d^T q;
 //   pcg_update:  y += alpha d,  r -= alpha q,  r^T r,  r^T M^-1 r.
+// The step y += alpha d is taken by the next matvec, which reads d anyway
+// (for lanes of 2 and more channels every other matvec takes two steps).
 // With the Jacobi preconditioner the residual is stored scaled, as
 // w = n o M^-1 r (s = n M^-1 per vertex): the neighbours' share of A z is
 // n o z = w, so the matvec gathers the stored residual itself, and
