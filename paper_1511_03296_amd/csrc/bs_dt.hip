@@ -19,11 +19,12 @@
 //     samples gives each lane M consecutive samples, whose composed map the
 //     wave scans (six shuffle steps), and every lane then replays its samples
 //     from the value entering its run;
-//   - vertical pass: a block per 32 columns of a channel, its 32 segments of
+//   - vertical pass: a block per 16 columns of a channel, its 64 segments of
 //     rows one thread row each; segment maps meet in LDS, every thread composes
 //     the maps of the segments before its own (after its own, backwards) and
 //     replays its segment.  Lanes run along rows, so every load and store of a
-//     wave covers whole 128-byte row pieces.
+//     wave covers four 64-byte row pieces (with 32 columns per block, whole
+//     128-byte lines, the pass was 20 % slower for lack of blocks).
 // The domain distances are computed once per call: 16-bit sums of absolute
 // code differences (at most 765) to the left and upper neighbour, one 32-bit
 // word per pixel.  A sample reads its own word (the distance of the edge
@@ -36,9 +37,9 @@ namespace bs {
 
 constexpr int kDtRowM = 16;         // samples per lane and chunk of a row (1024 per chunk)
 constexpr int kDtRowBlock = 256;    // 4 waves, one row each
-constexpr int kDtColW = 32;         // columns per block of the vertical pass
-constexpr int kDtSegs = 32;         // row segments per block
-constexpr int kDtColBlock = kDtColW * kDtSegs;
+constexpr int kDtColW = 16;         // columns per block of the vertical pass
+constexpr int kDtColBlock = 1024;   // threads per block of the vertical pass
+constexpr int kDtSegs = kDtColBlock / kDtColW;   // row segments per block
 constexpr int kDtMaxIters = 16;
 
 // Feedback coefficient a^d of an edge whose colour distance is `dist`:
