@@ -19,12 +19,15 @@
 //     samples gives each lane M consecutive samples, whose composed map the
 //     wave scans (six shuffle steps), and every lane then replays its samples
 //     from the value entering its run;
-//   - vertical pass: a block per 16 columns of a channel, its 64 segments of
-//     rows one thread row each; segment maps meet in LDS, every thread composes
-//     the maps of the segments before its own (after its own, backwards) and
-//     replays its segment.  Lanes run along rows, so every load and store of a
-//     wave covers four 64-byte row pieces (with 32 columns per block, whole
-//     128-byte lines, the pass was 20 % slower for lack of blocks).
+//   - vertical pass: a block per 8 columns of a channel, 64 segments of rows
+//     per column, a thread per segment holding its samples in registers (up
+//     to 2048 rows); the segment maps are scanned in LDS by one wave per
+//     column, and every thread replays its segment from the value entering it.
+//     Lanes run along rows, so every load and store of a wave covers eight
+//     32-byte row pieces.  Taller images stream their segments (dt_cols: a
+//     block per 16 columns, maps composed serially from LDS).
+//   - rows are read and written with 16-byte vector accesses when every row
+//     starts 16-byte aligned.
 // The domain distances are computed once per call: 16-bit sums of absolute
 // code differences (at most 765) to the left and upper neighbour, one 32-bit
 // word per pixel.  A sample reads its own word (the distance of the edge
@@ -74,8 +77,57 @@ __device__ inline void dt_after(float& A, float& B, float mA, float mB) {
     A = mA * A;
 }
 
+// M consecutive samples of a row from e0: 16-byte vector accesses when the
+// row is 16-byte aligned and the run lies inside it (VEC), else one by one.
+template <bool VEC, int M>
+__device__ inline void load_run(const float* p, int e0, int W, float (&v)[M]) {
+    if (VEC && e0 + M <= W) {
+#pragma unroll
+        for (int j = 0; j < M; j += 4) {
+            const float4 t = *reinterpret_cast<const float4*>(p + e0 + j);
+            v[j] = t.x;
+            v[j + 1] = t.y;
+            v[j + 2] = t.z;
+            v[j + 3] = t.w;
+        }
+    } else {
+#pragma unroll
+        for (int j = 0; j < M; ++j) v[j] = e0 + j < W ? p[e0 + j] : 0.0f;
+    }
+}
+template <bool VEC, int M>
+__device__ inline void load_run(const uint32_t* p, int e0, int W, uint32_t (&v)[M]) {
+    if (VEC && e0 + M <= W) {
+#pragma unroll
+        for (int j = 0; j < M; j += 4) {
+            const uint4 t = *reinterpret_cast<const uint4*>(p + e0 + j);
+            v[j] = t.x;
+            v[j + 1] = t.y;
+            v[j + 2] = t.z;
+            v[j + 3] = t.w;
+        }
+    } else {
+#pragma unroll
+        for (int j = 0; j < M; ++j) v[j] = e0 + j < W ? p[e0 + j] : 0u;
+    }
+}
+template <bool VEC, int M>
+__device__ inline void store_run(float* p, int e0, int W, const float (&v)[M]) {
+    if (VEC && e0 + M <= W) {
+#pragma unroll
+        for (int j = 0; j < M; j += 4)
+            *reinterpret_cast<float4*>(p + e0 + j) = make_float4(v[j], v[j + 1], v[j + 2], v[j + 3]);
+    } else {
+#pragma unroll
+        for (int j = 0; j < M; ++j)
+            if (e0 + j < W) p[e0 + j] = v[j];
+    }
+}
+
 // Horizontal pass of one iteration over every row of every channel:
-// src -> dst (src == dst allowed).
+// src -> dst (src == dst allowed).  VEC: rows are 16-byte aligned (W a
+// multiple of 4 and 16-byte aligned planes).
+template <bool VEC>
 __global__ void __launch_bounds__(kDtRowBlock) dt_rows(const float* src, float* dst,
                                                        const uint32_t* __restrict__ dist,
                                                        int H, int W, int C, float k,
@@ -96,12 +148,14 @@ __global__ void __launch_bounds__(kDtRowBlock) dt_rows(const float* src, float* 
         float v[M], w[M];
         for (int ci = 0; ci < nchunks; ++ci) {
             const int e0 = ci * (int)chunk + lane * M;
+            uint32_t dw[M];
+            load_run<VEC, M>(in, e0, W, v);
+            load_run<VEC, M>(drow, e0, W, dw);
 #pragma unroll
             for (int j = 0; j < M; ++j) {
                 const int e = e0 + j;
                 // beyond the row: the identity map; the first sample: w = 0
-                v[j] = e < W ? in[e] : 0.0f;
-                w[j] = e >= W ? 1.0f : (e == 0 ? 0.0f : dt_weight(drow[e] & 0xffffu, k, ratio));
+                w[j] = e >= W ? 1.0f : (e == 0 ? 0.0f : dt_weight(dw[j] & 0xffffu, k, ratio));
             }
             float A = 1.0f, B = 0.0f;
 #pragma unroll
@@ -124,9 +178,9 @@ __global__ void __launch_bounds__(kDtRowBlock) dt_rows(const float* src, float* 
             for (int j = 0; j < M; ++j) {
                 yv = fmaf(w[j], yv, (1.0f - w[j]) * v[j]);
                 v[j] = yv;
-                // the last chunk's outputs stay in v for the backward recursion
-                if (ci + 1 < nchunks && e0 + j < W) out[e0 + j] = yv;
             }
+            // the last chunk's outputs stay in v for the backward recursion
+            if (ci + 1 < nchunks) store_run<VEC, M>(out, e0, W, v);
             carry = __shfl(yv, 63);
         }
         // right to left over the forward pass's output: the last chunk is still
@@ -145,14 +199,21 @@ __global__ void __launch_bounds__(kDtRowBlock) dt_rows(const float* src, float* 
                     wb[j] = e >= W ? 1.0f : (e + 1 == W ? 0.0f : (j + 1 < M ? w[j + 1] : next0));
                 }
             } else {
+                // a chunk before the last lies inside the row
+                uint32_t dw[M];
+                load_run<VEC, M>(out, e0, W, v);
+                load_run<VEC, M>(drow, e0, W, dw);
+                // the edge ahead of the lane's last sample opens the next lane's
+                // run; lane 63's lies in the next chunk
+                uint32_t next = __shfl_down(dw[0], 1);
+                if (lane == 63 && e0 + M < W) next = drow[e0 + M];
 #pragma unroll
                 for (int j = 0; j < M; ++j) {
                     const int e = e0 + j;
                     // the edge ahead (e, e+1); the last sample: w = 0
-                    v[j] = e < W ? out[e] : 0.0f;
+                    const uint32_t da = j + 1 < M ? dw[j + 1] : next;
                     wb[j] = e >= W ? 1.0f
-                                   : (e + 1 == W ? 0.0f
-                                                 : dt_weight(drow[e + 1] & 0xffffu, k, ratio));
+                                   : (e + 1 == W ? 0.0f : dt_weight(da & 0xffffu, k, ratio));
                 }
             }
             float A = 1.0f, B = 0.0f;
@@ -175,8 +236,9 @@ __global__ void __launch_bounds__(kDtRowBlock) dt_rows(const float* src, float* 
 #pragma unroll
             for (int j = M - 1; j >= 0; --j) {
                 yv = fmaf(wb[j], yv, (1.0f - wb[j]) * v[j]);
-                if (e0 + j < W) out[e0 + j] = yv;
+                v[j] = yv;
             }
+            store_run<VEC, M>(out, e0, W, v);
             carry = __shfl(yv, 0);
         }
     }
@@ -248,8 +310,9 @@ __device__ inline void col_up(float* xc, const uint32_t* dc, int W, int H, int r
     }
 }
 
-// Vertical pass of one iteration, in place: block (channel, 32-column strip),
-// kDtSegs segments of rows per column.
+// Vertical pass of one iteration for images of any height, in place: block
+// (channel, 16-column strip), kDtSegs segments of rows per column streamed
+// from memory (compose, replay, both ways).
 __global__ void __launch_bounds__(kDtColBlock) dt_cols(float* x, const uint32_t* __restrict__ dist,
                                                        int H, int W, int strips, float k,
                                                        float ratio) {
@@ -288,6 +351,119 @@ __global__ void __launch_bounds__(kDtColBlock) dt_cols(float* x, const uint32_t*
         yv = cB;   // the last segment ends with w = 0
     }
     if (live) col_up<true>(xc, dc, W, H, r0, r1, k, ratio, A, B, yv);
+}
+
+// Vertical pass with every column segment held in registers, for images of
+// at most 64 * LMAX rows: a block takes CW columns of a channel (CW waves),
+// 64 segments of L = ceil(H / 64) <= LMAX rows each per column, so every
+// sample and distance is read once and every output written once.  The
+// segment maps are scanned by one wave per column (lane = segment, six
+// shuffle steps), downwards and then upwards.  Blocks are dealt to the dies in
+// contiguous runs of column strips, so a die's L2 holds whole cache lines of
+// the rows.  Eight columns (32-byte row pieces) measured best on the 1024x768
+// stereo image: 4 % ahead of 16 columns, level with 4.  Taller images (more
+// than 64 * 32 rows) take the streaming pass dt_cols.
+constexpr int kDtRegSegs = 64;
+constexpr int kDtRegCW = 8;
+
+// The exclusive scan of the segment maps of column `col` held in LDS
+// (sA[seg][col], sB[seg][col]), in place: DOWN composes the maps above a
+// segment, !DOWN those below it.
+template <bool DOWN, int CWP>
+__device__ inline void scan_segment_maps(float (*sA)[CWP], float (*sB)[CWP], int col) {
+    const int lane = threadIdx.x & 63;
+    float A = sA[lane][col], B = sB[lane][col];
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const float pA = DOWN ? __shfl_up(A, o) : __shfl_down(A, o);
+        const float pB = DOWN ? __shfl_up(B, o) : __shfl_down(B, o);
+        if (DOWN ? lane >= o : lane + o < 64) {
+            B = fmaf(A, pB, B);
+            A = A * pA;
+        }
+    }
+    float eA = DOWN ? __shfl_up(A, 1) : __shfl_down(A, 1);
+    float eB = DOWN ? __shfl_up(B, 1) : __shfl_down(B, 1);
+    if (lane == (DOWN ? 0 : 63)) {
+        eA = 1.0f;
+        eB = 0.0f;
+    }
+    sA[lane][col] = eA;
+    sB[lane][col] = eB;
+}
+
+template <int CW, int LMAX>
+__global__ void __launch_bounds__(CW * 64) dt_cols_reg(float* x, const uint32_t* __restrict__ dist,
+                                                       int H, int W, int strips, int tiles,
+                                                       float k, float ratio) {
+    static_assert(CW * 64 / kDtRegSegs == CW, "one wave per column of the block");
+    __shared__ float sA[kDtRegSegs][CW + 1], sB[kDtRegSegs][CW + 1];
+    const int nb = gridDim.x;
+    const int tile = nb % kXcds == 0 ? partial_slot(blockIdx.x, nb) : blockIdx.x;
+    if (tile >= tiles) return;   // the whole block: the grid is rounded up to the dies
+    const int col_in = threadIdx.x % CW, seg = threadIdx.x / CW;
+    const int c = tile / strips;
+    const int col = (tile - c * strips) * CW + col_in;
+    const bool live = col < W;
+    const int L = (H + kDtRegSegs - 1) / kDtRegSegs;
+    const int r0 = min(H, seg * L), n = min(H, r0 + L) - r0;
+    float* xc = x + ((int64_t)c * H + r0) * W + col;
+    const uint32_t* dc = dist + (int64_t)r0 * W + col;
+    float v[LMAX], w[LMAX];
+    uint32_t dw[LMAX];
+#pragma unroll
+    for (int j = 0; j < LMAX; ++j) {
+        const bool ok = live && j < n;
+        v[j] = ok ? xc[(int64_t)j * W] : 0.0f;
+        dw[j] = ok ? dc[(int64_t)j * W] >> 16 : 0u;
+    }
+    // the edge below the segment's last row opens the next segment
+    const bool below = live && n > 0 && r0 + n < H;
+    const float wlast = below ? dt_weight(dc[(int64_t)n * W] >> 16, k, ratio) : 0.0f;
+    // edge (r-1, r) of row r = r0 + j; the image's first row: 0; beyond the
+    // segment: the identity map (w = 1 with v = 0)
+#pragma unroll
+    for (int j = 0; j < LMAX; ++j)
+        w[j] = j < n ? (r0 + j == 0 ? 0.0f : dt_weight(dw[j], k, ratio)) : 1.0f;
+    // downwards
+    float A = 1.0f, B = 0.0f;
+#pragma unroll
+    for (int j = 0; j < LMAX; ++j) dt_after(A, B, w[j], (1.0f - w[j]) * v[j]);
+    sA[seg][col_in] = A;
+    sB[seg][col_in] = B;
+    __syncthreads();
+    scan_segment_maps<true, CW + 1>(sA, sB, threadIdx.x >> 6);
+    __syncthreads();
+    float yv = sB[seg][col_in];   // the image's first row has w = 0: the map at 0
+#pragma unroll
+    for (int j = 0; j < LMAX; ++j) {
+        yv = fmaf(w[j], yv, (1.0f - w[j]) * v[j]);
+        v[j] = yv;
+    }
+    __syncthreads();   // every thread has read its prefix
+    // upwards over the downward output: row r takes the edge (r, r+1), the
+    // image's last row 0
+    A = 1.0f;
+    B = 0.0f;
+#pragma unroll
+    for (int j = LMAX - 1; j >= 0; --j) {
+        const float u = j + 1 < n ? w[j + 1 < LMAX ? j + 1 : LMAX - 1]
+                                    : (j + 1 == n ? wlast : 1.0f);
+        dt_after(A, B, u, (1.0f - u) * v[j]);
+    }
+    sA[seg][col_in] = A;
+    sB[seg][col_in] = B;
+    __syncthreads();
+    scan_segment_maps<false, CW + 1>(sA, sB, threadIdx.x >> 6);
+    __syncthreads();
+    yv = sB[seg][col_in];   // the image's last row has w = 0
+#pragma unroll
+    for (int j = LMAX - 1; j >= 0; --j) {
+        const float u = j + 1 < n ? w[j + 1 < LMAX ? j + 1 : LMAX - 1]
+                                    : (j + 1 == n ? wlast : 1.0f);
+        yv = fmaf(u, yv, (1.0f - u) * v[j]);
+        if (live && j < n) xc[(int64_t)j * W] = yv;
+    }
 }
 
 constexpr int kDtSumBlocks = 256;
@@ -406,14 +582,41 @@ bs_status run_dt(const float* src, float* dst, const uint32_t* dist, int H, int 
     const int row_blocks =
         (int)std::min<int64_t>(ceil_div(lines, kDtRowBlock / 64), (int64_t)1 << 16);
     const int strips = (int)ceil_div(W, kDtColW);
+    // segments in registers: rows per segment, column strips, tiles and the
+    // grid rounded up to whole dies
+    const int reg_rows = (int)ceil_div(H, kDtRegSegs);
+    const int reg_strips = (int)ceil_div(W, kDtRegCW);
+    const int reg_tiles = C * reg_strips;
+    const int reg_grid = (int)ceil_div(reg_tiles, kXcds) * kXcds;
+    // 16-byte row accesses: every row starts on a 16-byte boundary
+    const bool vec = W % 4 == 0 && ((uintptr_t)src & 15) == 0 && ((uintptr_t)dst & 15) == 0 &&
+                     ((uintptr_t)dist & 15) == 0;
     for (int i = 1; i <= N; ++i) {
         const double sig = (double)p.sigma_s * std::sqrt(3.0) * std::ldexp(1.0, N - i) /
                            std::sqrt(std::ldexp(1.0, 2 * N) - 1.0);
         const float k = (float)(-std::sqrt(2.0) / sig / std::log(2.0));
-        BS_LAUNCH(s, K_DT_ROWS, "dt_rows", dt_rows, dim3(row_blocks), dim3(kDtRowBlock), 0, s,
-                  i == 1 ? src : dst, dst, dist, H, W, C, k, (float)ratio);
-        BS_LAUNCH(s, K_DT_COLS, "dt_cols", dt_cols, dim3(C * strips), dim3(kDtColBlock), 0, s,
-                  dst, dist, H, W, strips, k, (float)ratio);
+        const float* in = i == 1 ? src : dst;
+        if (vec)
+            BS_LAUNCH(s, K_DT_ROWS, "dt_rows", dt_rows<true>, dim3(row_blocks),
+                      dim3(kDtRowBlock), 0, s, in, dst, dist, H, W, C, k, (float)ratio);
+        else
+            BS_LAUNCH(s, K_DT_ROWS, "dt_rows", dt_rows<false>, dim3(row_blocks),
+                      dim3(kDtRowBlock), 0, s, in, dst, dist, H, W, C, k, (float)ratio);
+        if (reg_rows <= 8)
+            BS_LAUNCH(s, K_DT_COLS, "dt_cols", (dt_cols_reg<kDtRegCW, 8>), dim3(reg_grid),
+                      dim3(kDtRegCW * 64), 0, s, dst, dist, H, W, reg_strips, reg_tiles, k,
+                      (float)ratio);
+        else if (reg_rows <= 16)
+            BS_LAUNCH(s, K_DT_COLS, "dt_cols", (dt_cols_reg<kDtRegCW, 16>), dim3(reg_grid),
+                      dim3(kDtRegCW * 64), 0, s, dst, dist, H, W, reg_strips, reg_tiles, k,
+                      (float)ratio);
+        else if (reg_rows <= 32)
+            BS_LAUNCH(s, K_DT_COLS, "dt_cols", (dt_cols_reg<kDtRegCW, 32>), dim3(reg_grid),
+                      dim3(kDtRegCW * 64), 0, s, dst, dist, H, W, reg_strips, reg_tiles, k,
+                      (float)ratio);
+        else
+            BS_LAUNCH(s, K_DT_COLS, "dt_cols", dt_cols, dim3(C * strips), dim3(kDtColBlock), 0,
+                      s, dst, dist, H, W, strips, k, (float)ratio);
     }
     return BS_OK;
 }

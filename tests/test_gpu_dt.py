@@ -46,6 +46,8 @@ def _run(ref, x, ss, sr, iters=3, inplace=False):
     (17, 1100, 3, 16.0, 16.0),     # three row chunks, 17 rows in 16 segments
     (95, 161, 21, 4.0, 8.0),       # 21 channels, ragged column strips
     (200, 300, 1, 64.0, 4.0),      # wide support, strong edges
+    (1500, 37, 2, 8.0, 8.0),       # 24 rows per column segment
+    (2049, 20, 1, 16.0, 32.0),     # 33 rows per segment: segments streamed
 ])
 def test_domain_transform_against_oracle(H, W, C, ss, sr):
     say(f"domain transform {H}x{W} C={C} sigma_s={ss} sigma_r={sr}")
