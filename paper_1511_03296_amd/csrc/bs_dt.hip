@@ -51,23 +51,124 @@ __device__ inline float dt_weight(uint32_t dist, float k, float ratio) {
     return exp2f(k * fmaf(ratio, (float)dist, 1.0f));
 }
 
+// M consecutive samples of a row from e0 (0 beyond the row): 16-byte vector
+// loads when the row is 16-byte aligned (VEC: W a multiple of 4, so a group
+// of four lies wholly inside the row or wholly past it), else one by one.
+// Every load is issued unconditionally from an address clamped into the row
+// and a select zeroes what lies past it: a load under a branch is waited for
+// where the branches join, which would serialise the loads.
+template <typename T> struct Vec4;
+template <> struct Vec4<float> { using type = float4; };
+template <> struct Vec4<uint32_t> { using type = uint4; };
+
+template <bool VEC, int M, typename T>
+__device__ inline void load_run(const T* p, int e0, int W, T (&v)[M]) {
+    if constexpr (VEC) {
+#pragma unroll
+        for (int j = 0; j < M; j += 4) {
+            const typename Vec4<T>::type t =
+                *reinterpret_cast<const typename Vec4<T>::type*>(p + min(e0 + j, W - 4));
+            const bool in = e0 + j < W;
+            v[j] = in ? t.x : T(0);
+            v[j + 1] = in ? t.y : T(0);
+            v[j + 2] = in ? t.z : T(0);
+            v[j + 3] = in ? t.w : T(0);
+        }
+    } else {
+#pragma unroll
+        for (int j = 0; j < M; ++j) {
+            const T t = p[min(e0 + j, W - 1)];
+            v[j] = e0 + j < W ? t : T(0);
+        }
+    }
+}
+
+// The guide values of four consecutive pixels (x0 .. x0+3) of row y in the
+// three channels (0 beyond the row), as load_run reads them.
+template <bool VEC>
+__device__ inline void load4(const float* __restrict__ ref, int64_t P, int W, int y, int x0,
+                             float (&v)[3][4]) {
+    const int64_t row = (int64_t)y * W;
+#pragma unroll
+    for (int ch = 0; ch < 3; ++ch) load_run<VEC, 4>(ref + ch * P + row, x0, W, v[ch]);
+}
+
+// The 8-bit codes of the three channels packed into the low three bytes.
+__device__ inline uint32_t pack_codes(float r, float g, float b) {
+    return (uint32_t)quantise8(r) | ((uint32_t)quantise8(g) << 8) | ((uint32_t)quantise8(b) << 16);
+}
+
+// Sum over the three packed channels of |a_c - b_c|.
+__device__ inline uint32_t code_dist(uint32_t a, uint32_t b) {
+    uint32_t d = 0;
+#pragma unroll
+    for (int ch = 0; ch < 3; ++ch) {
+        const int u = (int)((a >> (8 * ch)) & 255u), v = (int)((b >> (8 * ch)) & 255u);
+        d += (uint32_t)abs(u - v);
+    }
+    return d;
+}
+
 // Domain distances of every pixel: low half the edge to the left neighbour,
-// high half the edge to the upper one (0 where there is none).
+// high half the edge to the upper one (0 where there is none).  A lane takes
+// four consecutive pixels of kDtStepRows rows (grid: 256-column pieces by
+// groups of 4 x kDtStepRows rows, a wave per row group): every code is
+// computed once per row plus once for the row above the group, and the left
+// neighbour comes from the lane before (lane 0 reads it).  Every load of the
+// lane is issued before the first code is computed (rows past the image are
+// clamped to its last row and not stored; the pixel left of the row's first
+// to itself).
+constexpr int kDtStepRows = 4;
+
+template <bool VEC>
 __global__ void __launch_bounds__(kBlock) dt_steps(const float* __restrict__ ref, int H, int W,
                                                    uint32_t* __restrict__ dist) {
+    const int lane = threadIdx.x & 63;
+    const int x0 = blockIdx.x * 256 + lane * 4;
+    const int y0 = (blockIdx.y * (kBlock / 64) + (threadIdx.x >> 6)) * kDtStepRows;
+    if (y0 >= H) return;   // the whole wave
     const int64_t P = (int64_t)H * W;
-    for (int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x; p < P;
-         p += (int64_t)gridDim.x * kBlock) {
-        const int y = (int)(p / W), x = (int)(p - (int64_t)y * W);
-        uint32_t dh = 0, dv = 0;
+    float v[kDtStepRows + 1][3][4];   // row y0 - 1 (clamped to 0), then the group's rows
+    float lv[kDtStepRows][3];         // the pixel left of x0 in each row
 #pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            const float* ch = ref + c * P;
-            const int q = quantise8(ch[p]);
-            if (x > 0) dh += (uint32_t)abs(q - quantise8(ch[p - 1]));
-            if (y > 0) dv += (uint32_t)abs(q - quantise8(ch[p - W]));
+    for (int r = 0; r <= kDtStepRows; ++r)
+        load4<VEC>(ref, P, W, min(max(y0 + r - 1, 0), H - 1), x0, v[r]);
+    const int xl = x0 > 0 ? x0 - 1 : 0;
+#pragma unroll
+    for (int r = 0; r < kDtStepRows; ++r) {
+        const int64_t q = (int64_t)min(y0 + r, H - 1) * W + min(xl, W - 1);
+#pragma unroll
+        for (int ch = 0; ch < 3; ++ch) lv[r][ch] = ref[ch * P + q];
+    }
+    uint32_t up[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) up[j] = pack_codes(v[0][0][j], v[0][1][j], v[0][2][j]);
+#pragma unroll
+    for (int r = 0; r < kDtStepRows; ++r) {
+        const int y = y0 + r;
+        uint32_t c[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) c[j] = pack_codes(v[r + 1][0][j], v[r + 1][1][j], v[r + 1][2][j]);
+        const uint32_t from_lane = __shfl_up(c[3], 1);
+        const uint32_t left = lane == 0 ? pack_codes(lv[r][0], lv[r][1], lv[r][2]) : from_lane;
+        uint32_t o[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const uint32_t dh = x0 + j > 0 ? code_dist(c[j], j ? c[j - 1] : left) : 0u;
+            const uint32_t dv = y > 0 ? code_dist(c[j], up[j]) : 0u;
+            o[j] = dh | (dv << 16);
+            up[j] = c[j];
         }
-        dist[p] = dh | (dv << 16);
+        if (y < H) {
+            uint32_t* d = dist + (int64_t)y * W;
+            if (VEC && x0 + 4 <= W) {
+                *reinterpret_cast<uint4*>(d + x0) = make_uint4(o[0], o[1], o[2], o[3]);
+            } else {
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+                    if (x0 + j < W) d[x0 + j] = o[j];
+            }
+        }
     }
 }
 
@@ -77,40 +178,6 @@ __device__ inline void dt_after(float& A, float& B, float mA, float mB) {
     A = mA * A;
 }
 
-// M consecutive samples of a row from e0: 16-byte vector accesses when the
-// row is 16-byte aligned and the run lies inside it (VEC), else one by one.
-template <bool VEC, int M>
-__device__ inline void load_run(const float* p, int e0, int W, float (&v)[M]) {
-    if (VEC && e0 + M <= W) {
-#pragma unroll
-        for (int j = 0; j < M; j += 4) {
-            const float4 t = *reinterpret_cast<const float4*>(p + e0 + j);
-            v[j] = t.x;
-            v[j + 1] = t.y;
-            v[j + 2] = t.z;
-            v[j + 3] = t.w;
-        }
-    } else {
-#pragma unroll
-        for (int j = 0; j < M; ++j) v[j] = e0 + j < W ? p[e0 + j] : 0.0f;
-    }
-}
-template <bool VEC, int M>
-__device__ inline void load_run(const uint32_t* p, int e0, int W, uint32_t (&v)[M]) {
-    if (VEC && e0 + M <= W) {
-#pragma unroll
-        for (int j = 0; j < M; j += 4) {
-            const uint4 t = *reinterpret_cast<const uint4*>(p + e0 + j);
-            v[j] = t.x;
-            v[j + 1] = t.y;
-            v[j + 2] = t.z;
-            v[j + 3] = t.w;
-        }
-    } else {
-#pragma unroll
-        for (int j = 0; j < M; ++j) v[j] = e0 + j < W ? p[e0 + j] : 0u;
-    }
-}
 template <bool VEC, int M>
 __device__ inline void store_run(float* p, int e0, int W, const float (&v)[M]) {
     if (VEC && e0 + M <= W) {
@@ -205,8 +272,11 @@ __global__ void __launch_bounds__(kDtRowBlock) dt_rows(const float* src, float* 
                 load_run<VEC, M>(drow, e0, W, dw);
                 // the edge ahead of the lane's last sample opens the next lane's
                 // run; lane 63's lies in the next chunk
-                uint32_t next = __shfl_down(dw[0], 1);
-                if (lane == 63 && e0 + M < W) next = drow[e0 + M];
+                // (the shuffle runs on every lane: one under a branch would read
+                // 0 from the lanes the branch leaves out)
+                const uint32_t ahead = drow[min(e0 + M, W - 1)];
+                const uint32_t from_next = __shfl_down(dw[0], 1);
+                const uint32_t next = lane == 63 ? ahead : from_next;
 #pragma unroll
                 for (int j = 0; j < M; ++j) {
                     const int e = e0 + j;
@@ -260,10 +330,13 @@ __device__ inline void col_down(float* xc, const uint32_t* dc, int W, int r0, in
         float xv[kDtBatch];
         uint32_t dv[kDtBatch];
 #pragma unroll
-        for (int j = 0; j < kDtBatch; ++j) {
+        for (int j = 0; j < kDtBatch; ++j) {   // rows past the segment: clamped, zeroed
+            const int jj = min(j, r1 - 1 - rb);
+            const float xl = xb[(int64_t)jj * W];
+            const uint32_t dl = db[(int64_t)jj * W];
             const bool ok = rb + j < r1;
-            xv[j] = ok ? xb[j * W] : 0.0f;
-            dv[j] = ok && rb + j > 0 ? db[j * W] >> 16 : 0u;
+            xv[j] = ok ? xl : 0.0f;
+            dv[j] = ok && rb + j > 0 ? dl >> 16 : 0u;
         }
 #pragma unroll
         for (int j = 0; j < kDtBatch; ++j) {
@@ -290,10 +363,14 @@ __device__ inline void col_up(float* xc, const uint32_t* dc, int W, int H, int r
         float xv[kDtBatch];
         uint32_t dv[kDtBatch];
 #pragma unroll
-        for (int j = 0; j < kDtBatch; ++j) {
+        for (int j = 0; j < kDtBatch; ++j) {   // rows before the segment: clamped, zeroed
+            const int jj = min(j, rt - r0);
+            const float xl = xb[-(int64_t)jj * W];
+            // the edge ahead of the image's last row does not exist: row H - 1
+            const uint32_t dl = db[-(int64_t)(rt + 1 == H ? max(jj, 1) : jj) * W];
             const bool ok = rt - j >= r0;
-            xv[j] = ok ? xb[-j * W] : 0.0f;
-            dv[j] = ok && rt - j + 1 < H ? db[-j * W] >> 16 : 0u;
+            xv[j] = ok ? xl : 0.0f;
+            dv[j] = ok && rt - j + 1 < H ? dl >> 16 : 0u;
         }
 #pragma unroll
         for (int j = 0; j < kDtBatch; ++j) {
@@ -408,18 +485,26 @@ __global__ void __launch_bounds__(CW * 64) dt_cols_reg(float* x, const uint32_t*
     const int L = (H + kDtRegSegs - 1) / kDtRegSegs;
     const int r0 = min(H, seg * L), n = min(H, r0 + L) - r0;
     float* xc = x + ((int64_t)c * H + r0) * W + col;
-    const uint32_t* dc = dist + (int64_t)r0 * W + col;
+    // loads from addresses clamped into the image (column, then row), the
+    // samples outside the segment zeroed by a select: no load under a branch
+    const int colc = min(col, W - 1);
+    const float* xp = x + (int64_t)c * H * W + colc;
+    const uint32_t* dp = dist + colc;
     float v[LMAX], w[LMAX];
     uint32_t dw[LMAX];
 #pragma unroll
     for (int j = 0; j < LMAX; ++j) {
+        const int64_t at = (int64_t)min(r0 + j, H - 1) * W;
+        const float xv = xp[at];
+        const uint32_t dv = dp[at];
         const bool ok = live && j < n;
-        v[j] = ok ? xc[(int64_t)j * W] : 0.0f;
-        dw[j] = ok ? dc[(int64_t)j * W] >> 16 : 0u;
+        v[j] = ok ? xv : 0.0f;
+        dw[j] = ok ? dv >> 16 : 0u;
     }
     // the edge below the segment's last row opens the next segment
+    const uint32_t dl = dp[(int64_t)min(r0 + n, H - 1) * W];
     const bool below = live && n > 0 && r0 + n < H;
-    const float wlast = below ? dt_weight(dc[(int64_t)n * W] >> 16, k, ratio) : 0.0f;
+    const float wlast = below ? dt_weight(dl >> 16, k, ratio) : 0.0f;
     // edge (r-1, r) of row r = r0 + j; the image's first row: 0; beyond the
     // segment: the identity map (w = 1 with v = 0)
 #pragma unroll
@@ -468,22 +553,38 @@ __global__ void __launch_bounds__(CW * 64) dt_cols_reg(float* x, const uint32_t*
 
 constexpr int kDtSumBlocks = 256;
 
-// Per-block float64 partial sums of z [P] (kDtSumBlocks blocks).
+// Sum of a float64 over the block (kBlock threads), the same order in every
+// block: the waves' shuffle trees, then the four wave sums in turn.
+__device__ inline double block_sum(double v, double* red) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    __syncthreads();   // `red` may still be read from an earlier call
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    double t = 0.0;
+#pragma unroll
+    for (int w = 0; w < kBlock / 64; ++w) t += red[w];
+    return t;
+}
+
+// Per-block float64 partial sums of z [P] (kDtSumBlocks blocks); four loads
+// in flight per thread.
 __global__ void __launch_bounds__(kBlock) dt_partial_sums(const float* __restrict__ z,
                                                           int64_t P,
                                                           double* __restrict__ part) {
-    __shared__ double red[kBlock];
-    double s = 0.0;
-    for (int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x; p < P;
-         p += (int64_t)kDtSumBlocks * kBlock)
-        s += (double)z[p];
-    red[threadIdx.x] = s;
-    __syncthreads();
-    for (int o = kBlock / 2; o > 0; o >>= 1) {
-        if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
-        __syncthreads();
+    __shared__ double red[kBlock / 64];
+    constexpr int64_t stride = (int64_t)kDtSumBlocks * kBlock;
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    for (; p + 3 * stride < P; p += 4 * stride) {
+        s0 += (double)z[p];
+        s1 += (double)z[p + stride];
+        s2 += (double)z[p + 2 * stride];
+        s3 += (double)z[p + 3 * stride];
     }
-    if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+    for (; p < P; p += stride) s0 += (double)z[p];
+    const double t = block_sum((s0 + s1) + (s2 + s3), red);
+    if (threadIdx.x == 0) part[blockIdx.x] = t;
 }
 
 // The two signals of the variance, about the mean mu of z (every block sums
@@ -494,17 +595,13 @@ __global__ void __launch_bounds__(kBlock) dt_moments(const float* __restrict__ z
                                                      const double* __restrict__ part,
                                                      float* __restrict__ s) {
     static_assert(kDtSumBlocks == kBlock, "one partial per thread");
-    __shared__ double red[kBlock];
-    red[threadIdx.x] = part[threadIdx.x];
-    __syncthreads();
-    for (int o = kBlock / 2; o > 0; o >>= 1) {
-        if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
-        __syncthreads();
-    }
-    const float mu = (float)(red[0] / (double)P);
-    for (int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x; p < P;
-         p += (int64_t)gridDim.x * kBlock) {
-        const float d = z[p] - mu;
+    __shared__ double red[kBlock / 64];
+    int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const float z0 = p < P ? z[p] : 0.0f;   // in flight during the sum of the partials
+    const float mu = (float)(block_sum(part[threadIdx.x], red) / (double)P);
+    for (float zv = z0; p < P; p += (int64_t)gridDim.x * kBlock) {
+        if (p != (int64_t)blockIdx.x * kBlock + threadIdx.x) zv = z[p];
+        const float d = zv - mu;
         s[p] = d;
         s[P + p] = d * d;
     }
@@ -518,7 +615,7 @@ __global__ void __launch_bounds__(kBlock) dt_conf(const float* __restrict__ s, i
     const int64_t P = (int64_t)H * W;
     for (int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x; p < P;
          p += (int64_t)gridDim.x * kBlock) {
-        const int x = (int)(p % W);
+        const int x = (int)((uint32_t)p % (uint32_t)W);   // P < 2^30
         const float m1 = s[p];
         const float V = fmaxf(s[P + p] - m1 * m1, 0.0f);
         c[p] = x < zero_cols ? 0.0f : expf(-V * inv2s2);
@@ -570,6 +667,20 @@ bs_status check_ws(void* ws, size_t ws_bytes, int32_t H, int32_t W) {
     if (ws_bytes < need)
         return fail(BS_EWORKSPACE, "domain-transform workspace needs " + std::to_string(need) +
                                        " bytes");
+    return BS_OK;
+}
+
+// The domain distances of the guide into `dist`.
+bs_status launch_steps(const float* ref, int H, int W, uint32_t* dist, hipStream_t s) {
+    const dim3 grid((unsigned)ceil_div(W, 256), (unsigned)ceil_div(H, (kBlock / 64) * kDtStepRows));
+    // 16-byte accesses: every plane and row starts 16-byte aligned
+    const bool vec = W % 4 == 0 && ((uintptr_t)ref & 15) == 0 && ((uintptr_t)dist & 15) == 0;
+    if (vec)
+        BS_LAUNCH(s, K_DT_OTHER, "dt_steps", dt_steps<true>, grid, dim3(kBlock), 0, s, ref, H, W,
+                  dist);
+    else
+        BS_LAUNCH(s, K_DT_OTHER, "dt_steps", dt_steps<false>, grid, dim3(kBlock), 0, s, ref, H,
+                  W, dist);
     return BS_OK;
 }
 
@@ -648,8 +759,7 @@ extern "C" bs_status bs_domain_transform(const float* ref, int32_t H, int32_t W,
     if ((st = check_ws(ws, ws_bytes, H, W)) != BS_OK) return st;
     hipStream_t s = (hipStream_t)stream;
     const DtWs w = layout_dt(P, ws);
-    BS_LAUNCH(s, K_DT_OTHER, "dt_steps", dt_steps, dim3(grid_blocks(ceil_div(P, kBlock))),
-              dim3(kBlock), 0, s, ref, H, W, w.dist);
+    if ((st = launch_steps(ref, H, W, w.dist, s)) != BS_OK) return st;
     return run_dt(x, out, w.dist, H, W, C, *params, s);
 }
 
@@ -670,7 +780,7 @@ extern "C" bs_status bs_dt_confidence(const float* ref, int32_t H, int32_t W, co
     const int64_t P = (int64_t)H * W;
     const DtWs w = layout_dt(P, ws);
     const dim3 pg(grid_blocks(ceil_div(P, kBlock)));
-    BS_LAUNCH(s, K_DT_OTHER, "dt_steps", dt_steps, pg, dim3(kBlock), 0, s, ref, H, W, w.dist);
+    if ((st = launch_steps(ref, H, W, w.dist, s)) != BS_OK) return st;
     BS_LAUNCH(s, K_DT_OTHER, "dt_partial_sums", dt_partial_sums, dim3(kDtSumBlocks),
               dim3(kBlock), 0, s, z, P, w.part);
     BS_LAUNCH(s, K_DT_OTHER, "dt_moments", dt_moments, pg, dim3(kBlock), 0, s, z, P, w.part,
