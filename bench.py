@@ -112,9 +112,10 @@ KERNEL_CODE = os.path.join(ROOT, "paper_1511_03296_amd", "kernel_code.json")
 
 
 def _measured_traffic(workload: str):
-    """HBM bytes per pcg_matvec launch from the committed counter runs, if
-    every pcg_matvec kernel they covered still has the machine code it had
-    then (digests written by the build), else None."""
+    """HBM bytes per launch of the workload's dominant kernel (pcg_matvec, or
+    dt_cols for the domain transform) from the committed counter runs, if
+    every kernel of that family they covered still has the machine code it
+    had then (digests written by the build), else None."""
     if not (os.path.exists(TRAFFIC_FILE) and os.path.exists(KERNEL_CODE)):
         return None
     with open(TRAFFIC_FILE) as f:
