@@ -130,7 +130,17 @@ struct SplatCells {
         for (int k = threadIdx.x; k < cnt; k += B) {
             const int s0 = ptr[vbase + k] - ibase, s1 = ptr[vbase + k + 1] - ibase;
             double sc = 0.0;
-            for (int q = s0; q < s1; ++q) sc += (double)cv[lst[q]];
+            int q = s0;
+            // four pixels' LDS reads issued together, summed in ascending order
+            for (; q + 4 <= s1; q += 4) {
+                const int j0 = lst[q], j1 = lst[q + 1], j2 = lst[q + 2], j3 = lst[q + 3];
+                const float c0 = cv[j0], c1 = cv[j1], c2 = cv[j2], c3 = cv[j3];
+                sc += (double)c0;
+                sc += (double)c1;
+                sc += (double)c2;
+                sc += (double)c3;
+            }
+            for (; q < s1; ++q) sc += (double)cv[lst[q]];
             const double d = a.lam * a.nn[vbase + k] + sc;
             const float mi = d > 0.0 ? (float)(1.0 / d) : 0.0f;
             a.o.sc[vbase + k] = (float)sc;
@@ -151,11 +161,26 @@ struct SplatCells {
             for (int e = threadIdx.x; e < cnt * cn; e += B) {
                 const int k = e / cn, cc = e - k * cn;
                 const int s0 = ptr[vbase + k] - ibase, s1 = ptr[vbase + k + 1] - ibase;
+                const float* __restrict__ tc = tv + cc * n;
                 double acc = 0.0;
-                for (int q = s0; q < s1; ++q) {
+                int q = s0;
+                for (; q + 4 <= s1; q += 4) {
+                    int jl[4];
+                    float tq[4], wq[4];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) jl[u] = lst[q + u];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        tq[u] = tc[jl[u]];
+                        wq[u] = WEIGHTED ? cv[jl[u]] : 1.0f;
+                    }
+#pragma unroll
+                    for (int u = 0; u < 4; ++u)
+                        acc += WEIGHTED ? (double)wq[u] * (double)tq[u] : (double)tq[u];
+                }
+                for (; q < s1; ++q) {
                     const int jl = lst[q];
-                    acc += WEIGHTED ? (double)cv[jl] * (double)tv[cc * n + jl]
-                                    : (double)tv[cc * n + jl];
+                    acc += WEIGHTED ? (double)cv[jl] * (double)tc[jl] : (double)tc[jl];
                 }
                 b[(int64_t)(vbase + k) * Cp + c0 + cc] = (float)acc;
             }
