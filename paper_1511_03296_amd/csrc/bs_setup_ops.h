@@ -322,6 +322,25 @@ struct PyrSmall {
         const int32_t* counts;
         int C;
     };
+    // Sum over the children clist[j0 .. j1) of get(child), in ascending order,
+    // four children's loads issued together.
+    template <class F>
+    __device__ static double sum_children(const int32_t* clist, int j0, int j1, F get) {
+        double s = 0.0;
+        int j = j0;
+        for (; j + 4 <= j1; j += 4) {
+            int c[4];
+            float v[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) c[q] = clist[j + q];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) v[q] = get(c[q]);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) s += (double)v[q];
+        }
+        for (; j < j1; ++j) s += (double)get(clist[j]);
+        return s;
+    }
     __device__ static void run(const Args& A, int, int, int) {
         const PyrLevels& a = A.lv;
         const int K = A.counts[CNT_K];
@@ -336,12 +355,17 @@ struct PyrSmall {
             const int64_t n = (int64_t)Vk * C1;
             for (int64_t e = threadIdx.x; e < n; e += kThreads) {
                 const int u = (int)(e / C1), ch = (int)(e - (int64_t)u * C1);
-                double s = 0.0;
-                for (int j = cptr[u]; j < cptr[u + 1]; ++j) {
-                    const int c = clist[j];
-                    if (prev) s += (double)prev[(int64_t)c * C1 + ch];
-                    else s += (double)(ch < C ? A.b[(int64_t)c * C + ch] : A.sc[c]);
-                }
+                const int j0 = cptr[u], j1 = cptr[u + 1];
+                // the level below, or at level 1 [b | S c] (both read, one
+                // kept: no load under a branch inside the sum)
+                const double s =
+                    prev ? sum_children(clist, j0, j1,
+                                        [&](int c) { return prev[(int64_t)c * C1 + ch]; })
+                         : sum_children(clist, j0, j1, [&](int c) {
+                               const float bv = A.b[(int64_t)c * C + min(ch, C - 1)];
+                               const float sv = A.sc[c];
+                               return ch < C ? bv : sv;
+                           });
                 up[e] = (float)s;
             }
             __syncthreads();
