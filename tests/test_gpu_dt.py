@@ -178,3 +178,36 @@ def test_domain_transform_replays_from_a_graph():
     torch.cuda.synchronize()
     _check(out.cpu().numpy(), DT.domain_transform(p.ref, p.target * np.float32(0.5), 4.0, 8.0),
            "replay after new input")
+
+
+def _offset_view(a: np.ndarray, offset: int) -> torch.Tensor:
+    """a on the device in a buffer that starts `offset` floats past a 256-byte
+    boundary: 4-byte aligned, 16-byte aligned only when offset % 4 == 0."""
+    flat = torch.zeros(a.size + offset, dtype=torch.float32, device="cuda")
+    flat[offset:].copy_(torch.from_numpy(np.ascontiguousarray(a, np.float32).ravel()).cuda())
+    return flat[offset:].view(*a.shape)
+
+
+@pytest.mark.parametrize("offset", [1, 2, 3])
+def test_rows_not_16_byte_aligned(offset):
+    """Row widths that are multiples of 4 with reference, signal and output
+    buffers off a 16-byte boundary take the one-by-one row accesses: the same
+    results as aligned buffers, to the oracle's bar."""
+    from paper_1511_03296_amd import domain_transform, dt_confidence
+    rng = np.random.default_rng(40 + offset)
+    H, W, C = 37, 1100, 2
+    say(f"domain transform {H}x{W} C={C}, buffers {offset} floats off 16-byte alignment")
+    ref, _ = WL.voronoi_reference(rng, H, W, 40)
+    x = rng.normal(0.0, 1.0, (C, H, W)).astype(np.float32)
+    refd, xd = _offset_view(ref, offset), _offset_view(x, offset)
+    assert refd.data_ptr() % 16 != 0 and xd.data_ptr() % 16 != 0
+    out = _offset_view(np.zeros_like(x), 4 - offset)   # a third alignment for the output
+    got = domain_transform(refd, xd, 8.0, 16.0, out=out)
+    torch.cuda.synchronize()
+    aligned = _run(ref, x, 8.0, 16.0)
+    assert np.array_equal(got.cpu().numpy(), aligned)
+    _check(got.cpu().numpy(), DT.domain_transform(ref, x, 8.0, 16.0), "misaligned")
+    c = dt_confidence(refd, xd[0], 16.0, 32.0, 2.0, zero_cols=5)
+    c_al = dt_confidence(to_dev(ref), to_dev(x[0]), 16.0, 32.0, 2.0, zero_cols=5)
+    torch.cuda.synchronize()
+    assert torch.equal(c, c_al)
