@@ -211,3 +211,57 @@ def test_rows_not_16_byte_aligned(offset):
     c_al = dt_confidence(to_dev(ref), to_dev(x[0]), 16.0, 32.0, 2.0, zero_cols=5)
     torch.cuda.synchronize()
     assert torch.equal(c, c_al)
+
+
+def test_largest_image_rank_one_signal_on_a_flat_guide():
+    """H = W = 32768 (2^30 pixels, the largest image the calls take).  On a
+    flat guide every pass is the same 1-D operator on every line, so a rank-one
+    signal u v^T comes out as (U)(V)^T with U and V the oracle's passes over u
+    (columns) and v (rows) alone; the whole output is compared with that outer
+    product, and the confidence with V = DT(z^2) - DT(z)^2 built the same way
+    (z^2 = (u^2)(v^2)^T is rank one too)."""
+    from paper_1511_03296_amd import domain_transform, dt_confidence
+    H = W = 32768
+    ss, sr, sdt = 16.0, 8.0, 2.0
+    rng = np.random.default_rng(11)
+    u = rng.uniform(0.5, 1.5, H).astype(np.float32)
+    v = rng.uniform(0.5, 1.5, W).astype(np.float32)
+    say(f"domain transform {H}x{W} (2^30 pixels), flat guide, rank-one signal")
+
+    def line_filter(a):
+        J = np.asarray(a, np.float64)[None, None, :]
+        d = np.ones((1, a.size))
+        d[0, 0] = 0.0
+        for s in DT.iteration_sigmas(ss, DT.DEFAULT_ITERS):
+            J = DT.recursive_pass(J, d, s, axis=-1)
+        return J[0, 0]
+
+    U, V = line_filter(u), line_filter(v)
+    U2 = line_filter(u.astype(np.float64) ** 2)
+    V2 = line_filter(v.astype(np.float64) ** 2)
+    ref = torch.full((3, H, W), 0.5, dtype=torch.float32, device="cuda")
+    ud, vd = torch.from_numpy(u).cuda(), torch.from_numpy(v).cuda()
+    x = (ud[:, None] * vd[None, :]).unsqueeze(0)
+    out = domain_transform(ref, x, ss, sr)
+    conf = dt_confidence(ref, x[0], ss, sr, sdt)
+    torch.cuda.synchronize()
+    Ud, Vd = torch.from_numpy(U).cuda(), torch.from_numpy(V).cuda()
+    U2d, V2d = torch.from_numpy(U2).cuda(), torch.from_numpy(V2).cuda()
+    # max (z - mean z)^2 of the positive rank-one z: at its largest or smallest entry
+    u64, v64 = u.astype(np.float64), v.astype(np.float64)
+    mean = u64.mean() * v64.mean()
+    spread = max((u64.max() * v64.max() - mean) ** 2, (u64.min() * v64.min() - mean) ** 2)
+    scale = float((Ud.abs().max() * Vd.abs().max()))
+    err = 0.0
+    cerr = 0.0
+    for r0 in range(0, H, 4096):
+        want = Ud[r0:r0 + 4096, None] * Vd[None, :]
+        err = max(err, float((out[0, r0:r0 + 4096].double() - want).abs().max()))
+        var = (U2d[r0:r0 + 4096, None] * V2d[None, :] - want * want).clamp_min(0.0)
+        cwant = torch.exp(-var / (2.0 * sdt * sdt))
+        cerr = max(cerr, float((conf[r0:r0 + 4096].double() - cwant).abs().max()))
+    bound = 1e-5 * spread / (2.0 * sdt * sdt) + 1e-6
+    say(f"    max |err| / max |x| {err / scale:.2e}; confidence max |err| {cerr:.2e} "
+        f"(bound {bound:.2e})")
+    assert err / scale <= TOL
+    assert cerr <= bound
