@@ -769,18 +769,22 @@ bs_status run_bist(const PlanImpl& P, hipStream_t s) {
     bs_status st;
     BS_GO(BistInit, P.binit, K_BIST_OTHER, "bist_init");
     int last = 0;
-    for (int step = 0; step <= P.bist.max_iters; ++step) {
-        st = go<BistStep>(P.bstep, s, K_BIST_STEP, "bist_step", step);
-        if (st != BS_OK) return st;
-        last = step;
-        const int ce = P.bist.check_every;
-        if (ce > 0 && (step + 1) % ce == 0 && step < P.bist.max_iters) {
-            BS_LAUNCH(s, K_BIST_OTHER, "all_bist_done", all_bist_done, dim3(1), dim3(kBlock), 0, s,
-                      P.counts_tab, P.n, P.done_flag);
-            int32_t done = 0;
-            BS_TRY_HIP(hipMemcpyAsync(&done, P.done_flag, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-            BS_TRY_HIP(hipStreamSynchronize(s));
-            if (done) break;
+    {
+        // updates after every image's fixed point return at once: the polls lag
+        StopPoller poller(P.done_flag, 1, s, false);
+        for (int step = 0; step <= P.bist.max_iters; ++step) {
+            st = go<BistStep>(P.bstep, s, K_BIST_STEP, "bist_step", step);
+            if (st != BS_OK) return st;
+            last = step;
+            const int ce = P.bist.check_every;
+            if (ce > 0 && (step + 1) % ce == 0 && step < P.bist.max_iters) {
+                BS_LAUNCH(s, K_BIST_OTHER, "all_bist_done", all_bist_done, dim3(1), dim3(kBlock), 0,
+                          s, P.counts_tab, P.n, P.done_flag);
+                bool done = false;
+                st = poller.check(done);
+                if (st != BS_OK) return st;
+                if (done) break;
+            }
         }
     }
     st = go<BistDecide>(P.bdecide, s, K_BIST_OTHER, "bist_decide", last);

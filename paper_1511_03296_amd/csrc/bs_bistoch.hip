@@ -92,16 +92,19 @@ extern "C" bs_status bs_bistochastize(bs_grid* grid, const bs_bistoch_params* pa
     const int G = red_grid(g.vcap);
     const BistStep::Args sa = bist_step_args(g, p);
     int last = 0;
-    for (int step = 0; step <= p.max_iters; ++step) {
-        BS_LAUNCH(s, K_BIST_STEP, "bist_step", one_launch<BistStep>, dim3(G), dim3(kRedBlock), 0, s,
-                  sa, step);
-        last = step;
-        if (p.check_every > 0 && (step + 1) % p.check_every == 0 && step < p.max_iters) {
-            int32_t done = 0;
-            BS_TRY_HIP(hipMemcpyAsync(&done, g.counts + CNT_BIST_DONE, sizeof(int32_t),
-                                      hipMemcpyDeviceToHost, s));
-            BS_TRY_HIP(hipStreamSynchronize(s));
-            if (done) break;
+    {
+        // updates after the fixed point return at once: the polls lag behind
+        StopPoller poller(g.counts + CNT_BIST_DONE, 1, s, false);
+        for (int step = 0; step <= p.max_iters; ++step) {
+            BS_LAUNCH(s, K_BIST_STEP, "bist_step", one_launch<BistStep>, dim3(G), dim3(kRedBlock),
+                      0, s, sa, step);
+            last = step;
+            if (p.check_every > 0 && (step + 1) % p.check_every == 0 && step < p.max_iters) {
+                bool done = false;
+                const bs_status st = poller.check(done);
+                if (st != BS_OK) return st;
+                if (done) break;
+            }
         }
     }
     BS_LAUNCH(s, K_BIST_OTHER, "bist_decide", one_launch<BistDecide>, dim3(1), dim3(kRedBlock), 0,

@@ -11,6 +11,7 @@
 #include <cstdint>
 #include <cstring>
 #include <string>
+#include <unordered_map>
 
 #include "bsolve.h"
 
@@ -35,6 +36,84 @@ bs_status check_hip(hipError_t e, const char* what);
         hipError_t e_ = hipGetLastError();                           \
         if (e_ != hipSuccess) return ::bs::check_hip(e_, name);      \
     } while (0)
+
+// ---------------------------------------------------------------------------
+// Stop-flag polls.
+// ---------------------------------------------------------------------------
+// Convergence polls that do not idle the device.  check() enqueues a copy of
+// the device's stop flags into pinned host memory behind the launches made so
+// far, then waits only for the copy kLag check points back: the device always
+// has that many check periods of launches queued while the host reads flags.
+// The iterative kernels return at once after convergence, so the lag costs a
+// few microseconds per launch after it instead of a stream drain at every
+// check point.  The buffers and events belong to the calling thread (one set
+// per device); the destructor waits for the last copy, so that the next call
+// can reuse them.
+class StopPoller {
+  public:
+    static constexpr int kLag = 2;
+
+    // all_zero: stop once every flag reads 0 (per-image active counts); else
+    // once flag 0 reads nonzero (a done flag)
+    StopPoller(const int32_t* flags, int n, hipStream_t s, bool all_zero = true)
+        : flags_(flags), n_(n), s_(s), all_zero_(all_zero) {}
+    StopPoller(const StopPoller&) = delete;
+    StopPoller& operator=(const StopPoller&) = delete;
+    ~StopPoller() {
+        if (count_ > 0) (void)hipEventSynchronize(pool_->ev[(count_ - 1) % kSlots]);
+    }
+
+    // stop: an earlier check point found the stop condition
+    bs_status check(bool& stop) {
+        stop = false;
+        if (!pool_) {
+            int dev = 0;
+            BS_TRY_HIP(hipGetDevice(&dev));
+            static thread_local std::unordered_map<int, Pool> pools;
+            pool_ = &pools[dev];
+            if (!pool_->ev[0])
+                for (hipEvent_t& e : pool_->ev)
+                    BS_TRY_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+            if (pool_->cap < n_) {   // every earlier copy has completed (destructor)
+                if (pool_->host) BS_TRY_HIP(hipHostFree(pool_->host));
+                pool_->host = nullptr;
+                pool_->cap = 0;
+                BS_TRY_HIP(hipHostMalloc((void**)&pool_->host, sizeof(int32_t) * kSlots * n_,
+                                         hipHostMallocDefault));
+                pool_->cap = n_;
+            }
+        }
+        const int slot = count_ % kSlots;
+        BS_TRY_HIP(hipMemcpyAsync(pool_->host + (size_t)slot * n_, flags_, sizeof(int32_t) * n_,
+                                  hipMemcpyDeviceToHost, s_));
+        BS_TRY_HIP(hipEventRecord(pool_->ev[slot], s_));
+        ++count_;
+        if (count_ > kLag) {
+            const int old = (count_ - 1 - kLag) % kSlots;
+            BS_TRY_HIP(hipEventSynchronize(pool_->ev[old]));
+            const int32_t* f = pool_->host + (size_t)old * n_;
+            bool any = false;
+            for (int i = 0; i < n_; ++i) any = any || f[i] != 0;
+            stop = all_zero_ ? !any : f[0] != 0;
+        }
+        return BS_OK;
+    }
+
+  private:
+    static constexpr int kSlots = kLag + 1;
+    struct Pool {
+        int32_t* host = nullptr;   // pinned, [kSlots][cap]
+        int cap = 0;
+        hipEvent_t ev[kSlots] = {};
+    };
+    const int32_t* flags_;
+    int n_;
+    hipStream_t s_;
+    bool all_zero_;
+    Pool* pool_ = nullptr;
+    int count_ = 0;
+};
+
 
 // ---------------------------------------------------------------------------
 // Kernel timing hooks (see bs_timing.hip).

@@ -1471,7 +1471,7 @@ static bs_status run_pcg_k(const PcgArgs& a, int n, int G, int max_cp, bool sep,
     if (sep)
         BS_LAUNCH(s, K_PCG_REDUCE, "pcg_reduce", pcg_reduce<MULTI>, dim3(3 * max_cp, n), block, 0,
                   s, a, 0, 3);
-    std::vector<int32_t> poll(n);
+    StopPoller poller(act, n, s);
     int src = 0;   // the buffer holding d
     for (int it = 0; it < p.max_iters; ++it) {
         // with the hierarchical preconditioner every matvec is the exact form
@@ -1514,12 +1514,10 @@ static bs_status run_pcg_k(const PcgArgs& a, int n, int G, int max_cp, bool sep,
             BS_LAUNCH(s, K_PCG_REDUCE, "pcg_reduce", pcg_reduce<MULTI>, dim3(3 * max_cp, n), block,
                       0, s, a, 0, 3);
         if (p.check_every > 0 && (it + 1) % p.check_every == 0 && it + 1 < p.max_iters) {
-            BS_TRY_HIP(hipMemcpyAsync(poll.data(), act, sizeof(int32_t) * n,
-                                      hipMemcpyDeviceToHost, s));
-            BS_TRY_HIP(hipStreamSynchronize(s));
-            bool any = false;
-            for (int i = 0; i < n; ++i) any = any || poll[i] != 0;
-            if (!any) break;
+            bool stop = false;
+            const bs_status st = poller.check(stop);
+            if (st != BS_OK) return st;
+            if (stop) break;
         }
     }
     BS_LAUNCH(s, K_PCG_UPDATE, "pcg_flush", (pcg_flush<K, MULTI>), grid, block, 0, s, a, src);
