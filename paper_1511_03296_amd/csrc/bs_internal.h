@@ -48,10 +48,12 @@ bs_status check_hip(hipError_t e, const char* what);
 // few microseconds per launch after it instead of a stream drain at every
 // check point.  The buffers and events belong to the calling thread (one set
 // per device); the destructor waits for the last copy, so that the next call
-// can reuse them.
+// can reuse them.  A lag of one check point measured best: 2 % on the stereo
+// image and 15 % on the 64x48 one over a lag of two, whose extra launches
+// after convergence cost more than the host's wait saves.
 class StopPoller {
   public:
-    static constexpr int kLag = 2;
+    static constexpr int kLag = 1;
 
     // all_zero: stop once every flag reads 0 (per-image active counts); else
     // once flag 0 reads nonzero (a done flag)
