@@ -79,10 +79,14 @@ typedef struct bs_grid_params {
 /* Bistochastization (supplement Algorithm 1).  The iteration
  *     n <- sqrt(n o m / (B n)),  n = 1 initially
  * stops when max_v |n_v (B n)_v - m_v| / m_v <= tol or after max_iters
- * updates.  `check_every` > 0 makes the host read the device-side stop flag
- * after every `check_every` launches (a stream synchronisation); 0 enqueues
- * all max_iters + 1 launches without any synchronisation (graph-capturable;
- * launches after convergence do nothing). */
+ * updates.  `check_every` > 0 makes the host poll the device-side stop flag
+ * every `check_every` launches: the flag is copied to pinned host memory
+ * behind each check point and the host waits for the copy of the check point
+ * before (the device keeps one check period of launches queued, which do
+ * nothing once the fixed point is reached), and the call waits for its last
+ * copy before returning; 0 enqueues all max_iters + 1 launches without any
+ * synchronisation (graph-capturable; launches after convergence do
+ * nothing). */
 typedef struct bs_bistoch_params {
     int32_t max_iters;     /* default 200   */
     int32_t check_every;   /* default 8     */
