@@ -6,7 +6,8 @@ the API loads the library and raises ImportError if it has not been built
 (``python -m paper_1511_03296_amd.build``).
 """
 __all__ = ["BilateralGrid", "SolveOptions", "bilateral_solve", "read_stats", "BatchState",
-           "BatchPlan", "bilateral_solve_batch", "domain_transform", "dt_confidence"]
+           "BatchPlan", "bilateral_solve_batch", "domain_transform", "dt_confidence",
+           "NotConverged", "require_converged"]
 
 
 def __getattr__(name):

@@ -142,8 +142,11 @@ class BilateralGrid:
               rel_tol: float = 0.0, init: str = "hier", init_alpha: float = 4.0,
               init_beta: float = 0.0, check_every: int = 8, ws: torch.Tensor | None = None,
               y: torch.Tensor | None = None, stats: torch.Tensor | None = None,
-              precond: str = "jacobi", pre_alpha: float = 2.0, pre_beta: float = 5.0):
-        """Bilateral-space solution y [Vcap][C] and per-channel stats (device bytes)."""
+              precond: str = "jacobi", pre_alpha: float = 2.0, pre_beta: float = 5.0,
+              strict: bool = False):
+        """Bilateral-space solution y [Vcap][C] and per-channel stats (device bytes).
+        strict (with rel_tol > 0): raise NotConverged if a channel missed the
+        tolerance (reads the stats, so the call synchronises)."""
         C = int(target.shape[0])
         target = _dev_f32(target, "target", (C, self.H, self.W))
         conf = _dev_f32(conf, "confidence", (self.H, self.W))
@@ -160,6 +163,8 @@ class BilateralGrid:
                                ct.byref(p), y.data_ptr(), ws.data_ptr(), ws.numel(),
                                stats.data_ptr(), _stream()), "bs_solve")
         self._last_ws = ws
+        if strict and rel_tol > 0:
+            require_converged(stats, "solve")
         return y, stats
 
     def robust_solve(self, target: torch.Tensor, conf_init: torch.Tensor, lam: float,
@@ -226,8 +231,12 @@ class BilateralGrid:
                  init: str = "hier", init_alpha: float = 4.0, init_beta: float = 0.0,
                  check_every: int = 8, ws: torch.Tensor | None = None,
                  stats: torch.Tensor | None = None, want_g: bool = False,
-                 precond: str = "jacobi", pre_alpha: float = 2.0, pre_beta: float = 5.0):
-        """(dL/dt, dL/dc, dL/db or None) from dL/dx (Section 3)."""
+                 precond: str = "jacobi", pre_alpha: float = 2.0, pre_beta: float = 5.0,
+                 strict: bool = False):
+        """(dL/dt, dL/dc, dL/db or None, stats) from dL/dx (Section 3).  strict
+        (with rel_tol > 0): raise NotConverged if the adjoint solve missed the
+        tolerance, as when dL/dx does not vanish on a grid component without
+        confidence and A g = S dL/dx has no solution (synchronises)."""
         C = int(target.shape[0])
         target = _dev_f32(target, "target", (C, self.H, self.W))
         conf = _dev_f32(conf, "confidence", (self.H, self.W))
@@ -249,6 +258,8 @@ class BilateralGrid:
                                         ws.numel(), stats.data_ptr(), _stream()),
                 "bs_solve_backward")
         self._last_ws = ws
+        if strict and rel_tol > 0:
+            require_converged(stats, "adjoint solve")
         return gt, gc, g, stats
 
     def solve_ws_arrays(self, ws: torch.Tensor, C: int):
@@ -271,6 +282,29 @@ class BilateralGrid:
 def read_stats(stats: torch.Tensor) -> np.ndarray:
     """Per-channel solve stats (iters, reason, rel_residual, bnorm) as a NumPy record array."""
     return np.frombuffer(stats.cpu().numpy().tobytes(), dtype=_STATS_DTYPE)
+
+
+class NotConverged(RuntimeError):
+    """A solve to a tolerance stopped without meeting it."""
+
+
+# reasons of bs_chan_stats that end a solve to a tolerance without meeting it
+_FAILED = {2: "iteration cap reached", 4: "d^T A d <= 0"}
+
+
+def require_converged(stats: torch.Tensor, what: str = "solve") -> None:
+    """Raises NotConverged when a channel stopped at the iteration cap or on
+    d^T A d <= 0 instead of on the tolerance (the symptom of a system with no
+    solution, e.g. an adjoint whose dL/dx does not vanish on a grid component
+    without confidence, Section 3).  Reads the stats: synchronises."""
+    rec = read_stats(stats)
+    bad = [(c, int(r["reason"]), float(r["rel_residual"])) for c, r in enumerate(rec)
+           if int(r["reason"]) in _FAILED]
+    if bad:
+        detail = "; ".join(f"channel {c}: {_FAILED[k]}, rel. residual {res:.3g}"
+                           for c, k, res in bad[:4])
+        raise NotConverged(f"{what} did not meet its tolerance ({len(bad)} of {len(rec)} "
+                           f"channels): {detail}")
 
 
 def _dt_workspace(H: int, W: int, device, ws: torch.Tensor | None) -> torch.Tensor:

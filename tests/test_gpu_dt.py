@@ -48,6 +48,7 @@ def _run(ref, x, ss, sr, iters=3, inplace=False):
     (200, 300, 1, 64.0, 4.0),      # wide support, strong edges
     (1500, 37, 2, 8.0, 8.0),       # 24 rows per column segment
     (2049, 20, 1, 16.0, 32.0),     # 33 rows per segment: segments streamed
+    (33, 45, 64, 8.0, 4.0),        # the most channels a call takes
 ])
 def test_domain_transform_against_oracle(H, W, C, ss, sr):
     say(f"domain transform {H}x{W} C={C} sigma_s={ss} sigma_r={sr}")
