@@ -117,8 +117,10 @@ __device__ inline uint32_t code_dist(uint32_t a, uint32_t b) {
 // neighbour comes from the lane before (lane 0 reads it).  Every load of the
 // lane is issued before the first code is computed (rows past the image are
 // clamped to its last row and not stored; the pixel left of the row's first
-// to itself).
-constexpr int kDtStepRows = 4;
+// to itself).  One row per wave measured best: the pass is latency-bound, and
+// four rows per wave (the row above computed once per four) were 7 % slower
+// for a quarter of the waves.
+constexpr int kDtStepRows = 1;
 
 template <bool VEC>
 __global__ void __launch_bounds__(kBlock) dt_steps(const float* __restrict__ ref, int H, int W,
