@@ -278,16 +278,17 @@ def autograd_stats(inputs, spec, keep):
 
 class GraphForm:
     """The batch plan of the graph form: a calibration run that polls the stop
-    flags gives every image's iteration counts; the plan replayed from the
-    graph runs fixed caps above them (CAP_MARGIN), and the stats of every
-    replay say whether each channel stopped on the tolerance."""
+    flags gives every image's PCG and bistochastization iteration counts; the
+    plan replayed from the graph runs fixed caps above them (CAP_MARGIN), and
+    the stats of every replay say whether each channel stopped on the
+    tolerance and each grid's bistochastization before its cap."""
 
     def __init__(self, inputs, spec):
         self.inputs, self.spec = inputs, spec
         self.plan = None
         self.graphs = {}
 
-    def make(self, fwd_iters, bwd_iters, check_every):
+    def make(self, fwd_iters, bwd_iters, check_every, bist_iters=200):
         from paper_1511_03296_amd import BatchPlan, SolveOptions
         (_, ft), (_, bt) = self.spec["fwd"], self.spec["bwd"]
         lam = _lam(self.inputs)
@@ -295,7 +296,7 @@ class GraphForm:
                          [d["c"] for d in self.inputs], _sigmas(self.inputs),
                          SolveOptions(lam, fwd_iters, ft, check_every=check_every),
                          SolveOptions(lam, bwd_iters, bt, check_every=check_every),
-                         bist_check_every=check_every)
+                         bist_check_every=check_every, bist_max_iters=bist_iters)
         for g, d in zip(plan.grad_xs, self.inputs):
             g.copy_(d["gx"])
         return plan
@@ -311,6 +312,7 @@ class GraphForm:
         torch.cuda.synchronize()
         bst = [s.clone() for s in plan.stats]
         V = plan.vertex_counts()
+        bist = max(plan.bist_iters())
         plan.close()
         for i in range(len(V)):
             keep.append((V[i], fst[i], bst[i]))
@@ -319,6 +321,8 @@ class GraphForm:
         bmax = max(int(read_stats(s)["iters"].max()) for s in bst)
         self.caps = (int(math.ceil(fmax * CAP_MARGIN)) + CAP_EXTRA,
                      int(math.ceil(bmax * CAP_MARGIN)) + CAP_EXTRA)
+        # the bistochastization's updates are capped the same way
+        self.bist_cap = int(math.ceil(bist * CAP_MARGIN)) + CAP_EXTRA
         return self.caps
 
     def build(self):
@@ -326,7 +330,7 @@ class GraphForm:
         if self.plan is not None:
             self.plan.close()
         self.graphs = {}
-        self.plan = self.make(self.caps[0], self.caps[1], 0)
+        self.plan = self.make(self.caps[0], self.caps[1], 0, self.bist_cap)
         self.plan.forward()
         self.plan.backward()
         torch.cuda.synchronize()
@@ -348,7 +352,8 @@ class GraphForm:
         had a zero right-hand side)."""
         import torch
         torch.cuda.synchronize()
-        return all(set(s["reason"].tolist()) <= {1, 5} for s in self.plan.read_stats())
+        bist_ok = all(n < self.bist_cap for n in self.plan.bist_iters())
+        return bist_ok and all(set(s["reason"].tolist()) <= {1, 5} for s in self.plan.read_stats())
 
 
 def timed(step, steps):
@@ -582,11 +587,13 @@ def main() -> int:
         return 0
 
     keep, ranks = [], []
-    tuned, caps, converged, graph_form = None, None, None, None
+    tuned, caps, converged, graph_form, bist_cap = None, None, None, None, None
     if form == "graph":
         graph_form = GraphForm(inputs, spec)
         caps = graph_form.calibrate(keep)
-        print(f"bench: calibration run done, iteration caps {caps}", file=sys.stderr, flush=True)
+        bist_cap = graph_form.bist_cap
+        print(f"bench: calibration run done, iteration caps {caps}, bistochastization cap "
+              f"{bist_cap}", file=sys.stderr, flush=True)
         if not (args.no_autotune or args.profile):
             from paper_1511_03296_amd import autotune
 
@@ -716,6 +723,7 @@ def main() -> int:
                                    "pass": "forward only"}}
                       if spec.get("lowrank") is not None else {}),
                    **({"graph": {"iteration_caps": list(caps),
+                                 "bistochastization_cap": bist_cap,
                                  "all_channels_stopped_on_tolerance": converged}}
                       if caps else {}),
                    **({"lane_widths": {str(C): v["lane"]

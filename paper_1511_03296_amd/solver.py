@@ -591,6 +591,17 @@ class BatchPlan:
         L.check(L.lib.bs_batch_plan_grid(self._plan, int(i), ct.byref(g)), "bs_batch_plan_grid")
         return g
 
+    def bist_iters(self) -> list[int]:
+        """Bistochastization updates every image's grid took in the last
+        forward run (its cap when it did not converge; synchronises)."""
+        out = []
+        for i in range(self.n):
+            g = self.grid(i)
+            c = (ct.c_int32 * 3)()
+            L.check(L.lib.bs_read_counters(ct.byref(g), c, 3, _stream()), "bs_read_counters")
+            out.append(int(c[2]))   # the counter of updates applied
+        return out
+
     def vertex_counts(self) -> list[int]:
         """V of every image's grid (after a forward run; synchronises the stream)."""
         out = []
