@@ -626,6 +626,8 @@ struct Unpad {
 };
 
 // x[c][p] = y[idx[p]][c].
+constexpr int kSliceChunk = 4;   // channels per batch of loads (slice, gradient scatter)
+
 struct Slice {
     static constexpr int kThreads = kBlock;
     struct Args {
@@ -636,12 +638,28 @@ struct Slice {
     };
     __device__ static void run(const Args& a, int jb, int nb, int) {
         const int C = a.C, P = a.P;
+        const float* __restrict__ y = a.y;
+        float* __restrict__ x = a.x;
         const XcdTiles tl((P + kBlock - 1) / kBlock, jb, nb);
         for (int64_t tile = tl.first; tile < tl.end; tile += tl.step) {
             const int p = (int)(tile * kBlock) + threadIdx.x;
             if (p >= P) continue;
             const int64_t v = a.idx[p];
-            for (int c = 0; c < C; ++c) a.x[(int64_t)c * P + p] = a.y[v * C + c];
+            // kSliceChunk channels' loads issued together (channels past C read
+            // channel C - 1 and are not stored): a load and store per channel
+            // would wait for each load in turn
+            if (C == 1) {
+                x[p] = y[v];
+                continue;
+            }
+            for (int c0 = 0; c0 < C; c0 += kSliceChunk) {
+                float t[kSliceChunk];
+#pragma unroll
+                for (int k = 0; k < kSliceChunk; ++k) t[k] = y[v * C + min(c0 + k, C - 1)];
+#pragma unroll
+                for (int k = 0; k < kSliceChunk; ++k)
+                    if (c0 + k < C) x[(int64_t)(c0 + k) * P + p] = t[k];
+            }
         }
     }
 };
@@ -666,6 +684,10 @@ struct GradScatter {
     };
     __device__ static void run(const Args& a, int jb, int nb, int) {
         const int C = a.C, P = a.P, Cg = a.Cg;
+        const float* __restrict__ g = a.g;
+        const float* __restrict__ yhat = a.yhat;
+        const float* __restrict__ target = a.target;
+        float* __restrict__ gt = a.gt;
         const XcdTiles tl((P + kBlock - 1) / kBlock, jb, nb);
         for (int64_t tile = tl.first; tile < tl.end; tile += tl.step) {
             const int p = (int)(tile * kBlock) + threadIdx.x;
@@ -673,11 +695,30 @@ struct GradScatter {
             const int64_t v = a.idx[p];
             const float cp = a.conf[p];
             double s = 0.0;
-            for (int c = 0; c < C; ++c) {
-                const float gv = a.g[v * Cg + c];
-                a.gt[(int64_t)c * P + p] = cp * gv;
-                s = fma((double)gv,
-                        (double)a.target[(int64_t)c * P + p] - (double)a.yhat[v * C + c], s);
+            // as in the slice, kSliceChunk channels' loads at a time; the
+            // channels are summed in order
+            if (C == 1) {
+                const float gv = g[v * Cg];
+                gt[p] = cp * gv;
+                a.gc[p] = (float)((double)gv * ((double)target[p] - (double)yhat[v]));
+                continue;
+            }
+            for (int c0 = 0; c0 < C; c0 += kSliceChunk) {
+                float gv[kSliceChunk], tv[kSliceChunk], yv[kSliceChunk];
+#pragma unroll
+                for (int k = 0; k < kSliceChunk; ++k) {
+                    const int c = min(c0 + k, C - 1);
+                    gv[k] = g[v * Cg + c];
+                    tv[k] = target[(int64_t)c * P + p];
+                    yv[k] = yhat[v * C + c];
+                }
+#pragma unroll
+                for (int k = 0; k < kSliceChunk; ++k) {
+                    if (c0 + k < C) {
+                        gt[(int64_t)(c0 + k) * P + p] = cp * gv[k];
+                        s = fma((double)gv[k], (double)tv[k] - (double)yv[k], s);
+                    }
+                }
             }
             a.gc[p] = (float)s;
         }
