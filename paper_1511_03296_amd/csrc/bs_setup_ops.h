@@ -108,6 +108,7 @@ struct SplatCells {
     __device__ static void run(const Args& a, int c, int, int) {
         __shared__ float cv[CAP];
         __shared__ int32_t lst[CAP];
+        __shared__ int32_t sp[CAP + 1];   // the cell's vertex CSR, relative to ibase
         __shared__ float tv[kSplatVals];
         const int32_t* __restrict__ ptr = a.ptr;
         const float* __restrict__ vals = a.vals;
@@ -126,9 +127,10 @@ struct SplatCells {
             const int py = pq / W;
             lst[j] = (py - y0) * wx + (pq - py * W - x0);
         }
+        for (int k = threadIdx.x; k <= cnt; k += B) sp[k] = ptr[vbase + k] - ibase;
         __syncthreads();
         for (int k = threadIdx.x; k < cnt; k += B) {
-            const int s0 = ptr[vbase + k] - ibase, s1 = ptr[vbase + k + 1] - ibase;
+            const int s0 = sp[k], s1 = sp[k + 1];
             double sc = 0.0;
             int q = s0;
             // four pixels' LDS reads issued together, summed in ascending order
@@ -152,15 +154,26 @@ struct SplatCells {
         for (int c0 = 0; c0 < C; c0 += CH) {
             const int cn = min(CH, C - c0);
             __syncthreads();
-            for (int e = threadIdx.x; e < cn * n; e += B) {
+            // eight values' loads issued together while all eight exist
+            const int tot = cn * n;
+            auto val = [&](int e) {
                 const int cc = e / n, j = e - cc * n;
                 const int r = j / wx;
-                tv[cc * n + j] = vals[(int64_t)(c0 + cc) * P + (y0 + r) * W + x0 + (j - r * wx)];
+                return vals[(int64_t)(c0 + cc) * P + (y0 + r) * W + x0 + (j - r * wx)];
+            };
+            int e0 = threadIdx.x;
+            for (; e0 + 7 * B < tot; e0 += 8 * B) {
+                float t8[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) t8[u] = val(e0 + u * B);
+#pragma unroll
+                for (int u = 0; u < 8; ++u) tv[e0 + u * B] = t8[u];
             }
+            for (; e0 < tot; e0 += B) tv[e0] = val(e0);
             __syncthreads();
             for (int e = threadIdx.x; e < cnt * cn; e += B) {
                 const int k = e / cn, cc = e - k * cn;
-                const int s0 = ptr[vbase + k] - ibase, s1 = ptr[vbase + k + 1] - ibase;
+                const int s0 = sp[k], s1 = sp[k + 1];
                 const float* __restrict__ tc = tv + cc * n;
                 double acc = 0.0;
                 int q = s0;
