@@ -243,6 +243,26 @@ struct FlatInit {
 
 // Pyramid lift, level k >= 1: child sums of level k-1 for C channels of b and
 // S c (channel C).  up_k[u][ch] = sum over children of the child's value.
+// Sum over the children clist[j0 .. j1) of get(child), in ascending order,
+// four children's loads issued together.
+template <class F>
+__device__ inline double sum_children(const int32_t* __restrict__ clist, int j0, int j1, F get) {
+    double s = 0.0;
+    int j = j0;
+    for (; j + 4 <= j1; j += 4) {
+        int c[4];
+        float v[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) c[q] = clist[j + q];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) v[q] = get(c[q]);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) s += (double)v[q];
+    }
+    for (; j < j1; ++j) s += (double)get(clist[j]);
+    return s;
+}
+
 struct PyrUp {
     static constexpr int kThreads = kBlock;
     struct Args {
@@ -268,12 +288,17 @@ struct PyrUp {
             const int64_t e = tile * kBlock + threadIdx.x;
             if (e >= n) continue;
             const int u = (int)(e / C1), ch = (int)(e - (int64_t)u * C1);
-            double s = 0.0;
-            for (int j = a.cptr[u]; j < a.cptr[u + 1]; ++j) {
-                const int c = a.clist[j];
-                if (prev) s += (double)prev[(int64_t)c * C1 + ch];
-                else s += (double)(ch < C ? a.b[(int64_t)c * C + ch] : a.sc[c]);
-            }
+            const int j0 = a.cptr[u], j1 = a.cptr[u + 1];
+            // the level below, or at level 1 [b | S c] (both read, one kept:
+            // no load under a branch inside the sum)
+            const double s =
+                prev ? sum_children(a.clist, j0, j1,
+                                    [&](int c) { return prev[(int64_t)c * C1 + ch]; })
+                     : sum_children(a.clist, j0, j1, [&](int c) {
+                           const float bv = a.b[(int64_t)c * C + min(ch, C - 1)];
+                           const float sv = a.sc[c];
+                           return ch < C ? bv : sv;
+                       });
             a.up[e] = (float)s;
         }
     }
@@ -335,25 +360,6 @@ struct PyrSmall {
         const int32_t* counts;
         int C;
     };
-    // Sum over the children clist[j0 .. j1) of get(child), in ascending order,
-    // four children's loads issued together.
-    template <class F>
-    __device__ static double sum_children(const int32_t* clist, int j0, int j1, F get) {
-        double s = 0.0;
-        int j = j0;
-        for (; j + 4 <= j1; j += 4) {
-            int c[4];
-            float v[4];
-#pragma unroll
-            for (int q = 0; q < 4; ++q) c[q] = clist[j + q];
-#pragma unroll
-            for (int q = 0; q < 4; ++q) v[q] = get(c[q]);
-#pragma unroll
-            for (int q = 0; q < 4; ++q) s += (double)v[q];
-        }
-        for (; j < j1; ++j) s += (double)get(clist[j]);
-        return s;
-    }
     __device__ static void run(const Args& A, int, int, int) {
         const PyrLevels& a = A.lv;
         const int K = A.counts[CNT_K];
@@ -468,11 +474,12 @@ struct PrecLift {
         for (int64_t tile = tl.first; tile < tl.end; tile += tl.step) {
             const int u = (int)(tile * kBlock) + threadIdx.x;
             if (u >= Vk) continue;
-            double s = 0.0;
-            for (int j = a.cptr[u]; j < a.cptr[u + 1]; ++j) {
-                const int c = a.clist[j];
-                s += a.prev ? (double)a.prev[(int64_t)c * C1 + a.Cp] : (double)a.diag[c];
-            }
+            const int j0 = a.cptr[u], j1 = a.cptr[u + 1];
+            const float* __restrict__ prev = a.prev;
+            const double s =
+                prev ? sum_children(a.clist, j0, j1,
+                                    [&](int c) { return prev[(int64_t)c * C1 + a.Cp]; })
+                     : sum_children(a.clist, j0, j1, [&](int c) { return a.diag[c]; });
             a.up[(int64_t)u * C1 + a.Cp] = (float)s;
         }
     }
@@ -527,11 +534,13 @@ struct PrecUp {
             const int64_t e = tile * kBlock + threadIdx.x;
             if (e >= n) continue;
             const int u = (int)(e / Cp), ch = (int)(e - (int64_t)u * Cp);
-            double s = 0.0;
-            for (int j = a.cptr[u]; j < a.cptr[u + 1]; ++j) {
-                const int c = a.clist[j];
-                s += a.prev ? (double)a.prev[(int64_t)c * C1 + ch] : (double)a.r[(int64_t)c * Cp + ch];
-            }
+            const int j0 = a.cptr[u], j1 = a.cptr[u + 1];
+            const float* __restrict__ prev = a.prev;
+            const double s =
+                prev ? sum_children(a.clist, j0, j1,
+                                    [&](int c) { return prev[(int64_t)c * C1 + ch]; })
+                     : sum_children(a.clist, j0, j1,
+                                    [&](int c) { return a.r[(int64_t)c * Cp + ch]; });
             a.up[(int64_t)u * C1 + ch] = (float)s;
         }
     }
@@ -586,11 +595,12 @@ struct PrecSmall {
             const int64_t n = (int64_t)Vk * Cp;
             for (int64_t e = threadIdx.x; e < n; e += kThreads) {
                 const int u = (int)(e / Cp), ch = (int)(e - (int64_t)u * Cp);
-                double s = 0.0;
-                for (int j = a.cptr[k][u]; j < a.cptr[k][u + 1]; ++j) {
-                    const int c = a.clist[k][j];
-                    s += prev ? (double)prev[(int64_t)c * C1 + ch] : (double)A.r[(int64_t)c * Cp + ch];
-                }
+                const int j0 = a.cptr[k][u], j1 = a.cptr[k][u + 1];
+                const double s =
+                    prev ? sum_children(a.clist[k], j0, j1,
+                                        [&](int c) { return prev[(int64_t)c * C1 + ch]; })
+                         : sum_children(a.clist[k], j0, j1,
+                                        [&](int c) { return A.r[(int64_t)c * Cp + ch]; });
                 a.up[k][(int64_t)u * C1 + ch] = (float)s;
             }
             __syncthreads();
