@@ -41,3 +41,30 @@ def test_singular_adjoint_raises_when_strict():
     assert all(r in (2, 4) for r in reasons), reasons
     with pytest.raises(NotConverged):
         G.backward(t, zero, y, gx, p.lam, max_iters=300, rel_tol=1e-6, strict=True)
+
+
+@pytest.mark.parametrize("every", [1, 3, 8])
+def test_polled_runs_equal_unpolled_runs(every):
+    """Polls read the stop flags one check point behind while more launches
+    are queued; those launches change nothing once every channel has stopped,
+    so a polled solve, adjoint and bistochastization equal the runs that
+    enqueue every launch without polling (check_every = 0), bit for bit."""
+    from paper_1511_03296_amd import BilateralGrid, read_stats
+    p = WL.tiny_ramp(seed=3, channels=2)
+    say(f"polled (every {every}) against unpolled runs, 64x48 ramp, C=2")
+    ref, t, c = to_dev(p.ref), to_dev(p.target), to_dev(p.conf)
+    gx = to_dev(WL.random_grad(3, p.C, p.H, p.W))
+    out = []
+    for ce in (every, 0):
+        G = BilateralGrid(ref, p.sigma_xy, p.sigma_l, p.sigma_uv, check_every=ce)
+        y, st = G.solve(t, c, p.lam, max_iters=2000, rel_tol=1e-5, check_every=ce)
+        gt, gc, _, bst = G.backward(t, c, y, gx, p.lam, max_iters=2000, rel_tol=1e-6,
+                                    check_every=ce)
+        torch.cuda.synchronize()
+        V = G.vertex_count()   # rows of y past V are not written
+        out.append((G.counters(4), y[:V].clone(), gt.clone(), gc.clone(),
+                    read_stats(st)["iters"].tolist(), read_stats(bst)["iters"].tolist()))
+    (k1, y1, t1, c1, i1, b1), (k0, y0, t0, c0, i0, b0) = out
+    assert k1[2] == k0[2]            # bistochastization updates
+    assert i1 == i0 and b1 == b0     # PCG iterations per channel
+    assert torch.equal(y1, y0) and torch.equal(t1, t0) and torch.equal(c1, c0)
