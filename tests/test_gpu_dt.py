@@ -49,6 +49,9 @@ def _run(ref, x, ss, sr, iters=3, inplace=False):
     (1500, 37, 2, 8.0, 8.0),       # 24 rows per column segment
     (2049, 20, 1, 16.0, 32.0),     # 33 rows per segment: segments streamed
     (33, 45, 64, 8.0, 4.0),        # the most channels a call takes
+    (513, 28, 1, 8.0, 8.0),        # 9 rows per segment (first past 8)
+    (1024, 36, 2, 16.0, 8.0),      # 16 rows per segment exactly
+    (2048, 12, 1, 32.0, 16.0),     # 32 rows per segment exactly: the last in registers
 ])
 def test_domain_transform_against_oracle(H, W, C, ss, sr):
     say(f"domain transform {H}x{W} C={C} sigma_s={ss} sigma_r={sr}")
