@@ -460,18 +460,6 @@ __device__ inline void LevelWrite<B, CAP, Src>::run(const Args& a, int c, int, i
     }
 }
 
-// Binary search of `want` in the ascending keys [s, e); -1 if absent.
-__device__ inline int find_key(const uint64_t* __restrict__ key, int s, int e, uint64_t want) {
-    while (s < e) {
-        const int mid = (s + e) >> 1;
-        const uint64_t k = key[mid];
-        if (k == want) return mid;
-        if (k < want) s = mid + 1;
-        else e = mid;
-    }
-    return -1;
-}
-
 // Neighbour table of level 0: for each vertex and unit step along each of
 // (y, x, l, u, v), the neighbour's id or -1.  Colour neighbours share the
 // vertex's spatial cell; spatial neighbours lie in the adjacent cell; both are
@@ -502,6 +490,7 @@ __device__ inline void NeighbourTable::run(const Args& a, int jb, int nb, int) {
     const int64_t vcap = a.vcap;
     const int ncx = a.ncx, ncy = a.ncy;
     const int V = counts[CNT_V];
+    const int ncells = ncx * ncy;
     const XcdTiles tl((V + kBlock - 1) / kBlock, jb, nb);
     for (int64_t tile = tl.first; tile < tl.end; tile += tl.step) {
         const int v = (int)(tile * kBlock) + threadIdx.x;
@@ -509,29 +498,60 @@ __device__ inline void NeighbourTable::run(const Args& a, int jb, int nb, int) {
         const uint64_t k = key[v];
         const int cy = (int)(k >> 40), cx = (int)((k >> 24) & 0xffff);
         const int cell = cy * ncx + cx;
-        const int s = vbase[cell], e = vbase[cell + 1];
-        int rr[10];
-        // y
-        rr[0] = rr[1] = -1;
-        if (cy > 0) {
-            const int cc = cell - ncx;
-            rr[0] = find_key(key, vbase[cc], vbase[cc + 1], k - (1ull << 40));
-        }
-        if (cy + 1 < ncy) {
-            const int cc = cell + ncx;
-            rr[1] = find_key(key, vbase[cc], vbase[cc + 1], k + (1ull << 40));
-        }
-        // x
-        rr[2] = rr[3] = -1;
-        if (cx > 0) rr[2] = find_key(key, vbase[cell - 1], vbase[cell], k - (1ull << 24));
-        if (cx + 1 < ncx) rr[3] = find_key(key, vbase[cell + 1], vbase[cell + 2], k + (1ull << 24));
-        // l, u, v within the cell
+        // the key ranges of the ten searches: the cells above, below, left and
+        // right (read from clamped cell indices, empty where there is no such
+        // cell), and the vertex's own cell for the colour steps
+        const int up = max(cell - ncx, 0), dn = min(cell + ncx, ncells - 1);
+        const int lf = max(cell - 1, 0), rt = min(cell + 1, ncells - 1);
+        const int b_up0 = vbase[up], b_up1 = vbase[up + 1];
+        const int b_dn0 = vbase[dn], b_dn1 = vbase[dn + 1];
+        const int b_lf0 = vbase[lf], s = vbase[cell], e = vbase[cell + 1];
+        const int b_rt1 = vbase[rt + 1];
+        int lo[10], hi[10];
+        uint64_t want[10];
+        lo[0] = b_up0; hi[0] = cy > 0 ? b_up1 : b_up0; want[0] = k - (1ull << 40);
+        lo[1] = b_dn0; hi[1] = cy + 1 < ncy ? b_dn1 : b_dn0; want[1] = k + (1ull << 40);
+        lo[2] = b_lf0; hi[2] = cx > 0 ? s : b_lf0; want[2] = k - (1ull << 24);
+        lo[3] = e; hi[3] = cx + 1 < ncx ? b_rt1 : e; want[3] = k + (1ull << 24);
 #pragma unroll
         for (int d = 0; d < 3; ++d) {
             const int sh = 16 - 8 * d;
             const int f = (int)((k >> sh) & 0xff);
-            rr[4 + 2 * d] = f > 0 ? find_key(key, s, e, k - (1ull << sh)) : -1;
-            rr[5 + 2 * d] = f < 255 ? find_key(key, s, e, k + (1ull << sh)) : -1;
+            lo[4 + 2 * d] = s;
+            hi[4 + 2 * d] = f > 0 ? e : s;
+            want[4 + 2 * d] = k - (1ull << sh);
+            lo[5 + 2 * d] = s;
+            hi[5 + 2 * d] = f < 255 ? e : s;
+            want[5 + 2 * d] = k + (1ull << sh);
+        }
+        // the ten binary searches in lockstep: every round reads the midpoint
+        // of each unfinished search (finished ones read key 0), so their loads
+        // are in flight together rather than one search's chain after another
+        int rr[10];
+#pragma unroll
+        for (int j = 0; j < 10; ++j) rr[j] = -1;
+        for (bool any = true; any;) {
+            int mid[10];
+            uint64_t kv[10];
+#pragma unroll
+            for (int j = 0; j < 10; ++j) mid[j] = lo[j] < hi[j] ? (lo[j] + hi[j]) >> 1 : 0;
+#pragma unroll
+            for (int j = 0; j < 10; ++j) kv[j] = key[mid[j]];
+            any = false;
+#pragma unroll
+            for (int j = 0; j < 10; ++j) {
+                if (lo[j] < hi[j]) {
+                    if (kv[j] == want[j]) {
+                        rr[j] = mid[j];
+                        hi[j] = lo[j];
+                    } else if (kv[j] < want[j]) {
+                        lo[j] = mid[j] + 1;
+                    } else {
+                        hi[j] = mid[j];
+                    }
+                    any = any || lo[j] < hi[j];
+                }
+            }
         }
         bool fits = true;
 #pragma unroll
