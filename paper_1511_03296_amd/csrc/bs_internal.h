@@ -47,7 +47,9 @@ bs_status check_hip(hipError_t e, const char* what);
 // The iterative kernels return at once after convergence, so the lag costs a
 // few microseconds per launch after it instead of a stream drain at every
 // check point.  The buffers and events belong to the calling thread (one set
-// per device); the destructor waits for the last copy, so that the next call
+// per device, a few bytes per image, kept until the process ends: freeing
+// them from thread-exit destructors could run after the runtime's own
+// teardown); the destructor waits for the last copy, so that the next call
 // can reuse them.  A lag of one check point measured best: 2 % on the stereo
 // image and 15 % on the 64x48 one over a lag of two, whose extra launches
 // after convergence cost more than the host's wait saves.
